@@ -1,0 +1,289 @@
+"""Pins for the CPU oracle, independent of the oracle's own formulas.
+
+Each test ties a piece of the oracle to something the paper or mathematics
+fixes: closed forms of the kernel modes, a different series representation of
+them, brute-force quadrature of the physical-space operator, conservation,
+exact solutions and the fugacities printed in the table captions.
+"""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy import special
+
+import bnq_inputs as inp
+import oracle
+from tests.carleman_bruteforce import bruteforce_modes
+
+R = oracle.R_DEFAULT
+
+
+# ---------------------------------------------------------------- kernel modes
+def test_beta_at_origin_closed_forms():
+    # beta(0,0) = Btilde |B_R|-measure of {z.y = 0}: 2D 8 pi C R^2, 3D 8 pi^2 C R^4
+    for C in (1.0, 0.7):
+        b2 = oracle.beta_pairs(2, [[0, 0]], [[0, 0]], Cphi=C)[0]
+        b3 = oracle.beta_pairs(3, [[0, 0, 0]], [[0, 0, 0]], Cphi=C)[0]
+        assert b2 == pytest.approx(8 * math.pi * C * R * R, rel=1e-15)
+        assert b3 == pytest.approx(8 * math.pi ** 2 * C * R ** 4, rel=1e-15)
+
+
+def test_beta_3d_one_argument_zero_closed_form():
+    # beta(k,0) = beta(0,k) = 16 pi^2 C R^2 (1 - cos(R|k|)) / |k|^2.  The
+    # (0,k) side integrates psi over the sphere and so also pins the reading
+    # psi(s) = 2 pi R J1(Rs)/s (no sin factor in the great-circle measure).
+    rng = np.random.default_rng(3)
+    ks = rng.integers(-40, 41, size=(40, 3))
+    ks = ks[np.any(ks != 0, axis=1)]
+    z = np.zeros_like(ks)
+    s = np.linalg.norm(ks, axis=1)
+    exact = 16 * math.pi ** 2 * R * R * (1 - np.cos(R * s)) / s ** 2
+    assert np.max(np.abs(oracle.beta_pairs(3, ks, z) - exact)) < 1e-12
+    assert np.max(np.abs(oracle.beta_pairs(3, z, ks) - exact)) < 1e-12
+
+
+def test_beta_2d_one_argument_zero_closed_form():
+    # beta(k,0) = 8 pi C R^2 (1/x) int_0^x J0,  x = R|k|
+    #           = 8 pi C R^2 [J0(x) + (pi/2)(J1(x) H0(x) - J0(x) H1(x))]
+    rng = np.random.default_rng(4)
+    ks = rng.integers(-45, 46, size=(40, 2))
+    ks = ks[np.any(ks != 0, axis=1)]
+    x = R * np.linalg.norm(ks, axis=1)
+    intJ0 = x * special.j0(x) + math.pi * x / 2 * (special.j1(x) * special.struve(0, x)
+                                                   - special.j0(x) * special.struve(1, x))
+    exact = 8 * math.pi * R * R * intJ0 / x
+    z = np.zeros_like(ks)
+    assert np.max(np.abs(oracle.beta_pairs(2, ks, z) - exact)) < 1e-12
+    assert np.max(np.abs(oracle.beta_pairs(2, z, ks) - exact)) < 1e-12
+
+
+def _series_3d(a, b, dps=25):
+    # Funk–Hecke form of the same integral: plane-wave expansion of both
+    # exponentials; the great-circle constraint keeps even orders only.
+    mp.mp.dps = dps
+    Rm = 2 * mp.pi / (3 + mp.sqrt(2))
+    na, nb = mp.sqrt(sum(x * x for x in a)), mp.sqrt(sum(x * x for x in b))
+    cg = 0 if na == 0 or nb == 0 else mp.mpf(sum(x * y for x, y in zip(a, b))) / (na * nb)
+    nmax = int(float(Rm) * float(max(na, nb))) + 40
+    tot = mp.mpf(0)
+    for n in range(0, nmax + 1, 2):
+        Ja = mp.quad(lambda r: r * mp.besselj(n + 0.5, r * na) * mp.sqrt(mp.pi / (2 * r * na)) if na else
+                     (r if n == 0 else 0), [0, Rm])
+        Jb = mp.quad(lambda r: r * mp.besselj(n + 0.5, r * nb) * mp.sqrt(mp.pi / (2 * r * nb)) if nb else
+                     (r if n == 0 else 0), [0, Rm])
+        tot += (2 * n + 1) * mp.legendre(n, 0) * mp.legendre(n, cg) * Ja * Jb
+    return float(32 * mp.pi ** 2 * tot)
+
+
+def _series_2d(a, b, dps=25):
+    # Jacobi–Anger form of the same integral.
+    mp.mp.dps = dps
+    Rm = 2 * mp.pi / (3 + mp.sqrt(2))
+    na, nb = mp.sqrt(a[0] ** 2 + a[1] ** 2), mp.sqrt(b[0] ** 2 + b[1] ** 2)
+    g = mp.atan2(a[0] * b[1] - a[1] * b[0], a[0] * b[0] + a[1] * b[1])
+    nmax = int(float(Rm) * float(max(na, nb))) + 40
+    tot = mp.mpf(0)
+    for n in range(0, nmax + 1, 2):
+        An = mp.quad(lambda r: mp.besselj(n, r * na), [0, Rm])
+        Bn = mp.quad(lambda r: mp.besselj(n, r * nb), [0, Rm])
+        tot += (1 if n == 0 else 2) * (-1) ** (n // 2) * An * Bn * mp.cos(n * g)
+    return float(8 * mp.pi * tot)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_beta_matches_independent_series(d):
+    rng = np.random.default_rng(11 + d)
+    a = rng.integers(-9, 10, size=(4, d))
+    b = rng.integers(-9, 10, size=(4, d))
+    got = oracle.beta_pairs(d, a, b)
+    ref = [(_series_2d if d == 2 else _series_3d)(list(map(int, x)), list(map(int, y))) for x, y in zip(a, b)]
+    assert np.max(np.abs(got - np.array(ref))) < 1e-12
+
+
+@pytest.mark.parametrize("d,M", [(2, 45), (3, 55)])
+def test_beta_node_rule_converged(d, M):
+    rng = np.random.default_rng(5)
+    a = rng.integers(-M // 1.7, M // 1.7, size=(60, d))
+    b = rng.integers(-M // 1.7, M // 1.7, size=(60, d))
+    v1 = oracle.beta_pairs(d, a, b)
+    v2 = oracle.beta_pairs(d, a, b, scale=2.0)
+    assert np.max(np.abs(v1 - v2)) < 1e-12
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_beta_symmetries(d):
+    # evenness in each argument, symmetry in (k,l) (Btilde symmetric for b = 1),
+    # invariance under a common signed permutation of the axes
+    rng = np.random.default_rng(7)
+    a = rng.integers(-12, 13, size=(30, d))
+    b = rng.integers(-12, 13, size=(30, d))
+    base = oracle.beta_pairs(d, a, b, scale=1.3)
+    assert np.max(np.abs(oracle.beta_pairs(d, -a, b, scale=1.3) - base)) < 1e-12
+    assert np.max(np.abs(oracle.beta_pairs(d, a, -b, scale=1.3) - base)) < 1e-12
+    assert np.max(np.abs(oracle.beta_pairs(d, b, a, scale=1.3) - base)) < 1e-12
+    perm = rng.permutation(d)
+    sg = np.array([1, -1, -1][:d])
+    assert np.max(np.abs(oracle.beta_pairs(d, a[:, perm] * sg, b[:, perm] * sg, scale=1.3) - base)) < 1e-12
+
+
+# ---------------------------------------------------------------- DFT
+def test_dft_single_mode_and_round_trip():
+    N = 8
+    k = np.array([2, -3])
+    j = oracle.modes(N)
+    J = np.meshgrid(j, j, indexing="ij")
+    f = np.cos(2 * math.pi * (k[0] * J[0] + k[1] * J[1]) / N)
+    G = oracle.dft(f)
+    assert G[k[0] + 4, k[1] + 4] == pytest.approx(0.5, abs=1e-15)
+    assert G[-k[0] + 4, -k[1] + 4] == pytest.approx(0.5, abs=1e-15)
+    G[k[0] + 4, k[1] + 4] = G[-k[0] + 4, -k[1] + 4] = 0
+    assert np.max(np.abs(G)) < 1e-15
+    rng = np.random.default_rng(0)
+    g = rng.standard_normal((6, 6, 6))
+    assert np.max(np.abs(oracle.idft_real(oracle.dft(g)) - g)) < 1e-14
+
+
+# ---------------------------------------------------------------- Galerkin sums
+def _random_ghat(d, N, seed):
+    rng = np.random.default_rng(seed)
+    return oracle.dft(rng.standard_normal((N,) * d))
+
+
+@pytest.mark.parametrize("d,N,nodes", [(2, 4, (48, 16)), (2, 6, (64, 24)), (3, 2, (12, 20, 14, 10))])
+def test_galerkin_sums_equal_bruteforce_carleman(d, N, nodes):
+    G = _random_ghat(d, N, 100 + N)
+    tab = oracle.beta_table(d, N)
+    s = oracle.galerkin_sums(d, N, G, tab, want=("c", "q"))
+    bc, bq = bruteforce_modes(G, R, nodes=nodes)
+    scale_c = np.max(np.abs(s["c"]))
+    scale_q = np.max(np.abs(s["q"]))
+    assert np.max(np.abs(bc - s["c"])) < 1e-13 * max(1.0, scale_c)
+    assert np.max(np.abs(bq - s["q"])) < 1e-13 * max(1.0, scale_q)
+
+
+@pytest.mark.parametrize("d,N", [(2, 8), (3, 4)])
+def test_factored_equals_direct_triple_sum(d, N):
+    G = _random_ghat(d, N, 7)
+    tab = oracle.beta_table(d, N)
+    s = oracle.galerkin_sums(d, N, G, tab, want=("q", "t1"))
+    W, X = oracle.factored_sums(d, N, G, tab)
+    scale = np.max(np.abs(s["q"]))
+    assert np.max(np.abs(s["t1"] + X - s["q"])) < 1e-13 * scale
+    # W vanishes outside E = {-N..N-2}^d
+    Wr = np.abs(W)
+    assert np.max(Wr[(slice(None),) * (d - 1) + (-1,)]) == 0.0
+
+
+@pytest.mark.parametrize("d,N", [(2, 8), (3, 4)])
+def test_mass_conservation_exact(d, N):
+    # Qc_0 vanishes term by term (beta even in its second argument);
+    # Qq_0 vanishes by the cyclic symmetry of the triple sum.
+    rng = np.random.default_rng(9)
+    f = rng.uniform(0.1, 1.0, size=(N,) * d)
+    G = oracle.dft(f)
+    tab = oracle.beta_table(d, N)
+    s = oracle.galerkin_sums(d, N, G, tab, want=("c", "q"))
+    z = (N // 2,) * d
+    assert s["c"][z] == 0.0
+    assert abs(s["q"][z]) < 1e-14 * np.max(np.abs(s["q"]))
+
+
+@pytest.mark.parametrize("d,N", [(2, 8), (3, 4)])
+def test_constant_is_stationary(d, N):
+    o = oracle.Oracle(d, N)
+    f = np.full((N,) * d, 0.37)
+    for eps in (-1, 0, 1):
+        Q, Qh = o.collide(f, eps, L=5.0)
+        assert np.max(np.abs(Q)) < 1e-14
+
+
+def test_sparse_spectrum_matches_dense():
+    d, N = 2, 8
+    f, sm, co = inp.sparse_spectrum(d, N, seed=2, nmodes=5)
+    o = oracle.Oracle(d, N)
+    m = o.modes(f, eps=1)
+    Qc, T1, Xq = oracle.sparse_modes(d, N, sm, co, eps=1)
+    for dense, sp in ((m["Qc"], Qc), (m["T1"], T1), (m["Xq"], Xq)):
+        assert np.max(np.abs(dense - oracle.sparse_dense(d, N, sp))) < 1e-12 * np.max(np.abs(dense))
+
+
+# ---------------------------------------------------------------- exact solutions
+def test_bkw_fourth_moment_rate():
+    # Classical 2-D Maxwell molecules, B = C_phi = 1: for the BKW datum
+    # (K = 1/2) the fourth moment obeys dM4/dt = -(pi C/2)(M4 - 2 M2^2),
+    # i.e. dM4/dt = pi at t = 0 (M2 = 2, M4 = 6).  This fixes the whole chain
+    # Btilde = 2 C_phi, the kernel modes and the factor c (L/pi)^(d+gamma) up
+    # to the collision truncation |x|, |y| <= R = S, which costs ~1% here.
+    N, L = 48, 12.0
+    f0 = inp.bkw_2d(N, L, t=0.0, lam=1.0)
+    o = oracle.Oracle(2, N)
+    Q, _ = o.collide(f0, eps=0, L=L)
+    v = inp.velocity_grid(2, N, L)
+    r2 = np.sum(v * v, axis=-1)
+    dv = inp.cell_volume(2, N, L)
+    assert dv * np.sum(f0) == pytest.approx(1.0, abs=1e-9)
+    assert dv * np.sum(r2 ** 2 * f0) == pytest.approx(6.0, abs=1e-6)
+    dM4 = dv * np.sum(r2 ** 2 * Q)
+    assert dM4 == pytest.approx(math.pi, rel=2e-2)
+    # mass and energy rates vanish (energy only up to the truncation error)
+    assert abs(dv * np.sum(Q)) < 1e-13
+    assert abs(dv * np.sum(r2 * Q)) < 1e-3
+
+
+@pytest.mark.slow
+def test_bkw_profile_after_rk4():
+    N, L, lam, dt, nsteps = 48, 12.0, math.pi / 4, 0.05, 10
+    o = oracle.Oracle(2, N)
+    f = inp.bkw_2d(N, L, t=0.0, lam=lam)
+    for _ in range(nsteps):
+        f = o.rk4_step(f, dt, eps=0, L=L)
+    ref = inp.bkw_2d(N, L, t=dt * nsteps, lam=lam)
+    err = np.sqrt(np.sum((f - ref) ** 2) / np.sum(ref ** 2))
+    assert err < 1e-2
+
+
+def test_quantum_maxwellian_residual_decays():
+    # Section 5.1 protocol: f0 = M_q sampled on the box is an equilibrium; the
+    # discrete residual decays spectrally with N (2-D Fermi–Dirac, hbar = 3,
+    # rho = 1, sigma = T = 0.5, L = 4, u0 = 0, as in Table 1).  The same datum
+    # is far from stationary with the opposite sign of alpha, which pins
+    # alpha = -eps hbar^d (eps = -1 for fermions).
+    hbar, T, rho, L = 3.0, 0.5, 1.0, 4.0
+    alpha = hbar ** 2
+    z = math.exp(rho * alpha / (2 * math.pi * T)) - 1.0
+    res, wrong = [], []
+    for N in (16, 32):
+        o = oracle.Oracle(2, N)
+        f = inp.quantum_maxwellian(2, N, L, z=z, T=T, alpha=alpha)
+        res.append(np.max(np.abs(o.collide(f, eps=-1, L=L, hbar=hbar)[0])))
+        wrong.append(np.max(np.abs(o.collide(f, eps=+1, L=L, hbar=hbar)[0])))
+    assert res[1] < res[0] / 50
+    assert res[1] < 1e-5
+    assert min(wrong) > 1e4 * res[1]
+
+
+# ---------------------------------------------------------------- fixtures
+def test_printed_fugacities_2d():
+    # captions of Tables 1-4: 2-D, hbar = 3, rho = 1, T = sigma.
+    # FD: rho |alpha| / (2 pi T) = ln(1 + z);  BE: = -ln(1 - z).
+    alpha = 9.0
+    fd = lambda T: math.exp(alpha / (2 * math.pi * T)) - 1
+    be = lambda T: 1 - math.exp(-alpha / (2 * math.pi * T))
+    assert fd(0.5) == pytest.approx(16.5454, abs=5e-4)
+    assert fd(1.0) == pytest.approx(3.1887, abs=5e-4)
+    assert be(0.5) == pytest.approx(0.943, abs=5e-4)
+    assert be(1.0) == pytest.approx(0.7613, abs=5e-4)
+
+
+def test_moments_of_gaussian():
+    N, L = 32, 8.0
+    v = inp.velocity_grid(3, N, L)
+    T, u = 0.8, np.array([0.3, -0.2, 0.1])
+    f = np.exp(-np.sum((v - u) ** 2, axis=-1) / (2 * T)) / (2 * math.pi * T) ** 1.5
+    m = oracle.moments(f, L, eps=0)
+    assert m["rho"] == pytest.approx(1.0, abs=1e-10)
+    assert np.allclose(m["u"], u, atol=1e-10)
+    assert m["e"] == pytest.approx(1.5 * T, abs=1e-9)
+    # classical entropy of a Maxwellian: int f ln f = -(3/2)(1 + ln(2 pi T))
+    assert m["H"] == pytest.approx(-1.5 * (1 + math.log(2 * math.pi * T)), abs=1e-8)
