@@ -1,0 +1,164 @@
+/*
+ * bnq.h — C ABI of libbnq, an MI355X (gfx950) implementation of the
+ * spectral-Galerkin collision operator of the homogeneous Boltzmann–Nordheim
+ * equation (Mouton & Rey, "On deterministic numerical methods for the quantum
+ * Boltzmann–Nordheim equation I", arXiv 2110.13735).
+ *
+ * Problem (Section 2.2, homogeneous equation; Section 4.2, classical method
+ * lambda = 0, omega = 1, mu = (L/pi)^d):
+ *     d f_j / dt = c (L/pi)^(d+gamma) Q_j,     j in I_N = {-N/2 .. N/2-1}^d,
+ * on the velocity grid v_j = 2 L j / N of [-L, L)^d, where Q_j is the grid
+ * value of the truncated, periodised operator Q^R_alpha(G) (Section 3.2,
+ * indicator of Filbet–Hu–Jin, R = S = 2 pi / (3 + sqrt 2) as in Section 5.1)
+ * evaluated through the Fourier–Galerkin sums of the kernel-mode Lemma
+ * (Section 3.3):
+ *     Qhat_n = sum_{l+m=n} [beta(l,m) - beta(m,m)] G_l G_m
+ *            - alpha sum_{k+l+m=n} [beta(k+m,l+m) + beta(l,m) - beta(l+m,l)
+ *                                   - beta(l,l+m)] G_k G_l G_m,
+ *     G_k = N^-d sum_j f_j e^{-2 pi i k.j/N},
+ *     Q_j = Re sum_{n in I_N} Qhat_n e^{2 pi i n.j/N},
+ * with every index in I_N (linear, non-wrapping sums) and
+ *     alpha = -eps hbar^d   (eps = +1 bosons, -1 fermions, 0 classical).
+ * Kernels: d = 2 Maxwell molecules (gamma = 0, Btilde = 2 C_phi) and d = 3
+ * hard spheres (gamma = 1, Btilde = 4 C_phi), b = 1 (Section 3.5).
+ *
+ * Memory: every pointer named f, Q, Qhat is a DEVICE pointer owned by the
+ * caller (e.g. a torch tensor's data_ptr()).  f and Q are FP64 arrays of N^d
+ * values in C order with storage index j + N/2 (d = 2: [N][N], d = 3:
+ * [N][N][N]).  Qhat is interleaved complex128 in the same order, indexed
+ * n + N/2.  Host pointers are named *_host.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  All calls are
+ * asynchronous on that stream unless stated otherwise.
+ *
+ * Errors: every call returns a bnq_status; nothing else crosses the ABI.
+ * bnq_last_error() returns a thread-local message for the last failure.
+ * Plans are not thread-safe; the shared kernel-mode table cache is.
+ */
+#ifndef BNQ_H
+#define BNQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BNQ_OK = 0,
+    BNQ_EINVAL = -1,     /* bad argument (d, N, eps, L, null pointer, ...) */
+    BNQ_ENOMEM = -2,     /* device allocation failed or table budget exceeded */
+    BNQ_EHIP = -3,       /* a HIP runtime call failed */
+    BNQ_ENOTSUP = -4,    /* valid but not implemented (kernel, precision, N) */
+    BNQ_ENONFINITE = -5, /* health check: non-finite value in f */
+    BNQ_EBOUND = -6      /* health check: fermion f >= 1/|alpha| */
+} bnq_status;
+
+typedef void *bnq_stream_t; /* hipStream_t */
+typedef struct bnq_plan_s *bnq_plan_t;
+
+/* term selection bits (all set = the full operator) */
+#define BNQ_T_CLASSICAL 1 /* Q1c - Q2c                           */
+#define BNQ_T_QMULT 2     /* Q2q - Q3q - Q4q  (through W and X)   */
+#define BNQ_T_QTRI 4      /* Q1q              (the trilinear T1)  */
+#define BNQ_T_ALL 7
+
+#define BNQ_FP64 0
+
+#define BNQ_CORR_NONE 0 /* the paper's scheme */
+#define BNQ_CORR_MASS 1 /* subtract the mean of Q so that sum_j Q_j = 0 exactly */
+
+#define BNQ_RK4 0
+#define BNQ_EULER 1
+#define BNQ_SSPRK2 2
+
+typedef struct {
+    int32_t d;          /* 2 or 3 */
+    int32_t N;          /* even, 2 <= N <= 64 (3-D FP64 tables need N <= 32) */
+    int32_t eps;        /* +1 boson, -1 fermion, 0 classical */
+    int32_t precision;  /* BNQ_FP64 */
+    int32_t terms;      /* BNQ_T_* mask, default BNQ_T_ALL */
+    int32_t correction; /* BNQ_CORR_* */
+    double hbar;        /* default 1 */
+    double C_phi;       /* default 1 */
+    double c;           /* collision scaling, default 1 */
+    double L;           /* velocity box half-width, > 0 */
+} bnq_params;
+
+/* Fill *p with defaults: d = 3, N = 16, eps = 0, FP64, all terms, no
+ * correction, hbar = C_phi = c = 1, L = 8. */
+void bnq_params_default(bnq_params *p);
+
+/* Build a plan: validates *p, attaches (building on first use, in FP64 on
+ * the device) the kernel-mode tables shared by every plan with the same
+ * (d, N, C_phi), and allocates the plan's workspace on the current device.
+ * Tables are built on `stream` and the call synchronises it.  Errors:
+ * EINVAL, ENOTSUP, ENOMEM, EHIP.  On error *out is NULL. */
+bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out);
+
+/* Release the plan (waits for its stream work); drops its reference to the
+ * shared tables (freed with the last reference).  NULL is accepted. */
+bnq_status bnq_plan_destroy(bnq_plan_t plan);
+
+/* Device bytes the plan would need: *plan_bytes for its own workspace,
+ * *table_bytes for the shared tables (0 if already resident).  Host only. */
+bnq_status bnq_plan_footprint(const bnq_params *p, size_t *plan_bytes, size_t *table_bytes);
+
+/* Q = c (L/pi)^(d+gamma) Re IDFT(Qhat) for the grid distribution f (the right
+ * hand side of the semi-discrete equation).  If Qhat is non-NULL the
+ * Galerkin modes Qhat_n (before the prefactor) are also written.  f and Q
+ * must not alias.  Errors: EINVAL (null f or Q), EHIP. */
+bnq_status bnq_collide(bnq_plan_t plan, const double *f, double *Q, void *Qhat, bnq_stream_t stream);
+
+/* Advance f (in place) by one step of size dt of d f/dt = c (L/pi)^(d+gamma) Q(f)
+ * with scheme BNQ_RK4 (classical fourth order), BNQ_SSPRK2 (Shu–Osher second
+ * order) or BNQ_EULER, state and stage arithmetic in FP64.  Errors: EINVAL,
+ * EHIP. */
+bnq_status bnq_step(bnq_plan_t plan, double *f, double dt, int32_t scheme, bnq_stream_t stream);
+
+/* Discrete moments (Section 5 diagnostics, classical method), written to the
+ * host array out_host[BNQ_MOMENTS_LEN] in this order:
+ *   rho, u[0], u[1], u[2] (u[2] = 0 when d = 2), E_c, e, H, fmax, fmin,
+ *   n_excluded
+ * with rho = dv sum f, u = dv sum v f / rho, E_c = dv sum |v|^2 f,
+ * e = dv sum |v-u|^2 f / (2 rho), H = dv sum [f ln f + (1-alpha f)/alpha
+ * ln(1-alpha f)] (alpha != 0) or dv sum f ln f (alpha = 0) over the nodes with
+ * f > 0 and 1 - alpha f > 0, n_excluded = number of other nodes, dv =
+ * (2L/N)^d.  Synchronises `stream`.  Returns ENONFINITE if f holds a NaN or
+ * Inf, EBOUND if eps = -1 and max f >= 1/|alpha| (moments still written). */
+#define BNQ_MOMENTS_LEN 10
+bnq_status bnq_moments(bnq_plan_t plan, const double *f, double *out_host, bnq_stream_t stream);
+
+/* Kernel modes beta(a_i, b_i) read back from the plan's device tables, for
+ * n integer vector pairs a_host[3*i..], b_host[3*i..] (d = 2 uses components
+ * 1 and 2; component 0 must be 0).  Requires |a|_inf <= N-1 and
+ * |b|_inf <= N-1 (the trilinear table) -- or, with table = 1, a and b in
+ * I_N (the classical weight table: returns beta(a,b) - beta(b,b)), table = 2
+ * (the quantum pair weight: beta(a,b) - beta(a+b,a) - beta(a,a+b)).
+ * Synchronous; for tests and diagnostics.  Errors: EINVAL (out of range). */
+bnq_status bnq_table_lookup(bnq_plan_t plan, int32_t table, int64_t n, const int32_t *a_host,
+                            const int32_t *b_host, double *out_host);
+
+/* Work counts per evaluation of Qhat (plain Galerkin counts): classical pairs,
+ * W pairs, outer-sum pairs, trilinear terms; written to counts_host[4]. */
+bnq_status bnq_plan_counts(bnq_plan_t plan, double *counts_host);
+
+/* Kernel timing with HIP events recorded on the launch stream around every
+ * launch of each kernel family.  enable = 1 starts (and clears) recording,
+ * 0 stops.  bnq_plan_timing() synchronises the plan's last stream and writes
+ * for each family k < BNQ_NKERNELS: ms_host[k] = total milliseconds,
+ * launches_host[k] = number of launches.  Families: 0 dft, 1 pairs (classical
+ * + W), 2 outer sum, 3 trilinear, 4 partial reduction, 5 combine/inverse,
+ * 6 step update, 7 moments. */
+#define BNQ_NKERNELS 8
+bnq_status bnq_plan_set_timing(bnq_plan_t plan, int32_t enable);
+bnq_status bnq_plan_timing(bnq_plan_t plan, double *ms_host, int64_t *launches_host);
+
+const char *bnq_status_string(bnq_status s);
+const char *bnq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BNQ_H */

@@ -1,0 +1,203 @@
+"""Python binding of libbnq (include/bnq.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of libbnq.so, which must have been
+built in-tree (paper_2110_13735_amd/build_lib.py); importing this package
+without the library raises, there is no fallback.  Device arrays are passed as
+torch tensors (their data_ptr) or raw integer addresses; streams default to
+torch's current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libbnq.so")
+
+BNQ_OK, BNQ_EINVAL, BNQ_ENOMEM, BNQ_EHIP, BNQ_ENOTSUP, BNQ_ENONFINITE, BNQ_EBOUND = 0, -1, -2, -3, -4, -5, -6
+T_CLASSICAL, T_QMULT, T_QTRI, T_ALL = 1, 2, 4, 7
+FP64 = 0
+CORR_NONE, CORR_MASS = 0, 1
+RK4, EULER, SSPRK2 = 0, 1, 2
+MOMENTS_LEN = 10
+NKERNELS = 8
+KERNEL_FAMILIES = ("dft", "pairs", "outer", "trilinear", "reduce", "combine", "step", "moments")
+MOMENT_NAMES = ("rho", "u0", "u1", "u2", "Ec", "e", "H", "fmax", "fmin", "n_excluded")
+
+
+class BnqError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"bnq status {status}: {msg}")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("N", ctypes.c_int32), ("eps", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("terms", ctypes.c_int32), ("correction", ctypes.c_int32),
+                ("hbar", ctypes.c_double), ("C_phi", ctypes.c_double), ("c", ctypes.c_double),
+                ("L", ctypes.c_double)]
+
+
+@dataclass
+class Params:
+    d: int = 3
+    N: int = 16
+    eps: int = 0
+    L: float = 8.0
+    hbar: float = 1.0
+    C_phi: float = 1.0
+    c: float = 1.0
+    terms: int = T_ALL
+    correction: int = CORR_NONE
+    precision: int = FP64
+
+    def _c(self) -> _Params:
+        return _Params(self.d, self.N, self.eps, self.precision, self.terms, self.correction,
+                       self.hbar, self.C_phi, self.c, self.L)
+
+
+_lib = None
+
+
+def lib():
+    """Load libbnq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is missing: build it with paper_2110_13735_amd/build_lib.py")
+        L = ctypes.CDLL(LIBPATH)
+        vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        P = ctypes.POINTER(_Params)
+        L.bnq_params_default.argtypes = [P]
+        L.bnq_params_default.restype = None
+        L.bnq_plan.argtypes = [P, vp, ctypes.POINTER(vp)]
+        L.bnq_plan_destroy.argtypes = [vp]
+        L.bnq_plan_footprint.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+        L.bnq_collide.argtypes = [vp, vp, vp, vp, vp]
+        L.bnq_step.argtypes = [vp, vp, f64, i32, vp]
+        L.bnq_moments.argtypes = [vp, vp, vp, vp]
+        L.bnq_table_lookup.argtypes = [vp, i32, i64, vp, vp, vp]
+        L.bnq_plan_counts.argtypes = [vp, vp]
+        L.bnq_plan_set_timing.argtypes = [vp, i32]
+        L.bnq_plan_timing.argtypes = [vp, vp, vp]
+        for fn in ("bnq_plan", "bnq_plan_destroy", "bnq_plan_footprint", "bnq_collide", "bnq_step",
+                   "bnq_moments", "bnq_table_lookup", "bnq_plan_counts", "bnq_plan_set_timing",
+                   "bnq_plan_timing"):
+            getattr(L, fn).restype = ctypes.c_int
+        L.bnq_status_string.argtypes = [ctypes.c_int]
+        L.bnq_status_string.restype = ctypes.c_char_p
+        L.bnq_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st: int, allow=()):
+    if st != BNQ_OK and st not in allow:
+        raise BnqError(st, lib().bnq_last_error().decode(errors="replace"))
+    return st
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def footprint(p: Params):
+    """(plan workspace bytes, shared table bytes still to allocate)."""
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    cp = p._c()
+    _check(lib().bnq_plan_footprint(ctypes.byref(cp), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+class Plan:
+    """A libbnq plan (bnq_plan / bnq_plan_destroy)."""
+
+    def __init__(self, p: Params, stream=None):
+        self.params = p
+        self._h = ctypes.c_void_p()
+        cp = p._c()
+        _check(lib().bnq_plan(ctypes.byref(cp), _stream(stream), ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            _check(lib().bnq_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def collide(self, f, Q, Qhat=None, stream=None):
+        _check(lib().bnq_collide(self._h, _ptr(f), _ptr(Q), _ptr(Qhat), _stream(stream)))
+
+    def step(self, f, dt: float, scheme: int = RK4, stream=None):
+        _check(lib().bnq_step(self._h, _ptr(f), float(dt), int(scheme), _stream(stream)))
+
+    def moments(self, f, stream=None, check: bool = True) -> dict:
+        out = np.zeros(MOMENTS_LEN)
+        st = lib().bnq_moments(self._h, _ptr(f), out.ctypes.data, _stream(stream))
+        if check:
+            _check(st)
+        res = dict(zip(MOMENT_NAMES, out.tolist()))
+        res["status"] = st
+        return res
+
+    def lookup(self, table: int, a, b) -> np.ndarray:
+        a = np.ascontiguousarray(a, dtype=np.int32).reshape(-1, 3)
+        b = np.ascontiguousarray(b, dtype=np.int32).reshape(-1, 3)
+        out = np.zeros(a.shape[0])
+        _check(lib().bnq_table_lookup(self._h, int(table), a.shape[0], a.ctypes.data, b.ctypes.data,
+                                      out.ctypes.data))
+        return out
+
+    def counts(self) -> dict:
+        c = np.zeros(4)
+        _check(lib().bnq_plan_counts(self._h, c.ctypes.data))
+        return {"classical": c[0], "w_pairs": c[1], "outer": c[2], "trilinear": c[3]}
+
+    def set_timing(self, enable: bool):
+        _check(lib().bnq_plan_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self) -> dict:
+        ms = np.zeros(NKERNELS)
+        n = np.zeros(NKERNELS, dtype=np.int64)
+        _check(lib().bnq_plan_timing(self._h, ms.ctypes.data, n.ctypes.data))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_FAMILIES)}
+
+
+def terms_per_eval(p: Params, counts: dict) -> float:
+    """Collision terms of one evaluation with the selected terms (plain
+    Galerkin counts: classical pairs, W pairs, outer pairs, trilinear)."""
+    t = p.terms if p.eps != 0 else (p.terms & T_CLASSICAL)
+    n = 0.0
+    if t & T_CLASSICAL:
+        n += counts["classical"]
+    if t & T_QMULT:
+        n += counts["w_pairs"] + counts["outer"]
+    if t & T_QTRI:
+        n += counts["trilinear"]
+    return n

@@ -1,0 +1,905 @@
+// Host runtime of libbnq: the C ABI of include/bnq.h, plans, the shared
+// kernel-mode table cache and the orchestration of the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <queue>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/bnq.h"
+#include "bnq_internal.h"
+
+namespace bnq {
+void launch_gather(const double *base, const int64_t *idx, int64_t n, double *out, hipStream_t s);
+}
+
+using namespace bnq;
+
+namespace {
+
+thread_local std::string g_err;
+
+bnq_status fail(bnq_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(BNQ_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                            \
+    } while (0)
+
+#define LAUNCHCHK()                                                                    \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess)                                                          \
+            return fail(BNQ_EHIP, "kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                           \
+    } while (0)
+
+const double kR = 2.0 * M_PI / (3.0 + std::sqrt(2.0));  // R = S, pi = (3 + sqrt 2) S / 2
+const int kNq = 128;                                    // radial Gauss–Legendre nodes
+const int kMaxSlots = 2048;                             // trilinear partial arrays
+
+// ---------------------------------------------------------------------------
+Geo make_geo(int d, int N) {
+    Geo g;
+    g.d = d;
+    g.N = N;
+    g.h = N / 2;
+    g.e0 = d == 3 ? N : 1;
+    g.lo0 = d == 3 ? -N / 2 : 0;
+    g.nm = (int64_t)g.e0 * N * N;
+    g.eg0 = d == 3 ? 2 * N : 1;
+    g.neg = (int64_t)g.eg0 * 2 * N * 2 * N;
+    g.ea0 = d == 3 ? 2 * N - 1 : 1;
+    g.na = (int64_t)g.ea0 * (2 * N - 1) * (2 * N - 1);
+    g.ex0 = d == 3 ? N + 1 : 1;
+    g.next = (int64_t)g.ex0 * (N + 1) * (N + 1);
+    return g;
+}
+
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        long double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), pp = 0;
+        for (int it = 0; it < 100; ++it) {
+            long double p1 = 1, p2 = 0;
+            for (int j = 1; j <= n; ++j) {
+                long double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0L * j - 1) * z * p2 - (j - 1.0L) * p3) / j;
+            }
+            pp = n * (z * p1 - p2) / (z * z - 1);
+            long double z1 = z;
+            z = z1 - p1 / pp;
+            if (std::fabs((double)(z - z1)) < 1e-19) break;
+        }
+        x[i] = (double)-z;
+        x[n - 1 - i] = (double)z;
+        w[i] = w[n - 1 - i] = (double)(2.0L / ((1 - z * z) * pp * pp));
+    }
+}
+
+int mcut_of(double q) {
+    const double x = kR * std::sqrt(q);
+    return (int)std::ceil((x + 10.0 * std::cbrt(x) + 30.0) / 2.0);
+}
+
+// Signed axis permutations: 48 in 3-D; in 2-D the 8 that fix axis 0.
+std::vector<Rot> make_group(int d) {
+    std::vector<Rot> out;
+    int p[3] = {0, 1, 2};
+    do {
+        if (d == 2 && p[0] != 0) continue;
+        for (int sm = 0; sm < 8; ++sm) {
+            if (d == 2 && (sm & 1)) continue;
+            Rot r;
+            for (int i = 0; i < 3; ++i) {
+                r.perm[i] = p[i];
+                r.sgn[i] = (sm >> i) & 1 ? -1 : 1;
+            }
+            out.push_back(r);
+        }
+    } while (std::next_permutation(p, p + 3));
+    return out;
+}
+
+int rot_index(const std::vector<Rot> &grp, const int *perm, const int *sgn) {
+    for (size_t r = 0; r < grp.size(); ++r)
+        if (std::equal(perm, perm + 3, grp[r].perm) && std::equal(sgn, sgn + 3, grp[r].sgn)) return (int)r;
+    return -1;
+}
+
+// b = R b_c with b_c components sorted |b| descending (ties by axis index);
+// in 2-D axis 0 stays fixed.
+void canonicalize(int d, const int *b, int *bc, int *perm, int *sgn) {
+    int ax[3] = {0, 1, 2};
+    const int first = d == 3 ? 0 : 1;
+    std::stable_sort(ax + first, ax + 3, [&](int i, int j) { return std::abs(b[i]) > std::abs(b[j]); });
+    for (int j = 0; j < 3; ++j) bc[j] = std::abs(b[ax[j]]);
+    for (int j = 0; j < 3; ++j) perm[ax[j]] = j;
+    for (int i = 0; i < 3; ++i) sgn[i] = b[i] < 0 ? -1 : 1;
+}
+
+// ---------------------------------------------------------------------------
+// Shared kernel-mode tables for one (d, N, C_phi).
+struct TableSet {
+    int refs = 0;
+    int d = 0, N = 0;
+    double Cphi = 0;
+    int device = 0;
+    Geo g;
+    int qmax = 0, M = 0;
+    double *J = nullptr, *coef = nullptr, *lrA = nullptr, *lrB = nullptr;
+    int *mcut = nullptr;
+    std::vector<int> canon;      // 3 per row
+    std::vector<int> canon_row;  // [N][N][N] -> row or -1
+    int ncanon = 0;
+    int *canon_d = nullptr;
+    double *K = nullptr, *wc = nullptr, *wq = nullptr;
+    size_t bytes = 0;
+    Radial radial() const {
+        Radial r;
+        r.J = J;
+        r.mcut = mcut;
+        r.coef = coef;
+        r.lrA = lrA;
+        r.lrB = lrB;
+        r.M = M;
+        r.d = d;
+        return r;
+    }
+};
+
+std::mutex g_cache_mu;
+std::vector<TableSet *> g_cache;
+
+void canon_list(int d, int N, std::vector<int> &canon, std::vector<int> &row) {
+    canon.clear();
+    row.assign((size_t)N * N * N, -1);
+    int n = 0;
+    if (d == 3) {
+        for (int c0 = 0; c0 < N; ++c0)
+            for (int c1 = 0; c1 <= c0; ++c1)
+                for (int c2 = 0; c2 <= c1; ++c2) {
+                    canon.insert(canon.end(), {c0, c1, c2});
+                    row[((size_t)c0 * N + c1) * N + c2] = n++;
+                }
+    } else {
+        for (int c1 = 0; c1 < N; ++c1)
+            for (int c2 = 0; c2 <= c1; ++c2) {
+                canon.insert(canon.end(), {0, c1, c2});
+                row[((size_t)0 * N + c1) * N + c2] = n++;
+            }
+    }
+}
+
+size_t table_bytes(int d, int N) {
+    Geo g = make_geo(d, N);
+    std::vector<int> canon, row;
+    canon_list(d, N, canon, row);
+    const size_t ncanon = canon.size() / 3;
+    const int qmax = d * N * N;
+    const int M = mcut_of(qmax) + 1;
+    return sizeof(double) * (ncanon * (size_t)g.na + 2 * (size_t)g.nm * g.nm + (size_t)(qmax + 1) * M) +
+           sizeof(int) * (qmax + 1);
+}
+
+void free_tables(TableSet *t) {
+    hipFree(t->J);
+    hipFree(t->coef);
+    hipFree(t->lrA);
+    hipFree(t->lrB);
+    hipFree(t->mcut);
+    hipFree(t->canon_d);
+    hipFree(t->K);
+    hipFree(t->wc);
+    hipFree(t->wq);
+    delete t;
+}
+
+template <typename T>
+bnq_status dalloc(T **p, size_t count, const char *what) {
+    *p = nullptr;
+    if (count == 0) return BNQ_OK;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        hipGetLastError();
+        return fail(BNQ_ENOMEM, "hipMalloc of %zu bytes for %s failed: %s", count * sizeof(T), what,
+                    hipGetErrorString(e));
+    }
+    return BNQ_OK;
+}
+
+template <typename T>
+bnq_status upload(T **p, const std::vector<T> &v, const char *what) {
+    bnq_status st = dalloc(p, v.size(), what);
+    if (st) return st;
+    HIPCHK(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return BNQ_OK;
+}
+
+bnq_status build_tables(TableSet *t, hipStream_t s) {
+    const int d = t->d, N = t->N;
+    t->g = make_geo(d, N);
+    const Geo &g = t->g;
+    t->qmax = d * N * N;
+    t->M = mcut_of(t->qmax) + 1;
+    bnq_status st;
+    // host constants
+    std::vector<double> glx, glw;
+    gauss_legendre(kNq, glx, glw);
+    std::vector<int> mcut(t->qmax + 1);
+    for (int q = 0; q <= t->qmax; ++q) mcut[q] = std::min(mcut_of(q), t->M - 1);
+    std::vector<double> coef(t->M), lrA(2 * t->M + 4), lrB(2 * t->M + 4);
+    double p0 = 1.0;  // P_{2m}(0)
+    for (int m = 0; m < t->M; ++m) {
+        if (m > 0) p0 *= -(2.0 * m - 1.0) / (2.0 * m);
+        if (d == 3)
+            coef[m] = 32.0 * M_PI * M_PI * t->Cphi * (4.0 * m + 1.0) * p0;
+        else
+            coef[m] = 8.0 * M_PI * t->Cphi * (m == 0 ? 1.0 : 2.0) * ((m & 1) ? -1.0 : 1.0);
+    }
+    for (size_t n = 0; n < lrA.size(); ++n) {
+        lrA[n] = (2.0 * n + 1.0) / (n + 1.0);
+        lrB[n] = (double)n / (n + 1.0);
+    }
+    double *glx_d = nullptr, *glw_d = nullptr;
+    if ((st = upload(&glx_d, glx, "nodes")) || (st = upload(&glw_d, glw, "weights"))) {
+        hipFree(glx_d);
+        return st;
+    }
+    if ((st = upload(&t->mcut, mcut, "mcut")) || (st = upload(&t->coef, coef, "coef")) ||
+        (st = upload(&t->lrA, lrA, "lrA")) || (st = upload(&t->lrB, lrB, "lrB")) ||
+        (st = dalloc(&t->J, (size_t)(t->qmax + 1) * t->M, "radial table"))) {
+        hipFree(glx_d);
+        hipFree(glw_d);
+        return st;
+    }
+    double *scratch = nullptr;
+    if ((st = dalloc(&scratch, (size_t)(t->qmax + 1) * t->M * kNq, "radial scratch"))) {
+        hipFree(glx_d);
+        hipFree(glw_d);
+        return st;
+    }
+    launch_radial(d, kR, t->qmax, t->M, kNq, glx_d, glw_d, scratch, t->J, s);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(s));
+    hipFree(scratch);
+    hipFree(glx_d);
+    hipFree(glw_d);
+    // trilinear rows
+    canon_list(d, N, t->canon, t->canon_row);
+    t->ncanon = (int)(t->canon.size() / 3);
+    if ((st = upload(&t->canon_d, t->canon, "canonical list"))) return st;
+    if ((st = dalloc(&t->K, (size_t)t->ncanon * g.na, "trilinear kernel-mode table"))) return st;
+    if ((st = dalloc(&t->wc, (size_t)g.nm * g.nm, "classical weight table"))) return st;
+    if ((st = dalloc(&t->wq, (size_t)g.nm * g.nm, "quantum pair weight table"))) return st;
+    const Radial rad = t->radial();
+    launch_beta_rows(g, rad, t->canon_d, t->ncanon, t->K, s);
+    LAUNCHCHK();
+    launch_weights(g, rad, t->wc, t->wq, s);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(s));
+    t->bytes = table_bytes(d, N);
+    return BNQ_OK;
+}
+
+bnq_status acquire_tables(int d, int N, double Cphi, hipStream_t s, TableSet **out) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    for (TableSet *t : g_cache)
+        if (t->d == d && t->N == N && t->Cphi == Cphi && t->device == dev) {
+            t->refs++;
+            *out = t;
+            return BNQ_OK;
+        }
+    size_t freeb = 0, totalb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totalb));
+    const size_t need = table_bytes(d, N);
+    if (need > freeb)
+        return fail(BNQ_ENOMEM, "kernel-mode tables need %zu bytes, %zu free", need, freeb);
+    TableSet *t = new TableSet;
+    t->d = d;
+    t->N = N;
+    t->Cphi = Cphi;
+    t->device = dev;
+    bnq_status st = build_tables(t, s);
+    if (st) {
+        free_tables(t);
+        return st;
+    }
+    t->refs = 1;
+    g_cache.push_back(t);
+    *out = t;
+    return BNQ_OK;
+}
+
+void release_tables(TableSet *t) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (--t->refs > 0) return;
+    g_cache.erase(std::remove(g_cache.begin(), g_cache.end(), t), g_cache.end());
+    free_tables(t);
+}
+
+// ---------------------------------------------------------------------------
+// 1-D counts of the Galerkin sums (per axis; a d-D count is the d-th power).
+void counts_1d(int N, double &c1, double &w1, double &o1, double &t1) {
+    const int h = N / 2;
+    auto in = [&](int k) { return k >= -h && k < h; };
+    c1 = w1 = o1 = t1 = 0;
+    for (int l = -h; l < h; ++l)
+        for (int m = -h; m < h; ++m) {
+            w1 += 1;
+            if (in(l + m)) c1 += 1;
+        }
+    for (int n = -h; n < h; ++n)
+        for (int k = -h; k < h; ++k)
+            if (n - k >= -N && n - k <= N - 2) o1 += 1;
+    for (int k = -h; k < h; ++k)
+        for (int l = -h; l < h; ++l)
+            for (int m = -h; m < h; ++m)
+                if (in(k + l + m)) t1 += 1;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct bnq_plan_s {
+    bnq_params p;
+    Geo g;
+    TableSet *tabs = nullptr;
+    double alpha = 0, pref = 0;
+    std::vector<Rot> grp;
+    Rot *rots_d = nullptr;
+    double2 *tw = nullptr;
+    double2 *Ghat = nullptr, *tmp = nullptr, *tmp2 = nullptr, *Gr = nullptr, *W = nullptr, *Qc = nullptr,
+            *T1 = nullptr, *X = nullptr, *Qh = nullptr, *part = nullptr;
+    double *kbuf[4] = {nullptr, nullptr, nullptr, nullptr}, *ybuf = nullptr;
+    double *mom_part = nullptr, *mom_out = nullptr;
+    int nslots = 0;
+    int *slot_off = nullptr;
+    T1Item *items = nullptr;
+    T1B *bdesc = nullptr;
+    double counts[4] = {0, 0, 0, 0};
+    // timing
+    bool timing = false;
+    struct Ev {
+        int fam;
+        hipEvent_t a, b;
+    };
+    std::vector<Ev> evs;
+    std::vector<hipEvent_t> pool;
+    hipStream_t last = nullptr;
+};
+
+namespace {
+
+hipEvent_t ev_get(bnq_plan_s *P) {
+    if (!P->pool.empty()) {
+        hipEvent_t e = P->pool.back();
+        P->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Span {
+    bnq_plan_s *P;
+    int fam;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    Span(bnq_plan_s *P_, int fam_, hipStream_t s_) : P(P_), fam(fam_), s(s_) {
+        if (P->timing) {
+            a = ev_get(P);
+            if (a) hipEventRecord(a, s);
+        }
+    }
+    ~Span() {
+        if (P->timing && a) {
+            hipEvent_t b = ev_get(P);
+            if (b) {
+                hipEventRecord(b, s);
+                P->evs.push_back({fam, a, b});
+            } else {
+                P->pool.push_back(a);
+            }
+        }
+    }
+};
+
+bnq_status validate(const bnq_params *p) {
+    if (!p) return fail(BNQ_EINVAL, "params is NULL");
+    if (p->d != 2 && p->d != 3) return fail(BNQ_EINVAL, "d must be 2 or 3 (got %d)", p->d);
+    if (p->N < 2 || p->N > 64 || (p->N & 1)) return fail(BNQ_EINVAL, "N must be even in [2, 64] (got %d)", p->N);
+    if (p->eps < -1 || p->eps > 1) return fail(BNQ_EINVAL, "eps must be -1, 0 or 1 (got %d)", p->eps);
+    if (!(p->L > 0) || !std::isfinite(p->L)) return fail(BNQ_EINVAL, "L must be positive");
+    if (!(p->hbar > 0) || !(p->C_phi > 0) || !(p->c >= 0)) return fail(BNQ_EINVAL, "hbar, C_phi must be > 0, c >= 0");
+    if (p->precision != BNQ_FP64) return fail(BNQ_ENOTSUP, "only BNQ_FP64 is implemented");
+    if (p->terms < 0 || p->terms > BNQ_T_ALL) return fail(BNQ_EINVAL, "bad terms mask %d", p->terms);
+    if (p->correction != BNQ_CORR_NONE && p->correction != BNQ_CORR_MASS)
+        return fail(BNQ_EINVAL, "bad correction %d", p->correction);
+    return BNQ_OK;
+}
+
+size_t plan_workspace_bytes(const bnq_params *p, int nslots_est) {
+    Geo g = make_geo(p->d, p->N);
+    const size_t c = sizeof(double2), r = sizeof(double);
+    const size_t nrot = p->d == 3 ? 48 : 8;
+    return c * (6 * (size_t)g.nm + g.neg + nrot * g.next + (size_t)nslots_est * g.nm) + r * 5 * (size_t)g.nm;
+}
+
+bnq_status build_t1_work(bnq_plan_s *P) {
+    const Geo &g = P->g;
+    const TableSet *t = P->tabs;
+    const int d = g.d, N = g.N, h = g.h;
+    std::vector<T1B> bd;
+    struct It {
+        T1Item it;
+        double cost;
+    };
+    std::vector<It> items;
+    const int b0lo = d == 3 ? -N + 1 : 0, b0hi = d == 3 ? N - 2 : 0;
+    for (int b0 = b0lo; b0 <= b0hi; ++b0)
+        for (int b1 = -N + 1; b1 <= N - 2; ++b1)
+            for (int b2 = -N + 1; b2 <= N - 2; ++b2) {
+                const int b[3] = {b0, b1, b2};
+                int bc[3], perm[3], sgn[3];
+                canonicalize(d, b, bc, perm, sgn);
+                T1B B;
+                B.rot = rot_index(P->grp, perm, sgn);
+                B.kc = t->canon_row[((size_t)bc[0] * N + bc[1]) * N + bc[2]];
+                if (B.rot < 0 || B.kc < 0) return fail(BNQ_EINVAL, "internal: canonical form of b not found");
+                int lo[3], ext[3];
+                for (int i = 0; i < 3; ++i) {
+                    const int j = perm[i];
+                    const bool triv = d == 2 && i == 0;
+                    lo[j] = triv ? 0 : -h + (sgn[i] < 0 ? 1 : 0);
+                    ext[j] = triv ? 1 : N;
+                }
+                bool empty = false;
+                for (int j = 0; j < 3; ++j) {
+                    const int L0 = lo[j], H0 = lo[j] + ext[j] - 1, c = bc[j];
+                    B.bc[j] = c;
+                    B.wnlo[j] = L0 + c;
+                    B.wnhi[j] = H0;
+                    B.wplo[j] = std::max(L0, c - H0);
+                    B.wphi[j] = std::min(H0, c - L0);
+                    if (B.wnlo[j] > B.wnhi[j] || B.wplo[j] > B.wphi[j]) empty = true;
+                }
+                if (empty) continue;
+                const int wnx = B.wnhi[2] - B.wnlo[2] + 1;
+                B.nxb = (wnx + T1_RB - 1) / T1_RB;
+                B.pad = 0;
+                const int ntasks = B.nxb * (B.wnhi[1] - B.wnlo[1] + 1) * (B.wnhi[0] - B.wnlo[0] + 1);
+                const int wpx = B.wphi[2] - B.wplo[2] + 1;
+                const double rows = (double)(B.wphi[1] - B.wplo[1] + 1) * (B.wphi[0] - B.wplo[0] + 1);
+                const double cost = rows * ((wpx + 7) / 8 + 2) + 8;
+                const int bi = (int)bd.size();
+                bd.push_back(B);
+                for (int t0 = 0; t0 < ntasks; t0 += 64) {
+                    It x;
+                    x.it.b = bi;
+                    x.it.t0 = t0;
+                    x.it.nt = std::min(64, ntasks - t0);
+                    x.it.pad = 0;
+                    x.cost = cost;
+                    items.push_back(x);
+                }
+            }
+    // longest-processing-time-first static assignment (deterministic)
+    std::stable_sort(items.begin(), items.end(), [](const It &a, const It &b) { return a.cost > b.cost; });
+    const int ns = (int)std::max<size_t>(1, std::min<size_t>(kMaxSlots, items.size()));
+    std::priority_queue<std::pair<double, int>, std::vector<std::pair<double, int>>, std::greater<>> pq;
+    for (int s = 0; s < ns; ++s) pq.push({0.0, s});
+    std::vector<std::vector<T1Item>> per(ns);
+    for (const It &x : items) {
+        auto top = pq.top();
+        pq.pop();
+        per[top.second].push_back(x.it);
+        pq.push({top.first + x.cost, top.second});
+    }
+    std::vector<int> off(ns + 1, 0);
+    std::vector<T1Item> flat;
+    flat.reserve(items.size());
+    for (int s = 0; s < ns; ++s) {
+        off[s] = (int)flat.size();
+        flat.insert(flat.end(), per[s].begin(), per[s].end());
+    }
+    off[ns] = (int)flat.size();
+    P->nslots = ns;
+    bnq_status st;
+    if ((st = upload(&P->bdesc, bd, "trilinear b descriptors")) || (st = upload(&P->items, flat, "trilinear items")) ||
+        (st = upload(&P->slot_off, off, "trilinear slot offsets")))
+        return st;
+    return dalloc(&P->part, (size_t)ns * g.nm, "trilinear partial sums");
+}
+
+void destroy_plan(bnq_plan_s *P) {
+    if (!P) return;
+    hipFree(P->rots_d);
+    hipFree(P->tw);
+    hipFree(P->Ghat);
+    hipFree(P->tmp);
+    hipFree(P->tmp2);
+    hipFree(P->Gr);
+    hipFree(P->W);
+    hipFree(P->Qc);
+    hipFree(P->T1);
+    hipFree(P->X);
+    hipFree(P->Qh);
+    hipFree(P->part);
+    for (double *k : P->kbuf) hipFree(k);
+    hipFree(P->ybuf);
+    hipFree(P->mom_part);
+    hipFree(P->mom_out);
+    hipFree(P->slot_off);
+    hipFree(P->items);
+    hipFree(P->bdesc);
+    for (auto &e : P->evs) {
+        hipEventDestroy(e.a);
+        hipEventDestroy(e.b);
+    }
+    for (auto e : P->pool) hipEventDestroy(e);
+    if (P->tabs) release_tables(P->tabs);
+    delete P;
+}
+
+bnq_status collide_impl(bnq_plan_s *P, const double *f, double *Q, double2 *Qhat_out, hipStream_t s) {
+    const Geo &g = P->g;
+    const TableSet *t = P->tabs;
+    const int terms = P->p.eps == 0 ? (P->p.terms & BNQ_T_CLASSICAL) : P->p.terms;
+    {
+        Span sp(P, 0, s);
+        launch_dft_forward_real(g, f, P->tmp, P->Ghat, P->tw, s);
+        LAUNCHCHK();
+    }
+    const int want_c = (terms & BNQ_T_CLASSICAL) != 0, want_w = (terms & BNQ_T_QMULT) != 0;
+    if (want_c || want_w) {
+        Span sp(P, 1, s);
+        launch_pairs(g, P->Ghat, t->wc, t->wq, P->Qc, P->W, want_c, want_w, s);
+        LAUNCHCHK();
+    }
+    if (want_w) {
+        Span sp(P, 2, s);
+        launch_outer(g, P->Ghat, P->W, P->X, s);
+        LAUNCHCHK();
+    }
+    if (terms & BNQ_T_QTRI) {
+        {
+            Span sp(P, 4, s);
+            launch_rotate(g, P->Ghat, P->rots_d, (int)P->grp.size(), P->Gr, s);
+            LAUNCHCHK();
+            launch_zero(P->part, (int64_t)P->nslots * g.nm * (int64_t)sizeof(double2), s);
+            LAUNCHCHK();
+        }
+        {
+            Span sp(P, 3, s);
+            launch_trilinear(g, P->nslots, P->slot_off, P->items, P->bdesc, t->K, P->Gr, P->rots_d, P->part, s);
+            LAUNCHCHK();
+        }
+        {
+            Span sp(P, 4, s);
+            launch_reduce_partials(g, P->nslots, P->part, P->T1, s);
+            LAUNCHCHK();
+        }
+    }
+    {
+        Span sp(P, 5, s);
+        launch_combine(g, P->Qc, P->T1, P->X, terms, P->alpha, P->p.correction == BNQ_CORR_MASS, P->Qh, Qhat_out, s);
+        LAUNCHCHK();
+        launch_inverse_real(g, P->Qh, P->tmp, P->tmp2, Q, P->tw, P->pref, s);
+        LAUNCHCHK();
+    }
+    return BNQ_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void bnq_params_default(bnq_params *p) {
+    if (!p) return;
+    p->d = 3;
+    p->N = 16;
+    p->eps = 0;
+    p->precision = BNQ_FP64;
+    p->terms = BNQ_T_ALL;
+    p->correction = BNQ_CORR_NONE;
+    p->hbar = 1.0;
+    p->C_phi = 1.0;
+    p->c = 1.0;
+    p->L = 8.0;
+}
+
+bnq_status bnq_plan_footprint(const bnq_params *p, size_t *plan_bytes, size_t *table_bytes_out) {
+    bnq_status st = validate(p);
+    if (st) return st;
+    if (plan_bytes) *plan_bytes = plan_workspace_bytes(p, kMaxSlots);
+    if (table_bytes_out) {
+        size_t tb = table_bytes(p->d, p->N);
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        int dev = 0;
+        hipGetDevice(&dev);
+        for (TableSet *t : g_cache)
+            if (t->d == p->d && t->N == p->N && t->Cphi == p->C_phi && t->device == dev) tb = 0;
+        *table_bytes_out = tb;
+    }
+    return BNQ_OK;
+}
+
+bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
+    if (!out) return fail(BNQ_EINVAL, "out is NULL");
+    *out = nullptr;
+    bnq_status st = validate(p);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    bnq_plan_s *P = new bnq_plan_s;
+    P->p = *p;
+    P->g = make_geo(p->d, p->N);
+    const Geo &g = P->g;
+    P->alpha = -(double)p->eps * std::pow(p->hbar, p->d);
+    P->pref = p->c * std::pow(p->L / M_PI, p->d + (p->d == 3 ? 1 : 0));
+    P->grp = make_group(p->d);
+    P->last = s;
+    if ((st = acquire_tables(p->d, p->N, p->C_phi, s, &P->tabs))) {
+        destroy_plan(P);
+        return st;
+    }
+    std::vector<double2> tw(p->N);
+    for (int t = 0; t < p->N; ++t) {
+        const long double a = 2.0L * (long double)M_PI * t / p->N;
+        tw[t] = make_double2((double)std::cos(a), (double)-std::sin(a));
+    }
+    const size_t nm = g.nm;
+    if ((st = upload(&P->rots_d, P->grp, "rotations")) || (st = upload(&P->tw, tw, "twiddles")) ||
+        (st = dalloc(&P->Ghat, nm, "spectrum")) || (st = dalloc(&P->tmp, nm, "dft scratch")) ||
+        (st = dalloc(&P->tmp2, nm, "dft scratch")) || (st = dalloc(&P->Gr, P->grp.size() * (size_t)g.next, "rotated spectra")) ||
+        (st = dalloc(&P->W, (size_t)g.neg, "pair sum W")) || (st = dalloc(&P->Qc, nm, "classical modes")) ||
+        (st = dalloc(&P->T1, nm, "trilinear modes")) || (st = dalloc(&P->X, nm, "outer modes")) ||
+        (st = dalloc(&P->Qh, nm, "modes")) || (st = dalloc(&P->ybuf, nm, "stage")) ||
+        (st = dalloc(&P->mom_part, (size_t)MOM_BLOCKS * MOM_FIELDS, "moment partials")) ||
+        (st = dalloc(&P->mom_out, (size_t)MOM_FIELDS, "moments"))) {
+        destroy_plan(P);
+        return st;
+    }
+    for (int k = 0; k < 4; ++k)
+        if ((st = dalloc(&P->kbuf[k], nm, "stage"))) {
+            destroy_plan(P);
+            return st;
+        }
+    if ((st = build_t1_work(P))) {
+        destroy_plan(P);
+        return st;
+    }
+    double c1, w1, o1, t1;
+    counts_1d(p->N, c1, w1, o1, t1);
+    const int d = p->d;
+    P->counts[0] = std::pow(c1, d);
+    P->counts[1] = std::pow(w1, d);
+    P->counts[2] = std::pow(o1, d);
+    P->counts[3] = std::pow(t1, d);
+    *out = P;
+    return BNQ_OK;
+}
+
+bnq_status bnq_plan_destroy(bnq_plan_t plan) {
+    if (!plan) return BNQ_OK;
+    hipStreamSynchronize(plan->last);
+    destroy_plan(plan);
+    return BNQ_OK;
+}
+
+bnq_status bnq_collide(bnq_plan_t P, const double *f, double *Q, void *Qhat, bnq_stream_t stream) {
+    if (!P) return fail(BNQ_EINVAL, "plan is NULL");
+    if (!f || !Q) return fail(BNQ_EINVAL, "f and Q must be device pointers");
+    if ((const void *)f == (const void *)Q) return fail(BNQ_EINVAL, "f and Q must not alias");
+    hipStream_t s = (hipStream_t)stream;
+    P->last = s;
+    return collide_impl(P, f, Q, (double2 *)Qhat, s);
+}
+
+bnq_status bnq_step(bnq_plan_t P, double *f, double dt, int32_t scheme, bnq_stream_t stream) {
+    if (!P) return fail(BNQ_EINVAL, "plan is NULL");
+    if (!f) return fail(BNQ_EINVAL, "f is NULL");
+    if (!std::isfinite(dt)) return fail(BNQ_EINVAL, "dt must be finite");
+    hipStream_t s = (hipStream_t)stream;
+    P->last = s;
+    const int64_t n = P->g.nm;
+    double **k = P->kbuf;
+    bnq_status st;
+    if (scheme == BNQ_EULER) {
+        if ((st = collide_impl(P, f, k[0], nullptr, s))) return st;
+        Span sp(P, 6, s);
+        launch_axpy(n, f, dt, k[0], f, s);
+        LAUNCHCHK();
+        return BNQ_OK;
+    }
+    if (scheme == BNQ_SSPRK2) {
+        if ((st = collide_impl(P, f, k[0], nullptr, s))) return st;
+        {
+            Span sp(P, 6, s);
+            launch_axpy(n, f, dt, k[0], P->ybuf, s);
+            LAUNCHCHK();
+        }
+        if ((st = collide_impl(P, P->ybuf, k[1], nullptr, s))) return st;
+        Span sp(P, 6, s);
+        launch_ssprk2_final(n, f, P->ybuf, k[1], dt, s);
+        LAUNCHCHK();
+        return BNQ_OK;
+    }
+    if (scheme != BNQ_RK4) return fail(BNQ_EINVAL, "unknown scheme %d", scheme);
+    if ((st = collide_impl(P, f, k[0], nullptr, s))) return st;
+    const double a[3] = {0.5 * dt, 0.5 * dt, dt};
+    for (int stg = 1; stg < 4; ++stg) {
+        {
+            Span sp(P, 6, s);
+            launch_axpy(n, f, a[stg - 1], k[stg - 1], P->ybuf, s);
+            LAUNCHCHK();
+        }
+        if ((st = collide_impl(P, P->ybuf, k[stg], nullptr, s))) return st;
+    }
+    Span sp(P, 6, s);
+    launch_rk4_final(n, f, dt, k[0], k[1], k[2], k[3], s);
+    LAUNCHCHK();
+    return BNQ_OK;
+}
+
+bnq_status bnq_moments(bnq_plan_t P, const double *f, double *out_host, bnq_stream_t stream) {
+    if (!P) return fail(BNQ_EINVAL, "plan is NULL");
+    if (!f || !out_host) return fail(BNQ_EINVAL, "f and out_host must be non-NULL");
+    hipStream_t s = (hipStream_t)stream;
+    P->last = s;
+    {
+        Span sp(P, 7, s);
+        launch_moments(P->g, f, P->p.L, P->alpha, P->mom_part, MOM_BLOCKS, P->mom_out, s);
+        LAUNCHCHK();
+    }
+    double r[MOM_FIELDS];
+    HIPCHK(hipMemcpyAsync(r, P->mom_out, sizeof r, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double dv = std::pow(2.0 * P->p.L / P->p.N, P->p.d);
+    const double rho = dv * r[0];
+    double u[3] = {0, 0, 0};
+    // moments are reported with axis order (x0, x1, x2) of the storage
+    const int first = P->p.d == 3 ? 0 : 1;
+    for (int i = 0; i < 3; ++i) u[i] = rho != 0 ? dv * r[1 + i] / rho : 0.0;
+    const double Ec = dv * r[4];
+    const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    out_host[0] = rho;
+    for (int i = 0; i < 3; ++i) out_host[1 + i] = 0.0;
+    for (int i = first; i < 3; ++i) out_host[1 + i - first] = u[i];
+    out_host[4] = Ec;
+    out_host[5] = rho != 0 ? (Ec - rho * u2) / (2.0 * rho) : 0.0;
+    out_host[6] = dv * r[5];
+    out_host[7] = r[6];
+    out_host[8] = r[7];
+    out_host[9] = r[8] + r[9];
+    if (r[9] > 0) return fail(BNQ_ENONFINITE, "f holds %.0f non-finite values", r[9]);
+    if (P->p.eps == -1 && r[6] * std::fabs(P->alpha) >= 1.0)
+        return fail(BNQ_EBOUND, "fermion bound violated: max f = %.17g >= 1/|alpha|", r[6]);
+    return BNQ_OK;
+}
+
+bnq_status bnq_table_lookup(bnq_plan_t P, int32_t table, int64_t n, const int32_t *a, const int32_t *b,
+                            double *out) {
+    if (!P) return fail(BNQ_EINVAL, "plan is NULL");
+    if (n < 0 || (n > 0 && (!a || !b || !out))) return fail(BNQ_EINVAL, "bad arrays");
+    if (n == 0) return BNQ_OK;
+    const Geo &g = P->g;
+    const TableSet *t = P->tabs;
+    const int N = g.N, h = g.h, d = g.d;
+    std::vector<int64_t> idx(n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int *x = a + 3 * i, *y = b + 3 * i;
+        if (d == 2 && (x[0] != 0 || y[0] != 0)) return fail(BNQ_EINVAL, "d = 2 vectors need component 0 = 0");
+        if (table == 0) {
+            for (int c = 0; c < 3; ++c)
+                if (std::abs(x[c]) > N - 1 || std::abs(y[c]) > N - 1)
+                    return fail(BNQ_EINVAL, "pair %lld outside the trilinear table range", (long long)i);
+            int bc[3], perm[3], sgn[3];
+            canonicalize(d, y, bc, perm, sgn);
+            int ap[3];
+            for (int c = 0; c < 3; ++c) ap[perm[c]] = sgn[c] * x[c];
+            const int kc = t->canon_row[((size_t)bc[0] * N + bc[1]) * N + bc[2]];
+            idx[i] = (int64_t)kc * g.na + idx_A(g, ap[0], ap[1], ap[2]);
+        } else if (table == 1 || table == 2) {
+            for (int c = (d == 3 ? 0 : 1); c < 3; ++c)
+                if (x[c] < -h || x[c] >= h || y[c] < -h || y[c] >= h)
+                    return fail(BNQ_EINVAL, "pair %lld outside I_N", (long long)i);
+            idx[i] = idx_I(g, x[0], x[1], x[2]) * g.nm + idx_I(g, y[0], y[1], y[2]);
+        } else {
+            return fail(BNQ_EINVAL, "table must be 0, 1 or 2");
+        }
+    }
+    int64_t *idx_d = nullptr;
+    double *out_d = nullptr;
+    bnq_status st;
+    if ((st = upload(&idx_d, idx, "lookup indices")) || (st = dalloc(&out_d, (size_t)n, "lookup output"))) {
+        hipFree(idx_d);
+        return st;
+    }
+    const double *base = table == 0 ? t->K : (table == 1 ? t->wc : t->wq);
+    launch_gather(base, idx_d, n, out_d, nullptr);
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipMemcpy(out, out_d, sizeof(double) * n, hipMemcpyDeviceToHost);
+    hipFree(idx_d);
+    hipFree(out_d);
+    if (e1 != hipSuccess || e2 != hipSuccess)
+        return fail(BNQ_EHIP, "lookup failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    return BNQ_OK;
+}
+
+bnq_status bnq_plan_counts(bnq_plan_t P, double *counts) {
+    if (!P || !counts) return fail(BNQ_EINVAL, "NULL argument");
+    for (int i = 0; i < 4; ++i) counts[i] = P->counts[i];
+    return BNQ_OK;
+}
+
+bnq_status bnq_plan_set_timing(bnq_plan_t P, int32_t enable) {
+    if (!P) return fail(BNQ_EINVAL, "plan is NULL");
+    HIPCHK(hipStreamSynchronize(P->last));
+    for (auto &e : P->evs) {
+        P->pool.push_back(e.a);
+        P->pool.push_back(e.b);
+    }
+    P->evs.clear();
+    P->timing = enable != 0;
+    return BNQ_OK;
+}
+
+bnq_status bnq_plan_timing(bnq_plan_t P, double *ms, int64_t *launches) {
+    if (!P || !ms || !launches) return fail(BNQ_EINVAL, "NULL argument");
+    HIPCHK(hipStreamSynchronize(P->last));
+    for (int k = 0; k < BNQ_NKERNELS; ++k) {
+        ms[k] = 0;
+        launches[k] = 0;
+    }
+    for (auto &e : P->evs) {
+        float t = 0;
+        HIPCHK(hipEventElapsedTime(&t, e.a, e.b));
+        ms[e.fam] += t;
+        launches[e.fam] += 1;
+    }
+    return BNQ_OK;
+}
+
+const char *bnq_status_string(bnq_status s) {
+    switch (s) {
+        case BNQ_OK: return "ok";
+        case BNQ_EINVAL: return "invalid argument";
+        case BNQ_ENOMEM: return "out of device memory";
+        case BNQ_EHIP: return "HIP runtime error";
+        case BNQ_ENOTSUP: return "not supported";
+        case BNQ_ENONFINITE: return "non-finite value";
+        case BNQ_EBOUND: return "fermion bound violated";
+    }
+    return "unknown status";
+}
+
+const char *bnq_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

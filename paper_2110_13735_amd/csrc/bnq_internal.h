@@ -1,0 +1,120 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// libbnq.  Not part of the public ABI (see include/bnq.h).
+//
+// Geometry.  A d-dimensional mode grid is stored as 3-D with axis 0 trivial
+// (extent 1, mode 0) when d = 2.  Axis 2 is the fastest (C order).
+//   I_N   : modes {-N/2 .. N/2-1} per axis, storage index k + N/2
+//   Eg    : pair sums l + m live in {-N .. N-1} per axis (2N values; the top
+//           value N-1 is never reached, which lets the outer sum read W at
+//           n - k without bounds checks), storage index s + N
+//   A     : trilinear kernel-mode rows, arguments {-(N-1) .. N-1} per axis
+//           (2N-1 values), storage index a + N - 1
+//   Ext   : rotated spectra, modes {-N/2 .. N/2} per axis (N+1 values),
+//           storage index q + N/2
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bnq {
+
+struct Geo {
+    int d, N, h;
+    int e0;       // extent of axis 0 in I_N (1 or N)
+    int lo0;      // lowest mode of axis 0 (0 or -N/2)
+    int64_t nm;   // |I_N| = N^d
+    int eg0;      // extent of axis 0 in Eg (1 or 2N)
+    int64_t neg;  // |Eg|
+    int ea0;      // extent of axis 0 in A (1 or 2N-1)
+    int64_t na;   // |A|
+    int ex0;      // extent of axis 0 in Ext (1 or N+1)
+    int64_t next; // |Ext|
+};
+
+__host__ __device__ inline int64_t idx_I(const Geo &g, int k0, int k1, int k2) {
+    return ((int64_t)(k0 - g.lo0) * g.N + (k1 + g.h)) * g.N + (k2 + g.h);
+}
+__host__ __device__ inline int64_t idx_E(const Geo &g, int s0, int s1, int s2) {
+    const int E = 2 * g.N;
+    return ((int64_t)(g.d == 3 ? s0 + g.N : 0) * E + (s1 + g.N)) * E + (s2 + g.N);
+}
+__host__ __device__ inline int64_t idx_A(const Geo &g, int a0, int a1, int a2) {
+    const int A = 2 * g.N - 1;
+    return ((int64_t)(g.d == 3 ? a0 + g.N - 1 : 0) * A + (a1 + g.N - 1)) * A + (a2 + g.N - 1);
+}
+__host__ __device__ inline int64_t idx_X(const Geo &g, int q0, int q1, int q2) {
+    const int X = g.N + 1;
+    return ((int64_t)(g.d == 3 ? q0 + g.h : 0) * X + (q1 + g.h)) * X + (q2 + g.h);
+}
+
+// Signed axis permutation: (R x)_i = sgn[i] * x[perm[i]].
+struct Rot {
+    int perm[3];
+    int sgn[3];
+};
+
+// Per-b description for the trilinear sum in the rotated frame of b = R b_c.
+struct T1B {
+    int kc;          // row of the trilinear kernel-mode table (canonical b_c)
+    int rot;         // index of R
+    int bc[3];       // canonical b_c (components >= 0)
+    int wnlo[3], wnhi[3];  // output window in the rotated frame
+    int wplo[3], wphi[3];  // inner window in the rotated frame
+    int nxb;         // x-blocks of the output window
+    int pad;
+};
+
+struct T1Item {
+    int b;   // index into the T1B array
+    int t0;  // first task
+    int nt;  // number of tasks (<= 64)
+    int pad;
+};
+
+constexpr int T1_RB = 8;      // outputs per lane along x
+constexpr int T1_ROWS = 8;    // inner rows staged per barrier
+
+// Radial tables for the kernel-mode series.
+struct Radial {
+    const double *J;     // [qmax+1][M] radial integrals of even order 2m
+    const int *mcut;     // [qmax+1] last order index needed for |a|^2 = q
+    const double *coef;  // [M] series coefficients (include C_phi)
+    const double *lrA;   // [2M] Legendre recurrence constants (2n+1)/(n+1)
+    const double *lrB;   // [2M] n/(n+1)
+    int M;
+    int d;
+};
+
+// ---- launchers (defined in the .hip files) --------------------------------
+void launch_radial(int d, double R, int qmax, int M, int nq, const double *glx, const double *glw,
+                   double *S, double *J, hipStream_t s);
+void launch_beta_rows(const Geo &g, const Radial &rad, const int *canon, int ncanon, double *K,
+                      hipStream_t s);
+void launch_weights(const Geo &g, const Radial &rad, double *wc, double *wq, hipStream_t s);
+void launch_gather(const double *base, const int64_t *idx, int64_t n, double *out, hipStream_t s);
+
+void launch_dft_forward_real(const Geo &g, const double *f, double2 *tmp, double2 *out,
+                             const double2 *tw, hipStream_t s);
+void launch_rotate(const Geo &g, const double2 *G, const Rot *rots, int nrot, double2 *Gr, hipStream_t s);
+void launch_pairs(const Geo &g, const double2 *G, const double *wc, const double *wq, double2 *Qc,
+                  double2 *W, int want_c, int want_w, hipStream_t s);
+void launch_outer(const Geo &g, const double2 *G, const double2 *W, double2 *X, hipStream_t s);
+void launch_trilinear(const Geo &g, int nslots, const int *slot_off, const T1Item *items,
+                      const T1B *bdesc, const double *K, const double2 *Gr, const Rot *rots,
+                      double2 *part, hipStream_t s);
+void launch_zero(void *p, int64_t bytes, hipStream_t s);
+void launch_reduce_partials(const Geo &g, int nslots, const double2 *part, double2 *T1, hipStream_t s);
+void launch_combine(const Geo &g, const double2 *Qc, const double2 *T1, const double2 *X, int terms,
+                    double alpha, int mass_fix, double2 *Qh, double2 *Qh_out, hipStream_t s);
+void launch_inverse_real(const Geo &g, const double2 *Qh, double2 *tmp, double2 *tmp2, double *Q,
+                         const double2 *tw, double scale, hipStream_t s);
+
+void launch_axpy(int64_t n, const double *x, double a, const double *y, double *out, hipStream_t s);
+void launch_rk4_final(int64_t n, double *f, double dt, const double *k1, const double *k2,
+                      const double *k3, const double *k4, hipStream_t s);
+void launch_ssprk2_final(int64_t n, double *f, const double *y, const double *k2, double dt, hipStream_t s);
+void launch_moments(const Geo &g, const double *f, double L, double alpha, double *part, int nblk,
+                    double *out, hipStream_t s);
+constexpr int MOM_BLOCKS = 256;
+constexpr int MOM_FIELDS = 12;
+
+}  // namespace bnq

@@ -1,0 +1,115 @@
+// Time stepping and moments on the velocity grid, FP64.
+//
+// Classical method of Section 4.2: d f/dt = c (L/pi)^(d+gamma) Q(f); the RK
+// stage combinations are plain FP64 vector updates.  Moments and entropy
+// follow the diagnostics list of Section 5 (classical method, omega = 1):
+//   rho = dv sum f, u = dv sum v f / rho, E_c = dv sum |v|^2 f,
+//   e = (E_c - rho |u|^2) / (2 rho),
+//   H = dv sum [f ln f + (1 - alpha f)/alpha ln(1 - alpha f)]   (alpha != 0)
+//     = dv sum f ln f                                          (alpha  = 0)
+// over nodes with f > 0 and 1 - alpha f > 0.  Reductions use a fixed
+// assignment of nodes to blocks and a fixed tree, so results are
+// bit-reproducible.
+#include "bnq_internal.h"
+
+namespace bnq {
+
+__global__ void axpy_kernel(int64_t n, const double *x, double a, const double *y, double *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = fma(a, y[i], x[i]);
+}
+
+void launch_axpy(int64_t n, const double *x, double a, const double *y, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, x, a, y, out);
+}
+
+// f <- f + dt/6 (k1 + 2 k2 + 2 k3 + k4)
+__global__ void rk4_final_kernel(int64_t n, double *f, double dt, const double *k1, const double *k2,
+                                 const double *k3, const double *k4) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) f[i] = f[i] + (dt / 6.0) * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+}
+
+void launch_rk4_final(int64_t n, double *f, double dt, const double *k1, const double *k2, const double *k3,
+                      const double *k4, hipStream_t s) {
+    hipLaunchKernelGGL(rk4_final_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, f, dt, k1, k2, k3, k4);
+}
+
+// Shu–Osher SSP-RK2: y = f + dt k1;  f <- (f + y + dt k(y)) / 2
+__global__ void ssprk2_final_kernel(int64_t n, double *f, const double *y, const double *k2, double dt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) f[i] = 0.5 * (f[i] + fma(dt, k2[i], y[i]));
+}
+
+void launch_ssprk2_final(int64_t n, double *f, const double *y, const double *k2, double dt, hipStream_t s) {
+    hipLaunchKernelGGL(ssprk2_final_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, f, y, k2, dt);
+}
+
+// fields: 0 sum f, 1-3 sum v f, 4 sum |v|^2 f, 5 sum entropy density,
+//         6 max f, 7 min f, 8 excluded nodes, 9 non-finite nodes
+__global__ __launch_bounds__(256) void moments_part_kernel(Geo g, const double *f, double L, double alpha,
+                                                           double *part) {
+    __shared__ double red[256][MOM_FIELDS];
+    double acc[MOM_FIELDS];
+    for (int k = 0; k < MOM_FIELDS; ++k) acc[k] = 0.0;
+    acc[6] = -INFINITY;
+    acc[7] = INFINITY;
+    const double hstep = 2.0 * L / g.N;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.nm;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = f[i];
+        const double x2 = (double)((int)(i % g.N) - g.h) * hstep;
+        const double x1 = (double)((int)((i / g.N) % g.N) - g.h) * hstep;
+        const double x0 = g.d == 3 ? (double)((int)(i / ((int64_t)g.N * g.N)) - g.h) * hstep : 0.0;
+        if (!isfinite(v)) {
+            acc[9] += 1.0;
+            continue;
+        }
+        acc[0] += v;
+        acc[1] += x0 * v;
+        acc[2] += x1 * v;
+        acc[3] += x2 * v;
+        acc[4] += (x0 * x0 + x1 * x1 + x2 * x2) * v;
+        acc[6] = fmax(acc[6], v);
+        acc[7] = fmin(acc[7], v);
+        const double om = 1.0 - alpha * v;
+        if (v > 0.0 && om > 0.0) {
+            double hden = v * log(v);
+            if (alpha != 0.0) hden += om / alpha * log(om);
+            acc[5] += hden;
+        } else {
+            acc[8] += 1.0;
+        }
+    }
+    for (int k = 0; k < MOM_FIELDS; ++k) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int k = 0; k < MOM_FIELDS; ++k) {
+                const double a = red[threadIdx.x][k], b = red[threadIdx.x + w][k];
+                red[threadIdx.x][k] = k == 6 ? fmax(a, b) : (k == 7 ? fmin(a, b) : a + b);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < MOM_FIELDS) part[(int64_t)blockIdx.x * MOM_FIELDS + threadIdx.x] = red[0][threadIdx.x];
+}
+
+__global__ void moments_final_kernel(int nblk, const double *part, double *out) {
+    const int k = threadIdx.x;
+    if (k >= MOM_FIELDS) return;
+    double a = k == 6 ? -INFINITY : (k == 7 ? INFINITY : 0.0);
+    for (int b = 0; b < nblk; ++b) {
+        const double v = part[(int64_t)b * MOM_FIELDS + k];
+        a = k == 6 ? fmax(a, v) : (k == 7 ? fmin(a, v) : a + v);
+    }
+    out[k] = a;
+}
+
+void launch_moments(const Geo &g, const double *f, double L, double alpha, double *part, int nblk, double *out,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(moments_part_kernel, dim3(nblk), dim3(256), 0, s, g, f, L, alpha, part);
+    hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(64), 0, s, nblk, part, out);
+}
+
+}  // namespace bnq

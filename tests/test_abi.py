@@ -1,0 +1,73 @@
+"""CPU checks of the C ABI: the library loads and exports every declared
+entry point; parameter validation works without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2110_13735_amd as bnq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "bnq.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bnq_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_four_entry_points():
+    names = _declared()
+    for n in ("bnq_plan", "bnq_collide", "bnq_step", "bnq_moments"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(bnq.LIBPATH):
+        pytest.skip("libbnq.so not built")
+    lib = ctypes.CDLL(bnq.LIBPATH)
+    for n in _declared():
+        assert hasattr(lib, n), n
+
+
+def test_status_strings_and_defaults():
+    if not os.path.exists(bnq.LIBPATH):
+        pytest.skip("libbnq.so not built")
+    L = bnq.lib()
+    assert L.bnq_status_string(0) == b"ok"
+    assert L.bnq_status_string(-1) == b"invalid argument"
+    p = bnq._Params()
+    L.bnq_params_default(ctypes.byref(p))
+    assert (p.d, p.N, p.eps, p.terms) == (3, 16, 0, 7)
+    assert p.hbar == 1.0 and p.L == 8.0
+
+
+@pytest.mark.parametrize("kw", [dict(d=4), dict(N=7), dict(N=0), dict(N=66), dict(eps=2), dict(L=-1.0),
+                                dict(precision=3), dict(terms=9), dict(correction=5)])
+def test_invalid_params_rejected_on_host(kw):
+    if not os.path.exists(bnq.LIBPATH):
+        pytest.skip("libbnq.so not built")
+    p = bnq.Params(d=2, N=8, L=4.0)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    with pytest.raises(bnq.BnqError) as e:
+        bnq.footprint(p)
+    assert e.value.status in (bnq.BNQ_EINVAL, bnq.BNQ_ENOTSUP)
+
+
+def test_footprint_sizes():
+    if not os.path.exists(bnq.LIBPATH):
+        pytest.skip("libbnq.so not built")
+    plan_b, tab_b = bnq.footprint(bnq.Params(d=3, N=32, L=8.0))
+    # pair-weight tables 2 N^6 doubles plus the trilinear rows
+    assert tab_b > 2 * 32 ** 6 * 8
+    assert tab_b < 40e9
+    assert plan_b > 0
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(bnq, "LIBPATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(bnq, "_lib", None)
+    with pytest.raises(RuntimeError):
+        bnq.lib()
