@@ -1,0 +1,160 @@
+#!/usr/bin/env python3
+"""Benchmark: collision pair-terms/s of the spectral-Galerkin Boltzmann–Nordheim
+operator on one MI355X.
+
+Workload (default): 3-D fermions (eps = -1), N = 32^3 Fourier modes, FP64,
+hard spheres (Btilde = 4), hbar = 1, L = 8; f0 = 0.45 x a sum of three
+Gaussians with seeded centres in |v| <= 2 and variances in [0.3, 1], capped
+at 0.99 (seed 0).  One step = one classical RK4 step (four evaluations of
+the full operator: forward DFT, classical + W pair sums, outer sum,
+trilinear sum, combination, inverse DFT, stage updates) plus the FP64
+moments and entropy of the new state.  Kernel-mode tables are built once
+when the plan is created, outside the timed region.
+
+value = collision terms per step / seconds per step, where the terms of one
+evaluation are the plain Galerkin counts: classical pairs + W pairs + outer
+pairs + trilinear triples.
+
+Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "collision pair-terms/s at N=32^3 (FP32c vs FP64); p50/p99 solve latency"
+PEAK_FP64_VALU = 78.6e12  # MI355X dense FP64 vector, FLOP/s
+FLOPS_PER_T1_TERM = 4.0   # one real x complex multiply-add (two FMAs)
+
+
+def cpu_baseline(sample_N: int = 10, nthreads=None):
+    """The oracle, untouched, timed on the host: one full evaluation of Qhat
+    (direct Galerkin sums, including its own kernel-mode quadrature) of the
+    same workload recipe at 3-D N = sample_N."""
+    import numpy as np
+    import bnq_inputs as inp
+    import oracle
+
+    if nthreads:
+        os.environ["OMP_NUM_THREADS"] = str(nthreads)
+    f = inp.fermion_mixture_3d(N=sample_N, L=8.0, seed=0)
+    t0 = time.perf_counter()
+    o = oracle.Oracle(3, sample_N)
+    o.collide(f, eps=-1, L=8.0)
+    dt = time.perf_counter() - t0
+    n = sample_N
+    h = n // 2
+    rng = range(-h, h)
+    c1 = sum(1 for l in rng for m in rng if -h <= l + m < h)
+    o1 = sum(1 for a in rng for k in rng if -n <= a - k <= n - 2)
+    t1 = sum(1 for k in rng for l in rng for m in rng if -h <= k + l + m < h)
+    terms = c1 ** 3 + n ** 6 + o1 ** 3 + t1 ** 3
+    return {"value": terms / dt, "unit": "pair-terms/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"one full oracle evaluation (kernel-mode quadrature + direct sums) of the same recipe "
+                      f"at 3-D N={sample_N}: {terms:.3e} terms in {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=32)
+    ap.add_argument("--dt", type=float, default=0.01)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-N", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only; multi-GPU runs are not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import bnq_inputs as inp
+    import paper_2110_13735_amd as bnq
+
+    if not os.path.exists(bnq.LIBPATH):
+        import __graft_entry__
+        __graft_entry__.build()
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    N, L, eps = args.N, 8.0, -1
+    p = bnq.Params(d=3, N=N, eps=eps, L=L)
+    f0 = inp.fermion_mixture_3d(N=N, L=L, seed=0)
+    t_plan = time.perf_counter()
+    plan = bnq.Plan(p)
+    t_plan = time.perf_counter() - t_plan
+    counts = plan.counts()
+    terms_eval = bnq.terms_per_eval(p, counts)
+    terms_step = 4.0 * terms_eval
+    f = torch.tensor(f0, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        plan.step(f, args.dt, bnq.RK4)
+        return plan.moments(f, check=False)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mom = None
+    for _ in range(args.steps):
+        mom = one_step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = plan.timing()
+    plan.set_timing(False)
+    ms_step = 1e3 * elapsed / args.steps
+    value = terms_step / (elapsed / args.steps)
+
+    t1_ms, t1_n = kt["trilinear"]
+    t1_avg_s = (t1_ms / t1_n) * 1e-3 if t1_n else float("nan")
+    flops_launch = counts["trilinear"] * FLOPS_PER_T1_TERM
+    achieved = flops_launch / t1_avg_s / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU / 1e12,
+                "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP64_VALU, 4), "traffic": None,
+                "kernel": "trilinear_kernel", "avg_ms": round(t1_avg_s * 1e3, 3), "launches": t1_n,
+                "flops_per_launch": flops_launch}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair-terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3-D fermions eps=-1, N={N}^3, FP64, hard spheres, hbar=1, L=8, "
+                               f"three-Gaussian f0 (seed 0), RK4 dt={args.dt}, moments every step",
+                   "d": 3, "N": N, "eps": eps, "precision": "fp64", "scheme": "rk4", "dt": args.dt,
+                   "terms_per_eval": terms_eval, "evals_per_step": 4,
+                   "plan_build_s": round(t_plan, 3)},
+        "roofline": roofline,
+        "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kt.items()},
+        "moments_last": {k: mom[k] for k in ("rho", "e", "H", "fmax")},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_N)
+    plan.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -62,7 +62,7 @@ def lib():
         L.or_xsize.restype = i64
         L.or_beta_table.argtypes = [i32, i32, f64, f64, vp]
         L.or_beta_table.restype = i32
-        L.or_sums_direct.argtypes = [i32, i32, vp, vp, i32, i64, vp, vp, vp, vp]
+        L.or_sums_direct.argtypes = [i32, i32, vp, vp, i32, i64, vp, vp, vp, vp, vp]
         L.or_sums_direct.restype = None
         L.or_factored.argtypes = [i32, i32, vp, vp, vp, vp]
         L.or_factored.restype = None
@@ -172,10 +172,12 @@ def galerkin_sums(d: int, N: int, Ghat: np.ndarray, table: np.ndarray, want=("c"
     """Direct sums of the Fourier-modes Lemma for every n in I_N (or the
     linear indices in `select`).  Returns complex arrays shaped like Ghat
     (entries not selected are zero): 'c' = Qc, 'q' = Qq (all four quantum
-    terms), 't1' = the Q_{1,q} term alone."""
+    terms), 't1' = the Q_{1,q} term alone, 'g' = the classical gain term
+    Q_{1,c} = sum beta(l,m) G_l G_m (used as the cancellation scale)."""
     G = np.ascontiguousarray(_as3(Ghat, d), dtype=np.complex128)
     out = {k: np.zeros(Ghat.size, dtype=np.complex128) for k in want}
-    flag = (1 if "c" in want else 0) | (2 if "q" in want else 0) | (4 if "t1" in want else 0)
+    flag = (1 if "c" in want else 0) | (2 if "q" in want else 0) | (4 if "t1" in want else 0) | \
+        (8 if "g" in want else 0)
     dummy = np.zeros(2)
     ptr = lambda k: out[k].ctypes.data if k in out else dummy.ctypes.data
     if select is None:
@@ -184,7 +186,7 @@ def galerkin_sums(d: int, N: int, Ghat: np.ndarray, table: np.ndarray, want=("c"
         sel = np.ascontiguousarray(select, dtype=np.int64)
         nsel = sel.size
     lib().or_sums_direct(d, N, G.ctypes.data, table.ctypes.data, flag, nsel, sel.ctypes.data,
-                         ptr("c"), ptr("q"), ptr("t1"))
+                         ptr("c"), ptr("q"), ptr("t1"), ptr("g"))
     return {k: v.reshape(Ghat.shape) for k, v in out.items()}
 
 
@@ -216,10 +218,11 @@ class Oracle:
 
     def modes(self, f: np.ndarray, eps: int, hbar: float = 1.0, terms=("c", "x", "t1"), select=None):
         """Galerkin modes: dict with 'Ghat', 'Qc', 'T1', 'Xq' (= Qq - T1),
-        'Qhat' = Qc - alpha (T1 + Xq) restricted to `terms`."""
+        'Qhat' = Qc - alpha (T1 + Xq) restricted to `terms`, and 'gain' (the
+        classical gain term, a scale for judging cancellation)."""
         d, N = self.d, self.N
         G = dft(f)
-        want = ["c"]
+        want = ["c", "g"]
         if eps != 0 and ("x" in terms or "t1" in terms):
             want += ["q", "t1"]
         s = galerkin_sums(d, N, G, self.table, want=tuple(want), select=select)
@@ -234,13 +237,16 @@ class Oracle:
             Qh = Qh - alpha * T1
         if "x" in terms:
             Qh = Qh - alpha * Xq
-        return {"Ghat": G, "Qc": Qc, "T1": T1, "Xq": Xq, "Qhat": Qh}
+        return {"Ghat": G, "Qc": Qc, "T1": T1, "Xq": Xq, "Qhat": Qh, "gain": s["g"]}
 
     def collide(self, f: np.ndarray, eps: int, L: float, hbar: float = 1.0, c: float = 1.0,
-                terms=("c", "x", "t1")):
-        """Q on the grid, already multiplied by c (L/pi)^(d+gamma), and Qhat."""
+                terms=("c", "x", "t1"), full: bool = False):
+        """Q on the grid, already multiplied by c (L/pi)^(d+gamma), and Qhat
+        (with full=True also the dict of modes)."""
         m = self.modes(f, eps, hbar, terms)
         Q = prefactor(self.d, L, c) * idft_real(m["Qhat"])
+        if full:
+            return Q, m["Qhat"], m
         return Q, m["Qhat"]
 
     def rhs(self, f, eps, L, hbar=1.0, c=1.0):

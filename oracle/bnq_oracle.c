@@ -397,15 +397,17 @@ static inline cplx cget(const double *G, int64_t i) {
 
 #define BT(a0, a1, a2, b0, b1, b2) (btab[xidx(g, a0, a1, a2) * g->xsize + xidx(g, b0, b1, b2)])
 
-/* Classical sum for one output mode n. */
-static cplx classical_mode(const geom_t *g, const double *G, const double *btab, const int *n) {
+/* Classical sum for one output mode n (gain_only: the Q1c term alone,
+ * sum beta(l,m) G_l G_m, the scale against which cancellation is judged). */
+static cplx classical_mode(const geom_t *g, const double *G, const double *btab, const int *n, int gain_only) {
     cplx acc = {0.0, 0.0};
     for (int l0 = g->lo[0]; l0 <= g->hi[0]; ++l0)
         for (int l1 = g->lo[1]; l1 <= g->hi[1]; ++l1)
             for (int l2 = g->lo[2]; l2 <= g->hi[2]; ++l2) {
                 int m0 = n[0] - l0, m1 = n[1] - l1, m2 = n[2] - l2;
                 if (!in_grid(g, m0, m1, m2)) continue;
-                double w = BT(l0, l1, l2, m0, m1, m2) - BT(m0, m1, m2, m0, m1, m2);
+                double w = BT(l0, l1, l2, m0, m1, m2);
+                if (!gain_only) w -= BT(m0, m1, m2, m0, m1, m2);
                 cplx p = cmul(cget(G, gidx(g, l0, l1, l2)), cget(G, gidx(g, m0, m1, m2)));
                 acc.re += w * p.re;
                 acc.im += w * p.im;
@@ -448,9 +450,9 @@ static void mode_of(const geom_t *g, int64_t i, int *n) {
 /* Exported: direct sums for every output mode (or a subset when nsel >= 0:
  * `sel` lists linear output indices).  want: bit0 classical, bit1 quantum
  * (all four terms), bit2 T1 alone.  Outputs are complex over I_N (only the
- * selected entries are written). */
+ * selected entries are written); bit3 writes the classical gain term to Qg. */
 void or_sums_direct(int d, int N, const double *G, const double *btab, int want, int64_t nsel,
-                    const int64_t *sel, double *Qc, double *Qq, double *T1) {
+                    const int64_t *sel, double *Qc, double *Qq, double *T1, double *Qg) {
     geom_t g;
     geom_init(&g, d, N);
     int64_t nout = nsel >= 0 ? nsel : g.gsize;
@@ -459,8 +461,13 @@ void or_sums_direct(int d, int N, const double *G, const double *btab, int want,
         int64_t i = nsel >= 0 ? sel[q] : q;
         int n[3];
         mode_of(&g, i, n);
+        if (want & 8) {
+            cplx c = classical_mode(&g, G, btab, n, 1);
+            Qg[2 * i] = c.re;
+            Qg[2 * i + 1] = c.im;
+        }
         if (want & 1) {
-            cplx c = classical_mode(&g, G, btab, n);
+            cplx c = classical_mode(&g, G, btab, n, 0);
             Qc[2 * i] = c.re;
             Qc[2 * i + 1] = c.im;
         }

@@ -17,7 +17,9 @@ The delta(x.y) constraint is resolved in polar coordinates:
   d = 3, Btilde = 4 C_phi:
      int_{S^2} de int_0^pi dpsi int_0^R rho drho int_{-R}^{R} |rho'| drho'
          F(rho e, rho' (cos psi u1 + sin psi u2)),   (u1, u2) a basis of e-perp.
-The bracket is returned split into its classical part
+The bracket is returned split into its classical gain part
+    G(xi+x) G(xi+y),
+its classical part
     G(xi+x) G(xi+y) - G(xi) G(xi+x+y)
 and its cubic part
     G(xi+x)G(xi+y)G(xi+x+y) + G(xi)G(xi+x)G(xi+y)
@@ -64,19 +66,21 @@ def _modes_of(Q: np.ndarray, N: int, M: int) -> np.ndarray:
     return out
 
 
-def bruteforce_modes(Ghat: np.ndarray, R: float, Cphi: float = 1.0, nodes=None):
+def bruteforce_modes(Ghat: np.ndarray, R: float, Cphi: float = 1.0, nodes=None, gain: bool = False):
     """Return (classical modes, cubic modes) on I_N from physical-space
-    quadrature.  `nodes` overrides the default node counts."""
+    quadrature (and the classical gain modes when gain=True).  `nodes`
+    overrides the default node counts."""
     d, N = Ghat.ndim, Ghat.shape[0]
     M = 3 * N
     k, xi, E = _grid_phases(N, M, d)
     G0 = _eval_shifted(Ghat, np.zeros((1, d)), k, E)[0]
     Qc = np.zeros((M,) * d, dtype=np.complex128)
     Qq = np.zeros((M,) * d, dtype=np.complex128)
+    Qg = np.zeros((M,) * d, dtype=np.complex128)
 
     def accumulate(X, Y, w):
         """X: (A, d) first shifts, Y: (B, d) second shifts, w: (A, B) weights."""
-        nonlocal Qc, Qq
+        nonlocal Qc, Qq, Qg
         GX = _eval_shifted(Ghat, X, k, E)
         GY = _eval_shifted(Ghat, Y, k, E)
         XY = (X[:, None, :] + Y[None, :, :]).reshape(-1, d)
@@ -84,6 +88,7 @@ def bruteforce_modes(Ghat: np.ndarray, R: float, Cphi: float = 1.0, nodes=None):
         ww = w.reshape(w.shape + (1,) * d)
         gx = GX[:, None]
         gy = GY[None, :]
+        Qg += np.sum(ww * (gx * gy), axis=(0, 1))
         Qc += np.sum(ww * (gx * gy - G0 * GXY), axis=(0, 1))
         Qq += np.sum(ww * (gx * gy * GXY + G0 * gx * gy - G0 * GXY * gx - G0 * GXY * gy), axis=(0, 1))
 
@@ -120,4 +125,6 @@ def bruteforce_modes(Ghat: np.ndarray, R: float, Cphi: float = 1.0, nodes=None):
                     ep = math.cos(ps) * u1 + math.sin(ps) * u2
                     accumulate(rho[:, None] * e[None], rhop[:, None] * ep[None],
                                4 * Cphi * wsph * (math.pi / nps) * (wr * rho)[:, None] * wrp[None, :])
+    if gain:
+        return _modes_of(Qc, N, M), _modes_of(Qq, N, M), _modes_of(Qg, N, M)
     return _modes_of(Qc, N, M), _modes_of(Qq, N, M)

@@ -154,12 +154,13 @@ def _random_ghat(d, N, seed):
 def test_galerkin_sums_equal_bruteforce_carleman(d, N, nodes):
     G = _random_ghat(d, N, 100 + N)
     tab = oracle.beta_table(d, N)
-    s = oracle.galerkin_sums(d, N, G, tab, want=("c", "q"))
-    bc, bq = bruteforce_modes(G, R, nodes=nodes)
+    s = oracle.galerkin_sums(d, N, G, tab, want=("c", "q", "g"))
+    bc, bq, bg = bruteforce_modes(G, R, nodes=nodes, gain=True)
     scale_c = np.max(np.abs(s["c"]))
     scale_q = np.max(np.abs(s["q"]))
     assert np.max(np.abs(bc - s["c"])) < 1e-13 * max(1.0, scale_c)
     assert np.max(np.abs(bq - s["q"])) < 1e-13 * max(1.0, scale_q)
+    assert np.max(np.abs(bg - s["g"])) < 1e-13 * max(1.0, np.max(np.abs(s["g"])))
 
 
 @pytest.mark.parametrize("d,N", [(2, 8), (3, 4)])

@@ -1,8 +1,11 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-FP64 bar: norm-wise relative error <= 1e-12 on Qhat (Galerkin modes), on Q
-(grid values) and after a time step; kernel-mode tables <= 1e-12 absolute
-(beta(0,0) = 50.9 in 2-D and 324.1 in 3-D).
+FP64 bar: norm-wise error <= 1e-12 on Qhat (Galerkin modes), on Q (grid
+values) and after a time step, relative to max(|ref|, |classical gain|):
+near an equilibrium Qhat is a small difference of gain and loss terms of
+size |gain|, and no summation order resolves it better than ~1e-16 of that
+scale.  Kernel-mode tables <= 1e-12 absolute (beta(0,0) = 50.9 in 2-D and
+324.1 in 3-D).
 """
 import math
 
@@ -30,6 +33,19 @@ def _oracle(d, N):
 def _rel(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _check(got, ref, scale=0.0, tol=TOL):
+    err = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), scale, 1e-300)
+    assert err <= tol, f"error {err:.3e} > {tol:.1e} (|ref| {np.linalg.norm(ref):.3e}, scale {scale:.3e})"
+
+
+def _oracle_collide(d, N, f, eps, L, **kw):
+    o = _oracle(d, N)
+    Q, Qh, m = o.collide(f, eps, L, full=True, **kw)
+    gain = np.linalg.norm(m["gain"])
+    qgain = np.linalg.norm(oracle.prefactor(d, L, kw.get("c", 1.0)) * oracle.idft_real(m["gain"]))
+    return Q, Qh, gain, qgain
 
 
 def _gpu_collide(p, f):
@@ -94,6 +110,15 @@ def test_kernel_mode_tables_match_oracle_quadrature(d, N):
 CASES = [(2, 2), (2, 8), (2, 16), (2, 30), (3, 2), (3, 4), (3, 6), (3, 10)]
 
 
+def test_collide_3d_n12_boson():
+    d, N, eps, L = 3, 12, 1, 6.0
+    f = inp.gaussian_mixture(d, N, L, seed=1212, kmin=2)
+    Q, Qh = _gpu_collide(bnq.Params(d=d, N=N, eps=eps, L=L), f)
+    Qo, Qho, g, qg = _oracle_collide(d, N, f, eps, L)
+    _check(Qh, Qho, g)
+    _check(Q, Qo, qg)
+
+
 @pytest.mark.parametrize("d,N", CASES)
 @pytest.mark.parametrize("eps", [1, -1, 0])
 def test_collide_matches_oracle(d, N, eps):
@@ -101,21 +126,21 @@ def test_collide_matches_oracle(d, N, eps):
     f = inp.gaussian_mixture(d, N, L, seed=10 * N + d + eps, fmax=0.9 if eps == -1 else None)
     p = bnq.Params(d=d, N=N, eps=eps, L=L)
     Q, Qh = _gpu_collide(p, f)
-    Qo, Qho = _oracle(d, N).collide(f, eps, L)
-    assert _rel(Qh, Qho) <= TOL
-    assert _rel(Q, Qo) <= TOL
+    Qo, Qho, g, qg = _oracle_collide(d, N, f, eps, L)
+    _check(Qh, Qho, g)
+    _check(Q, Qo, qg)
 
 
 @pytest.mark.parametrize("d,N", [(2, 16), (3, 6)])
 @pytest.mark.parametrize("mask", [1, 2, 4, 3, 6])
 def test_each_term_separately(d, N, mask):
     L, eps, hbar = 4.0, 1, 1.3
-    f = inp.gaussian_mixture(d, N, L, seed=77)
+    f = inp.gaussian_mixture(d, N, L, seed=77, kmin=2)
     p = bnq.Params(d=d, N=N, eps=eps, L=L, hbar=hbar, terms=mask)
     Q, Qh = _gpu_collide(p, f)
-    Qo, Qho = _oracle(d, N).collide(f, eps, L, hbar=hbar, terms=_terms_tuple(mask))
-    assert _rel(Qh, Qho) <= TOL
-    assert _rel(Q, Qo) <= TOL
+    Qo, Qho, g, qg = _oracle_collide(d, N, f, eps, L, hbar=hbar, terms=_terms_tuple(mask))
+    _check(Qh, Qho, g)
+    _check(Q, Qo, qg)
 
 
 def test_scalings_hbar_cphi_c():
@@ -123,9 +148,10 @@ def test_scalings_hbar_cphi_c():
     f = inp.gaussian_mixture(d, N, L, seed=5)
     p = bnq.Params(d=d, N=N, eps=-1, L=L, hbar=0.7, C_phi=1.7, c=2.5)
     Q, Qh = _gpu_collide(p, f)
-    Qo, Qho = oracle.Oracle(d, N, Cphi=1.7).collide(f, -1, L, hbar=0.7, c=2.5)
-    assert _rel(Qh, Qho) <= TOL
-    assert _rel(Q, Qo) <= TOL
+    Qo, Qho, m = oracle.Oracle(d, N, Cphi=1.7).collide(f, -1, L, hbar=0.7, c=2.5, full=True)
+    g = np.linalg.norm(m["gain"])
+    _check(Qh, Qho, g)
+    _check(Q, Qo, np.linalg.norm(oracle.prefactor(d, L, 2.5) * oracle.idft_real(m["gain"])))
 
 
 def test_c1_boson_2d32_collide_and_rk4_step():
@@ -137,9 +163,9 @@ def test_c1_boson_2d32_collide_and_rk4_step():
     p = bnq.Params(d=d, N=N, eps=eps, L=L)
     Q, Qh = _gpu_collide(p, f)
     o = _oracle(d, N)
-    Qo, Qho = o.collide(f, eps, L)
-    assert _rel(Qh, Qho) <= TOL
-    assert _rel(Q, Qo) <= TOL
+    Qo, Qho, g, qg = _oracle_collide(d, N, f, eps, L)
+    _check(Qh, Qho, g)
+    _check(Q, Qo, qg)
     plan = bnq.Plan(p)
     ft = torch.tensor(f, device="cuda:0")
     plan.step(ft, 0.01, bnq.RK4)
