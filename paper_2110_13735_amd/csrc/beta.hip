@@ -124,24 +124,29 @@ __device__ static double beta_series(const Radial &rad, int qa, int qb, double d
     return sum;
 }
 
-// K[kc][a] = beta(a, b_c[kc]) for a in A.
+// K[kc][a] = beta(a, b_c[kc]) for a in A, stored as [a0][a2 (padded)][a1];
+// the x padding holds zeros.
 __global__ void beta_rows_kernel(Geo g, Radial rad, const int *canon, double *K) {
-    const int64_t ia = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int kc = blockIdx.y;
-    if (ia >= g.na) return;
+    if (i >= g.nak) return;
     const int A = 2 * g.N - 1;
-    const int a2 = (int)(ia % A) - (g.N - 1);
-    const int a1 = (int)((ia / A) % A) - (g.N - 1);
-    const int a0 = g.d == 3 ? (int)(ia / ((int64_t)A * A)) - (g.N - 1) : 0;
-    const int b0 = canon[3 * kc], b1 = canon[3 * kc + 1], b2 = canon[3 * kc + 2];
-    const int qa = a0 * a0 + a1 * a1 + a2 * a2;
-    const int qb = b0 * b0 + b1 * b1 + b2 * b2;
-    const int dab = abs(a0 * b0 + a1 * b1 + a2 * b2);
-    K[(int64_t)kc * g.na + ia] = beta_series(rad, qa, qb, (double)dab);
+    const int a1 = (int)(i % A) - (g.N - 1);
+    const int a2 = (int)((i / A) % g.kax) - (g.N - 1) - KPADLO;
+    const int a0 = g.d == 3 ? (int)(i / ((int64_t)A * g.kax)) - (g.N - 1) : 0;
+    double v = 0.0;
+    if (a2 >= -(g.N - 1) && a2 <= g.N - 1) {
+        const int b0 = canon[3 * kc], b1 = canon[3 * kc + 1], b2 = canon[3 * kc + 2];
+        const int qa = a0 * a0 + a1 * a1 + a2 * a2;
+        const int qb = b0 * b0 + b1 * b1 + b2 * b2;
+        const int dab = abs(a0 * b0 + a1 * b1 + a2 * b2);
+        v = beta_series(rad, qa, qb, (double)dab);
+    }
+    K[(int64_t)kc * g.nak + i] = v;
 }
 
 void launch_beta_rows(const Geo &g, const Radial &rad, const int *canon, int ncanon, double *K, hipStream_t s) {
-    dim3 grid((unsigned)((g.na + 255) / 256), (unsigned)ncanon);
+    dim3 grid((unsigned)((g.nak + 255) / 256), (unsigned)ncanon);
     hipLaunchKernelGGL(beta_rows_kernel, grid, dim3(256), 0, s, g, rad, canon, K);
 }
 

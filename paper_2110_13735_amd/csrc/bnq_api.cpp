@@ -70,6 +70,8 @@ Geo make_geo(int d, int N) {
     g.neg = (int64_t)g.eg0 * 2 * N * 2 * N;
     g.ea0 = d == 3 ? 2 * N - 1 : 1;
     g.na = (int64_t)g.ea0 * (2 * N - 1) * (2 * N - 1);
+    g.kax = 2 * N - 1 + KPADLO + KPADHI;
+    g.nak = (int64_t)g.ea0 * g.kax * (2 * N - 1);
     g.ex0 = d == 3 ? N + 1 : 1;
     g.next = (int64_t)g.ex0 * (N + 1) * (N + 1);
     return g;
@@ -199,7 +201,7 @@ size_t table_bytes(int d, int N) {
     const size_t ncanon = canon.size() / 3;
     const int qmax = d * N * N;
     const int M = mcut_of(qmax) + 1;
-    return sizeof(double) * (ncanon * (size_t)g.na + 2 * (size_t)g.nm * g.nm + (size_t)(qmax + 1) * M) +
+    return sizeof(double) * (ncanon * (size_t)g.nak + 2 * (size_t)g.nm * g.nm + (size_t)(qmax + 1) * M) +
            sizeof(int) * (qmax + 1);
 }
 
@@ -291,7 +293,7 @@ bnq_status build_tables(TableSet *t, hipStream_t s) {
     canon_list(d, N, t->canon, t->canon_row);
     t->ncanon = (int)(t->canon.size() / 3);
     if ((st = upload(&t->canon_d, t->canon, "canonical list"))) return st;
-    if ((st = dalloc(&t->K, (size_t)t->ncanon * g.na, "trilinear kernel-mode table"))) return st;
+    if ((st = dalloc(&t->K, (size_t)t->ncanon * g.nak, "trilinear kernel-mode table"))) return st;
     if ((st = dalloc(&t->wc, (size_t)g.nm * g.nm, "classical weight table"))) return st;
     if ((st = dalloc(&t->wq, (size_t)g.nm * g.nm, "quantum pair weight table"))) return st;
     const Radial rad = t->radial();
@@ -374,7 +376,8 @@ struct bnq_plan_s {
     Rot *rots_d = nullptr;
     double2 *tw = nullptr;
     double2 *Ghat = nullptr, *tmp = nullptr, *tmp2 = nullptr, *Gr = nullptr, *W = nullptr, *Qc = nullptr,
-            *T1 = nullptr, *X = nullptr, *Qh = nullptr, *part = nullptr;
+            *T1 = nullptr, *X = nullptr, *Qh = nullptr, *part = nullptr, *Pbuf = nullptr;
+    int nbdesc = 0;
     double *kbuf[4] = {nullptr, nullptr, nullptr, nullptr}, *ybuf = nullptr;
     double *mom_part = nullptr, *mom_out = nullptr;
     int nslots = 0;
@@ -448,7 +451,8 @@ size_t plan_workspace_bytes(const bnq_params *p, int nslots_est) {
     Geo g = make_geo(p->d, p->N);
     const size_t c = sizeof(double2), r = sizeof(double);
     const size_t nrot = p->d == 3 ? 48 : 8;
-    return c * (6 * (size_t)g.nm + g.neg + nrot * g.next + (size_t)nslots_est * g.nm) + r * 5 * (size_t)g.nm;
+    return c * (6 * (size_t)g.nm + g.neg + nrot * g.next + (size_t)nslots_est * g.nm + (size_t)g.nm * g.nm) +
+           r * 5 * (size_t)g.nm;
 }
 
 bnq_status build_t1_work(bnq_plan_s *P) {
@@ -461,6 +465,7 @@ bnq_status build_t1_work(bnq_plan_s *P) {
         double cost;
     };
     std::vector<It> items;
+    long long pofs = 0;
     const int b0lo = d == 3 ? -N + 1 : 0, b0hi = d == 3 ? N - 2 : 0;
     for (int b0 = b0lo; b0 <= b0hi; ++b0)
         for (int b1 = -N + 1; b1 <= N - 2; ++b1)
@@ -493,6 +498,9 @@ bnq_status build_t1_work(bnq_plan_s *P) {
                 const int wnx = B.wnhi[2] - B.wnlo[2] + 1;
                 B.nxb = (wnx + T1_RB - 1) / T1_RB;
                 B.pad = 0;
+                B.pofs = pofs;
+                pofs += (long long)(B.wphi[0] - B.wplo[0] + 1) * (B.wphi[1] - B.wplo[1] + 1) *
+                        (B.wphi[2] - B.wplo[2] + 1);
                 const int ntasks = B.nxb * (B.wnhi[1] - B.wnlo[1] + 1) * (B.wnhi[0] - B.wnlo[0] + 1);
                 const int wpx = B.wphi[2] - B.wplo[2] + 1;
                 const double rows = (double)(B.wphi[1] - B.wplo[1] + 1) * (B.wphi[0] - B.wplo[0] + 1);
@@ -509,17 +517,25 @@ bnq_status build_t1_work(bnq_plan_s *P) {
                     items.push_back(x);
                 }
             }
-    // longest-processing-time-first static assignment (deterministic)
-    std::stable_sort(items.begin(), items.end(), [](const It &a, const It &b) { return a.cost > b.cost; });
+    // Static, deterministic assignment with locality: items sorted by cost
+    // (descending), then canonical row, rotation and task, and dealt to the
+    // slots in snake order.  Slots progress through the sorted list nearly in
+    // lockstep, so at any time they share a few canonical rows (and pair
+    // products) in L2, and every slot receives a similar total cost.
+    std::stable_sort(items.begin(), items.end(), [&](const It &a, const It &b) {
+        if (a.cost != b.cost) return a.cost > b.cost;
+        const T1B &A = bd[a.it.b], &Bb = bd[b.it.b];
+        if (A.kc != Bb.kc) return A.kc < Bb.kc;
+        if (A.rot != Bb.rot) return A.rot < Bb.rot;
+        if (a.it.b != b.it.b) return a.it.b < b.it.b;
+        return a.it.t0 < b.it.t0;
+    });
     const int ns = (int)std::max<size_t>(1, std::min<size_t>(kMaxSlots, items.size()));
-    std::priority_queue<std::pair<double, int>, std::vector<std::pair<double, int>>, std::greater<>> pq;
-    for (int s = 0; s < ns; ++s) pq.push({0.0, s});
     std::vector<std::vector<T1Item>> per(ns);
-    for (const It &x : items) {
-        auto top = pq.top();
-        pq.pop();
-        per[top.second].push_back(x.it);
-        pq.push({top.first + x.cost, top.second});
+    for (size_t i = 0; i < items.size(); ++i) {
+        const size_t round = i / ns, j = i % ns;
+        const size_t slot = (round & 1) ? ns - 1 - j : j;
+        per[slot].push_back(items[i].it);
     }
     std::vector<int> off(ns + 1, 0);
     std::vector<T1Item> flat;
@@ -530,10 +546,12 @@ bnq_status build_t1_work(bnq_plan_s *P) {
     }
     off[ns] = (int)flat.size();
     P->nslots = ns;
+    P->nbdesc = (int)bd.size();
     bnq_status st;
     if ((st = upload(&P->bdesc, bd, "trilinear b descriptors")) || (st = upload(&P->items, flat, "trilinear items")) ||
         (st = upload(&P->slot_off, off, "trilinear slot offsets")))
         return st;
+    if ((st = dalloc(&P->Pbuf, (size_t)std::max<long long>(pofs, 1), "trilinear pair products"))) return st;
     return dalloc(&P->part, (size_t)ns * g.nm, "trilinear partial sums");
 }
 
@@ -551,6 +569,7 @@ void destroy_plan(bnq_plan_s *P) {
     hipFree(P->X);
     hipFree(P->Qh);
     hipFree(P->part);
+    hipFree(P->Pbuf);
     for (double *k : P->kbuf) hipFree(k);
     hipFree(P->ybuf);
     hipFree(P->mom_part);
@@ -592,12 +611,15 @@ bnq_status collide_impl(bnq_plan_s *P, const double *f, double *Q, double2 *Qhat
             Span sp(P, 4, s);
             launch_rotate(g, P->Ghat, P->rots_d, (int)P->grp.size(), P->Gr, s);
             LAUNCHCHK();
+            launch_pairprod(g, P->nbdesc, P->bdesc, P->Gr, P->Pbuf, s);
+            LAUNCHCHK();
             launch_zero(P->part, (int64_t)P->nslots * g.nm * (int64_t)sizeof(double2), s);
             LAUNCHCHK();
         }
         {
             Span sp(P, 3, s);
-            launch_trilinear(g, P->nslots, P->slot_off, P->items, P->bdesc, t->K, P->Gr, P->rots_d, P->part, s);
+            launch_trilinear(g, P->nslots, P->slot_off, P->items, P->bdesc, t->K, P->Gr, P->Pbuf, P->rots_d,
+                             P->part, s);
             LAUNCHCHK();
         }
         {
@@ -825,7 +847,7 @@ bnq_status bnq_table_lookup(bnq_plan_t P, int32_t table, int64_t n, const int32_
             int ap[3];
             for (int c = 0; c < 3; ++c) ap[perm[c]] = sgn[c] * x[c];
             const int kc = t->canon_row[((size_t)bc[0] * N + bc[1]) * N + bc[2]];
-            idx[i] = (int64_t)kc * g.na + idx_A(g, ap[0], ap[1], ap[2]);
+            idx[i] = (int64_t)kc * g.nak + idx_K(g, ap[0], ap[1], ap[2]);
         } else if (table == 1 || table == 2) {
             for (int c = (d == 3 ? 0 : 1); c < 3; ++c)
                 if (x[c] < -h || x[c] >= h || y[c] < -h || y[c] >= h)

@@ -7,8 +7,12 @@
 //   Eg    : pair sums l + m live in {-N .. N-1} per axis (2N values; the top
 //           value N-1 is never reached, which lets the outer sum read W at
 //           n - k without bounds checks), storage index s + N
-//   A     : trilinear kernel-mode rows, arguments {-(N-1) .. N-1} per axis
-//           (2N-1 values), storage index a + N - 1
+//   A     : trilinear kernel-mode rows, arguments {-(N-1) .. N-1} per axis.
+//           A row is stored [a0][a2][a1] (axis 1 fastest, so that lanes that
+//           own consecutive y read consecutive addresses); axis 2 (x) is
+//           padded with zeros by KPADLO below and KPADHI above, which lets
+//           the trilinear kernel's sliding window run past the window edges
+//           without clamping.
 //   Ext   : rotated spectra, modes {-N/2 .. N/2} per axis (N+1 values),
 //           storage index q + N/2
 #pragma once
@@ -26,6 +30,8 @@ struct Geo {
     int64_t neg;  // |Eg|
     int ea0;      // extent of axis 0 in A (1 or 2N-1)
     int64_t na;   // |A|
+    int kax;      // padded x extent of a stored row (2N-1 + KPADLO + KPADHI)
+    int64_t nak;  // stored row length ea0 * kax * (2N-1)
     int ex0;      // extent of axis 0 in Ext (1 or N+1)
     int64_t next; // |Ext|
 };
@@ -40,6 +46,12 @@ __host__ __device__ inline int64_t idx_E(const Geo &g, int s0, int s1, int s2) {
 __host__ __device__ inline int64_t idx_A(const Geo &g, int a0, int a1, int a2) {
     const int A = 2 * g.N - 1;
     return ((int64_t)(g.d == 3 ? a0 + g.N - 1 : 0) * A + (a1 + g.N - 1)) * A + (a2 + g.N - 1);
+}
+constexpr int KPADLO = 16, KPADHI = 8;
+// offset of a = (a0, a1, a2) inside a stored trilinear row
+__host__ __device__ inline int64_t idx_K(const Geo &g, int a0, int a1, int a2) {
+    const int A = 2 * g.N - 1;
+    return ((int64_t)(g.d == 3 ? a0 + g.N - 1 : 0) * g.kax + (a2 + g.N - 1 + KPADLO)) * A + (a1 + g.N - 1);
 }
 __host__ __device__ inline int64_t idx_X(const Geo &g, int q0, int q1, int q2) {
     const int X = g.N + 1;
@@ -61,6 +73,7 @@ struct T1B {
     int wplo[3], wphi[3];  // inner window in the rotated frame
     int nxb;         // x-blocks of the output window
     int pad;
+    long long pofs;  // offset of this b's pair products in the pair-product buffer
 };
 
 struct T1Item {
@@ -71,7 +84,6 @@ struct T1Item {
 };
 
 constexpr int T1_RB = 8;      // outputs per lane along x
-constexpr int T1_ROWS = 8;    // inner rows staged per barrier
 
 // Radial tables for the kernel-mode series.
 struct Radial {
@@ -98,9 +110,10 @@ void launch_rotate(const Geo &g, const double2 *G, const Rot *rots, int nrot, do
 void launch_pairs(const Geo &g, const double2 *G, const double *wc, const double *wq, double2 *Qc,
                   double2 *W, int want_c, int want_w, hipStream_t s);
 void launch_outer(const Geo &g, const double2 *G, const double2 *W, double2 *X, hipStream_t s);
+void launch_pairprod(const Geo &g, int nb, const T1B *bdesc, const double2 *Gr, double2 *Pbuf, hipStream_t s);
 void launch_trilinear(const Geo &g, int nslots, const int *slot_off, const T1Item *items,
-                      const T1B *bdesc, const double *K, const double2 *Gr, const Rot *rots,
-                      double2 *part, hipStream_t s);
+                      const T1B *bdesc, const double *K, const double2 *Gr, const double2 *Pbuf,
+                      const Rot *rots, double2 *part, hipStream_t s);
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_reduce_partials(const Geo &g, int nslots, const double2 *part, double2 *T1, hipStream_t s);
 void launch_combine(const Geo &g, const double2 *Qc, const double2 *T1, const double2 *X, int terms,

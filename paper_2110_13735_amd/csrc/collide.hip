@@ -120,63 +120,56 @@ void launch_rotate(const Geo &g, const double2 *G, const Rot *rots, int nrot, do
 }
 
 // ---------------------------------------------------------------------------
-// Pair sums.  One block = a 4 x 4 x 16 tile of outputs s (16 x 16 in 2-D);
-// all lanes walk the same l over the tile's reachable box, so G_l is a
-// broadcast load and the weight rows are read in 128-byte runs.
-constexpr int PT0 = 4, PT1 = 4, PT2 = 16;
-
+// Pair sums.  A workgroup of 256 lanes owns 256/(2N) whole x-rows of outputs
+// s (s2 = -N .. N-1 across the lanes) at one s0.  All lanes walk the same l
+// over the rows' reachable box, so G_l is a broadcast load and for fixed l
+// the weight rows wq[l][s - l] are read as contiguous runs.  Loads are
+// branch-free (indices clamped into range, invalid terms weighted by zero)
+// and the innermost loop is unrolled so that many table loads are in flight.
 __global__ __launch_bounds__(256) void pairs_kernel(Geo g, const double2 *G, const double *wc,
                                                     const double *wq, double2 *Qc, double2 *W, int want_c,
                                                     int want_w) {
     const int N = g.N, h = g.h;
-    const int t0 = g.d == 3 ? PT0 : 1, t1 = g.d == 3 ? PT1 : 16, t2 = PT2;
-    const int nt2 = (2 * N + t2 - 1) / t2, nt1 = (2 * N + t1 - 1) / t1;
-    int bid = blockIdx.x;
-    const int b2 = bid % nt2;
-    bid /= nt2;
-    const int b1 = bid % nt1;
-    const int b0 = bid / nt1;
+    const int rows = 256 / (2 * N);  // s1 rows per workgroup
     const int tid = threadIdx.x;
-    const int s2 = b2 * t2 + tid % t2 - N;
-    const int s1 = b1 * t1 + (tid / t2) % t1 - N;
-    const int s0 = g.d == 3 ? b0 * t0 + tid / (t2 * t1) - N : 0;
-    const bool valid = s2 < N && s1 < N && (g.d == 2 || s0 < N);
-    const bool inI = s2 >= -h && s2 < h && s1 >= -h && s1 < h && (g.d == 2 || (s0 >= -h && s0 < h));
-    // reachable l box of the tile: l and s - l in I_N
-    int lo[3], hi[3];
-    const int smin[3] = {g.d == 3 ? b0 * t0 - N : 0, b1 * t1 - N, b2 * t2 - N};
-    const int smax[3] = {g.d == 3 ? min(b0 * t0 + t0 - 1 - N, N - 1) : 0, min(b1 * t1 + t1 - 1 - N, N - 1),
-                         min(b2 * t2 + t2 - 1 - N, N - 1)};
-    for (int a = 0; a < 3; ++a) {
-        const int ilo = (a == 0 && g.d == 2) ? 0 : -h, ihi = (a == 0 && g.d == 2) ? 0 : h - 1;
-        lo[a] = max(ilo, smin[a] - ihi);
-        hi[a] = min(ihi, smax[a] - ilo);
-    }
+    const int s2 = tid % (2 * N) - N;
+    const int r = tid / (2 * N);
+    const int s1 = blockIdx.x * rows + r - N;
+    const int s0 = g.d == 3 ? (int)blockIdx.y - N : 0;
+    const bool valid = r < rows && s1 < N;
+    const bool inI = valid && s2 >= -h && s2 < h && s1 >= -h && s1 < h && (g.d == 2 || (s0 >= -h && s0 < h));
+    // reachable box of l: l and s - l in I_N for some s of the workgroup
+    const int s1min = blockIdx.x * rows - N, s1max = min(s1min + rows - 1, N - 1);
+    const int l0lo = g.d == 3 ? max(-h, s0 - (h - 1)) : 0, l0hi = g.d == 3 ? min(h - 1, s0 + h) : 0;
+    const int l1lo = max(-h, s1min - (h - 1)), l1hi = min(h - 1, s1max + h);
     double2 accw = make_double2(0.0, 0.0), accc = make_double2(0.0, 0.0);
     const bool do_c = want_c && inI;
-    for (int l0 = lo[0]; l0 <= hi[0]; ++l0) {
-        const int m0 = s0 - l0;
-        const bool ok0 = g.d == 2 || (m0 >= -h && m0 < h);
-        for (int l1 = lo[1]; l1 <= hi[1]; ++l1) {
+    for (int l0 = l0lo; l0 <= l0hi; ++l0) {
+        const int m0 = s0 - l0;  // in I_N by the choice of the l0 range
+        for (int l1 = l1lo; l1 <= l1hi; ++l1) {
             const int m1 = s1 - l1;
-            const bool ok1 = ok0 && m1 >= -h && m1 < h;
-            for (int l2 = lo[2]; l2 <= hi[2]; ++l2) {
+            const bool ok1 = valid && m1 >= -h && m1 < h;
+            const int m1c = min(max(m1, -h), h - 1);
+            const int64_t il0 = idx_I(g, l0, l1, -h);
+            const int64_t im0 = idx_I(g, m0, m1c, 0);
+#pragma unroll 8
+            for (int j = 0; j < N; ++j) {
+                const int l2 = j - h;
                 const int m2 = s2 - l2;
-                if (valid && ok1 && m2 >= -h && m2 < h) {
-                    const int64_t il = idx_I(g, l0, l1, l2), im = idx_I(g, m0, m1, m2);
-                    const double2 p = cmul(G[il], G[im]);
-                    const int64_t o = il * g.nm + im;
-                    if (want_w) {
-                        const double w = wq[o];
-                        accw.x = fma(w, p.x, accw.x);
-                        accw.y = fma(w, p.y, accw.y);
-                    }
-                    if (do_c) {
-                        const double w = wc[o];
-                        accc.x = fma(w, p.x, accc.x);
-                        accc.y = fma(w, p.y, accc.y);
-                    }
-                }
+                const bool ok = ok1 && m2 >= -h && m2 < h;
+                const int m2c = min(max(m2, -h), h - 1);
+                const int64_t il = il0 + j, im = im0 + m2c;
+                const double2 gl = G[il];
+                const double2 gm = G[im];
+                const int64_t o = il * g.nm + im;
+                const double w1 = want_w ? wq[o] : 0.0;
+                const double w2 = do_c ? wc[o] : 0.0;
+                const double2 p = cmul(gl, gm);
+                const double a1 = ok ? w1 : 0.0, a2 = ok ? w2 : 0.0;
+                accw.x = fma(a1, p.x, accw.x);
+                accw.y = fma(a1, p.y, accw.y);
+                accc.x = fma(a2, p.x, accc.x);
+                accc.y = fma(a2, p.y, accc.y);
             }
         }
     }
@@ -188,9 +181,9 @@ __global__ __launch_bounds__(256) void pairs_kernel(Geo g, const double2 *G, con
 void launch_pairs(const Geo &g, const double2 *G, const double *wc, const double *wq, double2 *Qc,
                   double2 *W, int want_c, int want_w, hipStream_t s) {
     const int N = g.N;
-    const int t0 = g.d == 3 ? PT0 : 1, t1 = g.d == 3 ? PT1 : 16, t2 = PT2;
-    const int nb = ((2 * N + t2 - 1) / t2) * ((2 * N + t1 - 1) / t1) * (g.d == 3 ? (2 * N + t0 - 1) / t0 : 1);
-    hipLaunchKernelGGL(pairs_kernel, dim3(nb), dim3(256), 0, s, g, G, wc, wq, Qc, W, want_c, want_w);
+    const int rows = 256 / (2 * N);
+    dim3 grid((unsigned)((2 * N + rows - 1) / rows), (unsigned)(g.d == 3 ? 2 * N : 1));
+    hipLaunchKernelGGL(pairs_kernel, grid, dim3(256), 0, s, g, G, wc, wq, Qc, W, want_c, want_w);
 }
 
 // ---------------------------------------------------------------------------
@@ -207,6 +200,7 @@ __global__ __launch_bounds__(256) void outer_kernel(Geo g, const double2 *G, con
         for (int k1 = -h; k1 < h; ++k1) {
             const double2 *Grow = G + idx_I(g, k0, k1, -h);
             const double2 *Wrow = W + idx_E(g, n0 - k0, n1 - k1, n2 + h);
+#pragma unroll 8
             for (int k2 = 0; k2 < N; ++k2) {
                 const double2 a = Grow[k2], b = Wrow[-k2];
                 acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
@@ -221,113 +215,224 @@ void launch_outer(const Geo &g, const double2 *G, const double2 *W, double2 *X, 
 }
 
 // ---------------------------------------------------------------------------
+// Pair products for the trilinear sum: for every b (in its rotated frame) and
+// every p in its inner window, P(b, p) = G_R(p) G_R(b_c - p), stored
+// contiguously per b in (pz, py, px) order.
+__global__ __launch_bounds__(256) void pairprod_kernel(Geo g, const T1B *bdesc, const double2 *Gr, double2 *Pbuf) {
+    const T1B B = bdesc[blockIdx.x];
+    const double2 *G = Gr + (int64_t)B.rot * g.next;
+    const int wpx = B.wphi[2] - B.wplo[2] + 1, wpy = B.wphi[1] - B.wplo[1] + 1;
+    const int n = wpx * wpy * (B.wphi[0] - B.wplo[0] + 1);
+    double2 *out = Pbuf + B.pofs;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int px = B.wplo[2] + e % wpx;
+        const int py = B.wplo[1] + (e / wpx) % wpy;
+        const int pz = B.wplo[0] + e / (wpx * wpy);
+        out[e] = cmul(G[idx_X(g, pz, py, px)], G[idx_X(g, B.bc[0] - pz, B.bc[1] - py, B.bc[2] - px)]);
+    }
+}
+
+void launch_pairprod(const Geo &g, int nb, const T1B *bdesc, const double2 *Gr, double2 *Pbuf, hipStream_t s) {
+    hipLaunchKernelGGL(pairprod_kernel, dim3(nb), dim3(256), 0, s, g, bdesc, Gr, Pbuf);
+}
+
+// ---------------------------------------------------------------------------
 // Trilinear sum.  One 64-lane workgroup per slot; each slot walks its static
 // list of items (b, range of <= 64 tasks) and accumulates into its own
 // partial array (no atomics; the slots are summed in a fixed order later).
-constexpr int T1_NPAD = 64;  // padded inner row length (N <= 64)
+//
+// A task is 8 consecutive outputs along x at one (y, z); tasks are numbered
+// y fastest so that the lanes of a wave read consecutive addresses of the
+// y-fastest kernel-mode rows.  For every inner row (py, pz) a lane slides a
+// 16-value window K(a_x), a_x = base + i - u, over the inner index u in blocks
+// of 8: block k uses lo_k[s] = K(base - 8k - 8 + s) and hi_k[s] =
+// K(base - 8k + s) = lo_{k-1}[s].  Three 8-value arrays rotate (at compile
+// time: the number of full blocks is a template parameter) so that the next
+// block's values are loaded while the current block computes, and the next
+// row's first window is loaded at the start of the current row.  The pair
+// products of a row are uniform across the wave and come in through scalar
+// loads.
+struct T1Ctx {
+    const double *pc;            // K(a_x = base) of the current row
+    const double2 *__restrict__ Pr;  // pair products of the current row
+    int64_t A;
+};
 
-__global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_off, const T1Item *items,
-                                                       const T1B *bdesc, const double *K, const double2 *Gr,
-                                                       const Rot *rots, double2 *part) {
-    __shared__ double2 P[T1_ROWS][T1_NPAD];
-    const int slot = blockIdx.x;
-    const int lane = threadIdx.x;
-    double2 *mypart = part + (int64_t)slot * g.nm;
-    const int N = g.N;
-    const int A = 2 * N - 1;
-    const int it_end = slot_off[slot + 1];
-    for (int it = slot_off[slot]; it < it_end; ++it) {
-        const T1Item item = items[it];
-        const T1B B = bdesc[item.b];
-        const Rot R = rots[B.rot];
-        const double2 *G = Gr + (int64_t)B.rot * g.next;
-        const double *Krow = K + (int64_t)B.kc * g.na;
-        const bool active = lane < item.nt;
-        const int t = item.t0 + lane;
-        const int wny = B.wnhi[1] - B.wnlo[1] + 1;
-        const int xb = t % B.nxb;
-        const int rest = t / B.nxb;
-        const int ny = B.wnlo[1] + rest % wny;
-        const int nz = B.wnlo[0] + rest / wny;
-        const int x0 = B.wnlo[2] + xb * T1_RB;
-        const int wpx = B.wphi[2] - B.wplo[2] + 1;
-        const int wpxp = (wpx + 7) & ~7;
-        const int wpy = B.wphi[1] - B.wplo[1] + 1;
-        const int nrows = wpy * (B.wphi[0] - B.wplo[0] + 1);
-        const int base = x0 - B.wplo[2];  // a_x = base + i - u
-        double zr[T1_RB], zi[T1_RB];
+template <int NF, int K>
+__device__ __forceinline__ void t1_full(const T1Ctx &c, double (&lo)[8], double (&hi)[8], double (&nx)[8],
+                                        double (&zr)[T1_RB], double (&zi)[T1_RB]) {
+    const double *q = c.pc - (int64_t)(8 * (K + 1) + 8) * c.A;
 #pragma unroll
-        for (int i = 0; i < T1_RB; ++i) zr[i] = zi[i] = 0.0;
-        for (int r0 = 0; r0 < nrows; r0 += T1_ROWS) {
-            const int nr = min(T1_ROWS, nrows - r0);
-            __syncthreads();
-            for (int e = lane; e < nr * wpxp; e += 64) {
-                const int rr = e / wpxp, u = e - rr * wpxp;
-                const int row = r0 + rr;
-                const int py = B.wplo[1] + row % wpy, pz = B.wplo[0] + row / wpy;
-                double2 v = make_double2(0.0, 0.0);
-                if (u < wpx) {
-                    const int px = B.wplo[2] + u;
-                    v = cmul(G[idx_X(g, pz, py, px)], G[idx_X(g, B.bc[0] - pz, B.bc[1] - py, B.bc[2] - px)]);
-                }
-                P[rr][u] = v;
-            }
-            __syncthreads();
-            if (!active) continue;
-            for (int rr = 0; rr < nr; ++rr) {
-                const int row = r0 + rr;
-                const int py = B.wplo[1] + row % wpy, pz = B.wplo[0] + row / wpy;
-                const double *Kr = Krow + ((int64_t)(g.d == 3 ? nz - pz + N - 1 : 0) * A + (ny - py + N - 1)) * A + (N - 1);
-                // kw[s] = K(a_x = base - ub + s - 8), clamped into the row
-                double kw[16];
+    for (int s = 0; s < 8; ++s) nx[s] = q[(int64_t)s * c.A];
 #pragma unroll
-                for (int s = 0; s < 16; ++s) kw[s] = Kr[min(max(base + s - 8, 1 - N), N - 1)];
-                for (int ub = 0; ub < wpxp; ub += 8) {
-                    if (ub > 0) {
+    for (int jj = 0; jj < 8; ++jj) {
+        const double2 p = c.Pr[8 * K + jj];
 #pragma unroll
-                        for (int s = 0; s < 8; ++s) kw[8 + s] = kw[s];
-#pragma unroll
-                        for (int s = 0; s < 8; ++s) kw[s] = Kr[min(max(base - ub + s - 8, 1 - N), N - 1)];
-                    }
-#pragma unroll
-                    for (int jj = 0; jj < 8; ++jj) {
-                        const double2 p = P[rr][ub + jj];
-#pragma unroll
-                        for (int i = 0; i < T1_RB; ++i) {
-                            const double k = kw[i - jj + 8];
-                            zr[i] = fma(k, p.x, zr[i]);
-                            zi[i] = fma(k, p.y, zi[i]);
-                        }
-                    }
-                }
-            }
+        for (int i = 0; i < T1_RB; ++i) {
+            const double k = (i - jj < 0) ? lo[i - jj + 8] : hi[i - jj];
+            zr[i] = fma(k, p.x, zr[i]);
+            zi[i] = fma(k, p.y, zi[i]);
         }
-        if (active) {
-            const int np[3] = {nz, ny, 0};
+    }
+}
+
+__device__ __forceinline__ void t1_tail(const T1Ctx &c, int u0, int rem, const double (&lo)[8],
+                                        const double (&hi)[8], double (&zr)[T1_RB], double (&zi)[T1_RB]) {
+#pragma unroll
+    for (int jj = 0; jj < 7; ++jj) {
+        if (jj < rem) {
+            const double2 p = c.Pr[u0 + jj];
 #pragma unroll
             for (int i = 0; i < T1_RB; ++i) {
-                const int nx = x0 + i;
-                if (nx <= B.wnhi[2]) {
-                    const double2 gk = G[idx_X(g, nz - B.bc[0], ny - B.bc[1], nx - B.bc[2])];
-                    const double2 c = cmul(gk, make_double2(zr[i], zi[i]));
-                    const int v[3] = {np[0], np[1], nx};
-                    const int o0 = R.sgn[0] * v[R.perm[0]];
-                    const int o1 = R.sgn[1] * v[R.perm[1]];
-                    const int o2 = R.sgn[2] * v[R.perm[2]];
-                    double2 *dst = mypart + idx_I(g, o0, o1, o2);
-                    double2 cur = *dst;
-                    cur.x += c.x;
-                    cur.y += c.y;
-                    *dst = cur;
-                }
+                const double k = (i - jj < 0) ? lo[i - jj + 8] : hi[i - jj];
+                zr[i] = fma(k, p.x, zr[i]);
+                zi[i] = fma(k, p.y, zi[i]);
             }
         }
     }
 }
 
+// Blocks K .. NF-1 of a row, ring slots (S0, S1, S2) = (lo_0, hi_0, spare),
+// then the tail.  Slot of lo_k: 0,2,1,...; hi_k: 1,0,2,...; prefetch: 2,1,0,...
+template <int NF, int K>
+__device__ __forceinline__ void t1_blocks(const T1Ctx &c, int rem, double (&S0)[8], double (&S1)[8],
+                                          double (&S2)[8], double (&zr)[T1_RB], double (&zi)[T1_RB]) {
+    if constexpr (K < NF) {
+        if constexpr (K % 3 == 0)
+            t1_full<NF, K>(c, S0, S1, S2, zr, zi);
+        else if constexpr (K % 3 == 1)
+            t1_full<NF, K>(c, S2, S0, S1, zr, zi);
+        else
+            t1_full<NF, K>(c, S1, S2, S0, zr, zi);
+        t1_blocks<NF, K + 1>(c, rem, S0, S1, S2, zr, zi);
+    } else {
+        if constexpr (K % 3 == 0)
+            t1_tail(c, 8 * K, rem, S0, S1, zr, zi);
+        else if constexpr (K % 3 == 1)
+            t1_tail(c, 8 * K, rem, S2, S0, zr, zi);
+        else
+            t1_tail(c, 8 * K, rem, S1, S2, zr, zi);
+    }
+}
+
+template <int NF>
+__device__ __forceinline__ void t1_rows(const Geo &g, const T1B &B, const double *Krow, const double2 *Pb, int ny,
+                                        int nz, int base, double (&zr)[T1_RB], double (&zi)[T1_RB]) {
+    const int N = g.N;
+    T1Ctx c;
+    c.A = 2 * N - 1;
+    const int wpx = B.wphi[2] - B.wplo[2] + 1;
+    const int wpy = B.wphi[1] - B.wplo[1] + 1;
+    const int nrows = wpy * (B.wphi[0] - B.wplo[0] + 1);
+    const int rem = wpx - 8 * NF;
+    auto rowptr = [&](int row) {
+        const int py = B.wplo[1] + row % wpy, pz = B.wplo[0] + row / wpy;
+        return Krow + idx_K(g, nz - pz, ny - py, 0) + (int64_t)base * c.A;
+    };
+    double xl[8], xh[8], yl[8], yh[8], sp[8];
+    {
+        const double *p0 = rowptr(0);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            xl[s] = p0[(int64_t)(s - 8) * c.A];
+            xh[s] = p0[(int64_t)s * c.A];
+        }
+    }
+    for (int row = 0; row < nrows; row += 2) {
+        {
+            const double *pn = rowptr(min(row + 1, nrows - 1));
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                yl[s] = pn[(int64_t)(s - 8) * c.A];
+                yh[s] = pn[(int64_t)s * c.A];
+            }
+            c.pc = rowptr(row);
+            c.Pr = Pb + (int64_t)row * wpx;
+            t1_blocks<NF, 0>(c, rem, xl, xh, sp, zr, zi);
+        }
+        if (row + 1 < nrows) {
+            const double *pn = rowptr(min(row + 2, nrows - 1));
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                xl[s] = pn[(int64_t)(s - 8) * c.A];
+                xh[s] = pn[(int64_t)s * c.A];
+            }
+            c.pc = rowptr(row + 1);
+            c.Pr = Pb + (int64_t)(row + 1) * wpx;
+            t1_blocks<NF, 0>(c, rem, yl, yh, sp, zr, zi);
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_off, const T1Item *items,
+                                                       const T1B *bdesc, const double *K, const double2 *Gr,
+                                                       const double2 *__restrict__ Pbuf, const Rot *rots,
+                                                       double2 *part) {
+    const int slot = blockIdx.x;
+    const int lane = threadIdx.x;
+    double2 *mypart = part + (int64_t)slot * g.nm;
+    const int it_end = slot_off[slot + 1];
+    for (int it = slot_off[slot]; it < it_end; ++it) {
+        const T1Item item = items[it];
+        const T1B B = bdesc[item.b];
+        const int t = item.t0 + lane;
+        const int wny = B.wnhi[1] - B.wnlo[1] + 1;
+        const int ny = B.wnlo[1] + t % wny;
+        const int rest = t / wny;
+        const int xb = rest % B.nxb;
+        const int nz = B.wnlo[0] + rest / B.nxb;
+        const int x0 = B.wnlo[2] + xb * T1_RB;
+        if (lane >= item.nt) {
+            __threadfence_block();
+            continue;
+        }
+        const double *Krow = K + (int64_t)B.kc * g.nak;
+        const double2 *Pb = Pbuf + B.pofs;
+        const int base = x0 - B.wplo[2];  // a_x = base + i - u
+        const int nfull = (B.wphi[2] - B.wplo[2] + 1) >> 3;
+        double zr[T1_RB], zi[T1_RB];
+#pragma unroll
+        for (int i = 0; i < T1_RB; ++i) zr[i] = zi[i] = 0.0;
+        switch (nfull) {
+            case 0: t1_rows<0>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
+            case 1: t1_rows<1>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
+            case 2: t1_rows<2>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
+            case 3: t1_rows<3>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
+            case 4: t1_rows<4>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
+            case 5: t1_rows<5>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
+            case 6: t1_rows<6>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
+            case 7: t1_rows<7>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
+            default: t1_rows<8>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
+        }
+        const Rot R = rots[B.rot];
+        const double2 *G = Gr + (int64_t)B.rot * g.next;
+#pragma unroll
+        for (int i = 0; i < T1_RB; ++i) {
+            const int nx = x0 + i;
+            if (nx <= B.wnhi[2]) {
+                const double2 gk = G[idx_X(g, nz - B.bc[0], ny - B.bc[1], nx - B.bc[2])];
+                const double2 cc = cmul(gk, make_double2(zr[i], zi[i]));
+                const int v[3] = {nz, ny, nx};
+                const int o0 = R.sgn[0] * v[R.perm[0]];
+                const int o1 = R.sgn[1] * v[R.perm[1]];
+                const int o2 = R.sgn[2] * v[R.perm[2]];
+                double2 *dst = mypart + idx_I(g, o0, o1, o2);
+                double2 cur = *dst;
+                cur.x += cc.x;
+                cur.y += cc.y;
+                *dst = cur;
+            }
+        }
+        // the next item may read back outputs written here by other lanes
+        __threadfence_block();
+    }
+}
+
 void launch_trilinear(const Geo &g, int nslots, const int *slot_off, const T1Item *items, const T1B *bdesc,
-                      const double *K, const double2 *Gr, const Rot *rots, double2 *part, hipStream_t s) {
-    hipLaunchKernelGGL(trilinear_kernel, dim3(nslots), dim3(64), 0, s, g, slot_off, items, bdesc, K, Gr, rots, part);
+                      const double *K, const double2 *Gr, const double2 *Pbuf, const Rot *rots, double2 *part,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(trilinear_kernel, dim3(nslots), dim3(64), 0, s, g, slot_off, items, bdesc, K, Gr, Pbuf, rots,
+                       part);
 }
 
 __global__ void zero_kernel(double *p, int64_t n) {
