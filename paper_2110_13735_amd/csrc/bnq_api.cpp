@@ -55,7 +55,8 @@ bnq_status fail(bnq_status st, const char *fmt, ...) {
 
 const double kR = 2.0 * M_PI / (3.0 + std::sqrt(2.0));  // R = S, pi = (3 + sqrt 2) S / 2
 const int kNq = 128;                                    // radial Gauss–Legendre nodes
-const int kMaxSlots = 2048;                             // trilinear partial arrays
+const int kMaxSlots = 4096;                             // trilinear partial arrays (upper bound)
+const int kCusPerXcd = 32;                              // compute units per XCD on gfx950
 
 // ---------------------------------------------------------------------------
 Geo make_geo(int d, int N) {
@@ -517,25 +518,50 @@ bnq_status build_t1_work(bnq_plan_s *P) {
                     items.push_back(x);
                 }
             }
-    // Static, deterministic assignment with locality: items sorted by cost
-    // (descending), then canonical row, rotation and task, and dealt to the
-    // slots in snake order.  Slots progress through the sorted list nearly in
-    // lockstep, so at any time they share a few canonical rows (and pair
-    // products) in L2, and every slot receives a similar total cost.
+    // Static, deterministic assignment.  One slot per resident wave (compute
+    // units x waves per CU).  Workgroups are dispatched to the XCDs round
+    // robin, so slot s runs on XCD s % nx and each XCD has its own L2.  The
+    // items, ordered by canonical row, rotation, b and task, are cut into nx
+    // contiguous runs of equal cost, one per XCD, so that a canonical row and
+    // a b's pair products are fetched into one L2 only.  Within an XCD the
+    // run is dealt to its slots in snake order: the slots walk through the run
+    // nearly in lockstep (sharing the rows in flight) and receive similar
+    // total cost.
     std::stable_sort(items.begin(), items.end(), [&](const It &a, const It &b) {
-        if (a.cost != b.cost) return a.cost > b.cost;
         const T1B &A = bd[a.it.b], &Bb = bd[b.it.b];
         if (A.kc != Bb.kc) return A.kc < Bb.kc;
         if (A.rot != Bb.rot) return A.rot < Bb.rot;
         if (a.it.b != b.it.b) return a.it.b < b.it.b;
         return a.it.t0 < b.it.t0;
     });
-    const int ns = (int)std::max<size_t>(1, std::min<size_t>(kMaxSlots, items.size()));
+    int dev = 0, cus = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int per_cu = trilinear_blocks_per_cu();
+    if (cus <= 0 || per_cu <= 0) return fail(BNQ_EHIP, "trilinear occupancy query failed");
+    const int nx = std::max(1, cus / kCusPerXcd);
+    int ns_want = std::min(kMaxSlots, cus * per_cu);
+    ns_want = std::max(nx, ns_want - ns_want % nx);
+    const int ns = (int)std::max<size_t>(1, std::min<size_t>(ns_want, items.size()));
     std::vector<std::vector<T1Item>> per(ns);
-    for (size_t i = 0; i < items.size(); ++i) {
-        const size_t round = i / ns, j = i % ns;
-        const size_t slot = (round & 1) ? ns - 1 - j : j;
-        per[slot].push_back(items[i].it);
+    if (ns < ns_want) {
+        for (size_t i = 0; i < items.size(); ++i) per[i].push_back(items[i].it);
+    } else {
+        double total = 0;
+        for (const It &x : items) total += x.cost;
+        const int spx = ns / nx;  // slots per XCD
+        size_t i = 0;
+        double acc = 0;
+        for (int x = 0; x < nx; ++x) {
+            const double cut = total * (x + 1) / nx;
+            size_t k = 0;
+            for (; i < items.size() && (x == nx - 1 || acc + 0.5 * items[i].cost <= cut); ++i, ++k) {
+                acc += items[i].cost;
+                const size_t round = k / spx, j = k % spx;
+                const size_t sj = (round & 1) ? spx - 1 - j : j;
+                per[x + nx * sj].push_back(items[i].it);
+            }
+        }
     }
     std::vector<int> off(ns + 1, 0);
     std::vector<T1Item> flat;

@@ -114,6 +114,7 @@ void launch_pairprod(const Geo &g, int nb, const T1B *bdesc, const double2 *Gr, 
 void launch_trilinear(const Geo &g, int nslots, const int *slot_off, const T1Item *items,
                       const T1B *bdesc, const double *K, const double2 *Gr, const double2 *Pbuf,
                       const Rot *rots, double2 *part, hipStream_t s);
+int trilinear_blocks_per_cu();  // resident 64-lane trilinear workgroups per CU (0 on error)
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_reduce_partials(const Geo &g, int nslots, const double2 *part, double2 *T1, hipStream_t s);
 void launch_combine(const Geo &g, const double2 *Qc, const double2 *T1, const double2 *X, int terms,

@@ -249,24 +249,33 @@ void launch_pairprod(const Geo &g, int nb, const T1B *bdesc, const double2 *Gr, 
 // K(base - 8k + s) = lo_{k-1}[s].  Three 8-value arrays rotate (at compile
 // time: the number of full blocks is a template parameter) so that the next
 // block's values are loaded while the current block computes, and the next
-// row's first window is loaded at the start of the current row.  The pair
-// products of a row are uniform across the wave and come in through scalar
-// loads.
+// row's first window is loaded at the start of the current row.
+//
+// Kernel-mode values come through a buffer resource over the canonical row:
+// one 32-bit lane offset per window, the 8 values of a window at scalar
+// offsets s * 8A.  The pair products of a row are uniform across the wave:
+// the next row's are fetched into a register (one per lane) while the current
+// row computes, then written to a two-row LDS ring and read as broadcasts.
 struct T1Ctx {
-    const double *pc;            // K(a_x = base) of the current row
-    const double2 *__restrict__ Pr;  // pair products of the current row
-    int64_t A;
+    __amdgpu_buffer_rsrc_t kr;  // canonical kernel-mode row
+    int voff;                   // byte offset of K(a_x = base) at this row's (a_z, a_y)
+    int sA;                     // bytes between consecutive a_x
+    const double2 *ps;          // LDS: pair products of the current row
 };
 
-template <int NF, int K>
+__device__ __forceinline__ double t1_kload(const T1Ctx &c, int voff, int s) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(c.kr, voff, s * c.sA, 0));
+}
+
+template <int K>
 __device__ __forceinline__ void t1_full(const T1Ctx &c, double (&lo)[8], double (&hi)[8], double (&nx)[8],
                                         double (&zr)[T1_RB], double (&zi)[T1_RB]) {
-    const double *q = c.pc - (int64_t)(8 * (K + 1) + 8) * c.A;
+    const int vq = c.voff - (8 * (K + 1) + 8) * c.sA;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) nx[s] = q[(int64_t)s * c.A];
+    for (int s = 0; s < 8; ++s) nx[s] = t1_kload(c, vq, s);
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj) {
-        const double2 p = c.Pr[8 * K + jj];
+        const double2 p = c.ps[8 * K + jj];
 #pragma unroll
         for (int i = 0; i < T1_RB; ++i) {
             const double k = (i - jj < 0) ? lo[i - jj + 8] : hi[i - jj];
@@ -281,7 +290,7 @@ __device__ __forceinline__ void t1_tail(const T1Ctx &c, int u0, int rem, const d
 #pragma unroll
     for (int jj = 0; jj < 7; ++jj) {
         if (jj < rem) {
-            const double2 p = c.Pr[u0 + jj];
+            const double2 p = c.ps[u0 + jj];
 #pragma unroll
             for (int i = 0; i < T1_RB; ++i) {
                 const double k = (i - jj < 0) ? lo[i - jj + 8] : hi[i - jj];
@@ -299,11 +308,11 @@ __device__ __forceinline__ void t1_blocks(const T1Ctx &c, int rem, double (&S0)[
                                           double (&S2)[8], double (&zr)[T1_RB], double (&zi)[T1_RB]) {
     if constexpr (K < NF) {
         if constexpr (K % 3 == 0)
-            t1_full<NF, K>(c, S0, S1, S2, zr, zi);
+            t1_full<K>(c, S0, S1, S2, zr, zi);
         else if constexpr (K % 3 == 1)
-            t1_full<NF, K>(c, S2, S0, S1, zr, zi);
+            t1_full<K>(c, S2, S0, S1, zr, zi);
         else
-            t1_full<NF, K>(c, S1, S2, S0, zr, zi);
+            t1_full<K>(c, S1, S2, S0, zr, zi);
         t1_blocks<NF, K + 1>(c, rem, S0, S1, S2, zr, zi);
     } else {
         if constexpr (K % 3 == 0)
@@ -315,51 +324,66 @@ __device__ __forceinline__ void t1_blocks(const T1Ctx &c, int rem, double (&S0)[
     }
 }
 
-template <int NF>
-__device__ __forceinline__ void t1_rows(const Geo &g, const T1B &B, const double *Krow, const double2 *Pb, int ny,
-                                        int nz, int base, double (&zr)[T1_RB], double (&zi)[T1_RB]) {
-    const int N = g.N;
-    T1Ctx c;
-    c.A = 2 * N - 1;
-    const int wpx = B.wphi[2] - B.wplo[2] + 1;
-    const int wpy = B.wphi[1] - B.wplo[1] + 1;
-    const int nrows = wpy * (B.wphi[0] - B.wplo[0] + 1);
-    const int rem = wpx - 8 * NF;
-    auto rowptr = [&](int row) {
-        const int py = B.wplo[1] + row % wpy, pz = B.wplo[0] + row / wpy;
-        return Krow + idx_K(g, nz - pz, ny - py, 0) + (int64_t)base * c.A;
-    };
-    double xl[8], xh[8], yl[8], yh[8], sp[8];
-    {
-        const double *p0 = rowptr(0);
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            xl[s] = p0[(int64_t)(s - 8) * c.A];
-            xh[s] = p0[(int64_t)s * c.A];
-        }
+// Walks the inner rows in (pz, py) order; the window offset of a row drops
+// by one value per py step (a_y = ny - py) and by one a_z plane per pz step.
+struct T1Rows {
+    int voff, py, wpy, dz, dy;  // current offset and py index; byte steps
+    __device__ __forceinline__ int next() const { return py + 1 < wpy ? voff - dy : voff - dz + (wpy - 1) * dy; }
+    __device__ __forceinline__ void advance() {
+        voff = next();
+        py = py + 1 < wpy ? py + 1 : 0;
     }
+};
+
+template <int NF>
+__device__ __forceinline__ void t1_rows(T1Ctx &c, T1Rows rw, int nrows, int wpx, int lane,
+                                        const double2 *__restrict__ Pb, double2 (*ps)[64], double (&zr)[T1_RB],
+                                        double (&zi)[T1_RB]) {
+    const int rem = wpx - 8 * NF;
+    double xl[8], xh[8], yl[8], yh[8], sp[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        xl[s] = t1_kload(c, rw.voff - 8 * c.sA, s);
+        xh[s] = t1_kload(c, rw.voff, s);
+    }
+    if (lane < wpx) ps[0][lane] = Pb[lane];
+    __syncthreads();
     for (int row = 0; row < nrows; row += 2) {
         {
-            const double *pn = rowptr(min(row + 1, nrows - 1));
+            const bool more = row + 1 < nrows;
+            const int vn = more ? rw.next() : rw.voff;
+            double2 pn = make_double2(0.0, 0.0);
+            if (more && lane < wpx) pn = Pb[(int64_t)(row + 1) * wpx + lane];
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
-                yl[s] = pn[(int64_t)(s - 8) * c.A];
-                yh[s] = pn[(int64_t)s * c.A];
+                yl[s] = t1_kload(c, vn - 8 * c.sA, s);
+                yh[s] = t1_kload(c, vn, s);
             }
-            c.pc = rowptr(row);
-            c.Pr = Pb + (int64_t)row * wpx;
+            c.voff = rw.voff;
+            c.ps = ps[0];
             t1_blocks<NF, 0>(c, rem, xl, xh, sp, zr, zi);
+            __syncthreads();
+            if (lane < wpx) ps[1][lane] = pn;
+            __syncthreads();
+            rw.advance();
         }
         if (row + 1 < nrows) {
-            const double *pn = rowptr(min(row + 2, nrows - 1));
+            const bool more = row + 2 < nrows;
+            const int vn = more ? rw.next() : rw.voff;
+            double2 pn = make_double2(0.0, 0.0);
+            if (more && lane < wpx) pn = Pb[(int64_t)(row + 2) * wpx + lane];
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
-                xl[s] = pn[(int64_t)(s - 8) * c.A];
-                xh[s] = pn[(int64_t)s * c.A];
+                xl[s] = t1_kload(c, vn - 8 * c.sA, s);
+                xh[s] = t1_kload(c, vn, s);
             }
-            c.pc = rowptr(row + 1);
-            c.Pr = Pb + (int64_t)(row + 1) * wpx;
+            c.voff = rw.voff;
+            c.ps = ps[1];
             t1_blocks<NF, 0>(c, rem, yl, yh, sp, zr, zi);
+            __syncthreads();
+            if (lane < wpx) ps[0][lane] = pn;
+            __syncthreads();
+            rw.advance();
         }
     }
 }
@@ -368,59 +392,70 @@ __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_of
                                                        const T1B *bdesc, const double *K, const double2 *Gr,
                                                        const double2 *__restrict__ Pbuf, const Rot *rots,
                                                        double2 *part) {
+    __shared__ double2 ps[2][64];
     const int slot = blockIdx.x;
     const int lane = threadIdx.x;
     double2 *mypart = part + (int64_t)slot * g.nm;
+    const int A = 2 * g.N - 1;
     const int it_end = slot_off[slot + 1];
     for (int it = slot_off[slot]; it < it_end; ++it) {
         const T1Item item = items[it];
         const T1B B = bdesc[item.b];
-        const int t = item.t0 + lane;
+        const bool active = lane < item.nt;
+        const int t = item.t0 + (active ? lane : 0);
         const int wny = B.wnhi[1] - B.wnlo[1] + 1;
         const int ny = B.wnlo[1] + t % wny;
         const int rest = t / wny;
         const int xb = rest % B.nxb;
         const int nz = B.wnlo[0] + rest / B.nxb;
         const int x0 = B.wnlo[2] + xb * T1_RB;
-        if (lane >= item.nt) {
-            __threadfence_block();
-            continue;
-        }
-        const double *Krow = K + (int64_t)B.kc * g.nak;
-        const double2 *Pb = Pbuf + B.pofs;
         const int base = x0 - B.wplo[2];  // a_x = base + i - u
-        const int nfull = (B.wphi[2] - B.wplo[2] + 1) >> 3;
+        const int wpx = B.wphi[2] - B.wplo[2] + 1;
+        T1Ctx c;
+        c.kr = __builtin_amdgcn_make_buffer_rsrc((void *)(K + (int64_t)B.kc * g.nak), (short)0,
+                                                 (int)(g.nak * (int64_t)sizeof(double)), 0x00020000);
+        c.sA = A * (int)sizeof(double);
+        T1Rows rw;
+        rw.voff = (int)(idx_K(g, nz - B.wplo[0], ny - B.wplo[1], base) * (int64_t)sizeof(double));
+        rw.py = 0;
+        rw.wpy = B.wphi[1] - B.wplo[1] + 1;
+        rw.dy = (int)sizeof(double);
+        rw.dz = (g.d == 3 ? g.kax * A : 0) * (int)sizeof(double);
+        const int nrows = rw.wpy * (B.wphi[0] - B.wplo[0] + 1);
+        const double2 *Pb = Pbuf + B.pofs;
         double zr[T1_RB], zi[T1_RB];
 #pragma unroll
         for (int i = 0; i < T1_RB; ++i) zr[i] = zi[i] = 0.0;
-        switch (nfull) {
-            case 0: t1_rows<0>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
-            case 1: t1_rows<1>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
-            case 2: t1_rows<2>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
-            case 3: t1_rows<3>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
-            case 4: t1_rows<4>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
-            case 5: t1_rows<5>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
-            case 6: t1_rows<6>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
-            case 7: t1_rows<7>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
-            default: t1_rows<8>(g, B, Krow, Pb, ny, nz, base, zr, zi); break;
+        switch (wpx >> 3) {
+            case 0: t1_rows<0>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
+            case 1: t1_rows<1>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
+            case 2: t1_rows<2>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
+            case 3: t1_rows<3>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
+            case 4: t1_rows<4>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
+            case 5: t1_rows<5>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
+            case 6: t1_rows<6>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
+            case 7: t1_rows<7>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
+            default: t1_rows<8>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
         }
-        const Rot R = rots[B.rot];
-        const double2 *G = Gr + (int64_t)B.rot * g.next;
+        if (active) {
+            const Rot R = rots[B.rot];
+            const double2 *G = Gr + (int64_t)B.rot * g.next;
 #pragma unroll
-        for (int i = 0; i < T1_RB; ++i) {
-            const int nx = x0 + i;
-            if (nx <= B.wnhi[2]) {
-                const double2 gk = G[idx_X(g, nz - B.bc[0], ny - B.bc[1], nx - B.bc[2])];
-                const double2 cc = cmul(gk, make_double2(zr[i], zi[i]));
-                const int v[3] = {nz, ny, nx};
-                const int o0 = R.sgn[0] * v[R.perm[0]];
-                const int o1 = R.sgn[1] * v[R.perm[1]];
-                const int o2 = R.sgn[2] * v[R.perm[2]];
-                double2 *dst = mypart + idx_I(g, o0, o1, o2);
-                double2 cur = *dst;
-                cur.x += cc.x;
-                cur.y += cc.y;
-                *dst = cur;
+            for (int i = 0; i < T1_RB; ++i) {
+                const int nx = x0 + i;
+                if (nx <= B.wnhi[2]) {
+                    const double2 gk = G[idx_X(g, nz - B.bc[0], ny - B.bc[1], nx - B.bc[2])];
+                    const double2 cc = cmul(gk, make_double2(zr[i], zi[i]));
+                    const int v[3] = {nz, ny, nx};
+                    const int o0 = R.sgn[0] * v[R.perm[0]];
+                    const int o1 = R.sgn[1] * v[R.perm[1]];
+                    const int o2 = R.sgn[2] * v[R.perm[2]];
+                    double2 *dst = mypart + idx_I(g, o0, o1, o2);
+                    double2 cur = *dst;
+                    cur.x += cc.x;
+                    cur.y += cc.y;
+                    *dst = cur;
+                }
             }
         }
         // the next item may read back outputs written here by other lanes
@@ -433,6 +468,12 @@ void launch_trilinear(const Geo &g, int nslots, const int *slot_off, const T1Ite
                       hipStream_t s) {
     hipLaunchKernelGGL(trilinear_kernel, dim3(nslots), dim3(64), 0, s, g, slot_off, items, bdesc, K, Gr, Pbuf, rots,
                        part);
+}
+
+int trilinear_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trilinear_kernel, 64, 0) != hipSuccess) return 0;
+    return nb;
 }
 
 __global__ void zero_kernel(double *p, int64_t n) {
