@@ -285,19 +285,33 @@ __device__ __forceinline__ void t1_full(const T1Ctx &c, double (&lo)[8], double 
     }
 }
 
+template <int R>
+__device__ __forceinline__ void t1_tail_n(const T1Ctx &c, int u0, const double (&lo)[8], const double (&hi)[8],
+                                          double (&zr)[T1_RB], double (&zi)[T1_RB]) {
+#pragma unroll
+    for (int jj = 0; jj < R; ++jj) {
+        const double2 p = c.ps[u0 + jj];
+#pragma unroll
+        for (int i = 0; i < T1_RB; ++i) {
+            const double k = (i - jj < 0) ? lo[i - jj + 8] : hi[i - jj];
+            zr[i] = fma(k, p.x, zr[i]);
+            zi[i] = fma(k, p.y, zi[i]);
+        }
+    }
+}
+
+// The last rem (< 8) inner values of a row, straight-line code per rem.
 __device__ __forceinline__ void t1_tail(const T1Ctx &c, int u0, int rem, const double (&lo)[8],
                                         const double (&hi)[8], double (&zr)[T1_RB], double (&zi)[T1_RB]) {
-#pragma unroll
-    for (int jj = 0; jj < 7; ++jj) {
-        if (jj < rem) {
-            const double2 p = c.ps[u0 + jj];
-#pragma unroll
-            for (int i = 0; i < T1_RB; ++i) {
-                const double k = (i - jj < 0) ? lo[i - jj + 8] : hi[i - jj];
-                zr[i] = fma(k, p.x, zr[i]);
-                zi[i] = fma(k, p.y, zi[i]);
-            }
-        }
+    switch (rem) {
+        case 1: t1_tail_n<1>(c, u0, lo, hi, zr, zi); break;
+        case 2: t1_tail_n<2>(c, u0, lo, hi, zr, zi); break;
+        case 3: t1_tail_n<3>(c, u0, lo, hi, zr, zi); break;
+        case 4: t1_tail_n<4>(c, u0, lo, hi, zr, zi); break;
+        case 5: t1_tail_n<5>(c, u0, lo, hi, zr, zi); break;
+        case 6: t1_tail_n<6>(c, u0, lo, hi, zr, zi); break;
+        case 7: t1_tail_n<7>(c, u0, lo, hi, zr, zi); break;
+        default: break;
     }
 }
 
@@ -329,62 +343,62 @@ __device__ __forceinline__ void t1_blocks(const T1Ctx &c, int rem, double (&S0)[
 struct T1Rows {
     int voff, py, wpy, dz, dy;  // current offset and py index; byte steps
     __device__ __forceinline__ int next() const { return py + 1 < wpy ? voff - dy : voff - dz + (wpy - 1) * dy; }
-    __device__ __forceinline__ void advance() {
-        voff = next();
-        py = py + 1 < wpy ? py + 1 : 0;
+    __device__ __forceinline__ void advance(bool more) {
+        const int vn = next();
+        const int pn = py + 1 < wpy ? py + 1 : 0;
+        voff = more ? vn : voff;
+        py = more ? pn : py;
     }
 };
+
+// One inner row: compute it from (lo0, hi0) and the staged pair products
+// ps[cur], while the next row's window (into nl, nh) and pair products are
+// fetched.  Past the last row the fetches repeat the last row's addresses and
+// the staged pair products are zero, so that rows can run in pairs without
+// branches (an odd row count ends with one row that adds nothing).
+template <int NF>
+__device__ __forceinline__ void t1_row(T1Ctx &c, T1Rows &rw, int row, int nrows, int wpx, int lane,
+                                       const double2 *__restrict__ Pb, double2 (*ps)[64], int cur,
+                                       double (&lo0)[8], double (&hi0)[8], double (&nl)[8], double (&nh)[8],
+                                       double (&sp)[8], double (&zr)[T1_RB], double (&zi)[T1_RB]) {
+    const bool more = row + 1 < nrows;
+    const int vn = more ? rw.next() : rw.voff;
+    const int prow = more ? row + 1 : nrows - 1;
+    const double2 pn = Pb[(int64_t)prow * wpx + min(lane, wpx - 1)];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        nl[s] = t1_kload(c, vn - 8 * c.sA, s);
+        nh[s] = t1_kload(c, vn, s);
+    }
+    c.voff = rw.voff;
+    c.ps = ps[cur];
+    t1_blocks<NF, 0>(c, wpx - 8 * NF, lo0, hi0, sp, zr, zi);
+    __syncthreads();
+    const bool keep = more && lane < wpx;
+    ps[cur ^ 1][lane] = make_double2(keep ? pn.x : 0.0, keep ? pn.y : 0.0);
+    __syncthreads();
+    rw.advance(more);
+}
 
 template <int NF>
 __device__ __forceinline__ void t1_rows(T1Ctx &c, T1Rows rw, int nrows, int wpx, int lane,
                                         const double2 *__restrict__ Pb, double2 (*ps)[64], double (&zr)[T1_RB],
                                         double (&zi)[T1_RB]) {
-    const int rem = wpx - 8 * NF;
     double xl[8], xh[8], yl[8], yh[8], sp[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         xl[s] = t1_kload(c, rw.voff - 8 * c.sA, s);
         xh[s] = t1_kload(c, rw.voff, s);
     }
-    if (lane < wpx) ps[0][lane] = Pb[lane];
+    {
+        const double2 p0 = Pb[min(lane, wpx - 1)];
+        const bool keep = lane < wpx;
+        ps[0][lane] = make_double2(keep ? p0.x : 0.0, keep ? p0.y : 0.0);
+    }
     __syncthreads();
     for (int row = 0; row < nrows; row += 2) {
-        {
-            const bool more = row + 1 < nrows;
-            const int vn = more ? rw.next() : rw.voff;
-            double2 pn = make_double2(0.0, 0.0);
-            if (more && lane < wpx) pn = Pb[(int64_t)(row + 1) * wpx + lane];
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                yl[s] = t1_kload(c, vn - 8 * c.sA, s);
-                yh[s] = t1_kload(c, vn, s);
-            }
-            c.voff = rw.voff;
-            c.ps = ps[0];
-            t1_blocks<NF, 0>(c, rem, xl, xh, sp, zr, zi);
-            __syncthreads();
-            if (lane < wpx) ps[1][lane] = pn;
-            __syncthreads();
-            rw.advance();
-        }
-        if (row + 1 < nrows) {
-            const bool more = row + 2 < nrows;
-            const int vn = more ? rw.next() : rw.voff;
-            double2 pn = make_double2(0.0, 0.0);
-            if (more && lane < wpx) pn = Pb[(int64_t)(row + 2) * wpx + lane];
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                xl[s] = t1_kload(c, vn - 8 * c.sA, s);
-                xh[s] = t1_kload(c, vn, s);
-            }
-            c.voff = rw.voff;
-            c.ps = ps[1];
-            t1_blocks<NF, 0>(c, rem, yl, yh, sp, zr, zi);
-            __syncthreads();
-            if (lane < wpx) ps[0][lane] = pn;
-            __syncthreads();
-            rw.advance();
-        }
+        t1_row<NF>(c, rw, row, nrows, wpx, lane, Pb, ps, 0, xl, xh, yl, yh, sp, zr, zi);
+        t1_row<NF>(c, rw, row + 1, nrows, wpx, lane, Pb, ps, 1, yl, yh, xl, xh, sp, zr, zi);
     }
 }
 
