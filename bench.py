@@ -30,6 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "collision pair-terms/s at N=32^3 (FP32c vs FP64); p50/p99 solve latency"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trilinear_3d32_fp64_hbm_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_13735_amd", "csrc", "collide.hip")
 PEAK_FP64_VALU = 78.6e12  # MI355X dense FP64 vector, FLOP/s
 FLOPS_PER_T1_TERM = 4.0   # one real x complex multiply-add (two FMAs)
 
@@ -61,6 +63,32 @@ def cpu_baseline(sample_N: int = 10, nthreads=None):
                       f"at 3-D N={sample_N}: {terms:.3e} terms in {dt:.2f} s"}
 
 
+def code_hash(path):
+    """SHA-256 of a C/HIP source with comments and blank space removed, so that
+    only a change of the code itself counts."""
+    import hashlib
+    import re
+    with open(path) as fh:
+        src = fh.read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = " ".join(src.split())
+    return hashlib.sha256(src.encode()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per trilinear launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE counters, or None when the kernel code has changed since the
+    counters were taken (the file records the code hash at measurement time)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_code_sha256") != code_hash(KERNEL_SOURCE):
+        return None
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +98,9 @@ def main():
     ap.add_argument("--dt", type=float, default=0.01)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-N", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run one 1 GiB device copy (read 1 GiB, write 1 GiB) so that a "
+                         "counter run can calibrate FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU only; multi-GPU runs are not supported", file=sys.stderr)
@@ -123,10 +154,20 @@ def main():
     t1_avg_s = (t1_ms / t1_n) * 1e-3 if t1_n else float("nan")
     flops_launch = counts["trilinear"] * FLOPS_PER_T1_TERM
     achieved = flops_launch / t1_avg_s / 1e12
+    tr = measured_traffic()
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU / 1e12,
-                "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP64_VALU, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP64_VALU, 4),
+                "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None,
                 "kernel": "trilinear_kernel", "avg_ms": round(t1_avg_s * 1e3, 3), "launches": t1_n,
                 "flops_per_launch": flops_launch}
+    if tr:
+        roofline["traffic_detail"] = {k: tr[k] for k in ("fetch_bytes", "write_bytes", "fetch_scale", "write_scale")}
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
 
     out = {
         "metric": METRIC,

@@ -4,15 +4,15 @@ This module is shared by the CPU oracle and the GPU path.  It only builds
 initial data on the velocity grid; it holds none of the collision operator's
 arithmetic (no Fourier transforms, no kernel modes, no sums).
 
-Velocity grid (Section 4.3, classical method with omega = 1):
+Velocity grid (section 'Numerical scheme for the velocity rescaled BNE', classical method with omega = 1):
     v_j = 2 L j / N,   j in I_N = {-N/2, ..., N/2 - 1}^d,   Delta v = (2L/N)^d.
 Arrays are numpy float64 of shape (N,)*d in C order; storage index = j + N/2.
 
 Initial data are sampled on the whole box [-L, L)^d, as the spectral-accuracy
-tests of Section 5.1 require (their residuals decay to 1e-8 at 64^2, which a
+tests of section 'Validation of spectral accuracy' require (their residuals decay to 1e-8 at 64^2, which a
 cut inside the box would prevent).  Where a recipe asks for a compact support,
 the datum is cut at |v| <= R_v = 2 L / (3 + sqrt 2), the velocity image of the
-radius S fixed by R = S, pi = (3 + sqrt 2) S / 2 (Section 5.1).
+radius S fixed by R = S, pi = (3 + sqrt 2) S / 2 (section 'Validation of spectral accuracy').
 
 Every generator takes an explicit seed and draws from numpy's PCG64.
 """
@@ -189,7 +189,7 @@ def bkw_2d(N: int, L: float, t: float, lam: float, truncate: bool = False):
 
 def quantum_maxwellian(d: int, N: int, L: float, z: float, T: float, alpha: float,
                        u=None, truncate: bool = False):
-    """Quantum Maxwellian of Section 2.2:
+    """Quantum Maxwellian of section 'Convergence towards a steady state':
         M_q(v) = (1/|alpha|) / ( z^{-1} exp(|v-u|^2 / (2T)) + sgn(alpha) ),
     alpha = +hbar^d (Fermi–Dirac) or -hbar^d (Bose–Einstein, needs 0 < z < 1).
     Returned on the grid (optionally cut at R_v)."""

@@ -4,14 +4,14 @@
  * equation (Mouton & Rey, "On deterministic numerical methods for the quantum
  * Boltzmann–Nordheim equation I", arXiv 2110.13735).
  *
- * Problem (Section 2.2, homogeneous equation; Section 4.2, classical method
+ * Problem (section 'Convergence towards a steady state', homogeneous equation; section 'Application to the space homogeneous BNE', classical method
  * lambda = 0, omega = 1, mu = (L/pi)^d):
  *     d f_j / dt = c (L/pi)^(d+gamma) Q_j,     j in I_N = {-N/2 .. N/2-1}^d,
  * on the velocity grid v_j = 2 L j / N of [-L, L)^d, where Q_j is the grid
- * value of the truncated, periodised operator Q^R_alpha(G) (Section 3.2,
- * indicator of Filbet–Hu–Jin, R = S = 2 pi / (3 + sqrt 2) as in Section 5.1)
+ * value of the truncated, periodised operator Q^R_alpha(G) (section 'Truncation and periodization of the BNE operator',
+ * indicator of Filbet–Hu–Jin, R = S = 2 pi / (3 + sqrt 2) as in section 'Validation of spectral accuracy')
  * evaluated through the Fourier–Galerkin sums of the kernel-mode Lemma
- * (Section 3.3):
+ * (section 'Fast spectral approximation of the BNE operator'):
  *     Qhat_n = sum_{l+m=n} [beta(l,m) - beta(m,m)] G_l G_m
  *            - alpha sum_{k+l+m=n} [beta(k+m,l+m) + beta(l,m) - beta(l+m,l)
  *                                   - beta(l,l+m)] G_k G_l G_m,
@@ -20,7 +20,7 @@
  * with every index in I_N (linear, non-wrapping sums) and
  *     alpha = -eps hbar^d   (eps = +1 bosons, -1 fermions, 0 classical).
  * Kernels: d = 2 Maxwell molecules (gamma = 0, Btilde = 2 C_phi) and d = 3
- * hard spheres (gamma = 1, Btilde = 4 C_phi), b = 1 (Section 3.5).
+ * hard spheres (gamma = 1, Btilde = 4 C_phi), b = 1 (section 'Fast computation of the collision modes').
  *
  * Memory: every pointer named f, Q, Qhat is a DEVICE pointer owned by the
  * caller (e.g. a torch tensor's data_ptr()).  f and Q are FP64 arrays of N^d
@@ -117,7 +117,7 @@ bnq_status bnq_collide(bnq_plan_t plan, const double *f, double *Q, void *Qhat, 
  * EHIP. */
 bnq_status bnq_step(bnq_plan_t plan, double *f, double dt, int32_t scheme, bnq_stream_t stream);
 
-/* Discrete moments (Section 5 diagnostics, classical method), written to the
+/* Discrete moments (section 'Numerical results' diagnostics, classical method), written to the
  * host array out_host[BNQ_MOMENTS_LEN] in this order:
  *   rho, u[0], u[1], u[2] (u[2] = 0 when d = 2), E_c, e, H, fmax, fmin,
  *   n_excluded

@@ -6,22 +6,22 @@ Python binding never import, link or call it, and the two share no code.
 
 What it computes (Mouton & Rey, arXiv 2110.13735), plainly and in FP64:
 
-* Fourier modes of the grid data (Section 4.3, step 2(a), with the d-dimensional
+* Fourier modes of the grid data (section 'Numerical scheme for the velocity rescaled BNE', step 2(a), with the d-dimensional
   normalisation N^-d):   G_k = N^-d sum_{j in I_N} f_j e^{-2 pi i k.j/N}.
-* Kernel modes beta(k,l) by quadrature of their definition (Lemma of Section
-  3.3, polar forms of Section 3.4); see bnq_oracle.c.
+* Kernel modes beta(k,l) by quadrature of their definition (Lemma of section
+  'Fast spectral approximation of the BNE operator', polar forms of section 'Expansion of the kernel modes'); see bnq_oracle.c.
 * The Galerkin sums of that Lemma for F = G = H, assembled as in the
-  decomposition of Section 3.1:
+  decomposition of section 'The Carleman representation':
       Qhat_n = Qc_n - alpha Qq_n,  alpha = -eps hbar^d  (eps = +1 boson,
       -1 fermion, 0 classical; the paper's alpha is +hbar^d for Fermi–Dirac).
-* The classical method of Section 4.2 (lambda = 0, omega = 1, mu = (L/pi)^d):
+* The classical method of section 'Application to the space homogeneous BNE' (lambda = 0, omega = 1, mu = (L/pi)^d):
       d f_j/dt = c (L/pi)^(d+gamma) Q_j,
       Q_j = Re sum_{n in I_N} Qhat_n e^{2 pi i n.j/N},
   with gamma = 0 (2-D Maxwell molecules) or 1 (3-D hard spheres), advanced by
   the classical fourth-order Runge–Kutta scheme.
-* Discrete moments and entropy of Section 5 (diagnostics list).
+* Discrete moments and entropy of section 'Numerical results' (diagnostics list).
 
-R = S = 2 pi/(3 + sqrt 2) (Section 5.1).  Functions with no independent pin
+R = S = 2 pi/(3 + sqrt 2) (section 'Validation of spectral accuracy').  Functions with no independent pin
 are marked "parity unpinned" in their docstrings.
 """
 from __future__ import annotations
@@ -87,7 +87,7 @@ def gamma_of(d: int) -> int:
 
 
 def prefactor(d: int, L: float, c: float = 1.0) -> float:
-    """c (L/pi)^(d+gamma): classical method of Section 4.2."""
+    """c (L/pi)^(d+gamma): classical method of section 'Application to the space homogeneous BNE'."""
     return c * (L / math.pi) ** (d + gamma_of(d))
 
 
@@ -318,7 +318,7 @@ def sparse_dense(d: int, N: int, table: dict) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
-# moments and entropy (Section 5, diagnostics), classical method
+# moments and entropy (section 'Numerical results', diagnostics), classical method
 def moments(f: np.ndarray, L: float, eps: int, hbar: float = 1.0) -> dict:
     """rho, u, E_c, e, entropy and extrema.  The entropy is
     Delta v sum [f ln f + (1 - alpha f)/alpha ln(1 - alpha f)] (alpha != 0) or

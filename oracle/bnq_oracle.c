@@ -10,9 +10,9 @@
  * Everything is plain FP64 with no blocking or fusion beyond the definitions:
  *
  *  (1) Kernel modes (Lemma on the Fourier modes of the truncated terms,
- *      Section 3.3):
+ *      section 'Fast spectral approximation of the BNE operator'):
  *        beta(k,l) = \int_{B(0,R)^2} Btilde(z,y) delta(z.y) e^{i(z.k+y.l)} dz dy
- *      evaluated by quadrature of its polar form (Section 3.4):
+ *      evaluated by quadrature of its polar form (section 'Expansion of the kernel modes'):
  *        2-D Maxwell molecules, Btilde = 2 C_phi:
  *          beta(k,l) = 2 C_phi \int_0^pi phi(k.e_t) phi(l.e_{t+pi/2}) dt,
  *          phi(s) = \int_{-R}^{R} e^{i r s} dr = 2R sinc(Rs),

@@ -1,4 +1,4 @@
-// Kernel-mode tables (Lemma of Section 3.3, polar forms of Section 3.4).
+// Kernel-mode tables (Lemma of section 'Fast spectral approximation of the BNE operator', polar forms of section 'Expansion of the kernel modes').
 //
 // beta(k,l) = int_{B(0,R)^2} Btilde(z,y) delta(z.y) e^{i(z.k + y.l)} dz dy is
 // evaluated through the expansion of both plane waves in angular harmonics

@@ -1,13 +1,13 @@
-// Evaluation of the Galerkin modes Qhat_n (Lemma of Section 3.3) and of the
+// Evaluation of the Galerkin modes Qhat_n (Lemma of section 'Fast spectral approximation of the BNE operator') and of the
 // grid values Q_j on gfx950, FP64.
 //
-//   forward DFT      G_k = N^-d sum_j f_j e^{-2 pi i k.j/N}        (Section 4.3, step 2a)
+//   forward DFT      G_k = N^-d sum_j f_j e^{-2 pi i k.j/N}        (section 'Numerical scheme for the velocity rescaled BNE', step 2a)
 //   pair sums        Qc_s = sum_{l+m=s} wc(l,m) G_l G_m   (s in I_N)
 //                    W_s  = sum_{l+m=s} wq(l,m) G_l G_m   (s in Eg)
 //   outer sum        X_n  = sum_k G_k W_{n-k}
 //   trilinear sum    T1_n = sum_{k+l+m=n} beta(k+m,l+m) G_k G_l G_m
 //                         = sum_b G_{n-b} sum_p beta(n-p, b) G_p G_{b-p}
-//   combination      Qhat = Qc - alpha (T1 + X)           (Section 3.1 decomposition)
+//   combination      Qhat = Qc - alpha (T1 + X)           (section 'The Carleman representation' decomposition)
 //   inverse DFT      Q_j = c (L/pi)^(d+gamma) Re sum_n Qhat_n e^{2 pi i n.j/N}
 //
 // The pair sums stream the two pair-weight tables once per evaluation

@@ -1,8 +1,8 @@
 // Time stepping and moments on the velocity grid, FP64.
 //
-// Classical method of Section 4.2: d f/dt = c (L/pi)^(d+gamma) Q(f); the RK
+// Classical method of section 'Application to the space homogeneous BNE': d f/dt = c (L/pi)^(d+gamma) Q(f); the RK
 // stage combinations are plain FP64 vector updates.  Moments and entropy
-// follow the diagnostics list of Section 5 (classical method, omega = 1):
+// follow the diagnostics list of section 'Numerical results' (classical method, omega = 1):
 //   rho = dv sum f, u = dv sum v f / rho, E_c = dv sum |v|^2 f,
 //   e = (E_c - rho |u|^2) / (2 rho),
 //   H = dv sum [f ln f + (1 - alpha f)/alpha ln(1 - alpha f)]   (alpha != 0)

@@ -5,7 +5,7 @@ trigonometric interpolant G_N(xi) = sum_{k in I_N} G_k e^{i k.xi},
 
     Q^R(G)(xi) = int_{B(0,R)^2} Btilde(x,y) delta(x.y) [ ... ] dx dy
 
-(the truncated operator of Section 3.2 with the Filbet–Hu–Jin indicator) by
+(the truncated operator of section 'Truncation and periodization of the BNE operator' with the Filbet–Hu–Jin indicator) by
 plain quadrature over x, y, on an oversampled xi grid, then takes the Fourier
 modes n in I_N of the result.  Q^R(G_N) is a trigonometric polynomial with
 frequencies in {-3N/2, ..., 3N/2 - 3}^d, so a grid of 3N points per axis

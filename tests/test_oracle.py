@@ -245,7 +245,7 @@ def test_bkw_profile_after_rk4():
 
 
 def test_quantum_maxwellian_residual_decays():
-    # Section 5.1 protocol: f0 = M_q sampled on the box is an equilibrium; the
+    # section 'Validation of spectral accuracy' protocol: f0 = M_q sampled on the box is an equilibrium; the
     # discrete residual decays spectrally with N (2-D Fermi–Dirac, hbar = 3,
     # rho = 1, sigma = T = 0.5, L = 4, u0 = 0, as in Table 1).  The same datum
     # is far from stationary with the opposite sign of alpha, which pins
