@@ -377,7 +377,7 @@ struct bnq_plan_s {
     Rot *rots_d = nullptr;
     double2 *tw = nullptr;
     double2 *Ghat = nullptr, *tmp = nullptr, *tmp2 = nullptr, *Gr = nullptr, *W = nullptr, *Qc = nullptr,
-            *T1 = nullptr, *X = nullptr, *Qh = nullptr, *part = nullptr, *Pbuf = nullptr;
+            *T1 = nullptr, *X = nullptr, *Qh = nullptr, *part = nullptr;
     int nbdesc = 0;
     double *kbuf[4] = {nullptr, nullptr, nullptr, nullptr}, *ybuf = nullptr;
     double *mom_part = nullptr, *mom_out = nullptr;
@@ -452,7 +452,7 @@ size_t plan_workspace_bytes(const bnq_params *p, int nslots_est) {
     Geo g = make_geo(p->d, p->N);
     const size_t c = sizeof(double2), r = sizeof(double);
     const size_t nrot = p->d == 3 ? 48 : 8;
-    return c * (6 * (size_t)g.nm + g.neg + nrot * g.next + (size_t)nslots_est * g.nm + (size_t)g.nm * g.nm) +
+    return c * (6 * (size_t)g.nm + g.neg + nrot * g.next + (size_t)nslots_est * g.nm) +
            r * 5 * (size_t)g.nm;
 }
 
@@ -466,7 +466,6 @@ bnq_status build_t1_work(bnq_plan_s *P) {
         double cost;
     };
     std::vector<It> items;
-    long long pofs = 0;
     const int b0lo = d == 3 ? -N + 1 : 0, b0hi = d == 3 ? N - 2 : 0;
     for (int b0 = b0lo; b0 <= b0hi; ++b0)
         for (int b1 = -N + 1; b1 <= N - 2; ++b1)
@@ -499,9 +498,6 @@ bnq_status build_t1_work(bnq_plan_s *P) {
                 const int wnx = B.wnhi[2] - B.wnlo[2] + 1;
                 B.nxb = (wnx + T1_RB - 1) / T1_RB;
                 B.pad = 0;
-                B.pofs = pofs;
-                pofs += (long long)(B.wphi[0] - B.wplo[0] + 1) * (B.wphi[1] - B.wplo[1] + 1) *
-                        (B.wphi[2] - B.wplo[2] + 1);
                 const int ntasks = B.nxb * (B.wnhi[1] - B.wnlo[1] + 1) * (B.wnhi[0] - B.wnlo[0] + 1);
                 const int wpx = B.wphi[2] - B.wplo[2] + 1;
                 const double rows = (double)(B.wphi[1] - B.wplo[1] + 1) * (B.wphi[0] - B.wplo[0] + 1);
@@ -577,7 +573,6 @@ bnq_status build_t1_work(bnq_plan_s *P) {
     if ((st = upload(&P->bdesc, bd, "trilinear b descriptors")) || (st = upload(&P->items, flat, "trilinear items")) ||
         (st = upload(&P->slot_off, off, "trilinear slot offsets")))
         return st;
-    if ((st = dalloc(&P->Pbuf, (size_t)std::max<long long>(pofs, 1), "trilinear pair products"))) return st;
     return dalloc(&P->part, (size_t)ns * g.nm, "trilinear partial sums");
 }
 
@@ -595,7 +590,6 @@ void destroy_plan(bnq_plan_s *P) {
     hipFree(P->X);
     hipFree(P->Qh);
     hipFree(P->part);
-    hipFree(P->Pbuf);
     for (double *k : P->kbuf) hipFree(k);
     hipFree(P->ybuf);
     hipFree(P->mom_part);
@@ -637,15 +631,12 @@ bnq_status collide_impl(bnq_plan_s *P, const double *f, double *Q, double2 *Qhat
             Span sp(P, 4, s);
             launch_rotate(g, P->Ghat, P->rots_d, (int)P->grp.size(), P->Gr, s);
             LAUNCHCHK();
-            launch_pairprod(g, P->nbdesc, P->bdesc, P->Gr, P->Pbuf, s);
-            LAUNCHCHK();
             launch_zero(P->part, (int64_t)P->nslots * g.nm * (int64_t)sizeof(double2), s);
             LAUNCHCHK();
         }
         {
             Span sp(P, 3, s);
-            launch_trilinear(g, P->nslots, P->slot_off, P->items, P->bdesc, t->K, P->Gr, P->Pbuf, P->rots_d,
-                             P->part, s);
+            launch_trilinear(g, P->nslots, P->slot_off, P->items, P->bdesc, t->K, P->Gr, P->rots_d, P->part, s);
             LAUNCHCHK();
         }
         {

@@ -73,7 +73,6 @@ struct T1B {
     int wplo[3], wphi[3];  // inner window in the rotated frame
     int nxb;         // x-blocks of the output window
     int pad;
-    long long pofs;  // offset of this b's pair products in the pair-product buffer
 };
 
 struct T1Item {
@@ -110,10 +109,9 @@ void launch_rotate(const Geo &g, const double2 *G, const Rot *rots, int nrot, do
 void launch_pairs(const Geo &g, const double2 *G, const double *wc, const double *wq, double2 *Qc,
                   double2 *W, int want_c, int want_w, hipStream_t s);
 void launch_outer(const Geo &g, const double2 *G, const double2 *W, double2 *X, hipStream_t s);
-void launch_pairprod(const Geo &g, int nb, const T1B *bdesc, const double2 *Gr, double2 *Pbuf, hipStream_t s);
 void launch_trilinear(const Geo &g, int nslots, const int *slot_off, const T1Item *items,
-                      const T1B *bdesc, const double *K, const double2 *Gr, const double2 *Pbuf,
-                      const Rot *rots, double2 *part, hipStream_t s);
+                      const T1B *bdesc, const double *K, const double2 *Gr, const Rot *rots, double2 *part,
+                      hipStream_t s);
 int trilinear_blocks_per_cu();  // resident 64-lane trilinear workgroups per CU (0 on error)
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_reduce_partials(const Geo &g, int nslots, const double2 *part, double2 *T1, hipStream_t s);

@@ -215,28 +215,6 @@ void launch_outer(const Geo &g, const double2 *G, const double2 *W, double2 *X, 
 }
 
 // ---------------------------------------------------------------------------
-// Pair products for the trilinear sum: for every b (in its rotated frame) and
-// every p in its inner window, P(b, p) = G_R(p) G_R(b_c - p), stored
-// contiguously per b in (pz, py, px) order.
-__global__ __launch_bounds__(256) void pairprod_kernel(Geo g, const T1B *bdesc, const double2 *Gr, double2 *Pbuf) {
-    const T1B B = bdesc[blockIdx.x];
-    const double2 *G = Gr + (int64_t)B.rot * g.next;
-    const int wpx = B.wphi[2] - B.wplo[2] + 1, wpy = B.wphi[1] - B.wplo[1] + 1;
-    const int n = wpx * wpy * (B.wphi[0] - B.wplo[0] + 1);
-    double2 *out = Pbuf + B.pofs;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int px = B.wplo[2] + e % wpx;
-        const int py = B.wplo[1] + (e / wpx) % wpy;
-        const int pz = B.wplo[0] + e / (wpx * wpy);
-        out[e] = cmul(G[idx_X(g, pz, py, px)], G[idx_X(g, B.bc[0] - pz, B.bc[1] - py, B.bc[2] - px)]);
-    }
-}
-
-void launch_pairprod(const Geo &g, int nb, const T1B *bdesc, const double2 *Gr, double2 *Pbuf, hipStream_t s) {
-    hipLaunchKernelGGL(pairprod_kernel, dim3(nb), dim3(256), 0, s, g, bdesc, Gr, Pbuf);
-}
-
-// ---------------------------------------------------------------------------
 // Trilinear sum.  One 64-lane workgroup per slot; each slot walks its static
 // list of items (b, range of <= 64 tasks) and accumulates into its own
 // partial array (no atomics; the slots are summed in a fixed order later).
@@ -254,8 +232,9 @@ void launch_pairprod(const Geo &g, int nb, const T1B *bdesc, const double2 *Gr, 
 // Kernel-mode values come through a buffer resource over the canonical row:
 // one 32-bit lane offset per window, the 8 values of a window at scalar
 // offsets s * 8A.  The pair products of a row are uniform across the wave:
-// the next row's are fetched into a register (one per lane) while the current
-// row computes, then written to a two-row LDS ring and read as broadcasts.
+// the next row's are formed (one p_x per lane, from the rotated spectrum)
+// while the current row computes, then written to a two-row LDS ring and read
+// as broadcasts.
 struct T1Ctx {
     __amdgpu_buffer_rsrc_t kr;  // canonical kernel-mode row
     int voff;                   // byte offset of K(a_x = base) at this row's (a_z, a_y)
@@ -341,13 +320,30 @@ __device__ __forceinline__ void t1_blocks(const T1Ctx &c, int rem, double (&S0)[
 // Walks the inner rows in (pz, py) order; the window offset of a row drops
 // by one value per py step (a_y = ny - py) and by one a_z plane per pz step.
 struct T1Rows {
-    int voff, py, wpy, dz, dy;  // current offset and py index; byte steps
+    int voff, py, pz, wpy, dz, dy;  // current offset, (py, pz) indices in the window; byte steps
     __device__ __forceinline__ int next() const { return py + 1 < wpy ? voff - dy : voff - dz + (wpy - 1) * dy; }
     __device__ __forceinline__ void advance(bool more) {
         const int vn = next();
-        const int pn = py + 1 < wpy ? py + 1 : 0;
+        const bool wrap = py + 1 >= wpy;
         voff = more ? vn : voff;
-        py = more ? pn : py;
+        pz = more && wrap ? pz + 1 : pz;
+        py = more ? (wrap ? 0 : py + 1) : py;
+    }
+};
+
+// Pair products P_b(p) = G_R(p) G_R(b_c - p) of the inner window, formed on
+// the fly from the rotated spectrum (one lane per p_x of a row).
+struct T1Pairs {
+    const double2 *G;  // rotated spectrum G_R on {-N/2 .. N/2}^d
+    int X, h, d3;      // N + 1, N / 2, d == 3
+    int px, qx;        // storage x-indices of p_x and b_c,x - p_x for this lane
+    int bz, by;        // b_c,z and b_c,y
+    int pzlo, pylo;    // inner window start
+    __device__ __forceinline__ double2 at(int pzi, int pyi) const {
+        const int pz = pzlo + pzi, py = pylo + pyi;
+        const int64_t ip = ((int64_t)(d3 ? pz + h : 0) * X + (py + h)) * X + px;
+        const int64_t iq = ((int64_t)(d3 ? bz - pz + h : 0) * X + (by - py + h)) * X + qx;
+        return cmul(G[ip], G[iq]);
     }
 };
 
@@ -358,13 +354,15 @@ struct T1Rows {
 // branches (an odd row count ends with one row that adds nothing).
 template <int NF>
 __device__ __forceinline__ void t1_row(T1Ctx &c, T1Rows &rw, int row, int nrows, int wpx, int lane,
-                                       const double2 *__restrict__ Pb, double2 (*ps)[64], int cur,
+                                       const T1Pairs &pr, double2 (*ps)[64], int cur,
                                        double (&lo0)[8], double (&hi0)[8], double (&nl)[8], double (&nh)[8],
                                        double (&sp)[8], double (&zr)[T1_RB], double (&zi)[T1_RB]) {
     const bool more = row + 1 < nrows;
     const int vn = more ? rw.next() : rw.voff;
-    const int prow = more ? row + 1 : nrows - 1;
-    const double2 pn = Pb[(int64_t)prow * wpx + min(lane, wpx - 1)];
+    const bool wrap = rw.py + 1 >= rw.wpy;
+    const int npy = more ? (wrap ? 0 : rw.py + 1) : rw.py;
+    const int npz = more && wrap ? rw.pz + 1 : rw.pz;
+    const double2 pn = pr.at(npz, npy);
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         nl[s] = t1_kload(c, vn - 8 * c.sA, s);
@@ -381,9 +379,8 @@ __device__ __forceinline__ void t1_row(T1Ctx &c, T1Rows &rw, int row, int nrows,
 }
 
 template <int NF>
-__device__ __forceinline__ void t1_rows(T1Ctx &c, T1Rows rw, int nrows, int wpx, int lane,
-                                        const double2 *__restrict__ Pb, double2 (*ps)[64], double (&zr)[T1_RB],
-                                        double (&zi)[T1_RB]) {
+__device__ __forceinline__ void t1_rows(T1Ctx &c, T1Rows rw, int nrows, int wpx, int lane, const T1Pairs &pr,
+                                        double2 (*ps)[64], double (&zr)[T1_RB], double (&zi)[T1_RB]) {
     double xl[8], xh[8], yl[8], yh[8], sp[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
@@ -391,21 +388,20 @@ __device__ __forceinline__ void t1_rows(T1Ctx &c, T1Rows rw, int nrows, int wpx,
         xh[s] = t1_kload(c, rw.voff, s);
     }
     {
-        const double2 p0 = Pb[min(lane, wpx - 1)];
+        const double2 p0 = pr.at(0, 0);
         const bool keep = lane < wpx;
         ps[0][lane] = make_double2(keep ? p0.x : 0.0, keep ? p0.y : 0.0);
     }
     __syncthreads();
     for (int row = 0; row < nrows; row += 2) {
-        t1_row<NF>(c, rw, row, nrows, wpx, lane, Pb, ps, 0, xl, xh, yl, yh, sp, zr, zi);
-        t1_row<NF>(c, rw, row + 1, nrows, wpx, lane, Pb, ps, 1, yl, yh, xl, xh, sp, zr, zi);
+        t1_row<NF>(c, rw, row, nrows, wpx, lane, pr, ps, 0, xl, xh, yl, yh, sp, zr, zi);
+        t1_row<NF>(c, rw, row + 1, nrows, wpx, lane, pr, ps, 1, yl, yh, xl, xh, sp, zr, zi);
     }
 }
 
 __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_off, const T1Item *items,
                                                        const T1B *bdesc, const double *K, const double2 *Gr,
-                                                       const double2 *__restrict__ Pbuf, const Rot *rots,
-                                                       double2 *part) {
+                                                       const Rot *rots, double2 *part) {
     __shared__ double2 ps[2][64];
     const int slot = blockIdx.x;
     const int lane = threadIdx.x;
@@ -432,28 +428,39 @@ __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_of
         T1Rows rw;
         rw.voff = (int)(idx_K(g, nz - B.wplo[0], ny - B.wplo[1], base) * (int64_t)sizeof(double));
         rw.py = 0;
+        rw.pz = 0;
         rw.wpy = B.wphi[1] - B.wplo[1] + 1;
         rw.dy = (int)sizeof(double);
         rw.dz = (g.d == 3 ? g.kax * A : 0) * (int)sizeof(double);
         const int nrows = rw.wpy * (B.wphi[0] - B.wplo[0] + 1);
-        const double2 *Pb = Pbuf + B.pofs;
+        const double2 *G = Gr + (int64_t)B.rot * g.next;
+        T1Pairs pr;
+        pr.G = G;
+        pr.X = g.N + 1;
+        pr.h = g.h;
+        pr.d3 = g.d == 3;
+        pr.px = B.wplo[2] + min(lane, wpx - 1) + g.h;
+        pr.qx = B.bc[2] - (B.wplo[2] + min(lane, wpx - 1)) + g.h;
+        pr.bz = B.bc[0];
+        pr.by = B.bc[1];
+        pr.pzlo = B.wplo[0];
+        pr.pylo = B.wplo[1];
         double zr[T1_RB], zi[T1_RB];
 #pragma unroll
         for (int i = 0; i < T1_RB; ++i) zr[i] = zi[i] = 0.0;
         switch (wpx >> 3) {
-            case 0: t1_rows<0>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
-            case 1: t1_rows<1>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
-            case 2: t1_rows<2>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
-            case 3: t1_rows<3>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
-            case 4: t1_rows<4>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
-            case 5: t1_rows<5>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
-            case 6: t1_rows<6>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
-            case 7: t1_rows<7>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
-            default: t1_rows<8>(c, rw, nrows, wpx, lane, Pb, ps, zr, zi); break;
+            case 0: t1_rows<0>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            case 1: t1_rows<1>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            case 2: t1_rows<2>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            case 3: t1_rows<3>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            case 4: t1_rows<4>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            case 5: t1_rows<5>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            case 6: t1_rows<6>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            case 7: t1_rows<7>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            default: t1_rows<8>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
         }
         if (active) {
             const Rot R = rots[B.rot];
-            const double2 *G = Gr + (int64_t)B.rot * g.next;
 #pragma unroll
             for (int i = 0; i < T1_RB; ++i) {
                 const int nx = x0 + i;
@@ -478,10 +485,8 @@ __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_of
 }
 
 void launch_trilinear(const Geo &g, int nslots, const int *slot_off, const T1Item *items, const T1B *bdesc,
-                      const double *K, const double2 *Gr, const double2 *Pbuf, const Rot *rots, double2 *part,
-                      hipStream_t s) {
-    hipLaunchKernelGGL(trilinear_kernel, dim3(nslots), dim3(64), 0, s, g, slot_off, items, bdesc, K, Gr, Pbuf, rots,
-                       part);
+                      const double *K, const double2 *Gr, const Rot *rots, double2 *part, hipStream_t s) {
+    hipLaunchKernelGGL(trilinear_kernel, dim3(nslots), dim3(64), 0, s, g, slot_off, items, bdesc, K, Gr, rots, part);
 }
 
 int trilinear_blocks_per_cu() {
