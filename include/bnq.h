@@ -57,6 +57,7 @@ typedef enum {
 
 typedef void *bnq_stream_t; /* hipStream_t */
 typedef struct bnq_plan_s *bnq_plan_t;
+typedef struct bnq_batch_s *bnq_batch_t;
 
 /* term selection bits (all set = the full operator) */
 #define BNQ_T_CLASSICAL 1 /* Q1c - Q2c                           */
@@ -154,6 +155,33 @@ bnq_status bnq_plan_counts(bnq_plan_t plan, double *counts_host);
 #define BNQ_NKERNELS 8
 bnq_status bnq_plan_set_timing(bnq_plan_t plan, int32_t enable);
 bnq_status bnq_plan_timing(bnq_plan_t plan, double *ms_host, int64_t *launches_host);
+
+/* ---- Batches ------------------------------------------------------------
+ * Many independent instances of the same problem (the homogeneous equation
+ * of section 'Convergence towards a steady state', each with its own plan and
+ * state) evaluated together.  Plans that share (d, N, C_phi) form a group:
+ * each group runs one launch per kernel for all of its instances, and one
+ * trilinear launch over the merged work of all of them; every instance's
+ * result is bitwise identical to what its own plan computes alone.
+ *
+ * bnq_batch_create(): plans[i] (distinct, same device) and its state f[i]
+ *   (device, FP64, the plan's layout; distinct).  The batch keeps these
+ *   pointers: plans and states must outlive it, and a plan must not be used
+ *   on its own while a batch call that includes it is in flight.
+ *   Errors: EINVAL (NULL / duplicate / other device), ENOMEM.
+ * bnq_batch_collide(): Q[i] <- operator of f[i] (as bnq_collide), Qhat[i]
+ *   optional (Qhat may be NULL, or hold NULL entries).
+ * bnq_batch_step(): advances every f[i] in place by dt[i] (host array of n)
+ *   with scheme (as bnq_step).  use_graph != 0 captures the whole step into a
+ *   HIP graph on the first call and replays it while (scheme, dt, stream)
+ *   are unchanged (a change recaptures); it needs a non-default stream.
+ * bnq_batch_destroy(): waits for the batch's work and frees its arrays (not
+ *   the plans or states). */
+bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f, bnq_batch_t *out);
+bnq_status bnq_batch_destroy(bnq_batch_t batch);
+bnq_status bnq_batch_collide(bnq_batch_t batch, double *const *Q, void *const *Qhat, bnq_stream_t stream);
+bnq_status bnq_batch_step(bnq_batch_t batch, const double *dt, int32_t scheme, int32_t use_graph,
+                          bnq_stream_t stream);
 
 const char *bnq_status_string(bnq_status s);
 const char *bnq_last_error(void);

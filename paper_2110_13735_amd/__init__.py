@@ -83,9 +83,14 @@ def lib():
         L.bnq_plan_counts.argtypes = [vp, vp]
         L.bnq_plan_set_timing.argtypes = [vp, i32]
         L.bnq_plan_timing.argtypes = [vp, vp, vp]
+        L.bnq_batch_create.argtypes = [i32, vp, vp, ctypes.POINTER(vp)]
+        L.bnq_batch_destroy.argtypes = [vp]
+        L.bnq_batch_collide.argtypes = [vp, vp, vp, vp]
+        L.bnq_batch_step.argtypes = [vp, vp, i32, i32, vp]
         for fn in ("bnq_plan", "bnq_plan_destroy", "bnq_plan_footprint", "bnq_collide", "bnq_step",
                    "bnq_moments", "bnq_table_lookup", "bnq_plan_counts", "bnq_plan_set_timing",
-                   "bnq_plan_timing"):
+                   "bnq_plan_timing", "bnq_batch_create", "bnq_batch_destroy", "bnq_batch_collide",
+                   "bnq_batch_step"):
             getattr(L, fn).restype = ctypes.c_int
         L.bnq_status_string.argtypes = [ctypes.c_int]
         L.bnq_status_string.restype = ctypes.c_char_p
@@ -187,6 +192,50 @@ class Plan:
         n = np.zeros(NKERNELS, dtype=np.int64)
         _check(lib().bnq_plan_timing(self._h, ms.ctypes.data, n.ctypes.data))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_FAMILIES)}
+
+
+class Batch:
+    """A libbnq batch (bnq_batch_create / bnq_batch_destroy): plans[i] with
+    state tensor f[i], evaluated together.  Keeps references to both."""
+
+    def __init__(self, plans, f):
+        if len(plans) != len(f) or not plans:
+            raise ValueError("need as many state tensors as plans (at least one)")
+        self.plans = list(plans)
+        self.f = list(f)
+        n = len(plans)
+        ph = (ctypes.c_void_p * n)(*[pl._h.value for pl in plans])
+        fp = (ctypes.c_void_p * n)(*[_ptr(x) for x in f])
+        self._h = ctypes.c_void_p()
+        _check(lib().bnq_batch_create(n, ph, fp, ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            _check(lib().bnq_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def collide(self, Q, Qhat=None, stream=None):
+        n = len(self.plans)
+        qp = (ctypes.c_void_p * n)(*[_ptr(x) for x in Q])
+        hp = None if Qhat is None else (ctypes.c_void_p * n)(*[_ptr(x) for x in Qhat])
+        _check(lib().bnq_batch_collide(self._h, qp, hp, _stream(stream)))
+
+    def step(self, dt, scheme: int = RK4, graph: bool = False, stream=None):
+        n = len(self.plans)
+        dts = np.broadcast_to(np.asarray(dt, dtype=np.float64), (n,)).copy()
+        _check(lib().bnq_batch_step(self._h, dts.ctypes.data, int(scheme), 1 if graph else 0, _stream(stream)))
 
 
 def terms_per_eval(p: Params, counts: dict) -> float:

@@ -385,6 +385,10 @@ struct bnq_plan_s {
     int *slot_off = nullptr;
     T1Item *items = nullptr;
     T1B *bdesc = nullptr;
+    std::vector<T1Item> items_h;  // per-slot item lists (host copy), slot offsets
+    std::vector<int> off_h;
+    Inst ih{};                    // workspace pointers and scalars (host copy)
+    Inst *inst_d = nullptr;       // device copy, one entry
     double counts[4] = {0, 0, 0, 0};
     // timing
     bool timing = false;
@@ -396,6 +400,8 @@ struct bnq_plan_s {
     std::vector<hipEvent_t> pool;
     hipStream_t last = nullptr;
 };
+
+struct bnq_batch_s;
 
 namespace {
 
@@ -416,13 +422,13 @@ struct Span {
     hipStream_t s;
     hipEvent_t a = nullptr;
     Span(bnq_plan_s *P_, int fam_, hipStream_t s_) : P(P_), fam(fam_), s(s_) {
-        if (P->timing) {
+        if (P && P->timing) {
             a = ev_get(P);
             if (a) hipEventRecord(a, s);
         }
     }
     ~Span() {
-        if (P->timing && a) {
+        if (P && P->timing && a) {
             hipEvent_t b = ev_get(P);
             if (b) {
                 hipEventRecord(b, s);
@@ -509,7 +515,7 @@ bnq_status build_t1_work(bnq_plan_s *P) {
                     x.it.b = bi;
                     x.it.t0 = t0;
                     x.it.nt = std::min(64, ntasks - t0);
-                    x.it.pad = 0;
+                    x.it.inst = 0;
                     x.cost = cost;
                     items.push_back(x);
                 }
@@ -569,6 +575,8 @@ bnq_status build_t1_work(bnq_plan_s *P) {
     off[ns] = (int)flat.size();
     P->nslots = ns;
     P->nbdesc = (int)bd.size();
+    P->items_h = flat;
+    P->off_h = off;
     bnq_status st;
     if ((st = upload(&P->bdesc, bd, "trilinear b descriptors")) || (st = upload(&P->items, flat, "trilinear items")) ||
         (st = upload(&P->slot_off, off, "trilinear slot offsets")))
@@ -597,6 +605,7 @@ void destroy_plan(bnq_plan_s *P) {
     hipFree(P->slot_off);
     hipFree(P->items);
     hipFree(P->bdesc);
+    hipFree(P->inst_d);
     for (auto &e : P->evs) {
         hipEventDestroy(e.a);
         hipEventDestroy(e.b);
@@ -606,50 +615,178 @@ void destroy_plan(bnq_plan_s *P) {
     delete P;
 }
 
-bnq_status collide_impl(bnq_plan_s *P, const double *f, double *Q, double2 *Qhat_out, hipStream_t s) {
-    const Geo &g = P->g;
-    const TableSet *t = P->tabs;
-    const int terms = P->p.eps == 0 ? (P->p.terms & BNQ_T_CLASSICAL) : P->p.terms;
+// A set of instances evaluated together: one plan alone, or the instances of
+// a batch that share geometry and tables.  Kernels index the device array D;
+// the trilinear work lists of all instances are merged (per slot, the
+// instances' own lists one after the other, so that every instance's partial
+// sums are formed in exactly the order of its solo evaluation).
+struct Exec {
+    Geo g;
+    const TableSet *t = nullptr;
+    const double2 *tw = nullptr;
+    const Rot *rots = nullptr;
+    int nrot = 0, nslots = 0;
+    const int *slot_off = nullptr;
+    const T1Item *items = nullptr;
+    const T1B *bdesc = nullptr;
+    const Inst *D = nullptr;
+    std::vector<Inst> Dh;       // host copies of D
+    bnq_plan_s *timer = nullptr;  // plan whose timing spans record this run
+};
+
+Exec exec_of(bnq_plan_s *P) {
+    Exec E;
+    E.g = P->g;
+    E.t = P->tabs;
+    E.tw = P->tw;
+    E.rots = P->rots_d;
+    E.nrot = (int)P->grp.size();
+    E.nslots = P->nslots;
+    E.slot_off = P->slot_off;
+    E.items = P->items;
+    E.bdesc = P->bdesc;
+    E.D = P->inst_d;
+    E.Dh.assign(1, P->ih);
+    E.timer = P;
+    return E;
+}
+
+// Chunks of at most BNQ_MAXB instances, IOs filled by fill(io, z, instance).
+template <typename F>
+std::vector<IOs> make_ios(int n, const double *dt, F fill) {
+    std::vector<IOs> v;
+    for (int z0 = 0; z0 < n; z0 += BNQ_MAXB) {
+        IOs io;
+        std::memset(&io, 0, sizeof io);
+        io.n = std::min(BNQ_MAXB, n - z0);
+        for (int z = 0; z < io.n; ++z) {
+            io.inst[z] = z0 + z;
+            io.dt[z] = dt ? dt[z0 + z] : 0.0;
+            fill(io, z, z0 + z);
+        }
+        v.push_back(io);
+    }
+    return v;
+}
+
+bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s) {
+    const Geo &g = E.g;
+    int any = 0, max_slots = 0;
+    for (const Inst &I : E.Dh) {
+        any |= I.terms;
+        if (I.terms & BNQ_T_QTRI) max_slots = std::max(max_slots, I.nslots);
+    }
     {
-        Span sp(P, 0, s);
-        launch_dft_forward_real(g, f, P->tmp, P->Ghat, P->tw, s);
-        LAUNCHCHK();
-    }
-    const int want_c = (terms & BNQ_T_CLASSICAL) != 0, want_w = (terms & BNQ_T_QMULT) != 0;
-    if (want_c || want_w) {
-        Span sp(P, 1, s);
-        launch_pairs(g, P->Ghat, t->wc, t->wq, P->Qc, P->W, want_c, want_w, s);
-        LAUNCHCHK();
-    }
-    if (want_w) {
-        Span sp(P, 2, s);
-        launch_outer(g, P->Ghat, P->W, P->X, s);
-        LAUNCHCHK();
-    }
-    if (terms & BNQ_T_QTRI) {
-        {
-            Span sp(P, 4, s);
-            launch_rotate(g, P->Ghat, P->rots_d, (int)P->grp.size(), P->Gr, s);
+        Span sp(E.timer, 0, s);
+        for (const IOs &io : ios) {
+            launch_dft_forward_real(g, E.D, io, E.tw, s);
             LAUNCHCHK();
-            launch_zero(P->part, (int64_t)P->nslots * g.nm * (int64_t)sizeof(double2), s);
+        }
+    }
+    if (any & (BNQ_T_CLASSICAL | BNQ_T_QMULT)) {
+        Span sp(E.timer, 1, s);
+        for (const IOs &io : ios) {
+            launch_pairs(g, E.D, io, E.t->wc, E.t->wq, s);
+            LAUNCHCHK();
+        }
+    }
+    if (any & BNQ_T_QMULT) {
+        Span sp(E.timer, 2, s);
+        for (const IOs &io : ios) {
+            launch_outer(g, E.D, io, s);
+            LAUNCHCHK();
+        }
+    }
+    if (any & BNQ_T_QTRI) {
+        {
+            Span sp(E.timer, 4, s);
+            for (const IOs &io : ios) {
+                launch_rotate(g, E.D, io, E.rots, E.nrot, s);
+                LAUNCHCHK();
+                launch_zero_part(g, E.D, io, max_slots, s);
+                LAUNCHCHK();
+            }
+        }
+        {
+            Span sp(E.timer, 3, s);
+            launch_trilinear(g, E.nslots, E.slot_off, E.items, E.bdesc, E.t->K, E.D, E.rots, s);
             LAUNCHCHK();
         }
         {
-            Span sp(P, 3, s);
-            launch_trilinear(g, P->nslots, P->slot_off, P->items, P->bdesc, t->K, P->Gr, P->rots_d, P->part, s);
-            LAUNCHCHK();
-        }
-        {
-            Span sp(P, 4, s);
-            launch_reduce_partials(g, P->nslots, P->part, P->T1, s);
-            LAUNCHCHK();
+            Span sp(E.timer, 4, s);
+            for (const IOs &io : ios) {
+                launch_reduce_partials(g, E.D, io, s);
+                LAUNCHCHK();
+            }
         }
     }
     {
-        Span sp(P, 5, s);
-        launch_combine(g, P->Qc, P->T1, P->X, terms, P->alpha, P->p.correction == BNQ_CORR_MASS, P->Qh, Qhat_out, s);
-        LAUNCHCHK();
-        launch_inverse_real(g, P->Qh, P->tmp, P->tmp2, Q, P->tw, P->pref, s);
+        Span sp(E.timer, 5, s);
+        for (const IOs &io : ios) {
+            launch_combine(g, E.D, io, s);
+            LAUNCHCHK();
+            launch_inverse_real(g, E.D, io, E.tw, s);
+            LAUNCHCHK();
+        }
+    }
+    return BNQ_OK;
+}
+
+// One time step of every instance: f[i] advanced in place by dt[i].
+bnq_status run_step(const Exec &E, double *const *f, const double *dt, int scheme, hipStream_t s) {
+    const int n = (int)E.Dh.size();
+    if (scheme != BNQ_EULER && scheme != BNQ_SSPRK2 && scheme != BNQ_RK4)
+        return fail(BNQ_EINVAL, "unknown scheme %d", scheme);
+    auto coll = [&](int stage) {
+        return make_ios(n, dt, [&](IOs &io, int z, int i) {
+            io.in[z] = stage == 0 ? f[i] : E.Dh[i].ybuf;
+            io.out[z] = E.Dh[i].k[stage];
+        });
+    };
+    const std::vector<IOs> upd = make_ios(n, dt, [&](IOs &io, int z, int i) {
+        io.in[z] = f[i];
+        io.out[z] = f[i];
+    });
+    bnq_status st;
+    if ((st = run_collide(E, coll(0), s))) return st;
+    if (scheme == BNQ_EULER) {
+        Span sp(E.timer, 6, s);
+        for (const IOs &io : upd) {
+            launch_stage(E.g, E.D, io, 1.0, 0, 1, s);
+            LAUNCHCHK();
+        }
+        return BNQ_OK;
+    }
+    if (scheme == BNQ_SSPRK2) {
+        {
+            Span sp(E.timer, 6, s);
+            for (const IOs &io : upd) {
+                launch_stage(E.g, E.D, io, 1.0, 0, 0, s);
+                LAUNCHCHK();
+            }
+        }
+        if ((st = run_collide(E, coll(1), s))) return st;
+        Span sp(E.timer, 6, s);
+        for (const IOs &io : upd) {
+            launch_ssprk2_final(E.g, E.D, io, s);
+            LAUNCHCHK();
+        }
+        return BNQ_OK;
+    }
+    const double a[3] = {0.5, 0.5, 1.0};
+    for (int stg = 1; stg < 4; ++stg) {
+        {
+            Span sp(E.timer, 6, s);
+            for (const IOs &io : upd) {
+                launch_stage(E.g, E.D, io, a[stg - 1], stg - 1, 0, s);
+                LAUNCHCHK();
+            }
+        }
+        if ((st = run_collide(E, coll(stg), s))) return st;
+    }
+    Span sp(E.timer, 6, s);
+    for (const IOs &io : upd) {
+        launch_rk4_final(E.g, E.D, io, s);
         LAUNCHCHK();
     }
     return BNQ_OK;
@@ -734,6 +871,31 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         destroy_plan(P);
         return st;
     }
+    {
+        Inst &I = P->ih;
+        I.Ghat = P->Ghat;
+        I.tmp = P->tmp;
+        I.tmp2 = P->tmp2;
+        I.Gr = P->Gr;
+        I.W = P->W;
+        I.Qc = P->Qc;
+        I.T1 = P->T1;
+        I.X = P->X;
+        I.Qh = P->Qh;
+        I.part = P->part;
+        I.ybuf = P->ybuf;
+        for (int k = 0; k < 4; ++k) I.k[k] = P->kbuf[k];
+        I.alpha = P->alpha;
+        I.pref = P->pref;
+        I.terms = p->eps == 0 ? (p->terms & BNQ_T_CLASSICAL) : p->terms;
+        I.mass_fix = p->correction == BNQ_CORR_MASS;
+        I.nslots = P->nslots;
+        I.pad = 0;
+        if ((st = upload(&P->inst_d, std::vector<Inst>(1, I), "instance descriptor"))) {
+            destroy_plan(P);
+            return st;
+        }
+    }
     double c1, w1, o1, t1;
     counts_1d(p->N, c1, w1, o1, t1);
     const int d = p->d;
@@ -758,7 +920,12 @@ bnq_status bnq_collide(bnq_plan_t P, const double *f, double *Q, void *Qhat, bnq
     if ((const void *)f == (const void *)Q) return fail(BNQ_EINVAL, "f and Q must not alias");
     hipStream_t s = (hipStream_t)stream;
     P->last = s;
-    return collide_impl(P, f, Q, (double2 *)Qhat, s);
+    const Exec E = exec_of(P);
+    return run_collide(E, make_ios(1, nullptr, [&](IOs &io, int z, int) {
+                           io.in[z] = f;
+                           io.out[z] = Q;
+                           io.qhat[z] = (double2 *)Qhat;
+                       }), s);
 }
 
 bnq_status bnq_step(bnq_plan_t P, double *f, double dt, int32_t scheme, bnq_stream_t stream) {
@@ -767,44 +934,8 @@ bnq_status bnq_step(bnq_plan_t P, double *f, double dt, int32_t scheme, bnq_stre
     if (!std::isfinite(dt)) return fail(BNQ_EINVAL, "dt must be finite");
     hipStream_t s = (hipStream_t)stream;
     P->last = s;
-    const int64_t n = P->g.nm;
-    double **k = P->kbuf;
-    bnq_status st;
-    if (scheme == BNQ_EULER) {
-        if ((st = collide_impl(P, f, k[0], nullptr, s))) return st;
-        Span sp(P, 6, s);
-        launch_axpy(n, f, dt, k[0], f, s);
-        LAUNCHCHK();
-        return BNQ_OK;
-    }
-    if (scheme == BNQ_SSPRK2) {
-        if ((st = collide_impl(P, f, k[0], nullptr, s))) return st;
-        {
-            Span sp(P, 6, s);
-            launch_axpy(n, f, dt, k[0], P->ybuf, s);
-            LAUNCHCHK();
-        }
-        if ((st = collide_impl(P, P->ybuf, k[1], nullptr, s))) return st;
-        Span sp(P, 6, s);
-        launch_ssprk2_final(n, f, P->ybuf, k[1], dt, s);
-        LAUNCHCHK();
-        return BNQ_OK;
-    }
-    if (scheme != BNQ_RK4) return fail(BNQ_EINVAL, "unknown scheme %d", scheme);
-    if ((st = collide_impl(P, f, k[0], nullptr, s))) return st;
-    const double a[3] = {0.5 * dt, 0.5 * dt, dt};
-    for (int stg = 1; stg < 4; ++stg) {
-        {
-            Span sp(P, 6, s);
-            launch_axpy(n, f, a[stg - 1], k[stg - 1], P->ybuf, s);
-            LAUNCHCHK();
-        }
-        if ((st = collide_impl(P, P->ybuf, k[stg], nullptr, s))) return st;
-    }
-    Span sp(P, 6, s);
-    launch_rk4_final(n, f, dt, k[0], k[1], k[2], k[3], s);
-    LAUNCHCHK();
-    return BNQ_OK;
+    const Exec E = exec_of(P);
+    return run_step(E, &f, &dt, scheme, s);
 }
 
 bnq_status bnq_moments(bnq_plan_t P, const double *f, double *out_host, bnq_stream_t stream) {
@@ -940,5 +1071,195 @@ const char *bnq_status_string(bnq_status s) {
 }
 
 const char *bnq_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches (a fixed set of plans and state arrays evaluated together).
+struct bnq_batch_s {
+    struct Group {
+        Exec E;
+        std::vector<int> members;  // positions in the batch
+        Inst *D = nullptr;
+        int *slot_off = nullptr;
+        T1Item *items = nullptr;
+    };
+    std::vector<bnq_plan_s *> plans;
+    std::vector<double *> f;
+    std::vector<Group> groups;
+    hipGraphExec_t gexec = nullptr;  // captured step, replayed while (scheme, dt, stream) match
+    int g_scheme = -1;
+    std::vector<double> g_dt;
+    hipStream_t g_stream = nullptr;
+};
+
+namespace {
+
+void destroy_batch(bnq_batch_s *B) {
+    if (!B) return;
+    if (B->gexec) hipGraphExecDestroy(B->gexec);
+    for (auto &G : B->groups) {
+        hipFree(G.D);
+        hipFree(G.slot_off);
+        hipFree(G.items);
+    }
+    delete B;
+}
+
+bnq_status batch_step_enqueue(bnq_batch_s *B, const double *dt, int scheme, hipStream_t s) {
+    for (auto &G : B->groups) {
+        std::vector<double *> fs;
+        std::vector<double> dts;
+        for (int m : G.members) {
+            fs.push_back(B->f[m]);
+            dts.push_back(dt[m]);
+        }
+        bnq_status st = run_step(G.E, fs.data(), dts.data(), scheme, s);
+        if (st) return st;
+    }
+    return BNQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f, bnq_batch_t *out) {
+    if (!out) return fail(BNQ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !plans || !f) return fail(BNQ_EINVAL, "need n >= 1 plans and state arrays");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i] || !f[i]) return fail(BNQ_EINVAL, "plan or state %d is NULL", i);
+        if (plans[i]->tabs->device != dev) return fail(BNQ_EINVAL, "plan %d lives on another device", i);
+        for (int j = 0; j < i; ++j) {
+            if (plans[j] == plans[i]) return fail(BNQ_EINVAL, "plan %d appears twice", i);
+            if (f[j] == f[i]) return fail(BNQ_EINVAL, "state array %d appears twice", i);
+        }
+    }
+    bnq_batch_s *B = new bnq_batch_s;
+    B->plans.assign(plans, plans + n);
+    B->f.assign(f, f + n);
+    std::map<const TableSet *, int> gidx;
+    for (int i = 0; i < n; ++i) {
+        auto it = gidx.find(plans[i]->tabs);
+        if (it == gidx.end()) {
+            gidx[plans[i]->tabs] = (int)B->groups.size();
+            B->groups.emplace_back();
+            B->groups.back().members.push_back(i);
+        } else {
+            B->groups[it->second].members.push_back(i);
+        }
+    }
+    for (auto &G : B->groups) {
+        bnq_plan_s *P0 = plans[G.members[0]];
+        G.E = exec_of(P0);
+        G.E.timer = nullptr;
+        G.E.Dh.clear();
+        int ns = 0;
+        for (int m : G.members) {
+            G.E.Dh.push_back(plans[m]->ih);
+            ns = std::max(ns, plans[m]->nslots);
+        }
+        std::vector<int> off(ns + 1, 0);
+        std::vector<T1Item> items;
+        for (int sl = 0; sl < ns; ++sl) {
+            off[sl] = (int)items.size();
+            for (size_t j = 0; j < G.members.size(); ++j) {
+                const bnq_plan_s *P = plans[G.members[j]];
+                if (!(P->ih.terms & BNQ_T_QTRI) || sl >= P->nslots) continue;
+                for (int k = P->off_h[sl]; k < P->off_h[sl + 1]; ++k) {
+                    T1Item x = P->items_h[k];
+                    x.inst = (int)j;
+                    items.push_back(x);
+                }
+            }
+        }
+        off[ns] = (int)items.size();
+        bnq_status st;
+        if ((st = upload(&G.D, G.E.Dh, "batch instance descriptors")) ||
+            (st = upload(&G.slot_off, off, "batch slot offsets")) ||
+            (!items.empty() && (st = upload(&G.items, items, "batch trilinear items")))) {
+            destroy_batch(B);
+            return st;
+        }
+        G.E.D = G.D;
+        G.E.nslots = ns;
+        G.E.slot_off = G.slot_off;
+        G.E.items = G.items;
+    }
+    *out = B;
+    return BNQ_OK;
+}
+
+bnq_status bnq_batch_destroy(bnq_batch_t B) {
+    if (!B) return BNQ_OK;
+    if (B->g_stream) hipStreamSynchronize(B->g_stream);
+    for (auto *P : B->plans) hipStreamSynchronize(P->last);
+    destroy_batch(B);
+    return BNQ_OK;
+}
+
+bnq_status bnq_batch_collide(bnq_batch_t B, double *const *Q, void *const *Qhat, bnq_stream_t stream) {
+    if (!B || !Q) return fail(BNQ_EINVAL, "batch and Q must be non-NULL");
+    const int n = (int)B->f.size();
+    for (int i = 0; i < n; ++i) {
+        if (!Q[i]) return fail(BNQ_EINVAL, "Q[%d] is NULL", i);
+        if ((const void *)Q[i] == (const void *)B->f[i]) return fail(BNQ_EINVAL, "Q[%d] aliases its state", i);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    for (auto *P : B->plans) P->last = s;
+    for (auto &G : B->groups) {
+        const int m = (int)G.members.size();
+        bnq_status st = run_collide(G.E, make_ios(m, nullptr, [&](IOs &io, int z, int j) {
+                                        const int i = G.members[j];
+                                        io.in[z] = B->f[i];
+                                        io.out[z] = Q[i];
+                                        io.qhat[z] = Qhat ? (double2 *)Qhat[i] : nullptr;
+                                    }), s);
+        if (st) return st;
+    }
+    return BNQ_OK;
+}
+
+bnq_status bnq_batch_step(bnq_batch_t B, const double *dt, int32_t scheme, int32_t use_graph, bnq_stream_t stream) {
+    if (!B || !dt) return fail(BNQ_EINVAL, "batch and dt must be non-NULL");
+    const int n = (int)B->f.size();
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(dt[i])) return fail(BNQ_EINVAL, "dt[%d] must be finite", i);
+    hipStream_t s = (hipStream_t)stream;
+    for (auto *P : B->plans) P->last = s;
+    if (!use_graph) return batch_step_enqueue(B, dt, scheme, s);
+    if (!s) return fail(BNQ_EINVAL, "graph replay needs a non-default stream");
+    const std::vector<double> dtv(dt, dt + n);
+    if (!B->gexec || B->g_scheme != scheme || B->g_dt != dtv || B->g_stream != s) {
+        if (B->gexec) {
+            HIPCHK(hipStreamSynchronize(B->g_stream ? B->g_stream : s));
+            hipGraphExecDestroy(B->gexec);
+            B->gexec = nullptr;
+        }
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        bnq_status st = batch_step_enqueue(B, dt, scheme, s);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (st) {
+            if (graph) hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return fail(BNQ_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&B->gexec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            B->gexec = nullptr;
+            return fail(BNQ_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+        }
+        B->g_scheme = scheme;
+        B->g_dt = dtv;
+        B->g_stream = s;
+    }
+    HIPCHK(hipGraphLaunch(B->gexec, s));
+    return BNQ_OK;
+}
 
 }  // extern "C"

@@ -76,10 +76,10 @@ struct T1B {
 };
 
 struct T1Item {
-    int b;   // index into the T1B array
-    int t0;  // first task
-    int nt;  // number of tasks (<= 64)
-    int pad;
+    int b;     // index into the T1B array
+    int t0;    // first task
+    int nt;    // number of tasks (<= 64)
+    int inst;  // instance (index into the launch's Inst array)
 };
 
 constexpr int T1_RB = 8;      // outputs per lane along x
@@ -95,6 +95,59 @@ struct Radial {
     int d;
 };
 
+// Pointers read from memory (the Inst and IOs tables) are generic; kernels
+// convert them to the global address space so that their accesses compile to
+// global (not flat) memory instructions.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__host__ __device__ __forceinline__ gptr<T> glob(T *p) {
+    return (gptr<T>)p;
+}
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld2(const double2 *p, int64_t i) {
+    const dvec2 v = ((gptr<const dvec2>)p)[i];
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st2(double2 *p, int64_t i, double2 a) {
+    dvec2 v;
+    v.x = a.x;
+    v.y = a.y;
+    ((gptr<dvec2>)p)[i] = v;
+}
+
+// ---- instances --------------------------------------------------------------
+// Every evaluation kernel runs over a set of instances that share the geometry
+// and the tables (one plan alone, or a batch group); blockIdx.z (or the work
+// item) selects the instance.
+constexpr int BNQ_MAXB = 64;  // instances per launch
+
+// Workspace of one instance (device memory, fixed for the plan's lifetime).
+struct Inst {
+    double2 *Ghat, *tmp, *tmp2, *Gr, *W, *Qc, *T1, *X, *Qh, *part;
+    double *ybuf, *k[4];
+    double alpha;  // -eps hbar^d
+    double pref;   // c (L/pi)^(d+gamma)
+    int terms;     // BNQ_T_* mask actually evaluated
+    int mass_fix;  // 1: Re Qhat_0 := 0
+    int nslots;    // trilinear partial arrays in part
+    int pad;
+};
+
+// Buffers a kernel can be pointed at.
+enum BufSel { BUF_IN = 0, BUF_OUT, BUF_TMP, BUF_TMP2, BUF_GHAT, BUF_QH, BUF_Y, BUF_K0 };
+
+// Per-call pointers, passed by value: instance z of a launch is Inst[inst[z]],
+// reads grid values from in[z] and writes them to out[z].
+struct IOs {
+    const double *in[BNQ_MAXB];
+    double *out[BNQ_MAXB];
+    double2 *qhat[BNQ_MAXB];  // optional copy of Qhat (may be NULL)
+    double dt[BNQ_MAXB];
+    int inst[BNQ_MAXB];
+    int n;
+};
+
 // ---- launchers (defined in the .hip files) --------------------------------
 void launch_radial(int d, double R, int qmax, int M, int nq, const double *glx, const double *glw,
                    double *S, double *J, hipStream_t s);
@@ -103,27 +156,26 @@ void launch_beta_rows(const Geo &g, const Radial &rad, const int *canon, int nca
 void launch_weights(const Geo &g, const Radial &rad, double *wc, double *wq, hipStream_t s);
 void launch_gather(const double *base, const int64_t *idx, int64_t n, double *out, hipStream_t s);
 
-void launch_dft_forward_real(const Geo &g, const double *f, double2 *tmp, double2 *out,
-                             const double2 *tw, hipStream_t s);
-void launch_rotate(const Geo &g, const double2 *G, const Rot *rots, int nrot, double2 *Gr, hipStream_t s);
-void launch_pairs(const Geo &g, const double2 *G, const double *wc, const double *wq, double2 *Qc,
-                  double2 *W, int want_c, int want_w, hipStream_t s);
-void launch_outer(const Geo &g, const double2 *G, const double2 *W, double2 *X, hipStream_t s);
-void launch_trilinear(const Geo &g, int nslots, const int *slot_off, const T1Item *items,
-                      const T1B *bdesc, const double *K, const double2 *Gr, const Rot *rots, double2 *part,
-                      hipStream_t s);
+// DFT of grid values io.in -> Ghat (forward, scale N^-d) and Qh -> io.out
+// (inverse, real part, scale Inst::pref).
+void launch_dft_forward_real(const Geo &g, const Inst *D, const IOs &io, const double2 *tw, hipStream_t s);
+void launch_inverse_real(const Geo &g, const Inst *D, const IOs &io, const double2 *tw, hipStream_t s);
+void launch_rotate(const Geo &g, const Inst *D, const IOs &io, const Rot *rots, int nrot, hipStream_t s);
+void launch_pairs(const Geo &g, const Inst *D, const IOs &io, const double *wc, const double *wq, hipStream_t s);
+void launch_outer(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
+void launch_zero_part(const Geo &g, const Inst *D, const IOs &io, int max_slots, hipStream_t s);
+void launch_trilinear(const Geo &g, int nslots, const int *slot_off, const T1Item *items, const T1B *bdesc,
+                      const double *K, const Inst *D, const Rot *rots, hipStream_t s);
 int trilinear_blocks_per_cu();  // resident 64-lane trilinear workgroups per CU (0 on error)
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
-void launch_reduce_partials(const Geo &g, int nslots, const double2 *part, double2 *T1, hipStream_t s);
-void launch_combine(const Geo &g, const double2 *Qc, const double2 *T1, const double2 *X, int terms,
-                    double alpha, int mass_fix, double2 *Qh, double2 *Qh_out, hipStream_t s);
-void launch_inverse_real(const Geo &g, const double2 *Qh, double2 *tmp, double2 *tmp2, double *Q,
-                         const double2 *tw, double scale, hipStream_t s);
+void launch_reduce_partials(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
+void launch_combine(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 
-void launch_axpy(int64_t n, const double *x, double a, const double *y, double *out, hipStream_t s);
-void launch_rk4_final(int64_t n, double *f, double dt, const double *k1, const double *k2,
-                      const double *k3, const double *k4, hipStream_t s);
-void launch_ssprk2_final(int64_t n, double *f, const double *y, const double *k2, double dt, hipStream_t s);
+// Stage updates: y = in + a dt k[ks] into Inst::ybuf (to_out = 0) or into
+// io.out (to_out = 1); the final RK4 / SSP-RK2 combinations update io.out.
+void launch_stage(const Geo &g, const Inst *D, const IOs &io, double a, int ks, int to_out, hipStream_t s);
+void launch_rk4_final(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
+void launch_ssprk2_final(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 void launch_moments(const Geo &g, const double *f, double L, double alpha, double *part, int nblk,
                     double *out, hipStream_t s);
 constexpr int MOM_BLOCKS = 256;

@@ -27,25 +27,34 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
 }
 
+__device__ __forceinline__ const void *sel_ptr(const Inst &I, const IOs &io, int z, int sel) {
+    switch (sel) {
+        case BUF_IN: return io.in[z];
+        case BUF_OUT: return io.out[z];
+        case BUF_TMP: return I.tmp;
+        case BUF_TMP2: return I.tmp2;
+        case BUF_GHAT: return I.Ghat;
+        case BUF_QH: return I.Qh;
+        case BUF_Y: return I.ybuf;
+        default: return I.k[sel - BUF_K0];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // DFT along one axis.  in/out are [e0][N][N] (axis 0 extent e0); the axis
 // `ax` has extent N.  tw[t] = exp(-2 pi i t / N); sign = -1 forward, +1 inverse.
-template <typename Tin>
-__device__ __forceinline__ double2 load_c(const Tin *p, int64_t i);
-template <>
-__device__ __forceinline__ double2 load_c<double>(const double *p, int64_t i) {
-    return make_double2(p[i], 0.0);
-}
-template <>
-__device__ __forceinline__ double2 load_c<double2>(const double2 *p, int64_t i) {
-    return p[i];
-}
+__device__ __forceinline__ double2 load_c(const double *p, int64_t i) { return make_double2(glob(p)[i], 0.0); }
+__device__ __forceinline__ double2 load_c(const double2 *p, int64_t i) { return ld2(p, i); }
 
-template <typename Tin, int MODE>  // MODE 0: complex out, 1: real part * scale
-__global__ void dft_axis_kernel(Geo g, const Tin *in, double2 *out, double *rout, int ax, int sign,
-                                double scale, const double2 *tw) {
+// MODE 0: complex out; 1: real part.  smode: scale 1, 1/N or Inst::pref.
+template <typename Tin, int MODE>
+__global__ void dft_axis_kernel(Geo g, const Inst *D, IOs io, int sin, int sout, int ax, int sign, int smode,
+                                const double2 *tw) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.nm) return;
+    const int z = blockIdx.z;
+    const Inst &I = D[io.inst[z]];
+    const Tin *in = (const Tin *)sel_ptr(I, io, z, sin);
     const int N = g.N, h = g.h;
     const int64_t stride = ax == 2 ? 1 : (ax == 1 ? N : (int64_t)N * N);
     const int kpos = (int)((i / stride) % N);
@@ -58,49 +67,51 @@ __global__ void dft_axis_kernel(Geo g, const Tin *in, double2 *out, double *rout
         if (t < 0) t += N;
         double2 w = tw[t];
         if (sign > 0) w.y = -w.y;
-        const double2 v = load_c<Tin>(in, base + (int64_t)jp * stride);
+        const double2 v = load_c(in, base + (int64_t)jp * stride);
         re = fma(v.x, w.x, fma(-v.y, w.y, re));
         im = fma(v.x, w.y, fma(v.y, w.x, im));
     }
+    const double scale = smode == 0 ? 1.0 : (smode == 1 ? 1.0 / N : I.pref);
     if (MODE == 0)
-        out[i] = make_double2(re * scale, im * scale);
+        st2((double2 *)sel_ptr(I, io, z, sout), i, make_double2(re * scale, im * scale));
     else
-        rout[i] = re * scale;
+        glob((double *)sel_ptr(I, io, z, sout))[i] = re * scale;
 }
 
-void launch_dft_forward_real(const Geo &g, const double *f, double2 *tmp, double2 *out,
-                             const double2 *tw, hipStream_t s) {
-    const unsigned nb = (unsigned)((g.nm + 255) / 256);
-    const double sc = 1.0 / g.N;
+static dim3 grid_nm(const Geo &g, const IOs &io) { return dim3((unsigned)((g.nm + 255) / 256), 1, (unsigned)io.n); }
+
+void launch_dft_forward_real(const Geo &g, const Inst *D, const IOs &io, const double2 *tw, hipStream_t s) {
+    const dim3 gr = grid_nm(g, io);
     if (g.d == 2) {
-        hipLaunchKernelGGL((dft_axis_kernel<double, 0>), dim3(nb), dim3(256), 0, s, g, f, tmp, (double *)nullptr, 2, -1, sc, tw);
-        hipLaunchKernelGGL((dft_axis_kernel<double2, 0>), dim3(nb), dim3(256), 0, s, g, (const double2 *)tmp, out, (double *)nullptr, 1, -1, sc, tw);
+        hipLaunchKernelGGL((dft_axis_kernel<double, 0>), gr, dim3(256), 0, s, g, D, io, (int)BUF_IN, (int)BUF_TMP, 2, -1, 1, tw);
+        hipLaunchKernelGGL((dft_axis_kernel<double2, 0>), gr, dim3(256), 0, s, g, D, io, (int)BUF_TMP, (int)BUF_GHAT, 1, -1, 1, tw);
     } else {
-        hipLaunchKernelGGL((dft_axis_kernel<double, 0>), dim3(nb), dim3(256), 0, s, g, f, out, (double *)nullptr, 2, -1, sc, tw);
-        hipLaunchKernelGGL((dft_axis_kernel<double2, 0>), dim3(nb), dim3(256), 0, s, g, (const double2 *)out, tmp, (double *)nullptr, 1, -1, sc, tw);
-        hipLaunchKernelGGL((dft_axis_kernel<double2, 0>), dim3(nb), dim3(256), 0, s, g, (const double2 *)tmp, out, (double *)nullptr, 0, -1, sc, tw);
+        hipLaunchKernelGGL((dft_axis_kernel<double, 0>), gr, dim3(256), 0, s, g, D, io, (int)BUF_IN, (int)BUF_GHAT, 2, -1, 1, tw);
+        hipLaunchKernelGGL((dft_axis_kernel<double2, 0>), gr, dim3(256), 0, s, g, D, io, (int)BUF_GHAT, (int)BUF_TMP, 1, -1, 1, tw);
+        hipLaunchKernelGGL((dft_axis_kernel<double2, 0>), gr, dim3(256), 0, s, g, D, io, (int)BUF_TMP, (int)BUF_GHAT, 0, -1, 1, tw);
     }
 }
 
-void launch_inverse_real(const Geo &g, const double2 *Qh, double2 *tmp, double2 *tmp2, double *Q,
-                         const double2 *tw, double scale, hipStream_t s) {
-    const unsigned nb = (unsigned)((g.nm + 255) / 256);
+void launch_inverse_real(const Geo &g, const Inst *D, const IOs &io, const double2 *tw, hipStream_t s) {
+    const dim3 gr = grid_nm(g, io);
     if (g.d == 2) {
-        hipLaunchKernelGGL((dft_axis_kernel<double2, 0>), dim3(nb), dim3(256), 0, s, g, Qh, tmp, (double *)nullptr, 1, +1, 1.0, tw);
-        hipLaunchKernelGGL((dft_axis_kernel<double2, 1>), dim3(nb), dim3(256), 0, s, g, (const double2 *)tmp, (double2 *)nullptr, Q, 2, +1, scale, tw);
+        hipLaunchKernelGGL((dft_axis_kernel<double2, 0>), gr, dim3(256), 0, s, g, D, io, (int)BUF_QH, (int)BUF_TMP, 1, +1, 0, tw);
+        hipLaunchKernelGGL((dft_axis_kernel<double2, 1>), gr, dim3(256), 0, s, g, D, io, (int)BUF_TMP, (int)BUF_OUT, 2, +1, 2, tw);
     } else {
-        hipLaunchKernelGGL((dft_axis_kernel<double2, 0>), dim3(nb), dim3(256), 0, s, g, Qh, tmp, (double *)nullptr, 0, +1, 1.0, tw);
-        hipLaunchKernelGGL((dft_axis_kernel<double2, 0>), dim3(nb), dim3(256), 0, s, g, (const double2 *)tmp, tmp2, (double *)nullptr, 1, +1, 1.0, tw);
-        hipLaunchKernelGGL((dft_axis_kernel<double2, 1>), dim3(nb), dim3(256), 0, s, g, (const double2 *)tmp2, (double2 *)nullptr, Q, 2, +1, scale, tw);
+        hipLaunchKernelGGL((dft_axis_kernel<double2, 0>), gr, dim3(256), 0, s, g, D, io, (int)BUF_QH, (int)BUF_TMP, 0, +1, 0, tw);
+        hipLaunchKernelGGL((dft_axis_kernel<double2, 0>), gr, dim3(256), 0, s, g, D, io, (int)BUF_TMP, (int)BUF_TMP2, 1, +1, 0, tw);
+        hipLaunchKernelGGL((dft_axis_kernel<double2, 1>), gr, dim3(256), 0, s, g, D, io, (int)BUF_TMP2, (int)BUF_OUT, 2, +1, 2, tw);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Rotated spectra: Gr[r][q] = G(R_r q) if R_r q in I_N, else 0, q in Ext.
-__global__ void rotate_kernel(Geo g, const double2 *G, const Rot *rots, double2 *Gr) {
+// Only instances that evaluate the trilinear term.
+__global__ void rotate_kernel(Geo g, const Inst *D, IOs io, const Rot *rots) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
-    if (i >= g.next) return;
+    const Inst &I = D[io.inst[blockIdx.z]];
+    if (i >= g.next || !(I.terms & 4)) return;
     const int X = g.N + 1;
     int q[3];
     q[2] = (int)(i % X) - g.h;
@@ -111,12 +122,12 @@ __global__ void rotate_kernel(Geo g, const double2 *G, const Rot *rots, double2 
     for (int a = 0; a < 3; ++a) y[a] = R.sgn[a] * q[R.perm[a]];
     const bool in = y[1] >= -g.h && y[1] < g.h && y[2] >= -g.h && y[2] < g.h &&
                     (g.d == 2 ? y[0] == 0 : (y[0] >= -g.h && y[0] < g.h));
-    Gr[(int64_t)r * g.next + i] = in ? G[idx_I(g, y[0], y[1], y[2])] : make_double2(0.0, 0.0);
+    st2(I.Gr, (int64_t)r * g.next + i, in ? ld2(I.Ghat, idx_I(g, y[0], y[1], y[2])) : make_double2(0.0, 0.0));
 }
 
-void launch_rotate(const Geo &g, const double2 *G, const Rot *rots, int nrot, double2 *Gr, hipStream_t s) {
-    dim3 grid((unsigned)((g.next + 255) / 256), (unsigned)nrot);
-    hipLaunchKernelGGL(rotate_kernel, grid, dim3(256), 0, s, g, G, rots, Gr);
+void launch_rotate(const Geo &g, const Inst *D, const IOs &io, const Rot *rots, int nrot, hipStream_t s) {
+    dim3 grid((unsigned)((g.next + 255) / 256), (unsigned)nrot, (unsigned)io.n);
+    hipLaunchKernelGGL(rotate_kernel, grid, dim3(256), 0, s, g, D, io, rots);
 }
 
 // ---------------------------------------------------------------------------
@@ -126,9 +137,12 @@ void launch_rotate(const Geo &g, const double2 *G, const Rot *rots, int nrot, do
 // the weight rows wq[l][s - l] are read as contiguous runs.  Loads are
 // branch-free (indices clamped into range, invalid terms weighted by zero)
 // and the innermost loop is unrolled so that many table loads are in flight.
-__global__ __launch_bounds__(256) void pairs_kernel(Geo g, const double2 *G, const double *wc,
-                                                    const double *wq, double2 *Qc, double2 *W, int want_c,
-                                                    int want_w) {
+__global__ __launch_bounds__(256) void pairs_kernel(Geo g, const Inst *D, IOs io, const double *wc,
+                                                    const double *wq) {
+    const Inst &I = D[io.inst[blockIdx.z]];
+    const int want_c = (I.terms & 1) != 0, want_w = (I.terms & 2) != 0;
+    if (!want_c && !want_w) return;
+    const double2 *G = I.Ghat;
     const int N = g.N, h = g.h;
     const int rows = 256 / (2 * N);  // s1 rows per workgroup
     const int tid = threadIdx.x;
@@ -159,8 +173,8 @@ __global__ __launch_bounds__(256) void pairs_kernel(Geo g, const double2 *G, con
                 const bool ok = ok1 && m2 >= -h && m2 < h;
                 const int m2c = min(max(m2, -h), h - 1);
                 const int64_t il = il0 + j, im = im0 + m2c;
-                const double2 gl = G[il];
-                const double2 gm = G[im];
+                const double2 gl = ld2(G, il);
+                const double2 gm = ld2(G, im);
                 const int64_t o = il * g.nm + im;
                 const double w1 = want_w ? wq[o] : 0.0;
                 const double w2 = do_c ? wc[o] : 0.0;
@@ -174,23 +188,24 @@ __global__ __launch_bounds__(256) void pairs_kernel(Geo g, const double2 *G, con
         }
     }
     if (!valid) return;
-    if (want_w) W[idx_E(g, s0, s1, s2)] = accw;
-    if (do_c) Qc[idx_I(g, s0, s1, s2)] = accc;
+    if (want_w) st2(I.W, idx_E(g, s0, s1, s2), accw);
+    if (do_c) st2(I.Qc, idx_I(g, s0, s1, s2), accc);
 }
 
-void launch_pairs(const Geo &g, const double2 *G, const double *wc, const double *wq, double2 *Qc,
-                  double2 *W, int want_c, int want_w, hipStream_t s) {
+void launch_pairs(const Geo &g, const Inst *D, const IOs &io, const double *wc, const double *wq, hipStream_t s) {
     const int N = g.N;
     const int rows = 256 / (2 * N);
-    dim3 grid((unsigned)((2 * N + rows - 1) / rows), (unsigned)(g.d == 3 ? 2 * N : 1));
-    hipLaunchKernelGGL(pairs_kernel, grid, dim3(256), 0, s, g, G, wc, wq, Qc, W, want_c, want_w);
+    dim3 grid((unsigned)((2 * N + rows - 1) / rows), (unsigned)(g.d == 3 ? 2 * N : 1), (unsigned)io.n);
+    hipLaunchKernelGGL(pairs_kernel, grid, dim3(256), 0, s, g, D, io, wc, wq);
 }
 
 // ---------------------------------------------------------------------------
 // Outer sum X_n = sum_k G_k W_{n-k}; n - k always lies in Eg.
-__global__ __launch_bounds__(256) void outer_kernel(Geo g, const double2 *G, const double2 *W, double2 *X) {
+__global__ __launch_bounds__(256) void outer_kernel(Geo g, const Inst *D, IOs io) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.nm) return;
+    const Inst &I = D[io.inst[blockIdx.z]];
+    if (i >= g.nm || !(I.terms & 2)) return;
+    const double2 *G = I.Ghat, *W = I.W;
     const int N = g.N, h = g.h;
     const int n2 = (int)(i % N) - h, n1 = (int)((i / N) % N) - h;
     const int n0 = g.d == 3 ? (int)(i / ((int64_t)N * N)) - h : 0;
@@ -202,16 +217,16 @@ __global__ __launch_bounds__(256) void outer_kernel(Geo g, const double2 *G, con
             const double2 *Wrow = W + idx_E(g, n0 - k0, n1 - k1, n2 + h);
 #pragma unroll 8
             for (int k2 = 0; k2 < N; ++k2) {
-                const double2 a = Grow[k2], b = Wrow[-k2];
+                const double2 a = ld2(Grow, k2), b = ld2(Wrow, -k2);
                 acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
                 acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
             }
         }
-    X[i] = acc;
+    st2(I.X, i, acc);
 }
 
-void launch_outer(const Geo &g, const double2 *G, const double2 *W, double2 *X, hipStream_t s) {
-    hipLaunchKernelGGL(outer_kernel, dim3((unsigned)((g.nm + 255) / 256)), dim3(256), 0, s, g, G, W, X);
+void launch_outer(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
+    hipLaunchKernelGGL(outer_kernel, grid_nm(g, io), dim3(256), 0, s, g, D, io);
 }
 
 // ---------------------------------------------------------------------------
@@ -343,7 +358,7 @@ struct T1Pairs {
         const int pz = pzlo + pzi, py = pylo + pyi;
         const int64_t ip = ((int64_t)(d3 ? pz + h : 0) * X + (py + h)) * X + px;
         const int64_t iq = ((int64_t)(d3 ? bz - pz + h : 0) * X + (by - py + h)) * X + qx;
-        return cmul(G[ip], G[iq]);
+        return cmul(ld2(G, ip), ld2(G, iq));
     }
 };
 
@@ -400,17 +415,18 @@ __device__ __forceinline__ void t1_rows(T1Ctx &c, T1Rows rw, int nrows, int wpx,
 }
 
 __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_off, const T1Item *items,
-                                                       const T1B *bdesc, const double *K, const double2 *Gr,
-                                                       const Rot *rots, double2 *part) {
+                                                       const T1B *bdesc, const double *K, const Inst *D,
+                                                       const Rot *rots) {
     __shared__ double2 ps[2][64];
     const int slot = blockIdx.x;
     const int lane = threadIdx.x;
-    double2 *mypart = part + (int64_t)slot * g.nm;
     const int A = 2 * g.N - 1;
     const int it_end = slot_off[slot + 1];
     for (int it = slot_off[slot]; it < it_end; ++it) {
         const T1Item item = items[it];
         const T1B B = bdesc[item.b];
+        const Inst &I = D[item.inst];
+        double2 *mypart = I.part + (int64_t)slot * g.nm;
         const bool active = lane < item.nt;
         const int t = item.t0 + (active ? lane : 0);
         const int wny = B.wnhi[1] - B.wnlo[1] + 1;
@@ -433,7 +449,7 @@ __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_of
         rw.dy = (int)sizeof(double);
         rw.dz = (g.d == 3 ? g.kax * A : 0) * (int)sizeof(double);
         const int nrows = rw.wpy * (B.wphi[0] - B.wplo[0] + 1);
-        const double2 *G = Gr + (int64_t)B.rot * g.next;
+        const double2 *G = I.Gr + (int64_t)B.rot * g.next;
         T1Pairs pr;
         pr.G = G;
         pr.X = g.N + 1;
@@ -465,17 +481,17 @@ __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_of
             for (int i = 0; i < T1_RB; ++i) {
                 const int nx = x0 + i;
                 if (nx <= B.wnhi[2]) {
-                    const double2 gk = G[idx_X(g, nz - B.bc[0], ny - B.bc[1], nx - B.bc[2])];
+                    const double2 gk = ld2(G, idx_X(g, nz - B.bc[0], ny - B.bc[1], nx - B.bc[2]));
                     const double2 cc = cmul(gk, make_double2(zr[i], zi[i]));
                     const int v[3] = {nz, ny, nx};
                     const int o0 = R.sgn[0] * v[R.perm[0]];
                     const int o1 = R.sgn[1] * v[R.perm[1]];
                     const int o2 = R.sgn[2] * v[R.perm[2]];
-                    double2 *dst = mypart + idx_I(g, o0, o1, o2);
-                    double2 cur = *dst;
+                    const int64_t o = idx_I(g, o0, o1, o2);
+                    double2 cur = ld2(mypart, o);
                     cur.x += cc.x;
                     cur.y += cc.y;
-                    *dst = cur;
+                    st2(mypart, o, cur);
                 }
             }
         }
@@ -485,8 +501,8 @@ __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_of
 }
 
 void launch_trilinear(const Geo &g, int nslots, const int *slot_off, const T1Item *items, const T1B *bdesc,
-                      const double *K, const double2 *Gr, const Rot *rots, double2 *part, hipStream_t s) {
-    hipLaunchKernelGGL(trilinear_kernel, dim3(nslots), dim3(64), 0, s, g, slot_off, items, bdesc, K, Gr, rots, part);
+                      const double *K, const Inst *D, const Rot *rots, hipStream_t s) {
+    hipLaunchKernelGGL(trilinear_kernel, dim3(nslots), dim3(64), 0, s, g, slot_off, items, bdesc, K, D, rots);
 }
 
 int trilinear_blocks_per_cu() {
@@ -506,53 +522,73 @@ void launch_zero(void *p, int64_t bytes, hipStream_t s) {
     hipLaunchKernelGGL(zero_kernel, dim3(nb), dim3(256), 0, s, (double *)p, n);
 }
 
-__global__ void reduce_partials_kernel(Geo g, int nslots, const double2 *part, double2 *T1) {
+// Partial arrays of the instances that evaluate the trilinear term.
+__global__ void zero_part_kernel(Geo g, const Inst *D, IOs io) {
+    const Inst &I = D[io.inst[blockIdx.z]];
+    if (!(I.terms & 4)) return;
+    const int64_t n = (int64_t)I.nslots * g.nm * 2;
+    const gptr<double> p = glob((double *)I.part);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+void launch_zero_part(const Geo &g, const Inst *D, const IOs &io, int max_slots, hipStream_t s) {
+    const int64_t n = (int64_t)max_slots * g.nm * 2;
+    const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_part_kernel, dim3(nb, 1, (unsigned)io.n), dim3(256), 0, s, g, D, io);
+}
+
+__global__ void reduce_partials_kernel(Geo g, const Inst *D, IOs io) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.nm) return;
+    const Inst &I = D[io.inst[blockIdx.z]];
+    if (i >= g.nm || !(I.terms & 4)) return;
     double re = 0.0, im = 0.0;
-    for (int s = 0; s < nslots; ++s) {
-        const double2 v = part[(int64_t)s * g.nm + i];
+    for (int s = 0; s < I.nslots; ++s) {
+        const double2 v = ld2(I.part, (int64_t)s * g.nm + i);
         re += v.x;
         im += v.y;
     }
-    T1[i] = make_double2(re, im);
+    st2(I.T1, i, make_double2(re, im));
 }
 
-void launch_reduce_partials(const Geo &g, int nslots, const double2 *part, double2 *T1, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((g.nm + 255) / 256)), dim3(256), 0, s, g, nslots, part, T1);
+void launch_reduce_partials(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_partials_kernel, grid_nm(g, io), dim3(256), 0, s, g, D, io);
 }
 
 // Qhat = [Qc] - alpha ([T1] + [X]) with the selected terms; optionally the
 // real part of the n = 0 mode is removed (exact discrete mass conservation).
-__global__ void combine_kernel(Geo g, const double2 *Qc, const double2 *T1, const double2 *X, int terms,
-                               double alpha, int mass_fix, double2 *Qh, double2 *Qh_out) {
+__global__ void combine_kernel(Geo g, const Inst *D, IOs io) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.nm) return;
+    const int z = blockIdx.z;
+    const Inst &I = D[io.inst[z]];
+    const int terms = I.terms;
     double re = 0.0, im = 0.0;
     if (terms & 1) {
-        re = Qc[i].x;
-        im = Qc[i].y;
+        const double2 v = ld2(I.Qc, i);
+        re = v.x;
+        im = v.y;
     }
     double qr = 0.0, qi = 0.0;
     if (terms & 4) {
-        qr += T1[i].x;
-        qi += T1[i].y;
+        const double2 v = ld2(I.T1, i);
+        qr += v.x;
+        qi += v.y;
     }
     if (terms & 2) {
-        qr += X[i].x;
-        qi += X[i].y;
+        const double2 v = ld2(I.X, i);
+        qr += v.x;
+        qi += v.y;
     }
-    re -= alpha * qr;
-    im -= alpha * qi;
-    if (mass_fix && i == idx_I(g, 0, 0, 0)) re = 0.0;
-    Qh[i] = make_double2(re, im);
-    if (Qh_out) Qh_out[i] = make_double2(re, im);
+    re -= I.alpha * qr;
+    im -= I.alpha * qi;
+    if (I.mass_fix && i == idx_I(g, 0, 0, 0)) re = 0.0;
+    st2(I.Qh, i, make_double2(re, im));
+    if (io.qhat[z]) st2(io.qhat[z], i, make_double2(re, im));
 }
 
-void launch_combine(const Geo &g, const double2 *Qc, const double2 *T1, const double2 *X, int terms, double alpha,
-                    int mass_fix, double2 *Qh, double2 *Qh_out, hipStream_t s) {
-    hipLaunchKernelGGL(combine_kernel, dim3((unsigned)((g.nm + 255) / 256)), dim3(256), 0, s, g, Qc, T1, X, terms,
-                       alpha, mass_fix, Qh, Qh_out);
+void launch_combine(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
+    hipLaunchKernelGGL(combine_kernel, grid_nm(g, io), dim3(256), 0, s, g, D, io);
 }
 
 }  // namespace bnq

@@ -14,35 +14,50 @@
 
 namespace bnq {
 
-__global__ void axpy_kernel(int64_t n, const double *x, double a, const double *y, double *out) {
+static dim3 grid_nm(const Geo &g, const IOs &io) { return dim3((unsigned)((g.nm + 255) / 256), 1, (unsigned)io.n); }
+
+// y = in + a dt k[ks], into Inst::ybuf (to_out = 0) or io.out (to_out = 1)
+__global__ void stage_kernel(Geo g, const Inst *D, IOs io, double a, int ks, int to_out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = fma(a, y[i], x[i]);
+    if (i >= g.nm) return;
+    const int z = blockIdx.z;
+    const Inst &I = D[io.inst[z]];
+    const gptr<double> y = glob(to_out ? io.out[z] : I.ybuf);
+    y[i] = fma(a * io.dt[z], glob((const double *)I.k[ks])[i], glob(io.in[z])[i]);
 }
 
-void launch_axpy(int64_t n, const double *x, double a, const double *y, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, x, a, y, out);
+void launch_stage(const Geo &g, const Inst *D, const IOs &io, double a, int ks, int to_out, hipStream_t s) {
+    hipLaunchKernelGGL(stage_kernel, grid_nm(g, io), dim3(256), 0, s, g, D, io, a, ks, to_out);
 }
 
-// f <- f + dt/6 (k1 + 2 k2 + 2 k3 + k4)
-__global__ void rk4_final_kernel(int64_t n, double *f, double dt, const double *k1, const double *k2,
-                                 const double *k3, const double *k4) {
+// f <- f + dt/6 (k1 + 2 k2 + 2 k3 + k4), f = io.out
+__global__ void rk4_final_kernel(Geo g, const Inst *D, IOs io) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) f[i] = f[i] + (dt / 6.0) * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+    if (i >= g.nm) return;
+    const int z = blockIdx.z;
+    const Inst &I = D[io.inst[z]];
+    const gptr<double> f = glob(io.out[z]);
+    const double k0 = glob((const double *)I.k[0])[i], k1 = glob((const double *)I.k[1])[i];
+    const double k2 = glob((const double *)I.k[2])[i], k3 = glob((const double *)I.k[3])[i];
+    f[i] = f[i] + (io.dt[z] / 6.0) * (k0 + 2.0 * k1 + 2.0 * k2 + k3);
 }
 
-void launch_rk4_final(int64_t n, double *f, double dt, const double *k1, const double *k2, const double *k3,
-                      const double *k4, hipStream_t s) {
-    hipLaunchKernelGGL(rk4_final_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, f, dt, k1, k2, k3, k4);
+void launch_rk4_final(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
+    hipLaunchKernelGGL(rk4_final_kernel, grid_nm(g, io), dim3(256), 0, s, g, D, io);
 }
 
-// Shu–Osher SSP-RK2: y = f + dt k1;  f <- (f + y + dt k(y)) / 2
-__global__ void ssprk2_final_kernel(int64_t n, double *f, const double *y, const double *k2, double dt) {
+// Shu–Osher SSP-RK2: y = f + dt k1;  f <- (f + y + dt k(y)) / 2, f = io.out
+__global__ void ssprk2_final_kernel(Geo g, const Inst *D, IOs io) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) f[i] = 0.5 * (f[i] + fma(dt, k2[i], y[i]));
+    if (i >= g.nm) return;
+    const int z = blockIdx.z;
+    const Inst &I = D[io.inst[z]];
+    const gptr<double> f = glob(io.out[z]);
+    f[i] = 0.5 * (f[i] + fma(io.dt[z], glob((const double *)I.k[1])[i], glob((const double *)I.ybuf)[i]));
 }
 
-void launch_ssprk2_final(int64_t n, double *f, const double *y, const double *k2, double dt, hipStream_t s) {
-    hipLaunchKernelGGL(ssprk2_final_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, f, y, k2, dt);
+void launch_ssprk2_final(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
+    hipLaunchKernelGGL(ssprk2_final_kernel, grid_nm(g, io), dim3(256), 0, s, g, D, io);
 }
 
 // fields: 0 sum f, 1-3 sum v f, 4 sum |v|^2 f, 5 sum entropy density,

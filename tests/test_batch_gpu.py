@@ -1,0 +1,114 @@
+"""Batched evaluation (bnq_batch_*): every instance of a batch must give
+bitwise the result its own plan gives alone, eagerly and under HIP-graph
+replay.  The solo path is itself checked against the oracle by
+test_parity_gpu.py, so bitwise equality carries that parity over."""
+import numpy as np
+import pytest
+
+import bnq_inputs as inp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+bnq = pytest.importorskip("paper_2110_13735_amd")
+
+# (d, N, eps, C_phi, hbar): two (d, N, C_phi) groups share tables, one differs
+# only in C_phi (its own group), classical members skip the quantum terms.
+MIX = [
+    (2, 8, +1, 1.0, 1.0),
+    (2, 16, -1, 1.0, 1.0),
+    (2, 16, 0, 1.0, 1.0),
+    (2, 16, +1, 1.0, 0.7),
+    (3, 4, 0, 1.0, 1.0),
+    (3, 6, -1, 1.0, 1.0),
+    (3, 6, +1, 1.0, 0.8),
+    (3, 6, -1, 2.0, 1.0),
+]
+
+
+def _instances(seed0=0):
+    dev = torch.device("cuda:0")
+    plans, fs = [], []
+    for i, (d, N, eps, cphi, hbar) in enumerate(MIX):
+        L = 6.0 if d == 2 else 5.0
+        p = bnq.Params(d=d, N=N, eps=eps, L=L, C_phi=cphi, hbar=hbar)
+        f = inp.gaussian_mixture(d, N, L, seed=seed0 + i)
+        if eps == -1:
+            f = np.minimum(f, 0.9)
+        plans.append(bnq.Plan(p))
+        fs.append(torch.tensor(f, device=dev))
+    return plans, fs
+
+
+def test_batch_collide_bitwise_equals_solo():
+    plans, fs = _instances()
+    solo = []
+    for pl, f in zip(plans, fs):
+        Q = torch.empty_like(f)
+        Qh = torch.empty(f.shape, dtype=torch.complex128, device=f.device)
+        pl.collide(f, Q, Qh)
+        solo.append((Q, Qh))
+    torch.cuda.synchronize()
+    with bnq.Batch(plans, fs) as B:
+        Qs = [torch.full_like(f, np.nan) for f in fs]
+        Qhs = [torch.zeros(f.shape, dtype=torch.complex128, device=f.device) for f in fs]
+        B.collide(Qs, Qhs)
+        torch.cuda.synchronize()
+        for i, ((Q, Qh), Qb, Qhb) in enumerate(zip(solo, Qs, Qhs)):
+            assert torch.equal(Q, Qb), f"instance {i}: Q differs"
+            assert torch.equal(Qh, Qhb), f"instance {i}: Qhat differs"
+
+
+@pytest.mark.parametrize("scheme", [bnq.RK4, bnq.SSPRK2, bnq.EULER])
+def test_batch_step_eager_bitwise_equals_solo(scheme):
+    plans, fs = _instances(seed0=10)
+    ref = [f.clone() for f in fs]
+    dts = [0.01 * (1 + 0.1 * i) for i in range(len(plans))]
+    for pl, f, dt in zip(plans, ref, dts):
+        pl.step(f, dt, scheme)
+    torch.cuda.synchronize()
+    with bnq.Batch(plans, fs) as B:
+        B.step(dts, scheme)
+        torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(ref, fs)):
+        assert torch.equal(a, b), f"instance {i} differs after one step"
+
+
+def test_batch_graph_replays_bitwise():
+    plans, fs = _instances(seed0=20)
+    ref = [f.clone() for f in fs]
+    dt = 0.01
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with bnq.Batch(plans, fs) as B:
+        for rep in range(3):
+            # eager solo reference step, with the program's own work between replays
+            for pl, f in zip(plans, ref):
+                pl.step(f, dt)
+            torch.cuda.synchronize()
+            B.step(dt, bnq.RK4, graph=True, stream=s)
+            s.synchronize()
+            for i, (a, b) in enumerate(zip(ref, fs)):
+                assert torch.equal(a, b), f"replay {rep}, instance {i} differs"
+            _ = (fs[0] * 2.0).sum().item()  # unrelated eager work on the default stream
+        # a new dt recaptures
+        for pl, f in zip(plans, ref):
+            pl.step(f, 2 * dt)
+        torch.cuda.synchronize()
+        B.step(2 * dt, bnq.RK4, graph=True, stream=s)
+        s.synchronize()
+        for i, (a, b) in enumerate(zip(ref, fs)):
+            assert torch.equal(a, b), f"after recapture, instance {i} differs"
+
+
+def test_batch_invalid_uses_raise():
+    plans, fs = _instances(seed0=30)
+    with pytest.raises(bnq.BnqError):
+        bnq.Batch([plans[0], plans[0]], [fs[0], fs[1]])
+    with pytest.raises(bnq.BnqError):
+        bnq.Batch([plans[0], plans[1]], [fs[0], fs[0]])
+    with bnq.Batch(plans[:2], fs[:2]) as B:
+        with pytest.raises(bnq.BnqError):
+            B.step(0.01, bnq.RK4, graph=True, stream=0)  # default stream: no capture
+        with pytest.raises(bnq.BnqError):
+            B.collide([fs[0], torch.empty_like(fs[1])])  # output aliases a state
