@@ -134,6 +134,28 @@ def gaussian_mixture(d: int, N: int, L: float, seed: int, kmin: int = 1, kmax: i
     return f
 
 
+def mixed_instance(d: int, N: int, eps: int, seed: int):
+    """One instance of the mixed batch/serving workloads: a mixture of
+    K ~ U{1..4} isotropic Gaussians (Dirichlet(1) weights, centres uniform in
+    |v| <= 1.5, variances U[0.2, 1], mass 1) on a box sized to the draw,
+    L = (3 + sqrt 2)/2 (max|c| + 4 sqrt(max s)); fermion data (eps = -1) are
+    scaled so that max f < 0.98.  Returns (f, L)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    K = int(rng.integers(1, 5))
+    w = rng.dirichlet(np.ones(K))
+    cs = [_uniform_ball(rng, d, 1.5) for _ in range(K)]
+    ss = [float(rng.uniform(0.2, 1.0)) for _ in range(K)]
+    L = (3.0 + math.sqrt(2.0)) / 2.0 * (max(float(np.linalg.norm(c)) for c in cs) + 4.0 * math.sqrt(max(ss)))
+    v = velocity_grid(d, N, L)
+    g = np.zeros(v.shape[:-1])
+    for wi, c, s in zip(w, cs, ss):
+        g += wi * np.exp(-np.sum((v - c) ** 2, axis=-1) / (2.0 * s)) / (2 * math.pi * s) ** (d / 2)
+    f = _normalise_mass(g, d, N, L, 1.0)
+    if eps == -1 and float(f.max()) >= 0.98:
+        f = f * (0.97 / float(f.max()))
+    return np.ascontiguousarray(f), L
+
+
 def sparse_spectrum(d: int, N: int, seed: int, nmodes: int, amp: float = 1.0):
     """Real grid function with a sparse Fourier spectrum.
 

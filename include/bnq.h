@@ -156,6 +156,20 @@ bnq_status bnq_plan_counts(bnq_plan_t plan, double *counts_host);
 bnq_status bnq_plan_set_timing(bnq_plan_t plan, int32_t enable);
 bnq_status bnq_plan_timing(bnq_plan_t plan, double *ms_host, int64_t *launches_host);
 
+/* Autotuner.  Times the candidate trilinear work distributions of this plan
+ * (slots = resident waves or half of them; items dealt per XCD or over all
+ * slots) on one evaluation of f (device, the plan's layout), reps timed
+ * evaluations each, keeps the fastest for this plan, and records it for the
+ * device and (d, N) so that plans created afterwards in the process start
+ * with it.  ms_host (optional, 4 doubles) receives the mean time per
+ * evaluation of each candidate, choice_host (optional) the chosen index.
+ * Synchronises the stream.  Results stay within the parity tolerance of the
+ * default distribution but may differ from it in the last bits (a different
+ * summation order).  No-op for plans without the trilinear term.
+ * Errors: EINVAL, ENOMEM, EHIP. */
+bnq_status bnq_plan_autotune(bnq_plan_t plan, const double *f, int32_t reps, double *ms_host, int32_t *choice_host,
+                             bnq_stream_t stream);
+
 /* ---- Batches ------------------------------------------------------------
  * Many independent instances of the same problem (the homogeneous equation
  * of section 'Convergence towards a steady state', each with its own plan and

@@ -83,13 +83,14 @@ def lib():
         L.bnq_plan_counts.argtypes = [vp, vp]
         L.bnq_plan_set_timing.argtypes = [vp, i32]
         L.bnq_plan_timing.argtypes = [vp, vp, vp]
+        L.bnq_plan_autotune.argtypes = [vp, vp, i32, vp, vp, vp]
         L.bnq_batch_create.argtypes = [i32, vp, vp, ctypes.POINTER(vp)]
         L.bnq_batch_destroy.argtypes = [vp]
         L.bnq_batch_collide.argtypes = [vp, vp, vp, vp]
         L.bnq_batch_step.argtypes = [vp, vp, i32, i32, vp]
         for fn in ("bnq_plan", "bnq_plan_destroy", "bnq_plan_footprint", "bnq_collide", "bnq_step",
                    "bnq_moments", "bnq_table_lookup", "bnq_plan_counts", "bnq_plan_set_timing",
-                   "bnq_plan_timing", "bnq_batch_create", "bnq_batch_destroy", "bnq_batch_collide",
+                   "bnq_plan_timing", "bnq_plan_autotune", "bnq_batch_create", "bnq_batch_destroy", "bnq_batch_collide",
                    "bnq_batch_step"):
             getattr(L, fn).restype = ctypes.c_int
         L.bnq_status_string.argtypes = [ctypes.c_int]
@@ -183,6 +184,15 @@ class Plan:
         c = np.zeros(4)
         _check(lib().bnq_plan_counts(self._h, c.ctypes.data))
         return {"classical": c[0], "w_pairs": c[1], "outer": c[2], "trilinear": c[3]}
+
+    def autotune(self, f, reps: int = 2, stream=None):
+        """Pick the fastest trilinear work distribution on input f; returns
+        (chosen index, mean ms per evaluation of each candidate)."""
+        ms = np.zeros(4)
+        ch = ctypes.c_int32(-1)
+        _check(lib().bnq_plan_autotune(self._h, _ptr(f), int(reps), ms.ctypes.data, ctypes.byref(ch),
+                                       _stream(stream)))
+        return ch.value, ms
 
     def set_timing(self, enable: bool):
         _check(lib().bnq_plan_set_timing(self._h, 1 if enable else 0))

@@ -368,6 +368,19 @@ void counts_1d(int N, double &c1, double &w1, double &o1, double &t1) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+namespace {
+// Trilinear work distribution: slots = resident waves / slot_div; the items
+// are split into one run per XCD (xcd = 1) or dealt over all slots as one run.
+struct T1Tune {
+    int slot_div = 1;
+    int xcd = 1;
+};
+const T1Tune kTuneCandidates[] = {{1, 1}, {2, 1}, {1, 0}, {2, 0}};
+constexpr int kNumTune = 4;
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, T1Tune> g_tune;  // (device, d, N) -> choice of bnq_plan_autotune
+}  // namespace
+
 struct bnq_plan_s {
     bnq_params p;
     Geo g;
@@ -387,6 +400,7 @@ struct bnq_plan_s {
     T1B *bdesc = nullptr;
     std::vector<T1Item> items_h;  // per-slot item lists (host copy), slot offsets
     std::vector<int> off_h;
+    T1Tune tune;                  // trilinear work distribution
     Inst ih{};                    // workspace pointers and scalars (host copy)
     Inst *inst_d = nullptr;       // device copy, one entry
     double counts[4] = {0, 0, 0, 0};
@@ -402,6 +416,7 @@ struct bnq_plan_s {
 };
 
 struct bnq_batch_s;
+
 
 namespace {
 
@@ -541,8 +556,8 @@ bnq_status build_t1_work(bnq_plan_s *P) {
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const int per_cu = trilinear_blocks_per_cu();
     if (cus <= 0 || per_cu <= 0) return fail(BNQ_EHIP, "trilinear occupancy query failed");
-    const int nx = std::max(1, cus / kCusPerXcd);
-    int ns_want = std::min(kMaxSlots, cus * per_cu);
+    const int nx = P->tune.xcd ? std::max(1, cus / kCusPerXcd) : 1;
+    int ns_want = std::min(kMaxSlots, std::max(1, cus * per_cu / std::max(1, P->tune.slot_div)));
     ns_want = std::max(nx, ns_want - ns_want % nx);
     const int ns = (int)std::max<size_t>(1, std::min<size_t>(ns_want, items.size()));
     std::vector<std::vector<T1Item>> per(ns);
@@ -582,6 +597,25 @@ bnq_status build_t1_work(bnq_plan_s *P) {
         (st = upload(&P->slot_off, off, "trilinear slot offsets")))
         return st;
     return dalloc(&P->part, (size_t)ns * g.nm, "trilinear partial sums");
+}
+
+// Rebuilds the trilinear work lists and partial arrays for P->tune.
+bnq_status rebuild_t1(bnq_plan_s *P, hipStream_t s) {
+    HIPCHK(hipStreamSynchronize(s));
+    hipFree(P->bdesc);
+    hipFree(P->items);
+    hipFree(P->slot_off);
+    hipFree(P->part);
+    P->bdesc = nullptr;
+    P->items = nullptr;
+    P->slot_off = nullptr;
+    P->part = nullptr;
+    bnq_status st = build_t1_work(P);
+    if (st) return st;
+    P->ih.part = P->part;
+    P->ih.nslots = P->nslots;
+    HIPCHK(hipMemcpy(P->inst_d, &P->ih, sizeof(Inst), hipMemcpyHostToDevice));
+    return BNQ_OK;
 }
 
 void destroy_plan(bnq_plan_s *P) {
@@ -867,6 +901,13 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
             destroy_plan(P);
             return st;
         }
+    {
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(std::make_tuple(dev, p->d, p->N));
+        if (it != g_tune.end()) P->tune = it->second;
+    }
     if ((st = build_t1_work(P))) {
         destroy_plan(P);
         return st;
@@ -1026,6 +1067,58 @@ bnq_status bnq_table_lookup(bnq_plan_t P, int32_t table, int64_t n, const int32_
 bnq_status bnq_plan_counts(bnq_plan_t P, double *counts) {
     if (!P || !counts) return fail(BNQ_EINVAL, "NULL argument");
     for (int i = 0; i < 4; ++i) counts[i] = P->counts[i];
+    return BNQ_OK;
+}
+
+bnq_status bnq_plan_autotune(bnq_plan_t P, const double *f, int32_t reps, double *ms_host, int32_t *choice_host,
+                             bnq_stream_t stream) {
+    if (!P || !f) return fail(BNQ_EINVAL, "plan and f must be non-NULL");
+    if (reps < 1) return fail(BNQ_EINVAL, "reps must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    P->last = s;
+    double ms[kNumTune];
+    for (int c = 0; c < kNumTune; ++c) ms[c] = 0.0;
+    int best = 0;
+    if (P->ih.terms & BNQ_T_QTRI) {
+        double *Q = nullptr;
+        bnq_status st;
+        if ((st = dalloc(&Q, (size_t)P->g.nm, "autotune output"))) return st;
+        hipEvent_t a = nullptr, b = nullptr;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            hipFree(Q);
+            if (a) hipEventDestroy(a);
+            return fail(BNQ_EHIP, "event creation failed");
+        }
+        const bool timing = P->timing;
+        P->timing = false;
+        for (int c = 0; c < kNumTune && !st; ++c) {
+            P->tune = kTuneCandidates[c];
+            if ((st = rebuild_t1(P, s))) break;
+            if ((st = bnq_collide(P, f, Q, nullptr, stream))) break;  // warm-up
+            hipEventRecord(a, s);
+            for (int r = 0; r < reps && !st; ++r) st = bnq_collide(P, f, Q, nullptr, stream);
+            hipEventRecord(b, s);
+            if (hipEventSynchronize(b) != hipSuccess) st = fail(BNQ_EHIP, "autotune timing failed");
+            float t = 0;
+            hipEventElapsedTime(&t, a, b);
+            ms[c] = t / reps;
+            if (ms[c] < ms[best]) best = c;
+        }
+        P->timing = timing;
+        hipEventDestroy(a);
+        hipEventDestroy(b);
+        hipFree(Q);
+        if (st) return st;
+        P->tune = kTuneCandidates[best];
+        if ((st = rebuild_t1(P, s))) return st;
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[std::make_tuple(dev, P->p.d, P->p.N)] = P->tune;
+    }
+    if (ms_host)
+        for (int c = 0; c < kNumTune; ++c) ms_host[c] = ms[c];
+    if (choice_host) *choice_host = best;
     return BNQ_OK;
 }
 

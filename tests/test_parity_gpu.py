@@ -309,3 +309,21 @@ def test_invalid_calls_raise():
     with pytest.raises(bnq.BnqError):
         plan.lookup(0, [[0, 0, 9]], [[0, 0, 0]])
     plan.close()
+
+
+def test_autotune_keeps_parity():
+    import torch
+    d, N, eps, L = 3, 10, -1, 6.0
+    f0 = inp.gaussian_mixture(d, N, L, seed=77, fmax=0.9)
+    p = bnq.Params(d=d, N=N, eps=eps, L=L)
+    with bnq.Plan(p) as plan:
+        f = torch.tensor(f0, device="cuda:0")
+        choice, ms = plan.autotune(f, reps=1)
+        assert 0 <= choice < 4 and np.all(ms > 0) and ms[choice] == ms.min()
+        Q = torch.empty_like(f)
+        Qh = torch.empty(f.shape, dtype=torch.complex128, device=f.device)
+        plan.collide(f, Q, Qh)
+        torch.cuda.synchronize()
+        Qr, Qhr, gain, qgain = _oracle_collide(d, N, f0, eps, L)
+        _check(Qh.cpu().numpy(), Qhr, gain)
+        _check(Q.cpu().numpy(), Qr, qgain)
