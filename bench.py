@@ -33,6 +33,7 @@ METRIC = "collision pair-terms/s at N=32^3 (FP32c vs FP64); p50/p99 solve latenc
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trilinear_3d32_fp64_hbm_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_13735_amd", "csrc", "collide.hip")
 PEAK_FP64_VALU = 78.6e12  # MI355X dense FP64 vector, FLOP/s
+PEAK_FP32_VALU = 157.3e12  # MI355X dense FP32 vector, FLOP/s (published; counts packed FP32)
 FLOPS_PER_T1_TERM = 4.0   # one real x complex multiply-add (two FMAs)
 
 
@@ -96,6 +97,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=32)
     ap.add_argument("--dt", type=float, default=0.01)
+    ap.add_argument("--precision", choices=("fp64", "fp32c"), default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-N", type=int, default=10)
     ap.add_argument("--workload", choices=("c2", "batch", "serve"), default="c2",
@@ -128,7 +130,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     N, L, eps = args.N, 8.0, -1
-    p = bnq.Params(d=3, N=N, eps=eps, L=L)
+    prec = bnq.FP32C if args.precision == "fp32c" else bnq.FP64
+    p = bnq.Params(d=3, N=N, eps=eps, L=L, precision=prec)
     f0 = inp.fermion_mixture_3d(N=N, L=L, seed=0)
     t_plan = time.perf_counter()
     plan = bnq.Plan(p)
@@ -163,9 +166,10 @@ def main():
     t1_avg_s = (t1_ms / t1_n) * 1e-3 if t1_n else float("nan")
     flops_launch = counts["trilinear"] * FLOPS_PER_T1_TERM
     achieved = flops_launch / t1_avg_s / 1e12
-    tr = measured_traffic()
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU / 1e12,
-                "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP64_VALU, 4),
+    tr = measured_traffic() if prec == bnq.FP64 else None
+    peak = PEAK_FP32_VALU if prec == bnq.FP32C else PEAK_FP64_VALU
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": round(achieved * 1e12 / peak, 4),
                 "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None,
                 "kernel": "trilinear_kernel", "avg_ms": round(t1_avg_s * 1e3, 3), "launches": t1_n,
                 "flops_per_launch": flops_launch}
@@ -189,11 +193,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32c" if prec == bnq.FP32C else "f64",
         "data": "synthetic",
-        "config": {"workload": f"3-D fermions eps=-1, N={N}^3, FP64, hard spheres, hbar=1, L=8, "
+        "config": {"workload": f"3-D fermions eps=-1, N={N}^3, {args.precision.upper()}, hard spheres, hbar=1, L=8, "
                                f"three-Gaussian f0 (seed 0), RK4 dt={args.dt}, moments every step",
-                   "d": 3, "N": N, "eps": eps, "precision": "fp64", "scheme": "rk4", "dt": args.dt,
+                   "d": 3, "N": N, "eps": eps, "precision": args.precision, "scheme": "rk4", "dt": args.dt,
                    "terms_per_eval": terms_eval, "evals_per_step": 4,
                    "plan_build_s": round(t_plan, 3)},
         "roofline": roofline,

@@ -66,6 +66,7 @@ typedef struct bnq_batch_s *bnq_batch_t;
 #define BNQ_T_ALL 7
 
 #define BNQ_FP64 0
+#define BNQ_FP32C 1 /* FP32 spectra, tables and products; sums combined in FP64 (see bnq_params) */
 
 #define BNQ_CORR_NONE 0 /* the paper's scheme */
 #define BNQ_CORR_MASS 1 /* subtract the mean of Q so that sum_j Q_j = 0 exactly */
@@ -78,7 +79,13 @@ typedef struct {
     int32_t d;          /* 2 or 3 */
     int32_t N;          /* even, 2 <= N <= 64 (3-D FP64 tables need N <= 32) */
     int32_t eps;        /* +1 boson, -1 fermion, 0 classical */
-    int32_t precision;  /* BNQ_FP64 */
+    int32_t precision;  /* BNQ_FP64, or BNQ_FP32C: Ghat, the rotated spectra, the
+                           weight tables and the trilinear rows rounded to FP32
+                           (tables converted from the FP64 ones on first use),
+                           products and short partial sums (<= N pair terms, <= 2
+                           trilinear rows) in FP32, every longer sum in FP64; DFTs,
+                           the outer sum, combination and time stepping stay FP64.
+                           Parity bar against the FP64 oracle: 1e-5. */
     int32_t terms;      /* BNQ_T_* mask, default BNQ_T_ALL */
     int32_t correction; /* BNQ_CORR_* */
     double hbar;        /* default 1 */

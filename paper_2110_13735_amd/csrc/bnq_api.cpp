@@ -158,6 +158,7 @@ struct TableSet {
     int ncanon = 0;
     int *canon_d = nullptr;
     double *K = nullptr, *wc = nullptr, *wq = nullptr;
+    float *K32 = nullptr, *wc32 = nullptr, *wq32 = nullptr;  // FP32c copies, made on first use
     size_t bytes = 0;
     Radial radial() const {
         Radial r;
@@ -216,6 +217,9 @@ void free_tables(TableSet *t) {
     hipFree(t->K);
     hipFree(t->wc);
     hipFree(t->wq);
+    hipFree(t->K32);
+    hipFree(t->wc32);
+    hipFree(t->wq32);
     delete t;
 }
 
@@ -345,6 +349,44 @@ void release_tables(TableSet *t) {
     free_tables(t);
 }
 
+// FP32c copies of the tables (round to nearest), made once per table set.
+size_t table_bytes_f32(int d, int N) {
+    Geo g = make_geo(d, N);
+    std::vector<int> canon, row;
+    canon_list(d, N, canon, row);
+    return sizeof(float) * ((canon.size() / 3) * (size_t)g.nak + 2 * (size_t)g.nm * g.nm);
+}
+
+bnq_status ensure_f32(TableSet *t, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (t->K32) return BNQ_OK;
+    const size_t nk = (size_t)t->ncanon * t->g.nak, nw = (size_t)t->g.nm * t->g.nm;
+    float *K32 = nullptr, *wc32 = nullptr, *wq32 = nullptr;
+    bnq_status st;
+    if ((st = dalloc(&K32, nk, "FP32 trilinear table")) || (st = dalloc(&wc32, nw, "FP32 weights")) ||
+        (st = dalloc(&wq32, nw, "FP32 weights"))) {
+        hipFree(K32);
+        hipFree(wc32);
+        return st;
+    }
+    launch_to_f32(t->K, K32, (int64_t)nk, s);
+    launch_to_f32(t->wc, wc32, (int64_t)nw, s);
+    launch_to_f32(t->wq, wq32, (int64_t)nw, s);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        hipFree(K32);
+        hipFree(wc32);
+        hipFree(wq32);
+        return fail(BNQ_EHIP, "FP32 table conversion failed: %s", hipGetErrorString(e));
+    }
+    t->K32 = K32;
+    t->wc32 = wc32;
+    t->wq32 = wq32;
+    t->bytes += sizeof(float) * (nk + 2 * nw);
+    return BNQ_OK;
+}
+
 // ---------------------------------------------------------------------------
 // 1-D counts of the Galerkin sums (per axis; a d-D count is the d-th power).
 void counts_1d(int N, double &c1, double &w1, double &o1, double &t1) {
@@ -391,6 +433,7 @@ struct bnq_plan_s {
     double2 *tw = nullptr;
     double2 *Ghat = nullptr, *tmp = nullptr, *tmp2 = nullptr, *Gr = nullptr, *W = nullptr, *Qc = nullptr,
             *T1 = nullptr, *X = nullptr, *Qh = nullptr, *part = nullptr;
+    float2 *G32 = nullptr, *Gr32 = nullptr;  // FP32c spectra
     int nbdesc = 0;
     double *kbuf[4] = {nullptr, nullptr, nullptr, nullptr}, *ybuf = nullptr;
     double *mom_part = nullptr, *mom_out = nullptr;
@@ -462,7 +505,8 @@ bnq_status validate(const bnq_params *p) {
     if (p->eps < -1 || p->eps > 1) return fail(BNQ_EINVAL, "eps must be -1, 0 or 1 (got %d)", p->eps);
     if (!(p->L > 0) || !std::isfinite(p->L)) return fail(BNQ_EINVAL, "L must be positive");
     if (!(p->hbar > 0) || !(p->C_phi > 0) || !(p->c >= 0)) return fail(BNQ_EINVAL, "hbar, C_phi must be > 0, c >= 0");
-    if (p->precision != BNQ_FP64) return fail(BNQ_ENOTSUP, "only BNQ_FP64 is implemented");
+    if (p->precision != BNQ_FP64 && p->precision != BNQ_FP32C)
+        return fail(BNQ_EINVAL, "precision must be BNQ_FP64 or BNQ_FP32C (got %d)", p->precision);
     if (p->terms < 0 || p->terms > BNQ_T_ALL) return fail(BNQ_EINVAL, "bad terms mask %d", p->terms);
     if (p->correction != BNQ_CORR_NONE && p->correction != BNQ_CORR_MASS)
         return fail(BNQ_EINVAL, "bad correction %d", p->correction);
@@ -473,8 +517,9 @@ size_t plan_workspace_bytes(const bnq_params *p, int nslots_est) {
     Geo g = make_geo(p->d, p->N);
     const size_t c = sizeof(double2), r = sizeof(double);
     const size_t nrot = p->d == 3 ? 48 : 8;
+    const size_t f32 = p->precision == BNQ_FP32C ? sizeof(float2) * ((size_t)g.nm + nrot * g.next) : 0;
     return c * (6 * (size_t)g.nm + g.neg + nrot * g.next + (size_t)nslots_est * g.nm) +
-           r * 5 * (size_t)g.nm;
+           r * 5 * (size_t)g.nm + f32;
 }
 
 bnq_status build_t1_work(bnq_plan_s *P) {
@@ -554,7 +599,7 @@ bnq_status build_t1_work(bnq_plan_s *P) {
     int dev = 0, cus = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int per_cu = trilinear_blocks_per_cu();
+    const int per_cu = trilinear_blocks_per_cu(P->p.precision == BNQ_FP32C ? 1 : 0);
     if (cus <= 0 || per_cu <= 0) return fail(BNQ_EHIP, "trilinear occupancy query failed");
     const int nx = P->tune.xcd ? std::max(1, cus / kCusPerXcd) : 1;
     int ns_want = std::min(kMaxSlots, std::max(1, cus * per_cu / std::max(1, P->tune.slot_div)));
@@ -632,6 +677,8 @@ void destroy_plan(bnq_plan_s *P) {
     hipFree(P->X);
     hipFree(P->Qh);
     hipFree(P->part);
+    hipFree(P->G32);
+    hipFree(P->Gr32);
     for (double *k : P->kbuf) hipFree(k);
     hipFree(P->ybuf);
     hipFree(P->mom_part);
@@ -664,6 +711,7 @@ struct Exec {
     const T1Item *items = nullptr;
     const T1B *bdesc = nullptr;
     const Inst *D = nullptr;
+    int prec = 0;               // 0 FP64, 1 FP32c
     std::vector<Inst> Dh;       // host copies of D
     bnq_plan_s *timer = nullptr;  // plan whose timing spans record this run
 };
@@ -680,6 +728,7 @@ Exec exec_of(bnq_plan_s *P) {
     E.items = P->items;
     E.bdesc = P->bdesc;
     E.D = P->inst_d;
+    E.prec = P->p.precision == BNQ_FP32C ? 1 : 0;
     E.Dh.assign(1, P->ih);
     E.timer = P;
     return E;
@@ -715,12 +764,17 @@ bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s
         for (const IOs &io : ios) {
             launch_dft_forward_real(g, E.D, io, E.tw, s);
             LAUNCHCHK();
+            if (E.prec) {
+                launch_spectrum_f32(g, E.D, io, s);
+                LAUNCHCHK();
+            }
         }
     }
     if (any & (BNQ_T_CLASSICAL | BNQ_T_QMULT)) {
         Span sp(E.timer, 1, s);
         for (const IOs &io : ios) {
-            launch_pairs(g, E.D, io, E.t->wc, E.t->wq, s);
+            launch_pairs(g, E.prec, E.D, io, E.prec ? (const void *)E.t->wc32 : (const void *)E.t->wc,
+                         E.prec ? (const void *)E.t->wq32 : (const void *)E.t->wq, s);
             LAUNCHCHK();
         }
     }
@@ -735,7 +789,7 @@ bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s
         {
             Span sp(E.timer, 4, s);
             for (const IOs &io : ios) {
-                launch_rotate(g, E.D, io, E.rots, E.nrot, s);
+                launch_rotate(g, E.prec, E.D, io, E.rots, E.nrot, s);
                 LAUNCHCHK();
                 launch_zero_part(g, E.D, io, max_slots, s);
                 LAUNCHCHK();
@@ -743,7 +797,8 @@ bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s
         }
         {
             Span sp(E.timer, 3, s);
-            launch_trilinear(g, E.nslots, E.slot_off, E.items, E.bdesc, E.t->K, E.D, E.rots, s);
+            launch_trilinear(g, E.prec, E.nslots, E.slot_off, E.items, E.bdesc,
+                             E.prec ? (const void *)E.t->K32 : (const void *)E.t->K, E.D, E.rots, s);
             LAUNCHCHK();
         }
         {
@@ -850,12 +905,14 @@ bnq_status bnq_plan_footprint(const bnq_params *p, size_t *plan_bytes, size_t *t
     if (st) return st;
     if (plan_bytes) *plan_bytes = plan_workspace_bytes(p, kMaxSlots);
     if (table_bytes_out) {
-        size_t tb = table_bytes(p->d, p->N);
+        const bool f32 = p->precision == BNQ_FP32C;
+        size_t tb = table_bytes(p->d, p->N) + (f32 ? table_bytes_f32(p->d, p->N) : 0);
         std::lock_guard<std::mutex> lk(g_cache_mu);
         int dev = 0;
         hipGetDevice(&dev);
         for (TableSet *t : g_cache)
-            if (t->d == p->d && t->N == p->N && t->Cphi == p->C_phi && t->device == dev) tb = 0;
+            if (t->d == p->d && t->N == p->N && t->Cphi == p->C_phi && t->device == dev)
+                tb = (f32 && !t->K32) ? table_bytes_f32(p->d, p->N) : 0;
         *table_bytes_out = tb;
     }
     return BNQ_OK;
@@ -901,6 +958,12 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
             destroy_plan(P);
             return st;
         }
+    if (p->precision == BNQ_FP32C &&
+        ((st = ensure_f32(P->tabs, s)) || (st = dalloc(&P->G32, nm, "FP32 spectrum")) ||
+         (st = dalloc(&P->Gr32, P->grp.size() * (size_t)g.next, "FP32 rotated spectra")))) {
+        destroy_plan(P);
+        return st;
+    }
     {
         int dev = 0;
         HIPCHK(hipGetDevice(&dev));
@@ -924,6 +987,8 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         I.X = P->X;
         I.Qh = P->Qh;
         I.part = P->part;
+        I.G32 = P->G32;
+        I.Gr32 = P->Gr32;
         I.ybuf = P->ybuf;
         for (int k = 0; k < 4; ++k) I.k[k] = P->kbuf[k];
         I.alpha = P->alpha;
@@ -1234,11 +1299,12 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
     bnq_batch_s *B = new bnq_batch_s;
     B->plans.assign(plans, plans + n);
     B->f.assign(f, f + n);
-    std::map<const TableSet *, int> gidx;
+    std::map<std::pair<const TableSet *, int>, int> gidx;
     for (int i = 0; i < n; ++i) {
-        auto it = gidx.find(plans[i]->tabs);
+        const auto key = std::make_pair((const TableSet *)plans[i]->tabs, (int)plans[i]->p.precision);
+        auto it = gidx.find(key);
         if (it == gidx.end()) {
-            gidx[plans[i]->tabs] = (int)B->groups.size();
+            gidx[key] = (int)B->groups.size();
             B->groups.emplace_back();
             B->groups.back().members.push_back(i);
         } else {

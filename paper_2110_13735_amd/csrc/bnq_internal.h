@@ -109,6 +109,17 @@ __device__ __forceinline__ double2 ld2(const double2 *p, int64_t i) {
     const dvec2 v = ((gptr<const dvec2>)p)[i];
     return make_double2(v.x, v.y);
 }
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld2f(const float2 *p, int64_t i) {
+    const fvec2 v = ((gptr<const fvec2>)p)[i];
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st2f(float2 *p, int64_t i, float2 a) {
+    fvec2 v;
+    v.x = a.x;
+    v.y = a.y;
+    ((gptr<fvec2>)p)[i] = v;
+}
 __device__ __forceinline__ void st2(double2 *p, int64_t i, double2 a) {
     dvec2 v;
     v.x = a.x;
@@ -125,6 +136,7 @@ constexpr int BNQ_MAXB = 64;  // instances per launch
 // Workspace of one instance (device memory, fixed for the plan's lifetime).
 struct Inst {
     double2 *Ghat, *tmp, *tmp2, *Gr, *W, *Qc, *T1, *X, *Qh, *part;
+    float2 *G32, *Gr32;  // FP32c: rounded spectrum and rotated spectra
     double *ybuf, *k[4];
     double alpha;  // -eps hbar^d
     double pref;   // c (L/pi)^(d+gamma)
@@ -160,13 +172,18 @@ void launch_gather(const double *base, const int64_t *idx, int64_t n, double *ou
 // (inverse, real part, scale Inst::pref).
 void launch_dft_forward_real(const Geo &g, const Inst *D, const IOs &io, const double2 *tw, hipStream_t s);
 void launch_inverse_real(const Geo &g, const Inst *D, const IOs &io, const double2 *tw, hipStream_t s);
-void launch_rotate(const Geo &g, const Inst *D, const IOs &io, const Rot *rots, int nrot, hipStream_t s);
-void launch_pairs(const Geo &g, const Inst *D, const IOs &io, const double *wc, const double *wq, hipStream_t s);
+// prec 0: FP64; 1: FP32c (spectra and tables rounded to FP32, sums combined in FP64)
+void launch_spectrum_f32(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
+void launch_rotate(const Geo &g, int prec, const Inst *D, const IOs &io, const Rot *rots, int nrot, hipStream_t s);
+void launch_pairs(const Geo &g, int prec, const Inst *D, const IOs &io, const void *wc, const void *wq,
+                  hipStream_t s);
+void launch_to_f32(const double *in, float *out, int64_t n, hipStream_t s);
 void launch_outer(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 void launch_zero_part(const Geo &g, const Inst *D, const IOs &io, int max_slots, hipStream_t s);
-void launch_trilinear(const Geo &g, int nslots, const int *slot_off, const T1Item *items, const T1B *bdesc,
-                      const double *K, const Inst *D, const Rot *rots, hipStream_t s);
-int trilinear_blocks_per_cu();  // resident 64-lane trilinear workgroups per CU (0 on error)
+// prec 0: FP64 (K is double), 1: FP32c (K is float, spectra Inst::Gr32)
+void launch_trilinear(const Geo &g, int prec, int nslots, const int *slot_off, const T1Item *items,
+                      const T1B *bdesc, const void *K, const Inst *D, const Rot *rots, hipStream_t s);
+int trilinear_blocks_per_cu(int prec);  // resident 64-lane trilinear workgroups per CU (0 on error)
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_reduce_partials(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 void launch_combine(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);

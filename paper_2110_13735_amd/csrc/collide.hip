@@ -40,6 +40,25 @@ __device__ __forceinline__ const void *sel_ptr(const Inst &I, const IOs &io, int
     }
 }
 
+template <typename T>
+struct V2;
+template <>
+struct V2<double> {
+    using type = double2;
+};
+template <>
+struct V2<float> {
+    using type = float2;
+};
+
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double2 cmulT(double2 a, double2 b) { return cmul(a, b); }
+__device__ __forceinline__ float2 cmulT(float2 a, float2 b) { return cmulf(a, b); }
+__device__ __forceinline__ double2 ldT2(const double2 *p, int64_t i) { return ld2(p, i); }
+__device__ __forceinline__ float2 ldT2(const float2 *p, int64_t i) { return ld2f(p, i); }
+
 // ---------------------------------------------------------------------------
 // DFT along one axis.  in/out are [e0][N][N] (axis 0 extent e0); the axis
 // `ax` has extent N.  tw[t] = exp(-2 pi i t / N); sign = -1 forward, +1 inverse.
@@ -107,7 +126,7 @@ void launch_inverse_real(const Geo &g, const Inst *D, const IOs &io, const doubl
 // ---------------------------------------------------------------------------
 // Rotated spectra: Gr[r][q] = G(R_r q) if R_r q in I_N, else 0, q in Ext.
 // Only instances that evaluate the trilinear term.
-__global__ void rotate_kernel(Geo g, const Inst *D, IOs io, const Rot *rots) {
+__global__ void rotate_kernel(Geo g, const Inst *D, IOs io, const Rot *rots, int prec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     const Inst &I = D[io.inst[blockIdx.z]];
@@ -122,12 +141,31 @@ __global__ void rotate_kernel(Geo g, const Inst *D, IOs io, const Rot *rots) {
     for (int a = 0; a < 3; ++a) y[a] = R.sgn[a] * q[R.perm[a]];
     const bool in = y[1] >= -g.h && y[1] < g.h && y[2] >= -g.h && y[2] < g.h &&
                     (g.d == 2 ? y[0] == 0 : (y[0] >= -g.h && y[0] < g.h));
-    st2(I.Gr, (int64_t)r * g.next + i, in ? ld2(I.Ghat, idx_I(g, y[0], y[1], y[2])) : make_double2(0.0, 0.0));
+    const int64_t o = (int64_t)r * g.next + i;
+    if (prec == 0) {
+        st2(I.Gr, o, in ? ld2(I.Ghat, idx_I(g, y[0], y[1], y[2])) : make_double2(0.0, 0.0));
+    } else {
+        const float2 v = in ? ld2f(I.G32, idx_I(g, y[0], y[1], y[2])) : make_float2(0.0f, 0.0f);
+        st2f(I.Gr32, o, v);
+    }
 }
 
-void launch_rotate(const Geo &g, const Inst *D, const IOs &io, const Rot *rots, int nrot, hipStream_t s) {
+void launch_rotate(const Geo &g, int prec, const Inst *D, const IOs &io, const Rot *rots, int nrot, hipStream_t s) {
     dim3 grid((unsigned)((g.next + 255) / 256), (unsigned)nrot, (unsigned)io.n);
-    hipLaunchKernelGGL(rotate_kernel, grid, dim3(256), 0, s, g, D, io, rots);
+    hipLaunchKernelGGL(rotate_kernel, grid, dim3(256), 0, s, g, D, io, rots, prec);
+}
+
+// FP32c: the spectrum rounded to FP32 (round to nearest).
+__global__ void spectrum_f32_kernel(Geo g, const Inst *D, IOs io) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.nm) return;
+    const Inst &I = D[io.inst[blockIdx.z]];
+    const double2 v = ld2(I.Ghat, i);
+    st2f(I.G32, i, make_float2((float)v.x, (float)v.y));
+}
+
+void launch_spectrum_f32(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
+    hipLaunchKernelGGL(spectrum_f32_kernel, grid_nm(g, io), dim3(256), 0, s, g, D, io);
 }
 
 // ---------------------------------------------------------------------------
@@ -137,12 +175,17 @@ void launch_rotate(const Geo &g, const Inst *D, const IOs &io, const Rot *rots, 
 // the weight rows wq[l][s - l] are read as contiguous runs.  Loads are
 // branch-free (indices clamped into range, invalid terms weighted by zero)
 // and the innermost loop is unrolled so that many table loads are in flight.
-__global__ __launch_bounds__(256) void pairs_kernel(Geo g, const Inst *D, IOs io, const double *wc,
-                                                    const double *wq) {
+template <typename T>
+__global__ __launch_bounds__(256) void pairs_kernel(Geo g, const Inst *D, IOs io, const T *wc, const T *wq) {
     const Inst &I = D[io.inst[blockIdx.z]];
     const int want_c = (I.terms & 1) != 0, want_w = (I.terms & 2) != 0;
     if (!want_c && !want_w) return;
-    const double2 *G = I.Ghat;
+    using T2 = typename V2<T>::type;
+    const T2 *G;
+    if constexpr (sizeof(T) == 8)
+        G = I.Ghat;
+    else
+        G = I.G32;
     const int N = g.N, h = g.h;
     const int rows = 256 / (2 * N);  // s1 rows per workgroup
     const int tid = threadIdx.x;
@@ -166,6 +209,9 @@ __global__ __launch_bounds__(256) void pairs_kernel(Geo g, const Inst *D, IOs io
             const int m1c = min(max(m1, -h), h - 1);
             const int64_t il0 = idx_I(g, l0, l1, -h);
             const int64_t im0 = idx_I(g, m0, m1c, 0);
+            // FP64: every term goes straight into the FP64 sums.  FP32c: the
+            // N terms of one l-row are summed in FP32, the row sums in FP64.
+            T wr = 0, wi = 0, cr = 0, ci = 0;
 #pragma unroll 8
             for (int j = 0; j < N; ++j) {
                 const int l2 = j - h;
@@ -173,17 +219,30 @@ __global__ __launch_bounds__(256) void pairs_kernel(Geo g, const Inst *D, IOs io
                 const bool ok = ok1 && m2 >= -h && m2 < h;
                 const int m2c = min(max(m2, -h), h - 1);
                 const int64_t il = il0 + j, im = im0 + m2c;
-                const double2 gl = ld2(G, il);
-                const double2 gm = ld2(G, im);
+                const T2 gl = ldT2(G, il);
+                const T2 gm = ldT2(G, im);
                 const int64_t o = il * g.nm + im;
-                const double w1 = want_w ? wq[o] : 0.0;
-                const double w2 = do_c ? wc[o] : 0.0;
-                const double2 p = cmul(gl, gm);
-                const double a1 = ok ? w1 : 0.0, a2 = ok ? w2 : 0.0;
-                accw.x = fma(a1, p.x, accw.x);
-                accw.y = fma(a1, p.y, accw.y);
-                accc.x = fma(a2, p.x, accc.x);
-                accc.y = fma(a2, p.y, accc.y);
+                const T w1 = want_w ? wq[o] : (T)0;
+                const T w2 = do_c ? wc[o] : (T)0;
+                const T2 p = cmulT(gl, gm);
+                const T a1 = ok ? w1 : (T)0, a2 = ok ? w2 : (T)0;
+                if constexpr (sizeof(T) == 8) {
+                    accw.x = fma(a1, p.x, accw.x);
+                    accw.y = fma(a1, p.y, accw.y);
+                    accc.x = fma(a2, p.x, accc.x);
+                    accc.y = fma(a2, p.y, accc.y);
+                } else {
+                    wr = fmaf(a1, p.x, wr);
+                    wi = fmaf(a1, p.y, wi);
+                    cr = fmaf(a2, p.x, cr);
+                    ci = fmaf(a2, p.y, ci);
+                }
+            }
+            if constexpr (sizeof(T) == 4) {
+                accw.x += wr;
+                accw.y += wi;
+                accc.x += cr;
+                accc.y += ci;
             }
         }
     }
@@ -192,11 +251,17 @@ __global__ __launch_bounds__(256) void pairs_kernel(Geo g, const Inst *D, IOs io
     if (do_c) st2(I.Qc, idx_I(g, s0, s1, s2), accc);
 }
 
-void launch_pairs(const Geo &g, const Inst *D, const IOs &io, const double *wc, const double *wq, hipStream_t s) {
+void launch_pairs(const Geo &g, int prec, const Inst *D, const IOs &io, const void *wc, const void *wq,
+                  hipStream_t s) {
     const int N = g.N;
     const int rows = 256 / (2 * N);
     dim3 grid((unsigned)((2 * N + rows - 1) / rows), (unsigned)(g.d == 3 ? 2 * N : 1), (unsigned)io.n);
-    hipLaunchKernelGGL(pairs_kernel, grid, dim3(256), 0, s, g, D, io, wc, wq);
+    if (prec == 0)
+        hipLaunchKernelGGL(pairs_kernel<double>, grid, dim3(256), 0, s, g, D, io, (const double *)wc,
+                           (const double *)wq);
+    else
+        hipLaunchKernelGGL(pairs_kernel<float>, grid, dim3(256), 0, s, g, D, io, (const float *)wc,
+                           (const float *)wq);
 }
 
 // ---------------------------------------------------------------------------
@@ -250,44 +315,49 @@ void launch_outer(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
 // the next row's are formed (one p_x per lane, from the rotated spectrum)
 // while the current row computes, then written to a two-row LDS ring and read
 // as broadcasts.
+template <typename T>
 struct T1Ctx {
-    __amdgpu_buffer_rsrc_t kr;  // canonical kernel-mode row
-    int voff;                   // byte offset of K(a_x = base) at this row's (a_z, a_y)
-    int sA;                     // bytes between consecutive a_x
-    const double2 *ps;          // LDS: pair products of the current row
+    __amdgpu_buffer_rsrc_t kr;         // canonical kernel-mode row
+    int voff;                          // byte offset of K(a_x = base) at this row's (a_z, a_y)
+    int sA;                            // bytes between consecutive a_x
+    const typename V2<T>::type *ps;    // LDS: pair products of the current row
 };
 
-__device__ __forceinline__ double t1_kload(const T1Ctx &c, int voff, int s) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(c.kr, voff, s * c.sA, 0));
+template <typename T>
+__device__ __forceinline__ T t1_kload(const T1Ctx<T> &c, int voff, int s) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(c.kr, voff, s * c.sA, 0));
+    else
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(c.kr, voff, s * c.sA, 0));
 }
 
-template <int K>
-__device__ __forceinline__ void t1_full(const T1Ctx &c, double (&lo)[8], double (&hi)[8], double (&nx)[8],
-                                        double (&zr)[T1_RB], double (&zi)[T1_RB]) {
+template <typename T, int K>
+__device__ __forceinline__ void t1_full(const T1Ctx<T> &c, T (&lo)[8], T (&hi)[8], T (&nx)[8], T (&zr)[T1_RB],
+                                        T (&zi)[T1_RB]) {
     const int vq = c.voff - (8 * (K + 1) + 8) * c.sA;
 #pragma unroll
     for (int s = 0; s < 8; ++s) nx[s] = t1_kload(c, vq, s);
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj) {
-        const double2 p = c.ps[8 * K + jj];
+        const auto p = c.ps[8 * K + jj];
 #pragma unroll
         for (int i = 0; i < T1_RB; ++i) {
-            const double k = (i - jj < 0) ? lo[i - jj + 8] : hi[i - jj];
+            const T k = (i - jj < 0) ? lo[i - jj + 8] : hi[i - jj];
             zr[i] = fma(k, p.x, zr[i]);
             zi[i] = fma(k, p.y, zi[i]);
         }
     }
 }
 
-template <int R>
-__device__ __forceinline__ void t1_tail_n(const T1Ctx &c, int u0, const double (&lo)[8], const double (&hi)[8],
-                                          double (&zr)[T1_RB], double (&zi)[T1_RB]) {
+template <typename T, int R>
+__device__ __forceinline__ void t1_tail_n(const T1Ctx<T> &c, int u0, const T (&lo)[8], const T (&hi)[8],
+                                          T (&zr)[T1_RB], T (&zi)[T1_RB]) {
 #pragma unroll
     for (int jj = 0; jj < R; ++jj) {
-        const double2 p = c.ps[u0 + jj];
+        const auto p = c.ps[u0 + jj];
 #pragma unroll
         for (int i = 0; i < T1_RB; ++i) {
-            const double k = (i - jj < 0) ? lo[i - jj + 8] : hi[i - jj];
+            const T k = (i - jj < 0) ? lo[i - jj + 8] : hi[i - jj];
             zr[i] = fma(k, p.x, zr[i]);
             zi[i] = fma(k, p.y, zi[i]);
         }
@@ -295,40 +365,41 @@ __device__ __forceinline__ void t1_tail_n(const T1Ctx &c, int u0, const double (
 }
 
 // The last rem (< 8) inner values of a row, straight-line code per rem.
-__device__ __forceinline__ void t1_tail(const T1Ctx &c, int u0, int rem, const double (&lo)[8],
-                                        const double (&hi)[8], double (&zr)[T1_RB], double (&zi)[T1_RB]) {
+template <typename T>
+__device__ __forceinline__ void t1_tail(const T1Ctx<T> &c, int u0, int rem, const T (&lo)[8], const T (&hi)[8],
+                                        T (&zr)[T1_RB], T (&zi)[T1_RB]) {
     switch (rem) {
-        case 1: t1_tail_n<1>(c, u0, lo, hi, zr, zi); break;
-        case 2: t1_tail_n<2>(c, u0, lo, hi, zr, zi); break;
-        case 3: t1_tail_n<3>(c, u0, lo, hi, zr, zi); break;
-        case 4: t1_tail_n<4>(c, u0, lo, hi, zr, zi); break;
-        case 5: t1_tail_n<5>(c, u0, lo, hi, zr, zi); break;
-        case 6: t1_tail_n<6>(c, u0, lo, hi, zr, zi); break;
-        case 7: t1_tail_n<7>(c, u0, lo, hi, zr, zi); break;
+        case 1: t1_tail_n<T, 1>(c, u0, lo, hi, zr, zi); break;
+        case 2: t1_tail_n<T, 2>(c, u0, lo, hi, zr, zi); break;
+        case 3: t1_tail_n<T, 3>(c, u0, lo, hi, zr, zi); break;
+        case 4: t1_tail_n<T, 4>(c, u0, lo, hi, zr, zi); break;
+        case 5: t1_tail_n<T, 5>(c, u0, lo, hi, zr, zi); break;
+        case 6: t1_tail_n<T, 6>(c, u0, lo, hi, zr, zi); break;
+        case 7: t1_tail_n<T, 7>(c, u0, lo, hi, zr, zi); break;
         default: break;
     }
 }
 
 // Blocks K .. NF-1 of a row, ring slots (S0, S1, S2) = (lo_0, hi_0, spare),
 // then the tail.  Slot of lo_k: 0,2,1,...; hi_k: 1,0,2,...; prefetch: 2,1,0,...
-template <int NF, int K>
-__device__ __forceinline__ void t1_blocks(const T1Ctx &c, int rem, double (&S0)[8], double (&S1)[8],
-                                          double (&S2)[8], double (&zr)[T1_RB], double (&zi)[T1_RB]) {
+template <typename T, int NF, int K>
+__device__ __forceinline__ void t1_blocks(const T1Ctx<T> &c, int rem, T (&S0)[8], T (&S1)[8], T (&S2)[8],
+                                          T (&zr)[T1_RB], T (&zi)[T1_RB]) {
     if constexpr (K < NF) {
         if constexpr (K % 3 == 0)
-            t1_full<K>(c, S0, S1, S2, zr, zi);
+            t1_full<T, K>(c, S0, S1, S2, zr, zi);
         else if constexpr (K % 3 == 1)
-            t1_full<K>(c, S2, S0, S1, zr, zi);
+            t1_full<T, K>(c, S2, S0, S1, zr, zi);
         else
-            t1_full<K>(c, S1, S2, S0, zr, zi);
-        t1_blocks<NF, K + 1>(c, rem, S0, S1, S2, zr, zi);
+            t1_full<T, K>(c, S1, S2, S0, zr, zi);
+        t1_blocks<T, NF, K + 1>(c, rem, S0, S1, S2, zr, zi);
     } else {
         if constexpr (K % 3 == 0)
-            t1_tail(c, 8 * K, rem, S0, S1, zr, zi);
+            t1_tail<T>(c, 8 * K, rem, S0, S1, zr, zi);
         else if constexpr (K % 3 == 1)
-            t1_tail(c, 8 * K, rem, S2, S0, zr, zi);
+            t1_tail<T>(c, 8 * K, rem, S2, S0, zr, zi);
         else
-            t1_tail(c, 8 * K, rem, S1, S2, zr, zi);
+            t1_tail<T>(c, 8 * K, rem, S1, S2, zr, zi);
     }
 }
 
@@ -348,17 +419,19 @@ struct T1Rows {
 
 // Pair products P_b(p) = G_R(p) G_R(b_c - p) of the inner window, formed on
 // the fly from the rotated spectrum (one lane per p_x of a row).
+template <typename T>
 struct T1Pairs {
-    const double2 *G;  // rotated spectrum G_R on {-N/2 .. N/2}^d
-    int X, h, d3;      // N + 1, N / 2, d == 3
-    int px, qx;        // storage x-indices of p_x and b_c,x - p_x for this lane
-    int bz, by;        // b_c,z and b_c,y
-    int pzlo, pylo;    // inner window start
-    __device__ __forceinline__ double2 at(int pzi, int pyi) const {
+    using T2 = typename V2<T>::type;
+    const T2 *G;     // rotated spectrum G_R on {-N/2 .. N/2}^d
+    int X, h, d3;    // N + 1, N / 2, d == 3
+    int px, qx;      // storage x-indices of p_x and b_c,x - p_x for this lane
+    int bz, by;      // b_c,z and b_c,y
+    int pzlo, pylo;  // inner window start
+    __device__ __forceinline__ T2 at(int pzi, int pyi) const {
         const int pz = pzlo + pzi, py = pylo + pyi;
         const int64_t ip = ((int64_t)(d3 ? pz + h : 0) * X + (py + h)) * X + px;
         const int64_t iq = ((int64_t)(d3 ? bz - pz + h : 0) * X + (by - py + h)) * X + qx;
-        return cmul(ld2(G, ip), ld2(G, iq));
+        return cmulT(ldT2(G, ip), ldT2(G, iq));
     }
 };
 
@@ -367,17 +440,17 @@ struct T1Pairs {
 // fetched.  Past the last row the fetches repeat the last row's addresses and
 // the staged pair products are zero, so that rows can run in pairs without
 // branches (an odd row count ends with one row that adds nothing).
-template <int NF>
-__device__ __forceinline__ void t1_row(T1Ctx &c, T1Rows &rw, int row, int nrows, int wpx, int lane,
-                                       const T1Pairs &pr, double2 (*ps)[64], int cur,
-                                       double (&lo0)[8], double (&hi0)[8], double (&nl)[8], double (&nh)[8],
-                                       double (&sp)[8], double (&zr)[T1_RB], double (&zi)[T1_RB]) {
+template <typename T, int NF>
+__device__ __forceinline__ void t1_row(T1Ctx<T> &c, T1Rows &rw, int row, int nrows, int wpx, int lane,
+                                       const T1Pairs<T> &pr, typename V2<T>::type (*ps)[64], int cur, T (&lo0)[8],
+                                       T (&hi0)[8], T (&nl)[8], T (&nh)[8], T (&sp)[8], T (&zr)[T1_RB],
+                                       T (&zi)[T1_RB]) {
     const bool more = row + 1 < nrows;
     const int vn = more ? rw.next() : rw.voff;
     const bool wrap = rw.py + 1 >= rw.wpy;
     const int npy = more ? (wrap ? 0 : rw.py + 1) : rw.py;
     const int npz = more && wrap ? rw.pz + 1 : rw.pz;
-    const double2 pn = pr.at(npz, npy);
+    const auto pn = pr.at(npz, npy);
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         nl[s] = t1_kload(c, vn - 8 * c.sA, s);
@@ -385,39 +458,72 @@ __device__ __forceinline__ void t1_row(T1Ctx &c, T1Rows &rw, int row, int nrows,
     }
     c.voff = rw.voff;
     c.ps = ps[cur];
-    t1_blocks<NF, 0>(c, wpx - 8 * NF, lo0, hi0, sp, zr, zi);
+    t1_blocks<T, NF, 0>(c, wpx - 8 * NF, lo0, hi0, sp, zr, zi);
     __syncthreads();
     const bool keep = more && lane < wpx;
-    ps[cur ^ 1][lane] = make_double2(keep ? pn.x : 0.0, keep ? pn.y : 0.0);
+    ps[cur ^ 1][lane].x = keep ? pn.x : (T)0;
+    ps[cur ^ 1][lane].y = keep ? pn.y : (T)0;
     __syncthreads();
     rw.advance(more);
 }
 
-template <int NF>
-__device__ __forceinline__ void t1_rows(T1Ctx &c, T1Rows rw, int nrows, int wpx, int lane, const T1Pairs &pr,
-                                        double2 (*ps)[64], double (&zr)[T1_RB], double (&zi)[T1_RB]) {
-    double xl[8], xh[8], yl[8], yh[8], sp[8];
+// All inner rows of an item.  FP64 accumulates every row in zr/zi; FP32
+// accumulates a pair of rows (at most 128 terms per output) in FP32 and adds
+// it to the FP64 totals Zr/Zi.
+template <typename T, int NF>
+__device__ __forceinline__ void t1_rows(T1Ctx<T> &c, T1Rows rw, int nrows, int wpx, int lane, const T1Pairs<T> &pr,
+                                        typename V2<T>::type (*ps)[64], double (&Zr)[T1_RB], double (&Zi)[T1_RB]) {
+    T xl[8], xh[8], yl[8], yh[8], sp[8];
+    T zr[T1_RB], zi[T1_RB];
+#pragma unroll
+    for (int i = 0; i < T1_RB; ++i) zr[i] = zi[i] = (T)0;
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         xl[s] = t1_kload(c, rw.voff - 8 * c.sA, s);
         xh[s] = t1_kload(c, rw.voff, s);
     }
     {
-        const double2 p0 = pr.at(0, 0);
+        const auto p0 = pr.at(0, 0);
         const bool keep = lane < wpx;
-        ps[0][lane] = make_double2(keep ? p0.x : 0.0, keep ? p0.y : 0.0);
+        ps[0][lane].x = keep ? p0.x : (T)0;
+        ps[0][lane].y = keep ? p0.y : (T)0;
     }
     __syncthreads();
     for (int row = 0; row < nrows; row += 2) {
-        t1_row<NF>(c, rw, row, nrows, wpx, lane, pr, ps, 0, xl, xh, yl, yh, sp, zr, zi);
-        t1_row<NF>(c, rw, row + 1, nrows, wpx, lane, pr, ps, 1, yl, yh, xl, xh, sp, zr, zi);
+        t1_row<T, NF>(c, rw, row, nrows, wpx, lane, pr, ps, 0, xl, xh, yl, yh, sp, zr, zi);
+        t1_row<T, NF>(c, rw, row + 1, nrows, wpx, lane, pr, ps, 1, yl, yh, xl, xh, sp, zr, zi);
+        if constexpr (sizeof(T) == 4) {
+#pragma unroll
+            for (int i = 0; i < T1_RB; ++i) {
+                Zr[i] += (double)zr[i];
+                Zi[i] += (double)zi[i];
+                zr[i] = zi[i] = 0.0f;
+            }
+        }
+    }
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int i = 0; i < T1_RB; ++i) {
+            Zr[i] = zr[i];
+            Zi[i] = zi[i];
+        }
     }
 }
 
+template <typename T>
+__device__ __forceinline__ const typename V2<T>::type *rotated_of(const Inst &I) {
+    if constexpr (sizeof(T) == 8)
+        return I.Gr;
+    else
+        return I.Gr32;
+}
+
+template <typename T>
 __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_off, const T1Item *items,
-                                                       const T1B *bdesc, const double *K, const Inst *D,
+                                                       const T1B *bdesc, const T *K, const Inst *D,
                                                        const Rot *rots) {
-    __shared__ double2 ps[2][64];
+    using T2 = typename V2<T>::type;
+    __shared__ T2 ps[2][64];
     const int slot = blockIdx.x;
     const int lane = threadIdx.x;
     const int A = 2 * g.N - 1;
@@ -437,20 +543,20 @@ __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_of
         const int x0 = B.wnlo[2] + xb * T1_RB;
         const int base = x0 - B.wplo[2];  // a_x = base + i - u
         const int wpx = B.wphi[2] - B.wplo[2] + 1;
-        T1Ctx c;
+        T1Ctx<T> c;
         c.kr = __builtin_amdgcn_make_buffer_rsrc((void *)(K + (int64_t)B.kc * g.nak), (short)0,
-                                                 (int)(g.nak * (int64_t)sizeof(double)), 0x00020000);
-        c.sA = A * (int)sizeof(double);
+                                                 (int)(g.nak * (int64_t)sizeof(T)), 0x00020000);
+        c.sA = A * (int)sizeof(T);
         T1Rows rw;
-        rw.voff = (int)(idx_K(g, nz - B.wplo[0], ny - B.wplo[1], base) * (int64_t)sizeof(double));
+        rw.voff = (int)(idx_K(g, nz - B.wplo[0], ny - B.wplo[1], base) * (int64_t)sizeof(T));
         rw.py = 0;
         rw.pz = 0;
         rw.wpy = B.wphi[1] - B.wplo[1] + 1;
-        rw.dy = (int)sizeof(double);
-        rw.dz = (g.d == 3 ? g.kax * A : 0) * (int)sizeof(double);
+        rw.dy = (int)sizeof(T);
+        rw.dz = (g.d == 3 ? g.kax * A : 0) * (int)sizeof(T);
         const int nrows = rw.wpy * (B.wphi[0] - B.wplo[0] + 1);
-        const double2 *G = I.Gr + (int64_t)B.rot * g.next;
-        T1Pairs pr;
+        const T2 *G = rotated_of<T>(I) + (int64_t)B.rot * g.next;
+        T1Pairs<T> pr;
         pr.G = G;
         pr.X = g.N + 1;
         pr.h = g.h;
@@ -465,15 +571,15 @@ __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_of
 #pragma unroll
         for (int i = 0; i < T1_RB; ++i) zr[i] = zi[i] = 0.0;
         switch (wpx >> 3) {
-            case 0: t1_rows<0>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
-            case 1: t1_rows<1>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
-            case 2: t1_rows<2>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
-            case 3: t1_rows<3>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
-            case 4: t1_rows<4>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
-            case 5: t1_rows<5>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
-            case 6: t1_rows<6>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
-            case 7: t1_rows<7>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
-            default: t1_rows<8>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            case 0: t1_rows<T, 0>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            case 1: t1_rows<T, 1>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            case 2: t1_rows<T, 2>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            case 3: t1_rows<T, 3>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            case 4: t1_rows<T, 4>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            case 5: t1_rows<T, 5>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            case 6: t1_rows<T, 6>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            case 7: t1_rows<T, 7>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
+            default: t1_rows<T, 8>(c, rw, nrows, wpx, lane, pr, ps, zr, zi); break;
         }
         if (active) {
             const Rot R = rots[B.rot];
@@ -481,8 +587,8 @@ __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_of
             for (int i = 0; i < T1_RB; ++i) {
                 const int nx = x0 + i;
                 if (nx <= B.wnhi[2]) {
-                    const double2 gk = ld2(G, idx_X(g, nz - B.bc[0], ny - B.bc[1], nx - B.bc[2]));
-                    const double2 cc = cmul(gk, make_double2(zr[i], zi[i]));
+                    const T2 gq = ldT2(G, idx_X(g, nz - B.bc[0], ny - B.bc[1], nx - B.bc[2]));
+                    const double2 cc = cmul(make_double2(gq.x, gq.y), make_double2(zr[i], zi[i]));
                     const int v[3] = {nz, ny, nx};
                     const int o0 = R.sgn[0] * v[R.perm[0]];
                     const int o1 = R.sgn[1] * v[R.perm[1]];
@@ -500,15 +606,32 @@ __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_of
     }
 }
 
-void launch_trilinear(const Geo &g, int nslots, const int *slot_off, const T1Item *items, const T1B *bdesc,
-                      const double *K, const Inst *D, const Rot *rots, hipStream_t s) {
-    hipLaunchKernelGGL(trilinear_kernel, dim3(nslots), dim3(64), 0, s, g, slot_off, items, bdesc, K, D, rots);
+void launch_trilinear(const Geo &g, int prec, int nslots, const int *slot_off, const T1Item *items,
+                      const T1B *bdesc, const void *K, const Inst *D, const Rot *rots, hipStream_t s) {
+    if (prec == 0)
+        hipLaunchKernelGGL(trilinear_kernel<double>, dim3(nslots), dim3(64), 0, s, g, slot_off, items, bdesc,
+                           (const double *)K, D, rots);
+    else
+        hipLaunchKernelGGL(trilinear_kernel<float>, dim3(nslots), dim3(64), 0, s, g, slot_off, items, bdesc,
+                           (const float *)K, D, rots);
 }
 
-int trilinear_blocks_per_cu() {
+int trilinear_blocks_per_cu(int prec) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trilinear_kernel, 64, 0) != hipSuccess) return 0;
-    return nb;
+    const hipError_t e = prec == 0
+                             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trilinear_kernel<double>, 64, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trilinear_kernel<float>, 64, 0);
+    return e == hipSuccess ? nb : 0;
+}
+
+__global__ void to_f32_kernel(const double *in, float *out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
+}
+
+void launch_to_f32(const double *in, float *out, int64_t n, hipStream_t s) {
+    const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(to_f32_kernel, dim3(nb), dim3(256), 0, s, in, out, n);
 }
 
 __global__ void zero_kernel(double *p, int64_t n) {

@@ -1,0 +1,90 @@
+"""FP32c precision pattern: spectra, tables and short partial sums in FP32,
+long sums in FP64.  Parity with the FP64 oracle to 1e-5 (norm-wise, relative
+to max(|ref|, |classical gain|) as for FP64), at small sizes over several
+tiles and ragged windows and at the full 3-D N = 32 shape."""
+import numpy as np
+import pytest
+
+import bnq_inputs as inp
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+bnq = pytest.importorskip("paper_2110_13735_amd")
+
+TOL32 = 1e-5
+
+
+def _rel(got, ref, scale=0.0):
+    return np.linalg.norm(got - ref) / max(np.linalg.norm(ref), scale)
+
+
+def _gpu(p, f):
+    dev = torch.device("cuda:0")
+    with bnq.Plan(p) as plan:
+        ft = torch.tensor(f, device=dev)
+        Q = torch.empty_like(ft)
+        Qh = torch.empty(f.shape, dtype=torch.complex128, device=dev)
+        plan.collide(ft, Q, Qh)
+        torch.cuda.synchronize()
+        return Q.cpu().numpy(), Qh.cpu().numpy()
+
+
+@pytest.mark.parametrize("d,N", [(2, 8), (2, 16), (2, 30), (3, 4), (3, 6), (3, 10)])
+@pytest.mark.parametrize("eps", [1, -1, 0])
+def test_fp32c_collide_matches_oracle(d, N, eps):
+    L = 5.0
+    f = inp.gaussian_mixture(d, N, L, seed=7 * N + d + eps, fmax=0.9 if eps == -1 else None)
+    Q, Qh = _gpu(bnq.Params(d=d, N=N, eps=eps, L=L, precision=bnq.FP32C), f)
+    o = oracle.Oracle(d, N)
+    Qo, Qho, m = o.collide(f, eps, L, full=True)
+    gain = np.linalg.norm(m["gain"])
+    qgain = np.linalg.norm(oracle.prefactor(d, L) * oracle.idft_real(m["gain"]))
+    assert _rel(Qh, Qho, gain) <= TOL32
+    assert _rel(Q, Qo, qgain) <= TOL32
+
+
+def test_fp32c_is_not_fp64():
+    # the FP32c path must really round: it differs from FP64 beyond FP64 noise
+    d, N, eps, L = 3, 6, -1, 5.0
+    f = inp.gaussian_mixture(d, N, L, seed=3, fmax=0.9)
+    _, Qh64 = _gpu(bnq.Params(d=d, N=N, eps=eps, L=L), f)
+    _, Qh32 = _gpu(bnq.Params(d=d, N=N, eps=eps, L=L, precision=bnq.FP32C), f)
+    r = _rel(Qh32, Qh64)
+    assert 1e-12 < r <= TOL32
+
+
+def test_fp32c_full_size_3d32_sparse_spectrum():
+    d, N, L, eps = 3, 32, 8.0, -1
+    f, sm, co = inp.sparse_spectrum(d, N, seed=5, nmodes=8, amp=0.2)
+    Q, Qh = _gpu(bnq.Params(d=d, N=N, eps=eps, L=L, precision=bnq.FP32C), f)
+    Qc, T1, Xq = oracle.sparse_modes(d, N, sm, co, eps)
+    alpha = oracle.alpha_of(eps, d)
+    ref = oracle.sparse_dense(d, N, Qc) - alpha * (oracle.sparse_dense(d, N, T1) + oracle.sparse_dense(d, N, Xq))
+    assert _rel(Qh, ref) <= TOL32
+    assert _rel(Q, oracle.prefactor(d, L) * oracle.idft_real(ref)) <= TOL32
+
+
+def test_fp32c_and_fp64_instances_in_one_batch():
+    dev = torch.device("cuda:0")
+    specs = [(3, 6, -1, bnq.FP32C), (3, 6, -1, bnq.FP64), (2, 16, 1, bnq.FP32C), (3, 6, 1, bnq.FP32C)]
+    plans, fs = [], []
+    for i, (d, N, eps, prec) in enumerate(specs):
+        f = inp.gaussian_mixture(d, N, 5.0, seed=50 + i, fmax=0.9 if eps == -1 else None)
+        plans.append(bnq.Plan(bnq.Params(d=d, N=N, eps=eps, L=5.0, precision=prec)))
+        fs.append(torch.tensor(f, device=dev))
+    solo = []
+    for pl, f in zip(plans, fs):
+        Q = torch.empty_like(f)
+        pl.collide(f, Q)
+        solo.append(Q)
+    torch.cuda.synchronize()
+    with bnq.Batch(plans, fs) as B:
+        Qs = [torch.empty_like(f) for f in fs]
+        B.collide(Qs)
+        torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(solo, Qs)):
+        assert torch.equal(a, b), f"instance {i} differs from its solo evaluation"
+    for pl in plans:
+        pl.close()
