@@ -344,3 +344,17 @@ def moments(f: np.ndarray, L: float, eps: int, hbar: float = 1.0) -> dict:
         H = dv * np.sum(fo * np.log(fo) + (1.0 - alpha * fo) / alpha * np.log(1.0 - alpha * fo))
     return {"rho": rho, "u": u, "Ec": Ec, "e": e, "H": H, "fmax": float(f.max()),
             "fmin": float(f.min()), "n_excluded": int((~ok).sum())}
+
+
+def project_moments(Q: np.ndarray, d: int, N: int, L: float) -> np.ndarray:
+    """Conservation correction (not part of the paper's scheme): the grid
+    function closest to Q in the discrete L2 norm whose discrete mass,
+    momentum and kinetic energy vanish, i.e. Q minus its orthogonal projection
+    onto span{1, v_1..v_d, |v|^2} over the velocity nodes v_j = 2 L j / N.
+    Written as the definition: C Q' = 0 with Q' = Q - C^T (C C^T)^-1 C Q."""
+    axes = [(2.0 * L / N) * np.arange(-N // 2, N // 2)] * d
+    v = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, d)
+    C = np.concatenate([np.ones((1, v.shape[0])), v.T, np.sum(v * v, axis=1)[None, :]], axis=0)
+    q = Q.reshape(-1)
+    lam = np.linalg.solve(C @ C.T, C @ q)
+    return (q - C.T @ lam).reshape(Q.shape)

@@ -288,3 +288,26 @@ def test_moments_of_gaussian():
     assert m["e"] == pytest.approx(1.5 * T, abs=1e-9)
     # classical entropy of a Maxwellian: int f ln f = -(3/2)(1 + ln(2 pi T))
     assert m["H"] == pytest.approx(-1.5 * (1 + math.log(2 * math.pi * T)), abs=1e-8)
+
+
+@pytest.mark.parametrize("d,N", [(2, 8), (3, 6)])
+def test_moment_projection_properties(d, N):
+    # the correction removes exactly the span of {1, v, |v|^2}: the result has
+    # zero discrete moments, the correction lies in that span, and a function
+    # already orthogonal to it is left unchanged (idempotence)
+    L = 4.0
+    rng = np.random.default_rng(d * 100 + N)
+    Q = rng.standard_normal((N,) * d)
+    P = oracle.project_moments(Q, d, N, L)
+    axes = [(2.0 * L / N) * np.arange(-N // 2, N // 2)] * d
+    v = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1)
+    scale = np.sum(np.abs(Q)) * (1 + np.max(np.abs(v))) ** 2
+    assert abs(P.sum()) <= 1e-13 * scale
+    for a in range(d):
+        assert abs(np.sum(v[..., a] * P)) <= 1e-13 * scale
+    assert abs(np.sum(np.sum(v * v, axis=-1) * P)) <= 1e-13 * scale
+    D = (Q - P).reshape(-1)
+    basis = np.concatenate([np.ones((1, D.size)), v.reshape(-1, d).T, np.sum(v * v, axis=-1).reshape(1, -1)])
+    coef, *_ = np.linalg.lstsq(basis.T, D, rcond=None)
+    assert np.linalg.norm(basis.T @ coef - D) <= 1e-12 * np.linalg.norm(Q)
+    assert np.allclose(oracle.project_moments(P, d, N, L), P, rtol=0, atol=1e-13 * np.max(np.abs(Q)))
