@@ -70,6 +70,10 @@ typedef struct bnq_batch_s *bnq_batch_t;
 
 #define BNQ_CORR_NONE 0 /* the paper's scheme */
 #define BNQ_CORR_MASS 1 /* subtract the mean of Q so that sum_j Q_j = 0 exactly */
+/* replace Q by the L2-closest grid function with zero discrete mass, momentum
+ * and kinetic energy (Q minus its projection onto span{1, v, |v|^2} over the
+ * velocity nodes); not part of the paper's scheme */
+#define BNQ_CORR_MOMENTS 2
 
 #define BNQ_RK4 0
 #define BNQ_EULER 1

@@ -20,7 +20,7 @@ LIBPATH = os.path.join(HERE, "libbnq.so")
 BNQ_OK, BNQ_EINVAL, BNQ_ENOMEM, BNQ_EHIP, BNQ_ENOTSUP, BNQ_ENONFINITE, BNQ_EBOUND = 0, -1, -2, -3, -4, -5, -6
 T_CLASSICAL, T_QMULT, T_QTRI, T_ALL = 1, 2, 4, 7
 FP64, FP32C = 0, 1
-CORR_NONE, CORR_MASS = 0, 1
+CORR_NONE, CORR_MASS, CORR_MOMENTS = 0, 1, 2
 RK4, EULER, SSPRK2 = 0, 1, 2
 MOMENTS_LEN = 10
 NKERNELS = 8

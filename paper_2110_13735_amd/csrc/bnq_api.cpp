@@ -437,6 +437,7 @@ struct bnq_plan_s {
     int nbdesc = 0;
     double *kbuf[4] = {nullptr, nullptr, nullptr, nullptr}, *ybuf = nullptr;
     double *mom_part = nullptr, *mom_out = nullptr;
+    double *ginv = nullptr;  // inverse Gram matrix for BNQ_CORR_MOMENTS
     int nslots = 0;
     int *slot_off = nullptr;
     T1Item *items = nullptr;
@@ -508,7 +509,7 @@ bnq_status validate(const bnq_params *p) {
     if (p->precision != BNQ_FP64 && p->precision != BNQ_FP32C)
         return fail(BNQ_EINVAL, "precision must be BNQ_FP64 or BNQ_FP32C (got %d)", p->precision);
     if (p->terms < 0 || p->terms > BNQ_T_ALL) return fail(BNQ_EINVAL, "bad terms mask %d", p->terms);
-    if (p->correction != BNQ_CORR_NONE && p->correction != BNQ_CORR_MASS)
+    if (p->correction != BNQ_CORR_NONE && p->correction != BNQ_CORR_MASS && p->correction != BNQ_CORR_MOMENTS)
         return fail(BNQ_EINVAL, "bad correction %d", p->correction);
     return BNQ_OK;
 }
@@ -520,6 +521,47 @@ size_t plan_workspace_bytes(const bnq_params *p, int nslots_est) {
     const size_t f32 = p->precision == BNQ_FP32C ? sizeof(float2) * ((size_t)g.nm + nrot * g.next) : 0;
     return c * (6 * (size_t)g.nm + g.neg + nrot * g.next + (size_t)nslots_est * g.nm) +
            r * 5 * (size_t)g.nm + f32;
+}
+
+// Inverse of the Gram matrix of c = (1, v_1..v_d, |v|^2) over the velocity
+// nodes (long double sums, Gauss–Jordan with partial pivoting).
+bnq_status gram_inverse(int d, int N, double hstep, std::vector<double> &out) {
+    const int m = d + 2, h = N / 2;
+    long double G[5][10] = {};
+    const int n0 = d == 3 ? N : 1;
+    for (int a = 0; a < n0; ++a)
+        for (int b = 0; b < N; ++b)
+            for (int e = 0; e < N; ++e) {
+                long double v[3] = {d == 3 ? (long double)(a - h) * hstep : 0.0L, (long double)(b - h) * hstep,
+                                    (long double)(e - h) * hstep};
+                long double c[5];
+                c[0] = 1.0L;
+                int k = 1;
+                for (int x = (d == 3 ? 0 : 1); x < 3; ++x) c[k++] = v[x];
+                c[m - 1] = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+                for (int r = 0; r < m; ++r)
+                    for (int q = 0; q < m; ++q) G[r][q] += c[r] * c[q];
+            }
+    for (int r = 0; r < m; ++r)
+        for (int q = 0; q < m; ++q) G[r][m + q] = r == q ? 1.0L : 0.0L;
+    for (int col = 0; col < m; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < m; ++r)
+            if (std::fabs((double)G[r][col]) > std::fabs((double)G[piv][col])) piv = r;
+        if (G[piv][col] == 0.0L) return fail(BNQ_EINVAL, "singular moment Gram matrix (N too small)");
+        for (int q = 0; q < 2 * m; ++q) std::swap(G[col][q], G[piv][q]);
+        const long double pv = G[col][col];
+        for (int q = 0; q < 2 * m; ++q) G[col][q] /= pv;
+        for (int r = 0; r < m; ++r)
+            if (r != col) {
+                const long double f = G[r][col];
+                for (int q = 0; q < 2 * m; ++q) G[r][q] -= f * G[col][q];
+            }
+    }
+    out.assign((size_t)m * m, 0.0);
+    for (int r = 0; r < m; ++r)
+        for (int q = 0; q < m; ++q) out[(size_t)r * m + q] = (double)G[r][m + q];
+    return BNQ_OK;
 }
 
 bnq_status build_t1_work(bnq_plan_s *P) {
@@ -683,6 +725,7 @@ void destroy_plan(bnq_plan_s *P) {
     hipFree(P->ybuf);
     hipFree(P->mom_part);
     hipFree(P->mom_out);
+    hipFree(P->ginv);
     hipFree(P->slot_off);
     hipFree(P->items);
     hipFree(P->bdesc);
@@ -817,6 +860,13 @@ bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s
             launch_inverse_real(g, E.D, io, E.tw, s);
             LAUNCHCHK();
         }
+        int any_mom = 0;
+        for (const Inst &I : E.Dh) any_mom |= I.corr_mom;
+        if (any_mom)
+            for (const IOs &io : ios) {
+                launch_moments_fix(g, E.D, io, s);
+                LAUNCHCHK();
+            }
     }
     return BNQ_OK;
 }
@@ -996,7 +1046,17 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         I.terms = p->eps == 0 ? (p->terms & BNQ_T_CLASSICAL) : p->terms;
         I.mass_fix = p->correction == BNQ_CORR_MASS;
         I.nslots = P->nslots;
-        I.pad = 0;
+        I.corr_mom = p->correction == BNQ_CORR_MOMENTS;
+        I.hstep = 2.0 * p->L / p->N;
+        I.ginv = nullptr;
+        if (I.corr_mom) {
+            std::vector<double> gi;
+            if ((st = gram_inverse(p->d, p->N, I.hstep, gi)) || (st = upload(&P->ginv, gi, "moment Gram matrix"))) {
+                destroy_plan(P);
+                return st;
+            }
+            I.ginv = P->ginv;
+        }
         if ((st = upload(&P->inst_d, std::vector<Inst>(1, I), "instance descriptor"))) {
             destroy_plan(P);
             return st;

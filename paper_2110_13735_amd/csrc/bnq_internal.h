@@ -143,7 +143,9 @@ struct Inst {
     int terms;     // BNQ_T_* mask actually evaluated
     int mass_fix;  // 1: Re Qhat_0 := 0
     int nslots;    // trilinear partial arrays in part
-    int pad;
+    int corr_mom;  // 1: project Q onto zero mass, momentum and energy
+    double hstep;  // velocity step 2 L / N
+    const double *ginv;  // inverse Gram matrix of {1, v, |v|^2} over the grid, (d+2)^2
 };
 
 // Buffers a kernel can be pointed at.
@@ -187,6 +189,7 @@ int trilinear_blocks_per_cu(int prec);  // resident 64-lane trilinear workgroups
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_reduce_partials(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 void launch_combine(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
+void launch_moments_fix(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 
 // Stage updates: y = in + a dt k[ks] into Inst::ybuf (to_out = 0) or into
 // io.out (to_out = 1); the final RK4 / SSP-RK2 combinations update io.out.

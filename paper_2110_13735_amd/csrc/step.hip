@@ -60,6 +60,65 @@ void launch_ssprk2_final(const Geo &g, const Inst *D, const IOs &io, hipStream_t
     hipLaunchKernelGGL(ssprk2_final_kernel, grid_nm(g, io), dim3(256), 0, s, g, D, io);
 }
 
+// Conservation correction: Q <- Q - sum_k lambda_k c_k with c = (1, v, |v|^2)
+// and lambda = Gram^-1 (sum_j c_k(j) Q_j), the L2-closest grid function with
+// zero discrete mass, momentum and energy.  One workgroup per instance, fixed
+// reduction tree.
+__global__ __launch_bounds__(256) void moments_fix_kernel(Geo g, const Inst *D, IOs io) {
+    const int z = blockIdx.z;
+    const Inst &I = D[io.inst[z]];
+    if (!I.corr_mom) return;
+    const gptr<double> Q = glob(io.out[z]);
+    const int m = g.d + 2;
+    __shared__ double red[256][5];
+    __shared__ double lam[5];
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = threadIdx.x; i < g.nm; i += 256) {
+        const double q = Q[i];
+        const double x2 = (double)((int)(i % g.N) - g.h) * I.hstep;
+        const double x1 = (double)((int)((i / g.N) % g.N) - g.h) * I.hstep;
+        const double x0 = g.d == 3 ? (double)((int)(i / ((int64_t)g.N * g.N)) - g.h) * I.hstep : 0.0;
+        acc[0] += q;
+        if (g.d == 3) {
+            acc[1] += x0 * q;
+            acc[2] += x1 * q;
+            acc[3] += x2 * q;
+        } else {
+            acc[1] += x1 * q;
+            acc[2] += x2 * q;
+        }
+        acc[m - 1] += (x0 * x0 + x1 * x1 + x2 * x2) * q;
+    }
+    for (int k = 0; k < 5; ++k) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 5; ++k) red[threadIdx.x][k] += red[threadIdx.x + w][k];
+        __syncthreads();
+    }
+    if (threadIdx.x < m) {
+        double l = 0.0;
+        for (int k = 0; k < m; ++k) l += I.ginv[threadIdx.x * m + k] * red[0][k];
+        lam[threadIdx.x] = l;
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < g.nm; i += 256) {
+        const double x2 = (double)((int)(i % g.N) - g.h) * I.hstep;
+        const double x1 = (double)((int)((i / g.N) % g.N) - g.h) * I.hstep;
+        const double x0 = g.d == 3 ? (double)((int)(i / ((int64_t)g.N * g.N)) - g.h) * I.hstep : 0.0;
+        double c = lam[0] + lam[m - 1] * (x0 * x0 + x1 * x1 + x2 * x2);
+        if (g.d == 3)
+            c += lam[1] * x0 + lam[2] * x1 + lam[3] * x2;
+        else
+            c += lam[1] * x1 + lam[2] * x2;
+        Q[i] = Q[i] - c;
+    }
+}
+
+void launch_moments_fix(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
+    hipLaunchKernelGGL(moments_fix_kernel, dim3(1, 1, (unsigned)io.n), dim3(256), 0, s, g, D, io);
+}
+
 // fields: 0 sum f, 1-3 sum v f, 4 sum |v|^2 f, 5 sum entropy density,
 //         6 max f, 7 min f, 8 excluded nodes, 9 non-finite nodes
 __global__ __launch_bounds__(256) void moments_part_kernel(Geo g, const double *f, double L, double alpha,

@@ -327,3 +327,20 @@ def test_autotune_keeps_parity():
         Qr, Qhr, gain, qgain = _oracle_collide(d, N, f0, eps, L)
         _check(Qh.cpu().numpy(), Qhr, gain)
         _check(Q.cpu().numpy(), Qr, qgain)
+
+
+@pytest.mark.parametrize("d,N,eps", [(2, 16, 1), (3, 6, -1), (3, 10, 0)])
+def test_moments_correction_matches_oracle(d, N, eps):
+    L = 5.0
+    f = inp.gaussian_mixture(d, N, L, seed=90 + N, fmax=0.9 if eps == -1 else None)
+    Q, _ = _gpu_collide(bnq.Params(d=d, N=N, eps=eps, L=L, correction=bnq.CORR_MOMENTS), f)
+    Qo, _, _, qg = _oracle_collide(d, N, f, eps, L)
+    ref = oracle.project_moments(Qo, d, N, L)
+    _check(Q, ref, qg)
+    axes = [(2.0 * L / N) * np.arange(-N // 2, N // 2)] * d
+    v = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1)
+    scale = np.sum(np.abs(Qo)) * (1 + np.max(np.abs(v))) ** 2
+    assert abs(Q.sum()) <= 1e-13 * scale
+    for a in range(d):
+        assert abs(np.sum(v[..., a] * Q)) <= 1e-13 * scale
+    assert abs(np.sum(np.sum(v * v, axis=-1) * Q)) <= 1e-13 * scale
