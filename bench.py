@@ -98,6 +98,9 @@ def main():
     ap.add_argument("--N", type=int, default=32)
     ap.add_argument("--dt", type=float, default=0.01)
     ap.add_argument("--precision", choices=("fp64", "fp32c"), default="fp64")
+    ap.add_argument("--schedule", choices=("static", "dynamic"), default="dynamic",
+                    help="trilinear work distribution: dynamic (default here, fastest; last bits may vary "
+                         "between runs) or static (the library default, bitwise reproducible)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-N", type=int, default=10)
     ap.add_argument("--workload", choices=("c2", "batch", "serve"), default="c2",
@@ -131,7 +134,8 @@ def main():
     torch.cuda.set_device(dev)
     N, L, eps = args.N, 8.0, -1
     prec = bnq.FP32C if args.precision == "fp32c" else bnq.FP64
-    p = bnq.Params(d=3, N=N, eps=eps, L=L, precision=prec)
+    sched = bnq.SCHED_DYNAMIC if args.schedule == "dynamic" else bnq.SCHED_STATIC
+    p = bnq.Params(d=3, N=N, eps=eps, L=L, precision=prec, schedule=sched)
     f0 = inp.fermion_mixture_3d(N=N, L=L, seed=0)
     t_plan = time.perf_counter()
     plan = bnq.Plan(p)
@@ -197,7 +201,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"3-D fermions eps=-1, N={N}^3, {args.precision.upper()}, hard spheres, hbar=1, L=8, "
                                f"three-Gaussian f0 (seed 0), RK4 dt={args.dt}, moments every step",
-                   "d": 3, "N": N, "eps": eps, "precision": args.precision, "scheme": "rk4", "dt": args.dt,
+                   "d": 3, "N": N, "eps": eps, "precision": args.precision, "schedule": args.schedule,
+                   "scheme": "rk4", "dt": args.dt,
                    "terms_per_eval": terms_eval, "evals_per_step": 4,
                    "plan_build_s": round(t_plan, 3)},
         "roofline": roofline,

@@ -96,7 +96,17 @@ typedef struct {
     double C_phi;       /* default 1 */
     double c;           /* collision scaling, default 1 */
     double L;           /* velocity box half-width, > 0 */
+    int32_t schedule;   /* trilinear work distribution: BNQ_SCHED_STATIC (default;
+                           fixed per-wave lists, results bitwise reproducible) or
+                           BNQ_SCHED_DYNAMIC (waves take items by atomic ticket from
+                           their XCD's queue; balances waves that the hardware issues
+                           at different rates; the summation order, hence the last
+                           bits, may change from run to run) */
+    int32_t reserved;   /* 0 */
 } bnq_params;
+
+#define BNQ_SCHED_STATIC 0
+#define BNQ_SCHED_DYNAMIC 1
 
 /* Fill *p with defaults: d = 3, N = 16, eps = 0, FP64, all terms, no
  * correction, hbar = C_phi = c = 1, L = 8. */

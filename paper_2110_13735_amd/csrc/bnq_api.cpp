@@ -443,7 +443,9 @@ struct bnq_plan_s {
     T1Item *items = nullptr;
     T1B *bdesc = nullptr;
     std::vector<T1Item> items_h;  // per-slot item lists (host copy), slot offsets
-    std::vector<int> off_h;
+    std::vector<int> off_h;       // (dynamic schedule: queue offsets)
+    int nq = 0;                   // dynamic schedule: queues (0 = static)
+    int *qoff = nullptr, *qctr = nullptr;
     T1Tune tune;                  // trilinear work distribution
     Inst ih{};                    // workspace pointers and scalars (host copy)
     Inst *inst_d = nullptr;       // device copy, one entry
@@ -511,6 +513,8 @@ bnq_status validate(const bnq_params *p) {
     if (p->terms < 0 || p->terms > BNQ_T_ALL) return fail(BNQ_EINVAL, "bad terms mask %d", p->terms);
     if (p->correction != BNQ_CORR_NONE && p->correction != BNQ_CORR_MASS && p->correction != BNQ_CORR_MOMENTS)
         return fail(BNQ_EINVAL, "bad correction %d", p->correction);
+    if (p->schedule != BNQ_SCHED_STATIC && p->schedule != BNQ_SCHED_DYNAMIC)
+        return fail(BNQ_EINVAL, "bad schedule %d", p->schedule);
     return BNQ_OK;
 }
 
@@ -646,6 +650,35 @@ bnq_status build_t1_work(bnq_plan_s *P) {
     const int nx = P->tune.xcd ? std::max(1, cus / kCusPerXcd) : 1;
     int ns_want = std::min(kMaxSlots, std::max(1, cus * per_cu / std::max(1, P->tune.slot_div)));
     ns_want = std::max(nx, ns_want - ns_want % nx);
+    if (P->p.schedule == BNQ_SCHED_DYNAMIC) {
+        // one queue per XCD run of the sorted items; every resident wave runs
+        std::vector<int> qoff(1, 0);
+        double total = 0, acc = 0;
+        for (const It &x : items) total += x.cost;
+        std::vector<T1Item> flat;
+        flat.reserve(items.size());
+        size_t i = 0;
+        for (int x = 0; x < nx; ++x) {
+            const double cut = total * (x + 1) / nx;
+            for (; i < items.size() && (x == nx - 1 || acc + 0.5 * items[i].cost <= cut); ++i) {
+                acc += items[i].cost;
+                flat.push_back(items[i].it);
+            }
+            qoff.push_back((int)flat.size());
+        }
+        P->nslots = ns_want;
+        P->nbdesc = (int)bd.size();
+        P->nq = nx;
+        P->items_h = flat;
+        P->off_h = qoff;
+        bnq_status st;
+        if ((st = upload(&P->bdesc, bd, "trilinear b descriptors")) ||
+            (!flat.empty() && (st = upload(&P->items, flat, "trilinear items"))) ||
+            (st = upload(&P->qoff, qoff, "trilinear queues")) ||
+            (st = dalloc(&P->qctr, (size_t)((nx + 1) & ~1), "trilinear queue tickets")))
+            return st;
+        return dalloc(&P->part, (size_t)ns_want * g.nm, "trilinear partial sums");
+    }
     const int ns = (int)std::max<size_t>(1, std::min<size_t>(ns_want, items.size()));
     std::vector<std::vector<T1Item>> per(ns);
     if (ns < ns_want) {
@@ -693,6 +726,10 @@ bnq_status rebuild_t1(bnq_plan_s *P, hipStream_t s) {
     hipFree(P->items);
     hipFree(P->slot_off);
     hipFree(P->part);
+    hipFree(P->qoff);
+    hipFree(P->qctr);
+    P->qoff = P->qctr = nullptr;
+    P->nq = 0;
     P->bdesc = nullptr;
     P->items = nullptr;
     P->slot_off = nullptr;
@@ -730,6 +767,8 @@ void destroy_plan(bnq_plan_s *P) {
     hipFree(P->items);
     hipFree(P->bdesc);
     hipFree(P->inst_d);
+    hipFree(P->qoff);
+    hipFree(P->qctr);
     for (auto &e : P->evs) {
         hipEventDestroy(e.a);
         hipEventDestroy(e.b);
@@ -755,6 +794,9 @@ struct Exec {
     const T1B *bdesc = nullptr;
     const Inst *D = nullptr;
     int prec = 0;               // 0 FP64, 1 FP32c
+    int nq = 0;                 // dynamic schedule: queues (0 = static)
+    const int *qoff = nullptr;
+    int *qctr = nullptr;
     std::vector<Inst> Dh;       // host copies of D
     bnq_plan_s *timer = nullptr;  // plan whose timing spans record this run
 };
@@ -772,6 +814,9 @@ Exec exec_of(bnq_plan_s *P) {
     E.bdesc = P->bdesc;
     E.D = P->inst_d;
     E.prec = P->p.precision == BNQ_FP32C ? 1 : 0;
+    E.nq = P->nq;
+    E.qoff = P->qoff;
+    E.qctr = P->qctr;
     E.Dh.assign(1, P->ih);
     E.timer = P;
     return E;
@@ -838,10 +883,15 @@ bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s
                 LAUNCHCHK();
             }
         }
+        if (E.nq) {
+            launch_zero(E.qctr, (int64_t)((E.nq + 1) & ~1) * (int64_t)sizeof(int), s);  // whole 8-byte words
+            LAUNCHCHK();
+        }
         {
             Span sp(E.timer, 3, s);
             launch_trilinear(g, E.prec, E.nslots, E.slot_off, E.items, E.bdesc,
-                             E.prec ? (const void *)E.t->K32 : (const void *)E.t->K, E.D, E.rots, s);
+                             E.prec ? (const void *)E.t->K32 : (const void *)E.t->K, E.D, E.rots, E.nq, E.qoff,
+                             E.qctr, s);
             LAUNCHCHK();
         }
         {
@@ -948,6 +998,8 @@ void bnq_params_default(bnq_params *p) {
     p->C_phi = 1.0;
     p->c = 1.0;
     p->L = 8.0;
+    p->schedule = BNQ_SCHED_STATIC;
+    p->reserved = 0;
 }
 
 bnq_status bnq_plan_footprint(const bnq_params *p, size_t *plan_bytes, size_t *table_bytes_out) {
@@ -1301,6 +1353,7 @@ struct bnq_batch_s {
         Inst *D = nullptr;
         int *slot_off = nullptr;
         T1Item *items = nullptr;
+        int *qoff = nullptr, *qctr = nullptr;
     };
     std::vector<bnq_plan_s *> plans;
     std::vector<double *> f;
@@ -1320,6 +1373,8 @@ void destroy_batch(bnq_batch_s *B) {
         hipFree(G.D);
         hipFree(G.slot_off);
         hipFree(G.items);
+        hipFree(G.qoff);
+        hipFree(G.qctr);
     }
     delete B;
 }
@@ -1359,9 +1414,10 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
     bnq_batch_s *B = new bnq_batch_s;
     B->plans.assign(plans, plans + n);
     B->f.assign(f, f + n);
-    std::map<std::pair<const TableSet *, int>, int> gidx;
+    std::map<std::tuple<const TableSet *, int, int>, int> gidx;
     for (int i = 0; i < n; ++i) {
-        const auto key = std::make_pair((const TableSet *)plans[i]->tabs, (int)plans[i]->p.precision);
+        const auto key =
+            std::make_tuple((const TableSet *)plans[i]->tabs, (int)plans[i]->p.precision, (int)plans[i]->p.schedule);
         auto it = gidx.find(key);
         if (it == gidx.end()) {
             gidx[key] = (int)B->groups.size();
@@ -1381,28 +1437,52 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
             G.E.Dh.push_back(plans[m]->ih);
             ns = std::max(ns, plans[m]->nslots);
         }
-        std::vector<int> off(ns + 1, 0);
+        std::vector<int> off;
         std::vector<T1Item> items;
-        for (int sl = 0; sl < ns; ++sl) {
-            off[sl] = (int)items.size();
-            for (size_t j = 0; j < G.members.size(); ++j) {
-                const bnq_plan_s *P = plans[G.members[j]];
-                if (!(P->ih.terms & BNQ_T_QTRI) || sl >= P->nslots) continue;
-                for (int k = P->off_h[sl]; k < P->off_h[sl + 1]; ++k) {
-                    T1Item x = P->items_h[k];
-                    x.inst = (int)j;
-                    items.push_back(x);
+        const int nq = P0->nq;
+        if (nq) {
+            // dynamic: queue x holds every member's queue-x items, member by member
+            off.assign(1, 0);
+            for (int x = 0; x < nq; ++x) {
+                for (size_t j = 0; j < G.members.size(); ++j) {
+                    const bnq_plan_s *P = plans[G.members[j]];
+                    if (!(P->ih.terms & BNQ_T_QTRI)) continue;
+                    for (int k = P->off_h[x]; k < P->off_h[x + 1]; ++k) {
+                        T1Item it = P->items_h[k];
+                        it.inst = (int)j;
+                        items.push_back(it);
+                    }
+                }
+                off.push_back((int)items.size());
+            }
+        } else {
+            off.assign(ns + 1, 0);
+            for (int sl = 0; sl < ns; ++sl) {
+                off[sl] = (int)items.size();
+                for (size_t j = 0; j < G.members.size(); ++j) {
+                    const bnq_plan_s *P = plans[G.members[j]];
+                    if (!(P->ih.terms & BNQ_T_QTRI) || sl >= P->nslots) continue;
+                    for (int k = P->off_h[sl]; k < P->off_h[sl + 1]; ++k) {
+                        T1Item x = P->items_h[k];
+                        x.inst = (int)j;
+                        items.push_back(x);
+                    }
                 }
             }
+            off[ns] = (int)items.size();
         }
-        off[ns] = (int)items.size();
         bnq_status st;
         if ((st = upload(&G.D, G.E.Dh, "batch instance descriptors")) ||
-            (st = upload(&G.slot_off, off, "batch slot offsets")) ||
+            (!nq && (st = upload(&G.slot_off, off, "batch slot offsets"))) ||
+            (nq && (st = upload(&G.qoff, off, "batch queues"))) ||
+            (nq && (st = dalloc(&G.qctr, (size_t)((nq + 1) & ~1), "batch queue tickets"))) ||
             (!items.empty() && (st = upload(&G.items, items, "batch trilinear items")))) {
             destroy_batch(B);
             return st;
         }
+        G.E.nq = nq;
+        G.E.qoff = G.qoff;
+        G.E.qctr = G.qctr;
         G.E.D = G.D;
         G.E.nslots = ns;
         G.E.slot_off = G.slot_off;

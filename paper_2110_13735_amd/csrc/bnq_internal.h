@@ -183,8 +183,10 @@ void launch_to_f32(const double *in, float *out, int64_t n, hipStream_t s);
 void launch_outer(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 void launch_zero_part(const Geo &g, const Inst *D, const IOs &io, int max_slots, hipStream_t s);
 // prec 0: FP64 (K is double), 1: FP32c (K is float, spectra Inst::Gr32)
+// nq = 0: static per-slot lists; nq > 0: dynamic tickets over nq queues
 void launch_trilinear(const Geo &g, int prec, int nslots, const int *slot_off, const T1Item *items,
-                      const T1B *bdesc, const void *K, const Inst *D, const Rot *rots, hipStream_t s);
+                      const T1B *bdesc, const void *K, const Inst *D, const Rot *rots, int nq, const int *qoff,
+                      int *qctr, hipStream_t s);
 int trilinear_blocks_per_cu(int prec);  // resident 64-lane trilinear workgroups per CU (0 on error)
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_reduce_partials(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);

@@ -518,17 +518,43 @@ __device__ __forceinline__ const typename V2<T>::type *rotated_of(const Inst &I)
         return I.Gr32;
 }
 
+// Static schedule (nq = 0): slot blockIdx.x walks items[slot_off[slot] ..
+// slot_off[slot + 1]).  Dynamic schedule (nq > 0): the items are nq queues
+// (qoff), one per XCD; a wave takes the next item of its XCD's queue by
+// ticket (qctr, zeroed before the launch), then of the other queues.  Either
+// way a wave adds into partial array blockIdx.x of the item's instance.
 template <typename T>
 __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_off, const T1Item *items,
                                                        const T1B *bdesc, const T *K, const Inst *D,
-                                                       const Rot *rots) {
+                                                       const Rot *rots, int nq, const int *qoff, int *qctr) {
     using T2 = typename V2<T>::type;
     __shared__ T2 ps[2][64];
     const int slot = blockIdx.x;
     const int lane = threadIdx.x;
     const int A = 2 * g.N - 1;
-    const int it_end = slot_off[slot + 1];
-    for (int it = slot_off[slot]; it < it_end; ++it) {
+    int it = nq ? -1 : slot_off[slot] - 1;
+    const int it_end = nq ? 0 : slot_off[slot + 1];
+    int q = nq ? (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) % (unsigned)nq) : 0;
+    int qseen = 0;
+    for (;;) {
+        if (nq == 0) {
+            if (++it >= it_end) break;
+        } else {
+            int got = -1;
+            while (qseen < nq) {
+                int tk = 0;
+                if (lane == 0) tk = atomicAdd(qctr + q, 1);
+                tk = __builtin_amdgcn_readfirstlane(tk);
+                if (tk < qoff[q + 1] - qoff[q]) {
+                    got = qoff[q] + tk;
+                    break;
+                }
+                ++qseen;
+                q = q + 1 == nq ? 0 : q + 1;
+            }
+            if (got < 0) break;
+            it = got;
+        }
         const T1Item item = items[it];
         const T1B B = bdesc[item.b];
         const Inst &I = D[item.inst];
@@ -607,13 +633,14 @@ __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_of
 }
 
 void launch_trilinear(const Geo &g, int prec, int nslots, const int *slot_off, const T1Item *items,
-                      const T1B *bdesc, const void *K, const Inst *D, const Rot *rots, hipStream_t s) {
+                      const T1B *bdesc, const void *K, const Inst *D, const Rot *rots, int nq, const int *qoff,
+                      int *qctr, hipStream_t s) {
     if (prec == 0)
         hipLaunchKernelGGL(trilinear_kernel<double>, dim3(nslots), dim3(64), 0, s, g, slot_off, items, bdesc,
-                           (const double *)K, D, rots);
+                           (const double *)K, D, rots, nq, qoff, qctr);
     else
         hipLaunchKernelGGL(trilinear_kernel<float>, dim3(nslots), dim3(64), 0, s, g, slot_off, items, bdesc,
-                           (const float *)K, D, rots);
+                           (const float *)K, D, rots, nq, qoff, qctr);
 }
 
 int trilinear_blocks_per_cu(int prec) {

@@ -112,3 +112,28 @@ def test_batch_invalid_uses_raise():
             B.step(0.01, bnq.RK4, graph=True, stream=0)  # default stream: no capture
         with pytest.raises(bnq.BnqError):
             B.collide([fs[0], torch.empty_like(fs[1])])  # output aliases a state
+
+
+def test_dynamic_schedule_batch_matches_solo():
+    # dynamic tickets change the summation order between runs: compare to 1e-12
+    dev = torch.device("cuda:0")
+    plans, fs = [], []
+    for i, (d, N, eps) in enumerate([(3, 6, -1), (3, 6, 1), (3, 8, -1), (2, 16, 1)]):
+        f = inp.gaussian_mixture(d, N, 5.0, seed=70 + i, fmax=0.9 if eps == -1 else None)
+        plans.append(bnq.Plan(bnq.Params(d=d, N=N, eps=eps, L=5.0, schedule=bnq.SCHED_DYNAMIC)))
+        fs.append(torch.tensor(f, device=dev))
+    solo = []
+    for pl, f in zip(plans, fs):
+        Q = torch.empty_like(f)
+        pl.collide(f, Q)
+        solo.append(Q)
+    torch.cuda.synchronize()
+    with bnq.Batch(plans, fs) as B:
+        Qs = [torch.empty_like(f) for f in fs]
+        B.collide(Qs)
+        torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(solo, Qs)):
+        r = (torch.linalg.norm(a - b) / torch.linalg.norm(a)).item()
+        assert r <= 1e-12, f"instance {i}: {r}"
+    for pl in plans:
+        pl.close()

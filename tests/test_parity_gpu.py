@@ -344,3 +344,13 @@ def test_moments_correction_matches_oracle(d, N, eps):
     for a in range(d):
         assert abs(np.sum(v[..., a] * Q)) <= 1e-13 * scale
     assert abs(np.sum(np.sum(v * v, axis=-1) * Q)) <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("d,N,eps", [(2, 16, 1), (3, 10, -1)])
+def test_dynamic_schedule_matches_oracle(d, N, eps):
+    L = 5.0
+    f = inp.gaussian_mixture(d, N, L, seed=60 + N, fmax=0.9 if eps == -1 else None)
+    Q, Qh = _gpu_collide(bnq.Params(d=d, N=N, eps=eps, L=L, schedule=bnq.SCHED_DYNAMIC), f)
+    Qo, Qho, g, qg = _oracle_collide(d, N, f, eps, L)
+    _check(Qh, Qho, g)
+    _check(Q, Qo, qg)
