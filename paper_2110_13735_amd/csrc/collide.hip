@@ -304,10 +304,10 @@ void launch_outer(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
 // y-fastest kernel-mode rows.  For every inner row (py, pz) a lane slides a
 // 16-value window K(a_x), a_x = base + i - u, over the inner index u in blocks
 // of 8: block k uses lo_k[s] = K(base - 8k - 8 + s) and hi_k[s] =
-// K(base - 8k + s) = lo_{k-1}[s].  Three 8-value arrays rotate (at compile
-// time: the number of full blocks is a template parameter) so that the next
-// block's values are loaded while the current block computes, and the next
-// row's first window is loaded at the start of the current row.
+// K(base - 8k + s) = lo_{k-1}[s].  Four 8-value arrays rotate (at compile
+// time: the number of full blocks is a template parameter) so that the values
+// of block k + 2 are loaded while block k computes, and the next row's first
+// three arrays are loaded at the start of the current row.
 //
 // Kernel-mode values come through a buffer resource over the canonical row:
 // one 32-bit lane offset per window, the 8 values of a window at scalar
@@ -331,12 +331,16 @@ __device__ __forceinline__ T t1_kload(const T1Ctx<T> &c, int voff, int s) {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(c.kr, voff, s * c.sA, 0));
 }
 
-template <typename T, int K>
-__device__ __forceinline__ void t1_full(const T1Ctx<T> &c, T (&lo)[8], T (&hi)[8], T (&nx)[8], T (&zr)[T1_RB],
-                                        T (&zi)[T1_RB]) {
-    const int vq = c.voff - (8 * (K + 1) + 8) * c.sA;
+// Block K of a row: lo_K = K(base - 8K - 8 + s), hi_K = lo_{K-1}; issues the
+// loads of lo_{K+2} into nx (two blocks ahead) when PF.
+template <typename T, int K, bool PF>
+__device__ __forceinline__ void t1_full(const T1Ctx<T> &c, const T (&lo)[8], const T (&hi)[8], T (&nx)[8],
+                                        T (&zr)[T1_RB], T (&zi)[T1_RB]) {
+    if constexpr (PF) {
+        const int vq = c.voff - (8 * (K + 2) + 8) * c.sA;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) nx[s] = t1_kload(c, vq, s);
+        for (int s = 0; s < 8; ++s) nx[s] = t1_kload(c, vq, s);
+    }
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj) {
         const auto p = c.ps[8 * K + jj];
@@ -380,26 +384,29 @@ __device__ __forceinline__ void t1_tail(const T1Ctx<T> &c, int u0, int rem, cons
     }
 }
 
-// Blocks K .. NF-1 of a row, ring slots (S0, S1, S2) = (lo_0, hi_0, spare),
-// then the tail.  Slot of lo_k: 0,2,1,...; hi_k: 1,0,2,...; prefetch: 2,1,0,...
+// Blocks K .. NF-1 of a row, then the tail, over a four-slot ring: lo_j
+// lives in R[(j + 1) % 4] (R[0] = hi_0 = lo_{-1}, R[1] = lo_0, R[2] = lo_1 on
+// entry); block K reads R[(K + 1) % 4] and R[K % 4] and refills R[(K + 3) % 4]
+// with lo_{K+2}, needed two blocks later.
 template <typename T, int NF, int K>
-__device__ __forceinline__ void t1_blocks(const T1Ctx<T> &c, int rem, T (&S0)[8], T (&S1)[8], T (&S2)[8],
-                                          T (&zr)[T1_RB], T (&zi)[T1_RB]) {
+__device__ __forceinline__ void t1_blocks(const T1Ctx<T> &c, int rem, T (&R)[4][8], T (&zr)[T1_RB],
+                                          T (&zi)[T1_RB]) {
     if constexpr (K < NF) {
-        if constexpr (K % 3 == 0)
-            t1_full<T, K>(c, S0, S1, S2, zr, zi);
-        else if constexpr (K % 3 == 1)
-            t1_full<T, K>(c, S2, S0, S1, zr, zi);
-        else
-            t1_full<T, K>(c, S1, S2, S0, zr, zi);
-        t1_blocks<T, NF, K + 1>(c, rem, S0, S1, S2, zr, zi);
+        t1_full<T, K, (K + 2 <= NF)>(c, R[(K + 1) % 4], R[K % 4], R[(K + 3) % 4], zr, zi);
+        t1_blocks<T, NF, K + 1>(c, rem, R, zr, zi);
     } else {
-        if constexpr (K % 3 == 0)
-            t1_tail<T>(c, 8 * K, rem, S0, S1, zr, zi);
-        else if constexpr (K % 3 == 1)
-            t1_tail<T>(c, 8 * K, rem, S2, S0, zr, zi);
-        else
-            t1_tail<T>(c, 8 * K, rem, S1, S2, zr, zi);
+        t1_tail<T>(c, 8 * K, rem, R[(K + 1) % 4], R[K % 4], zr, zi);
+    }
+}
+
+// the first three ring slots of a row whose window offset is v
+template <typename T>
+__device__ __forceinline__ void t1_ring_start(const T1Ctx<T> &c, int v, T (&R)[4][8]) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        R[0][s] = t1_kload(c, v, s);
+        R[1][s] = t1_kload(c, v - 8 * c.sA, s);
+        R[2][s] = t1_kload(c, v - 16 * c.sA, s);
     }
 }
 
@@ -435,30 +442,26 @@ struct T1Pairs {
     }
 };
 
-// One inner row: compute it from (lo0, hi0) and the staged pair products
-// ps[cur], while the next row's window (into nl, nh) and pair products are
-// fetched.  Past the last row the fetches repeat the last row's addresses and
-// the staged pair products are zero, so that rows can run in pairs without
-// branches (an odd row count ends with one row that adds nothing).
+// One inner row: compute it from the ring R and the staged pair products
+// ps[cur], while the next row's first ring slots (into Rn) and pair products
+// are fetched.  Past the last row the fetches repeat the last row's
+// addresses and the staged pair products are zero, so that rows can run in
+// pairs without branches (an odd row count ends with one row that adds
+// nothing).
 template <typename T, int NF>
 __device__ __forceinline__ void t1_row(T1Ctx<T> &c, T1Rows &rw, int row, int nrows, int wpx, int lane,
-                                       const T1Pairs<T> &pr, typename V2<T>::type (*ps)[64], int cur, T (&lo0)[8],
-                                       T (&hi0)[8], T (&nl)[8], T (&nh)[8], T (&sp)[8], T (&zr)[T1_RB],
-                                       T (&zi)[T1_RB]) {
+                                       const T1Pairs<T> &pr, typename V2<T>::type (*ps)[64], int cur, T (&R)[4][8],
+                                       T (&Rn)[4][8], T (&zr)[T1_RB], T (&zi)[T1_RB]) {
     const bool more = row + 1 < nrows;
     const int vn = more ? rw.next() : rw.voff;
     const bool wrap = rw.py + 1 >= rw.wpy;
     const int npy = more ? (wrap ? 0 : rw.py + 1) : rw.py;
     const int npz = more && wrap ? rw.pz + 1 : rw.pz;
     const auto pn = pr.at(npz, npy);
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        nl[s] = t1_kload(c, vn - 8 * c.sA, s);
-        nh[s] = t1_kload(c, vn, s);
-    }
+    t1_ring_start(c, vn, Rn);
     c.voff = rw.voff;
     c.ps = ps[cur];
-    t1_blocks<T, NF, 0>(c, wpx - 8 * NF, lo0, hi0, sp, zr, zi);
+    t1_blocks<T, NF, 0>(c, wpx - 8 * NF, R, zr, zi);
     __syncthreads();
     const bool keep = more && lane < wpx;
     ps[cur ^ 1][lane].x = keep ? pn.x : (T)0;
@@ -473,15 +476,11 @@ __device__ __forceinline__ void t1_row(T1Ctx<T> &c, T1Rows &rw, int row, int nro
 template <typename T, int NF>
 __device__ __forceinline__ void t1_rows(T1Ctx<T> &c, T1Rows rw, int nrows, int wpx, int lane, const T1Pairs<T> &pr,
                                         typename V2<T>::type (*ps)[64], double (&Zr)[T1_RB], double (&Zi)[T1_RB]) {
-    T xl[8], xh[8], yl[8], yh[8], sp[8];
+    T RA[4][8], RB[4][8];
     T zr[T1_RB], zi[T1_RB];
 #pragma unroll
     for (int i = 0; i < T1_RB; ++i) zr[i] = zi[i] = (T)0;
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        xl[s] = t1_kload(c, rw.voff - 8 * c.sA, s);
-        xh[s] = t1_kload(c, rw.voff, s);
-    }
+    t1_ring_start(c, rw.voff, RA);
     {
         const auto p0 = pr.at(0, 0);
         const bool keep = lane < wpx;
@@ -490,8 +489,8 @@ __device__ __forceinline__ void t1_rows(T1Ctx<T> &c, T1Rows rw, int nrows, int w
     }
     __syncthreads();
     for (int row = 0; row < nrows; row += 2) {
-        t1_row<T, NF>(c, rw, row, nrows, wpx, lane, pr, ps, 0, xl, xh, yl, yh, sp, zr, zi);
-        t1_row<T, NF>(c, rw, row + 1, nrows, wpx, lane, pr, ps, 1, yl, yh, xl, xh, sp, zr, zi);
+        t1_row<T, NF>(c, rw, row, nrows, wpx, lane, pr, ps, 0, RA, RB, zr, zi);
+        t1_row<T, NF>(c, rw, row + 1, nrows, wpx, lane, pr, ps, 1, RB, RA, zr, zi);
         if constexpr (sizeof(T) == 4) {
 #pragma unroll
             for (int i = 0; i < T1_RB; ++i) {
