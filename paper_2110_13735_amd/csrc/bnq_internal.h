@@ -127,6 +127,31 @@ __device__ __forceinline__ void st2(double2 *p, int64_t i, double2 a) {
     ((gptr<dvec2>)p)[i] = v;
 }
 
+// complex products; FP64 / FP32 element types of the trilinear kernels
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+
+template <typename T>
+struct V2;
+template <>
+struct V2<double> {
+    using type = double2;
+};
+template <>
+struct V2<float> {
+    using type = float2;
+};
+
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double2 cmulT(double2 a, double2 b) { return cmul(a, b); }
+__device__ __forceinline__ float2 cmulT(float2 a, float2 b) { return cmulf(a, b); }
+__device__ __forceinline__ double2 ldT2(const double2 *p, int64_t i) { return ld2(p, i); }
+__device__ __forceinline__ float2 ldT2(const float2 *p, int64_t i) { return ld2f(p, i); }
+
+
 // ---- instances --------------------------------------------------------------
 // Every evaluation kernel runs over a set of instances that share the geometry
 // and the tables (one plan alone, or a batch group); blockIdx.z (or the work
@@ -187,6 +212,13 @@ void launch_zero_part(const Geo &g, const Inst *D, const IOs &io, int max_slots,
 void launch_trilinear(const Geo &g, int prec, int nslots, const int *slot_off, const T1Item *items,
                       const T1B *bdesc, const void *K, const Inst *D, const Rot *rots, int nq, const int *qoff,
                       int *qctr, hipStream_t s);
+void launch_t1_pairs(const Geo &g, int nslots, const int *slot_off, const T1Item *items, const T1B *bdesc,
+                     const double *K, const Inst *D, const Rot *rots, int nq, const int *qoff, int *qctr,
+                     hipStream_t s);
+void launch_t1_rows(const Geo &g, int nslots, const int *slot_off, const T1Item *items, const T1B *bdesc,
+                    const float *K, const Inst *D, const Rot *rots, int nq, const int *qoff, int *qctr, hipStream_t s);
+int t1_pairs_blocks_per_cu();
+int t1_rows_blocks_per_cu();
 int trilinear_blocks_per_cu(int prec);  // resident 64-lane trilinear workgroups per CU (0 on error)
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_reduce_partials(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);

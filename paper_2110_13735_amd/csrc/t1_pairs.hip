@@ -1,0 +1,451 @@
+// Trilinear sum T1 of the Galerkin operator, FP64 (section 'Fast spectral
+// approximation of the BNE operator'): inner rows in pairs.
+#include "bnq_internal.h"
+
+namespace bnq {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Trilinear sum.  One 64-lane workgroup per slot; each slot walks its static
+// list of items (b, range of <= 64 tasks) and accumulates into its own
+// partial array (no atomics; the slots are summed in a fixed order later).
+//
+// A task is 8 consecutive outputs along x at one (y, z); tasks are numbered
+// y fastest so that the lanes of a wave read consecutive addresses of the
+// y-fastest kernel-mode rows.  The inner rows (pz, py) are taken in pairs of
+// one plane, A = (pz, py) and B = (pz, py + 1): B needs a_y = ny - py - 1,
+// the value just below A's in the table, so one 16-byte load per lane brings
+// both (a pair at the end of a plane with an odd row count has an empty B).
+// For its two rows a lane slides a 16-value window K(a_x), a_x = base + i -
+// u, over the inner index u in blocks of 8: block k uses lo_k[s] = K(base -
+// 8k - 8 + s) and hi_k[s] = K(base - 8k + s) = lo_{k-1}[s].  Three 8-value
+// arrays rotate (at compile time: the number of full blocks is a template
+// parameter) so that the values of block k + 1 are loaded while block k
+// computes, and the next pair's first two arrays are loaded at the start of
+// the current pair.
+//
+// Kernel-mode values come through a buffer resource over the canonical row:
+// one 32-bit lane offset per window, the 8 values of a window at scalar
+// offsets s * 8A.  The pair products of a row are uniform across the wave:
+// the next pair's are formed (one p_x per lane, from the rotated spectrum)
+// while the current pair computes, then written to a two-stage LDS ring and
+// read as broadcasts.
+template <typename T>
+struct T1Ctx {
+    __amdgpu_buffer_rsrc_t kr;            // canonical kernel-mode row
+    int voff;                             // byte offset of K(a_x = base) at row A's (a_z, a_y)
+    int sA;                               // bytes between consecutive a_x
+    const typename V2<T>::type (*PA)[4], (*PB)[4];  // pair-product columns of rows A and B
+};
+
+// (K at row B, K at row A) of slot s of the window at voff: neighbours in the
+// y-fastest table, one load
+template <typename T>
+__device__ __forceinline__ typename V2<T>::type t1_kload(const T1Ctx<T> &c, int voff, int s) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(c.kr, voff - 8, s * c.sA, 0));
+    else
+        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(c.kr, voff - 4, s * c.sA, 0));
+}
+
+// column registers of pair products a row of NF full blocks can need
+// (positions below 8 NF + 8, never more than 64)
+template <int NF>
+constexpr int t1_ncol() { return (8 * NF + 7) / 16 + 1 < 4 ? (8 * NF + 7) / 16 + 1 : 4; }
+
+// The 16 FMAs of one row at inner position u: zr[i] += k[i] P(u).x,
+// zi[i] += k[i] P(u).y, P(u) taken from lane u % 16 of each 16-lane row of
+// (px, py) by a DPP row broadcast.  The leading s_nop covers the wait states
+// a DPP source needs after a VALU write of it (or of EXEC).  The statement is
+// volatile so that the loads placed between steps keep their places.
+#define T1_BC16(OP)                                                                 \
+    "s_nop 4\n\t"                                                                   \
+    OP " %0, %16, %18 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
+    OP " %8, %17, %18 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
+    OP " %1, %16, %19 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
+    OP " %9, %17, %19 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
+    OP " %2, %16, %20 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
+    OP " %10, %17, %20 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"             \
+    OP " %3, %16, %21 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
+    OP " %11, %17, %21 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"             \
+    OP " %4, %16, %22 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
+    OP " %12, %17, %22 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"             \
+    OP " %5, %16, %23 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
+    OP " %13, %17, %23 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"             \
+    OP " %6, %16, %24 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
+    OP " %14, %17, %24 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"             \
+    OP " %7, %16, %25 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
+    OP " %15, %17, %25 row_newbcast:%26 row_mask:0xf bank_mask:0xf"
+
+template <typename T, int U>
+__device__ __forceinline__ void t1_fma16(T (&zr)[T1_RB], T (&zi)[T1_RB], T px, T py, T k0, T k1, T k2, T k3, T k4,
+                                         T k5, T k6, T k7) {
+    if constexpr (sizeof(T) == 8)
+        asm volatile(T1_BC16("v_fmac_f64_dpp")
+                     : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zr[6]),
+                       "+v"(zr[7]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]),
+                       "+v"(zi[6]), "+v"(zi[7])
+                     : "v"(px), "v"(py), "v"(k0), "v"(k1), "v"(k2), "v"(k3), "v"(k4), "v"(k5), "v"(k6), "v"(k7),
+                       "i"(U % 16));
+    else
+        asm volatile(T1_BC16("v_fmac_f32_dpp")
+                     : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zr[6]),
+                       "+v"(zr[7]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]),
+                       "+v"(zi[6]), "+v"(zi[7])
+                     : "v"(px), "v"(py), "v"(k0), "v"(k1), "v"(k2), "v"(k3), "v"(k4), "v"(k5), "v"(k6), "v"(k7),
+                       "i"(U % 16));
+}
+
+// Inner position u = 8 K + jj of both rows of a pair: row A (the .y halves of
+// the window, pair products PA) then row B (.x halves, PB).
+template <typename T, int U, int JJ>
+__device__ __forceinline__ void t1_pos(const typename V2<T>::type (&lo)[8], const typename V2<T>::type (&hi)[8],
+                                       const typename V2<T>::type (&PA)[4], const typename V2<T>::type (&PB)[4],
+                                       T (&zr)[T1_RB], T (&zi)[T1_RB]) {
+    // positions stay below 64 (a row has at most N <= 64 inner values); the
+    // clamp only keeps the never-taken tail of an 8-block row in bounds
+    constexpr int C = U / 16 < 4 ? U / 16 : 3;
+#define T1_K(i, c) ((i) - JJ < 0 ? lo[(i) - JJ + 8].c : hi[(i) - JJ].c)
+    t1_fma16<T, U>(zr, zi, PA[C].x, PA[C].y, T1_K(0, y), T1_K(1, y), T1_K(2, y), T1_K(3, y), T1_K(4, y),
+                   T1_K(5, y), T1_K(6, y), T1_K(7, y));
+    t1_fma16<T, U>(zr, zi, PB[C].x, PB[C].y, T1_K(0, x), T1_K(1, x), T1_K(2, x), T1_K(3, x), T1_K(4, x),
+                   T1_K(5, x), T1_K(6, x), T1_K(7, x));
+#undef T1_K
+}
+
+// Block K of a pair: lo_K = K(base - 8K - 8 + s), hi_K = lo_{K-1}; issues the
+// loads of lo_{K+1} into nx first.
+template <typename T, int K>
+__device__ __forceinline__ void t1_full(const T1Ctx<T> &c, const typename V2<T>::type (&lo)[8],
+                                        const typename V2<T>::type (&hi)[8], typename V2<T>::type (&nx)[8],
+                                        T (&zr)[T1_RB], T (&zi)[T1_RB]) {
+    const int vq = c.voff - (8 * (K + 1) + 8) * c.sA;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) nx[s] = t1_kload(c, vq, s);
+    t1_pos<T, 8 * K + 0, 0>(lo, hi, *c.PA, *c.PB, zr, zi);
+    t1_pos<T, 8 * K + 1, 1>(lo, hi, *c.PA, *c.PB, zr, zi);
+    t1_pos<T, 8 * K + 2, 2>(lo, hi, *c.PA, *c.PB, zr, zi);
+    t1_pos<T, 8 * K + 3, 3>(lo, hi, *c.PA, *c.PB, zr, zi);
+    t1_pos<T, 8 * K + 4, 4>(lo, hi, *c.PA, *c.PB, zr, zi);
+    t1_pos<T, 8 * K + 5, 5>(lo, hi, *c.PA, *c.PB, zr, zi);
+    t1_pos<T, 8 * K + 6, 6>(lo, hi, *c.PA, *c.PB, zr, zi);
+    t1_pos<T, 8 * K + 7, 7>(lo, hi, *c.PA, *c.PB, zr, zi);
+}
+
+// the last rem (< 8) positions 8 NF + jj of a pair: uniform branches that
+// update the accumulators in place
+template <typename T, int NF>
+__device__ __forceinline__ void t1_tail(const T1Ctx<T> &c, int rem, const typename V2<T>::type (&lo)[8],
+                                        const typename V2<T>::type (&hi)[8], T (&zr)[T1_RB], T (&zi)[T1_RB]) {
+    if (rem > 0) t1_pos<T, 8 * NF + 0, 0>(lo, hi, *c.PA, *c.PB, zr, zi);
+    if (rem > 1) t1_pos<T, 8 * NF + 1, 1>(lo, hi, *c.PA, *c.PB, zr, zi);
+    if (rem > 2) t1_pos<T, 8 * NF + 2, 2>(lo, hi, *c.PA, *c.PB, zr, zi);
+    if (rem > 3) t1_pos<T, 8 * NF + 3, 3>(lo, hi, *c.PA, *c.PB, zr, zi);
+    if (rem > 4) t1_pos<T, 8 * NF + 4, 4>(lo, hi, *c.PA, *c.PB, zr, zi);
+    if (rem > 5) t1_pos<T, 8 * NF + 5, 5>(lo, hi, *c.PA, *c.PB, zr, zi);
+    if (rem > 6) t1_pos<T, 8 * NF + 6, 6>(lo, hi, *c.PA, *c.PB, zr, zi);
+}
+
+// Steps K .. NF of a pair (K < NF: full block K, K = NF: the tail).  Slot
+// block j (lo_j, j = -1 .. NF) of the pair is S[j + 1]; S[0] and S[1] arrive
+// from the previous pair.  Step K computes block K from S[K + 1] (lo) and
+// S[K] (hi) while loading lo_{K+1} into S[K + 2]; the last steps load the
+// next pair's first two slot blocks (N0 at step max(NF - 1, 0), N1 at step
+// NF), so that at most four slot blocks are live at once.
+template <typename T, int NF, int K>
+__device__ __forceinline__ void t1_steps(const T1Ctx<T> &c, int rem, int vn, typename V2<T>::type (&S)[NF + 2][8],
+                                         typename V2<T>::type (&N0)[8], typename V2<T>::type (&N1)[8],
+                                         T (&zr)[T1_RB], T (&zi)[T1_RB]) {
+    if constexpr (K == (NF > 0 ? NF - 1 : 0)) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) N0[s] = t1_kload(c, vn, s);
+    }
+    if constexpr (K == NF) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) N1[s] = t1_kload(c, vn - 8 * c.sA, s);
+    }
+    if constexpr (K < NF) {
+        t1_full<T, K>(c, S[K + 1], S[K], S[K + 2], zr, zi);
+        t1_steps<T, NF, K + 1>(c, rem, vn, S, N0, N1, zr, zi);
+    } else {
+        t1_tail<T, NF>(c, rem, S[K + 1], S[K], zr, zi);
+    }
+}
+
+// the first two slot blocks of a pair whose window offset is v
+template <typename T>
+__device__ __forceinline__ void t1_ring_start(const T1Ctx<T> &c, int v, typename V2<T>::type (&N0)[8],
+                                              typename V2<T>::type (&N1)[8]) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        N0[s] = t1_kload(c, v, s);
+        N1[s] = t1_kload(c, v - 8 * c.sA, s);
+    }
+}
+
+// Walks the row pairs in (pz, py) order, py = 0, 2, 4, ... within a plane;
+// the window offset of row (pz, py) is voff0 - pz dz - py dy.
+struct T1Rows {
+    int voff0, voff, py, pz, wpy, dz, dy;
+    __device__ __forceinline__ void next(int &z, int &y) const {
+        y = py + 2 < wpy ? py + 2 : 0;
+        z = py + 2 < wpy ? pz : pz + 1;
+    }
+    __device__ __forceinline__ int offset(int z, int y) const { return voff0 - z * dz - y * dy; }
+};
+
+// Pair products P_b(p) = G_R(p) G_R(b_c - p) of the inner window, formed on
+// the fly from the rotated spectrum (one lane per p_x of a row).
+template <typename T>
+struct T1Pairs {
+    using T2 = typename V2<T>::type;
+    const T2 *G;     // rotated spectrum G_R on {-N/2 .. N/2}^d
+    int X, h, d3;    // N + 1, N / 2, d == 3
+    int px, qx;      // storage x-indices of p_x and b_c,x - p_x for this lane
+    int bz, by;      // b_c,z and b_c,y
+    int pzlo, pylo;  // inner window start
+    __device__ __forceinline__ T2 at(int pzi, int pyi) const {
+        const int pz = pzlo + pzi, py = pylo + pyi;
+        const int64_t ip = ((int64_t)(d3 ? pz + h : 0) * X + (py + h)) * X + px;
+        const int64_t iq = ((int64_t)(d3 ? bz - pz + h : 0) * X + (by - py + h)) * X + qx;
+        return cmulT(ldT2(G, ip), ldT2(G, iq));
+    }
+};
+
+// Pair products of the next pair: lane l stores P(l) of rows A and B (zero
+// past the window, for an empty B, or past the last pair), then reads back
+// P(16 c + l % 16) of both rows for every column c.  The rows belong to the
+// single wavefront of the workgroup, whose LDS accesses complete in program
+// order.
+template <typename T, int NC>
+__device__ __forceinline__ void t1_exchange(typename V2<T>::type (*pl)[64], int lane, bool keepa, bool keepb,
+                                            const typename V2<T>::type &pa, const typename V2<T>::type &pb,
+                                            typename V2<T>::type (&PA)[4], typename V2<T>::type (&PB)[4]) {
+    typename V2<T>::type va, vb;
+    va.x = keepa ? pa.x : (T)0;
+    va.y = keepa ? pa.y : (T)0;
+    vb.x = keepb ? pb.x : (T)0;
+    vb.y = keepb ? pb.y : (T)0;
+    pl[0][lane] = va;
+    pl[1][lane] = vb;
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+        PA[cc] = pl[0][16 * cc + (lane & 15)];
+        PB[cc] = pl[1][16 * cc + (lane & 15)];
+    }
+}
+
+// One pair of inner rows: compute it from its first two slot blocks (N0,
+// N1 on entry; they are replaced by the next pair's) and its pair-product
+// columns (PA, PB; replaced by the next pair's).  Past the last pair the
+// fetches repeat the last pair's addresses and the pair products are zero.
+template <typename T, int NF>
+__device__ __forceinline__ void t1_pair(T1Ctx<T> &c, T1Rows &rw, int k, int npairs, int wpx, int lane,
+                                        const T1Pairs<T> &pr, typename V2<T>::type (*pl)[64],
+                                        typename V2<T>::type (&N0)[8], typename V2<T>::type (&N1)[8],
+                                        typename V2<T>::type (&PA)[4], typename V2<T>::type (&PB)[4],
+                                        T (&zr)[T1_RB], T (&zi)[T1_RB]) {
+    using T2 = typename V2<T>::type;
+    const bool more = k + 1 < npairs;
+    int npz, npy;
+    rw.next(npz, npy);
+    npz = more ? npz : rw.pz;
+    npy = more ? npy : rw.py;
+    const bool hasb = npy + 1 < rw.wpy;
+    const auto pna = pr.at(npz, npy);
+    const auto pnb = pr.at(npz, hasb ? npy + 1 : npy);
+    const int vn = rw.offset(npz, npy);
+    T2 S[NF + 2][8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        S[0][s] = N0[s];
+        S[1][s] = N1[s];
+    }
+    c.voff = rw.voff;
+    c.PA = &PA;
+    c.PB = &PB;
+    t1_steps<T, NF, 0>(c, wpx - 8 * NF, vn, S, N0, N1, zr, zi);
+    const bool keepa = more && lane < wpx;
+    t1_exchange<T, t1_ncol<NF>()>(pl, lane, keepa, keepa && hasb, pna, pnb, PA, PB);
+    rw.pz = npz;
+    rw.py = npy;
+    rw.voff = vn;
+}
+
+// All row pairs of an item.  FP64 accumulates every pair in zr/zi; FP32
+// accumulates one pair (at most 128 terms per output) in FP32 and adds it to
+// the FP64 totals Zr/Zi.
+template <typename T, int NF>
+__device__ __forceinline__ void t1_rows(T1Ctx<T> &c, T1Rows rw, int npairs, int wpx, int lane, const T1Pairs<T> &pr,
+                                        typename V2<T>::type (*pl)[64], double (&Zr)[T1_RB], double (&Zi)[T1_RB]) {
+    typename V2<T>::type N0[8], N1[8], PA[4], PB[4];
+    T zr[T1_RB], zi[T1_RB];
+#pragma unroll
+    for (int i = 0; i < T1_RB; ++i) zr[i] = zi[i] = (T)0;
+    t1_ring_start(c, rw.voff, N0, N1);
+    {
+        const bool hasb = 1 < rw.wpy;
+        const bool keepa = lane < wpx;
+        t1_exchange<T, t1_ncol<NF>()>(pl, lane, keepa, keepa && hasb, pr.at(0, 0), pr.at(0, hasb ? 1 : 0), PA, PB);
+    }
+    for (int k = 0; k < npairs; ++k) {
+        t1_pair<T, NF>(c, rw, k, npairs, wpx, lane, pr, pl, N0, N1, PA, PB, zr, zi);
+        if constexpr (sizeof(T) == 4) {
+#pragma unroll
+            for (int i = 0; i < T1_RB; ++i) {
+                Zr[i] += (double)zr[i];
+                Zi[i] += (double)zi[i];
+                zr[i] = zi[i] = 0.0f;
+            }
+        }
+    }
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int i = 0; i < T1_RB; ++i) {
+            Zr[i] = zr[i];
+            Zi[i] = zi[i];
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ const typename V2<T>::type *rotated_of(const Inst &I) {
+    if constexpr (sizeof(T) == 8)
+        return I.Gr;
+    else
+        return I.Gr32;
+}
+
+// Static schedule (nq = 0): slot blockIdx.x walks items[slot_off[slot] ..
+// slot_off[slot + 1]).  Dynamic schedule (nq > 0): the items are nq queues
+// (qoff), one per XCD; a wave takes the next item of its XCD's queue by
+// ticket (qctr, zeroed before the launch), then of the other queues.  Either
+// way a wave adds into partial array blockIdx.x of the item's instance.
+template <typename T>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void trilinear_kernel(Geo g, const int *slot_off, const T1Item *items,
+                                                       const T1B *bdesc, const T *K, const Inst *D,
+                                                       const Rot *rots, int nq, const int *qoff, int *qctr) {
+    using T2 = typename V2<T>::type;
+    __shared__ T2 pl[2][64];  // pair products of rows A and B, one p_x per lane
+    const int slot = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int A = 2 * g.N - 1;
+    int it = nq ? -1 : slot_off[slot] - 1;
+    const int it_end = nq ? 0 : slot_off[slot + 1];
+    int q = nq ? (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) % (unsigned)nq) : 0;
+    int qseen = 0;
+    for (;;) {
+        if (nq == 0) {
+            if (++it >= it_end) break;
+        } else {
+            int got = -1;
+            while (qseen < nq) {
+                int tk = 0;
+                if (lane == 0) tk = atomicAdd(qctr + q, 1);
+                tk = __builtin_amdgcn_readfirstlane(tk);
+                if (tk < qoff[q + 1] - qoff[q]) {
+                    got = qoff[q] + tk;
+                    break;
+                }
+                ++qseen;
+                q = q + 1 == nq ? 0 : q + 1;
+            }
+            if (got < 0) break;
+            it = got;
+        }
+        const T1Item item = items[it];
+        const T1B B = bdesc[item.b];
+        const Inst &I = D[item.inst];
+        double2 *mypart = I.part + (int64_t)slot * g.nm;
+        const bool active = lane < item.nt;
+        const int t = item.t0 + (active ? lane : 0);
+        const int wny = B.wnhi[1] - B.wnlo[1] + 1;
+        const int ny = B.wnlo[1] + t % wny;
+        const int rest = t / wny;
+        const int xb = rest % B.nxb;
+        const int nz = B.wnlo[0] + rest / B.nxb;
+        const int x0 = B.wnlo[2] + xb * T1_RB;
+        const int base = x0 - B.wplo[2];  // a_x = base + i - u
+        const int wpx = B.wphi[2] - B.wplo[2] + 1;
+        T1Ctx<T> c;
+        // the row is uniform; saying so keeps the buffer resource in scalar
+        // registers (otherwise every load becomes a loop over lanes)
+        const int kc = __builtin_amdgcn_readfirstlane(B.kc);
+        c.kr = __builtin_amdgcn_make_buffer_rsrc((void *)(K + (int64_t)kc * g.nak), (short)0,
+                                                 (int)(g.nak * (int64_t)sizeof(T)), 0x00020000);
+        c.sA = A * (int)sizeof(T);
+        T1Rows rw;
+        rw.voff0 = (int)(idx_K(g, nz - B.wplo[0], ny - B.wplo[1], base) * (int64_t)sizeof(T));
+        rw.voff = rw.voff0;
+        rw.py = 0;
+        rw.pz = 0;
+        rw.wpy = B.wphi[1] - B.wplo[1] + 1;
+        rw.dy = (int)sizeof(T);
+        rw.dz = (g.d == 3 ? g.kax * A : 0) * (int)sizeof(T);
+        const int npairs = (rw.wpy + 1) / 2 * (B.wphi[0] - B.wplo[0] + 1);
+        const T2 *G = rotated_of<T>(I) + (int64_t)B.rot * g.next;
+        T1Pairs<T> pr;
+        pr.G = G;
+        pr.X = g.N + 1;
+        pr.h = g.h;
+        pr.d3 = g.d == 3;
+        pr.px = B.wplo[2] + min(lane, wpx - 1) + g.h;
+        pr.qx = B.bc[2] - (B.wplo[2] + min(lane, wpx - 1)) + g.h;
+        pr.bz = B.bc[0];
+        pr.by = B.bc[1];
+        pr.pzlo = B.wplo[0];
+        pr.pylo = B.wplo[1];
+        double zr[T1_RB], zi[T1_RB];
+#pragma unroll
+        for (int i = 0; i < T1_RB; ++i) zr[i] = zi[i] = 0.0;
+        switch (wpx >> 3) {
+            case 0: t1_rows<T, 0>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
+            case 1: t1_rows<T, 1>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
+            case 2: t1_rows<T, 2>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
+            case 3: t1_rows<T, 3>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
+            case 4: t1_rows<T, 4>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
+            case 5: t1_rows<T, 5>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
+            case 6: t1_rows<T, 6>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
+            case 7: t1_rows<T, 7>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
+            default: t1_rows<T, 8>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
+        }
+        if (active) {
+            const Rot R = rots[B.rot];
+#pragma unroll
+            for (int i = 0; i < T1_RB; ++i) {
+                const int nx = x0 + i;
+                if (nx <= B.wnhi[2]) {
+                    const T2 gq = ldT2(G, idx_X(g, nz - B.bc[0], ny - B.bc[1], nx - B.bc[2]));
+                    const double2 cc = cmul(make_double2(gq.x, gq.y), make_double2(zr[i], zi[i]));
+                    const int v[3] = {nz, ny, nx};
+                    const int o0 = R.sgn[0] * v[R.perm[0]];
+                    const int o1 = R.sgn[1] * v[R.perm[1]];
+                    const int o2 = R.sgn[2] * v[R.perm[2]];
+                    const int64_t o = idx_I(g, o0, o1, o2);
+                    double2 cur = ld2(mypart, o);
+                    cur.x += cc.x;
+                    cur.y += cc.y;
+                    st2(mypart, o, cur);
+                }
+            }
+        }
+        // the next item may read back outputs written here by other lanes
+        __threadfence_block();
+    }
+}
+
+
+}  // namespace
+
+void launch_t1_pairs(const Geo &g, int nslots, const int *slot_off, const T1Item *items, const T1B *bdesc,
+                     const double *K, const Inst *D, const Rot *rots, int nq, const int *qoff, int *qctr, hipStream_t s) {
+    hipLaunchKernelGGL(trilinear_kernel<double>, dim3(nslots), dim3(64), 0, s, g, slot_off, items, bdesc, K, D, rots,
+                       nq, qoff, qctr);
+}
+
+int t1_pairs_blocks_per_cu() {
+    int nb = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trilinear_kernel<double>, 64, 0) == hipSuccess ? nb : 0;
+}
+
+}  // namespace bnq
