@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "collision pair-terms/s at N=32^3 (FP32c vs FP64); p50/p99 solve latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trilinear_3d32_fp64_hbm_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_13735_amd", "csrc", "collide.hip")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_13735_amd", "csrc", "t1_pairs.hip")
 PEAK_FP64_VALU = 78.6e12  # MI355X dense FP64 vector, FLOP/s
 PEAK_FP32_VALU = 157.3e12  # MI355X dense FP32 vector, FLOP/s (published; counts packed FP32)
 FLOPS_PER_T1_TERM = 4.0   # one real x complex multiply-add (two FMAs)
