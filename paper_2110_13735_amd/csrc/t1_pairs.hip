@@ -55,11 +55,13 @@ constexpr int t1_ncol() { return (8 * NF + 7) / 16 + 1 < 4 ? (8 * NF + 7) / 16 +
 
 // The 16 FMAs of one row at inner position u: zr[i] += k[i] P(u).x,
 // zi[i] += k[i] P(u).y, P(u) taken from lane u % 16 of each 16-lane row of
-// (px, py) by a DPP row broadcast.  The leading s_nop covers the wait states
-// a DPP source needs after a VALU write of it (or of EXEC).  The statement is
-// volatile so that the loads placed between steps keep their places.
+// (px, py) by a DPP row broadcast.  The leading s_nop 1 gives the two wait
+// states a DPP source needs after a VALU write of it; a VALU write of EXEC
+// would need five, and no instruction of this kernel makes one (the compiled
+// kernel is checked for v_cmpx by the test suite).  The statement is volatile
+// so that the loads placed between steps keep their places.
 #define T1_BC16(OP)                                                                 \
-    "s_nop 4\n\t"                                                                   \
+    "s_nop 1\n\t"                                                                   \
     OP " %0, %16, %18 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
     OP " %8, %17, %18 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
     OP " %1, %16, %19 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
