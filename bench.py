@@ -29,10 +29,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+STATS = {-1: "fermions", 0: "classical", 1: "bosons"}
 METRIC = "collision pair-terms/s at N=32^3 (FP32c vs FP64); p50/p99 solve latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trilinear_3d32_fp64_hbm_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_13735_amd", "csrc", "t1_pairs.hip")
 PEAK_FP64_VALU = 78.6e12  # MI355X dense FP64 vector, FLOP/s
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E, GB/s
 PEAK_FP32_VALU = 157.3e12  # MI355X dense FP32 vector, FLOP/s (published; counts packed FP32)
 FLOPS_PER_T1_TERM = 4.0   # one real x complex multiply-add (two FMAs)
 
@@ -98,6 +100,9 @@ def main():
     ap.add_argument("--N", type=int, default=32)
     ap.add_argument("--dt", type=float, default=0.01)
     ap.add_argument("--precision", choices=("fp64", "fp32c"), default="fp64")
+    ap.add_argument("--eps", type=int, choices=(-1, 0, 1), default=-1,
+                    help="statistics: -1 fermions (default, the trilinear-bound workload), +1 bosons, "
+                         "0 classical (only the weight streaming of the pair sums: HBM-bound)")
     ap.add_argument("--schedule", choices=("static", "dynamic"), default="dynamic",
                     help="trilinear work distribution: dynamic (default here, fastest; last bits may vary "
                          "between runs) or static (the library default, bitwise reproducible)")
@@ -132,7 +137,7 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    N, L, eps = args.N, 8.0, -1
+    N, L, eps = args.N, 8.0, args.eps
     prec = bnq.FP32C if args.precision == "fp32c" else bnq.FP64
     sched = bnq.SCHED_DYNAMIC if args.schedule == "dynamic" else bnq.SCHED_STATIC
     p = bnq.Params(d=3, N=N, eps=eps, L=L, precision=prec, schedule=sched)
@@ -166,19 +171,35 @@ def main():
     ms_step = 1e3 * elapsed / args.steps
     value = terms_step / (elapsed / args.steps)
 
-    t1_ms, t1_n = kt["trilinear"]
-    t1_avg_s = (t1_ms / t1_n) * 1e-3 if t1_n else float("nan")
-    flops_launch = counts["trilinear"] * FLOPS_PER_T1_TERM
-    achieved = flops_launch / t1_avg_s / 1e12
-    tr = measured_traffic() if prec == bnq.FP64 else None
-    peak = PEAK_FP32_VALU if prec == bnq.FP32C else PEAK_FP64_VALU
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": round(achieved * 1e12 / peak, 4),
-                "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None,
-                "kernel": "trilinear_kernel", "avg_ms": round(t1_avg_s * 1e3, 3), "launches": t1_n,
-                "flops_per_launch": flops_launch}
-    if tr:
-        roofline["traffic_detail"] = {k: tr[k] for k in ("fetch_bytes", "write_bytes", "fetch_scale", "write_scale")}
+    if eps != 0:
+        t1_ms, t1_n = kt["trilinear"]
+        t1_avg_s = (t1_ms / t1_n) * 1e-3 if t1_n else float("nan")
+        flops_launch = counts["trilinear"] * FLOPS_PER_T1_TERM
+        achieved = flops_launch / t1_avg_s / 1e12
+        tr = measured_traffic() if (prec == bnq.FP64 and eps == -1) else None
+        peak = PEAK_FP32_VALU if prec == bnq.FP32C else PEAK_FP64_VALU
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak / 1e12,
+                    "unit": "TFLOP/s", "frac": round(achieved * 1e12 / peak, 4),
+                    "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None,
+                    "kernel": "trilinear_kernel", "avg_ms": round(t1_avg_s * 1e3, 3), "launches": t1_n,
+                    "flops_per_launch": flops_launch}
+        if tr:
+            roofline["traffic_detail"] = {k: tr[k] for k in ("fetch_bytes", "write_bytes", "fetch_scale",
+                                                             "write_scale")}
+        roofline["measured_peaks"] = measured_peaks(torch, dev)
+        roofline["frac_of_measured_fp64_gemm"] = \
+            round(achieved / roofline["measured_peaks"]["fp64_gemm_tflops"], 4) if prec == bnq.FP64 else None
+    else:
+        # classical: the pair sums stream one weight per (l, m) with l + m in I_N
+        pr_ms, pr_n = kt["pairs"]
+        pr_avg_s = (pr_ms / pr_n) * 1e-3 if pr_n else float("nan")
+        bytes_launch = counts["classical"] * (4 if prec == bnq.FP32C else 8)
+        achieved = bytes_launch / pr_avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "kernel": "pairs_kernel",
+                    "avg_ms": round(pr_avg_s * 1e3, 4), "launches": pr_n, "bytes_per_launch": bytes_launch}
+        roofline["measured_peaks"] = measured_peaks(torch, dev)
+        roofline["frac_of_measured_copy"] = round(achieved / roofline["measured_peaks"]["hbm_copy_GB_s"], 4)
     if args.copy_calibration:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
         b = torch.empty_like(a)
@@ -199,7 +220,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32c" if prec == bnq.FP32C else "f64",
         "data": "synthetic",
-        "config": {"workload": f"3-D fermions eps=-1, N={N}^3, {args.precision.upper()}, hard spheres, hbar=1, L=8, "
+        "config": {"workload": f"3-D {STATS[eps]} eps={eps}, N={N}^3, {args.precision.upper()}, hard spheres, hbar=1, L=8, "
                                f"three-Gaussian f0 (seed 0), RK4 dt={args.dt}, moments every step",
                    "d": 3, "N": N, "eps": eps, "precision": args.precision, "schedule": args.schedule,
                    "scheme": "rk4", "dt": args.dt,
@@ -213,6 +234,38 @@ def main():
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_N)
     plan.close()
     print(json.dumps(out))
+
+
+def measured_peaks(torch, dev):
+    """What this machine sustains right now, beside the published peaks: a 1 GiB
+    device copy (read + write bytes / time) and an FP64 GEMM through the vendor
+    library (8192^3, 2 flops per multiply-add).  Both run after the timed
+    region; they are context for the roofline fraction, not part of the path."""
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * a.numel() * 8 * reps / (time.perf_counter() - t0) / 1e9
+    del a, b
+    n = 8192
+    x = torch.rand(n, n, dtype=torch.float64, device=dev)
+    y = torch.rand(n, n, dtype=torch.float64, device=dev)
+    z = torch.matmul(x, y)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        z = torch.matmul(x, y)
+    torch.cuda.synchronize()
+    gemm_tf = 2.0 * n ** 3 * reps / (time.perf_counter() - t0) / 1e12
+    del x, y, z
+    torch.cuda.empty_cache()
+    return {"hbm_copy_GB_s": round(copy_gbs, 1), "fp64_gemm_tflops": round(gemm_tf, 2)}
 
 
 BATCH_CELLS = {"mixed": [(2, 16), (2, 24), (2, 32), (3, 16), (3, 24)],

@@ -432,7 +432,7 @@ struct bnq_plan_s {
     Rot *rots_d = nullptr;
     double2 *tw = nullptr;
     double2 *Ghat = nullptr, *tmp = nullptr, *tmp2 = nullptr, *Gr = nullptr, *W = nullptr, *Qc = nullptr,
-            *T1 = nullptr, *X = nullptr, *Qh = nullptr, *part = nullptr;
+            *T1 = nullptr, *X = nullptr, *Qh = nullptr, *part = nullptr, *ppart = nullptr;
     float2 *G32 = nullptr, *Gr32 = nullptr;  // FP32c spectra
     int nbdesc = 0;
     double *kbuf[4] = {nullptr, nullptr, nullptr, nullptr}, *ybuf = nullptr;
@@ -523,7 +523,8 @@ size_t plan_workspace_bytes(const bnq_params *p, int nslots_est) {
     const size_t c = sizeof(double2), r = sizeof(double);
     const size_t nrot = p->d == 3 ? 48 : 8;
     const size_t f32 = p->precision == BNQ_FP32C ? sizeof(float2) * ((size_t)g.nm + nrot * g.next) : 0;
-    return c * (6 * (size_t)g.nm + g.neg + nrot * g.next + (size_t)nslots_est * g.nm) +
+    return c * (6 * (size_t)g.nm + g.neg + nrot * g.next + (size_t)nslots_est * g.nm +
+                (size_t)pair_split(g) * ((size_t)g.neg + g.nm)) +
            r * 5 * (size_t)g.nm + f32;
 }
 
@@ -751,6 +752,7 @@ void destroy_plan(bnq_plan_s *P) {
     hipFree(P->tmp2);
     hipFree(P->Gr);
     hipFree(P->W);
+    hipFree(P->ppart);
     hipFree(P->Qc);
     hipFree(P->T1);
     hipFree(P->X);
@@ -862,7 +864,9 @@ bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s
         Span sp(E.timer, 1, s);
         for (const IOs &io : ios) {
             launch_pairs(g, E.prec, E.D, io, E.prec ? (const void *)E.t->wc32 : (const void *)E.t->wc,
-                         E.prec ? (const void *)E.t->wq32 : (const void *)E.t->wq, s);
+                         E.prec ? (const void *)E.t->wq32 : (const void *)E.t->wq, (any & BNQ_T_QMULT) != 0, s);
+            LAUNCHCHK();
+            launch_pairs_reduce(g, E.D, io, s);
             LAUNCHCHK();
         }
     }
@@ -1048,6 +1052,7 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         (st = dalloc(&P->Ghat, nm, "spectrum")) || (st = dalloc(&P->tmp, nm, "dft scratch")) ||
         (st = dalloc(&P->tmp2, nm, "dft scratch")) || (st = dalloc(&P->Gr, P->grp.size() * (size_t)g.next, "rotated spectra")) ||
         (st = dalloc(&P->W, (size_t)g.neg, "pair sum W")) || (st = dalloc(&P->Qc, nm, "classical modes")) ||
+        (st = dalloc(&P->ppart, (size_t)pair_split(g) * ((size_t)g.neg + nm), "pair sum slices")) ||
         (st = dalloc(&P->T1, nm, "trilinear modes")) || (st = dalloc(&P->X, nm, "outer modes")) ||
         (st = dalloc(&P->Qh, nm, "modes")) || (st = dalloc(&P->ybuf, nm, "stage")) ||
         (st = dalloc(&P->mom_part, (size_t)MOM_BLOCKS * MOM_FIELDS, "moment partials")) ||
@@ -1084,6 +1089,7 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         I.tmp2 = P->tmp2;
         I.Gr = P->Gr;
         I.W = P->W;
+        I.ppart = P->ppart;
         I.Qc = P->Qc;
         I.T1 = P->T1;
         I.X = P->X;
@@ -1414,10 +1420,13 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
     bnq_batch_s *B = new bnq_batch_s;
     B->plans.assign(plans, plans + n);
     B->f.assign(f, f + n);
-    std::map<std::tuple<const TableSet *, int, int>, int> gidx;
+    // A dynamic group lets any of its waves take any member's items, so its
+    // members must have the same number of partial arrays.
+    std::map<std::tuple<const TableSet *, int, int, int>, int> gidx;
     for (int i = 0; i < n; ++i) {
-        const auto key =
-            std::make_tuple((const TableSet *)plans[i]->tabs, (int)plans[i]->p.precision, (int)plans[i]->p.schedule);
+        const bnq_plan_s *Pi = plans[i];
+        const int dyn_slots = (Pi->nq && (Pi->ih.terms & BNQ_T_QTRI)) ? Pi->nslots : 0;
+        const auto key = std::make_tuple((const TableSet *)Pi->tabs, (int)Pi->p.precision, (int)Pi->p.schedule, dyn_slots);
         auto it = gidx.find(key);
         if (it == gidx.end()) {
             gidx[key] = (int)B->groups.size();

@@ -159,8 +159,14 @@ __device__ __forceinline__ float2 ldT2(const float2 *p, int64_t i) { return ld2f
 constexpr int BNQ_MAXB = 64;  // instances per launch
 
 // Workspace of one instance (device memory, fixed for the plan's lifetime).
+// The pair sums split the l box of every output into this many slices along
+// its outermost axis (l_0 in 3-D, l_1 in 2-D), one workgroup per slice, and
+// add the slices in a fixed order afterwards.
+__host__ __device__ inline int pair_split(const Geo &g) { return g.N < (g.d == 3 ? 8 : 16) ? g.N : (g.d == 3 ? 8 : 16); }
+
 struct Inst {
     double2 *Ghat, *tmp, *tmp2, *Gr, *W, *Qc, *T1, *X, *Qh, *part;
+    double2 *ppart;  // pair-sum partials: pair_split(g) arrays over E_g (W), then as many over I_N (Qc)
     float2 *G32, *Gr32;  // FP32c: rounded spectrum and rotated spectra
     double *ybuf, *k[4];
     double alpha;  // -eps hbar^d
@@ -202,8 +208,9 @@ void launch_inverse_real(const Geo &g, const Inst *D, const IOs &io, const doubl
 // prec 0: FP64; 1: FP32c (spectra and tables rounded to FP32, sums combined in FP64)
 void launch_spectrum_f32(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 void launch_rotate(const Geo &g, int prec, const Inst *D, const IOs &io, const Rot *rots, int nrot, hipStream_t s);
-void launch_pairs(const Geo &g, int prec, const Inst *D, const IOs &io, const void *wc, const void *wq,
-                  hipStream_t s);
+void launch_pairs_reduce(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
+void launch_pairs(const Geo &g, int prec, const Inst *D, const IOs &io, const void *wc, const void *wq, int w_any,
+                  hipStream_t s);  // w_any: some instance of the launch needs the W pair sums
 void launch_to_f32(const double *in, float *out, int64_t n, hipStream_t s);
 void launch_outer(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 void launch_zero_part(const Geo &g, const Inst *D, const IOs &io, int max_slots, hipStream_t s);

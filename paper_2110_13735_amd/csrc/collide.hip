@@ -147,73 +147,85 @@ void launch_spectrum_f32(const Geo &g, const Inst *D, const IOs &io, hipStream_t
 }
 
 // ---------------------------------------------------------------------------
-// Pair sums.  A workgroup of 256 lanes owns 256/(2N) whole x-rows of outputs
-// s (s2 = -N .. N-1 across the lanes) at one s0.  All lanes walk the same l
-// over the rows' reachable box, so G_l is a broadcast load and for fixed l
-// the weight rows wq[l][s - l] are read as contiguous runs.  Loads are
-// branch-free (indices clamped into range, invalid terms weighted by zero)
-// and the innermost loop is unrolled so that many table loads are in flight.
-template <typename T>
-__global__ __launch_bounds__(256) void pairs_kernel(Geo g, const Inst *D, IOs io, const T *wc, const T *wq) {
-    const Inst &I = D[io.inst[blockIdx.z]];
-    const int want_c = (I.terms & 1) != 0, want_w = (I.terms & 2) != 0;
-    if (!want_c && !want_w) return;
+// Pair sums.  A workgroup of 256 lanes owns 256/ext whole x-rows of outputs
+// s at one s0 (s over E_g when the launch has W sums, ext = 2N; over I_N
+// otherwise, ext = N).  All lanes walk the same l over the rows' reachable
+// box, so G_l is a uniform (scalar) load and, for fixed l, the weights
+// w[l][s - l] of the lanes are contiguous runs of the table row of l.  The
+// plane m_0 = s_0 - l_0 of the spectrum is staged in LDS for the l_0 it
+// serves.  Weights come through a buffer resource over the N table rows of
+// one (l_0, l_1): a lane whose m = s - l falls outside I_N gets an offset past
+// the end, so that its load returns zero without touching memory.
+template <typename T, bool WW, bool CC>
+__device__ __forceinline__ void pairs_body(const Geo &g, const typename V2<T>::type *G, const T *wc, const T *wq,
+                                           typename V2<T>::type *gp, int s0, int s1, int s2, bool valid, bool do_c,
+                                           int l0lo, int l0hi, int l1lo, int l1hi, double2 &accw, double2 &accc) {
     using T2 = typename V2<T>::type;
-    const T2 *G;
-    if constexpr (sizeof(T) == 8)
-        G = I.Ghat;
-    else
-        G = I.G32;
     const int N = g.N, h = g.h;
-    const int rows = 256 / (2 * N);  // s1 rows per workgroup
-    const int tid = threadIdx.x;
-    const int s2 = tid % (2 * N) - N;
-    const int r = tid / (2 * N);
-    const int s1 = blockIdx.x * rows + r - N;
-    const int s0 = g.d == 3 ? (int)blockIdx.y - N : 0;
-    const bool valid = r < rows && s1 < N;
-    const bool inI = valid && s2 >= -h && s2 < h && s1 >= -h && s1 < h && (g.d == 2 || (s0 >= -h && s0 < h));
-    // reachable box of l: l and s - l in I_N for some s of the workgroup
-    const int s1min = blockIdx.x * rows - N, s1max = min(s1min + rows - 1, N - 1);
-    const int l0lo = g.d == 3 ? max(-h, s0 - (h - 1)) : 0, l0hi = g.d == 3 ? min(h - 1, s0 + h) : 0;
-    const int l1lo = max(-h, s1min - (h - 1)), l1hi = min(h - 1, s1max + h);
-    double2 accw = make_double2(0.0, 0.0), accc = make_double2(0.0, 0.0);
-    const bool do_c = want_c && inI;
+    const int64_t nm = g.nm;
+    const uint32_t OOB = 0x80000000u;
     for (int l0 = l0lo; l0 <= l0hi; ++l0) {
         const int m0 = s0 - l0;  // in I_N by the choice of the l0 range
+        __syncthreads();         // the previous plane is no longer read
+        {
+            const T2 *Gm = G + idx_I(g, m0, -h, -h);
+            for (int i = threadIdx.x; i < N * N; i += blockDim.x) gp[i] = ldT2(Gm, i);
+        }
+        __syncthreads();
         for (int l1 = l1lo; l1 <= l1hi; ++l1) {
             const int m1 = s1 - l1;
             const bool ok1 = valid && m1 >= -h && m1 < h;
-            const int m1c = min(max(m1, -h), h - 1);
-            const int64_t il0 = idx_I(g, l0, l1, -h);
-            const int64_t im0 = idx_I(g, m0, m1c, 0);
+            const int64_t il0 = idx_I(g, l0, l1, -h);  // first of the N table rows of this (l0, l1)
+            const int mrow = (int)idx_I(g, m0, ok1 ? m1 : -h, -h);
+            const int grow = ((ok1 ? m1 : -h) + h) * N;
+            const T2 *Gl = G + il0;
+            __amdgpu_buffer_rsrc_t rq, rc;
+            if constexpr (WW)
+                rq = __builtin_amdgcn_make_buffer_rsrc((void *)(wq + il0 * nm), (short)0,
+                                                       (int)((int64_t)N * nm * sizeof(T)), 0x00020000);
+            if constexpr (CC)
+                rc = __builtin_amdgcn_make_buffer_rsrc((void *)(wc + il0 * nm), (short)0,
+                                                       (int)((int64_t)N * nm * sizeof(T)), 0x00020000);
             // FP64: every term goes straight into the FP64 sums.  FP32c: the
             // N terms of one l-row are summed in FP32, the row sums in FP64.
             T wr = 0, wi = 0, cr = 0, ci = 0;
 #pragma unroll 8
             for (int j = 0; j < N; ++j) {
-                const int l2 = j - h;
-                const int m2 = s2 - l2;
+                const int m2 = s2 - (j - h);
                 const bool ok = ok1 && m2 >= -h && m2 < h;
-                const int m2c = min(max(m2, -h), h - 1);
-                const int64_t il = il0 + j, im = im0 + m2c;
-                const T2 gl = ldT2(G, il);
-                const T2 gm = ldT2(G, im);
-                const int64_t o = il * g.nm + im;
-                const T w1 = want_w ? wq[o] : (T)0;
-                const T w2 = do_c ? wc[o] : (T)0;
+                const T2 gl = Gl[j];
+                const T2 gm = gp[grow + (ok ? m2 + h : 0)];
+                const uint32_t vo = ok ? (uint32_t)((mrow + m2 + h) * (int)sizeof(T)) : OOB;
+                const int so = (int)((int64_t)j * nm * sizeof(T));
                 const T2 p = cmulT(gl, gm);
-                const T a1 = ok ? w1 : (T)0, a2 = ok ? w2 : (T)0;
-                if constexpr (sizeof(T) == 8) {
-                    accw.x = fma(a1, p.x, accw.x);
-                    accw.y = fma(a1, p.y, accw.y);
-                    accc.x = fma(a2, p.x, accc.x);
-                    accc.y = fma(a2, p.y, accc.y);
-                } else {
-                    wr = fmaf(a1, p.x, wr);
-                    wi = fmaf(a1, p.y, wi);
-                    cr = fmaf(a2, p.x, cr);
-                    ci = fmaf(a2, p.y, ci);
+                if constexpr (WW) {
+                    T a1;
+                    if constexpr (sizeof(T) == 8)
+                        a1 = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rq, vo, so, 0));
+                    else
+                        a1 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rq, vo, so, 0));
+                    if constexpr (sizeof(T) == 8) {
+                        accw.x = fma(a1, p.x, accw.x);
+                        accw.y = fma(a1, p.y, accw.y);
+                    } else {
+                        wr = fmaf(a1, p.x, wr);
+                        wi = fmaf(a1, p.y, wi);
+                    }
+                }
+                if constexpr (CC) {
+                    const uint32_t vc = do_c ? vo : OOB;
+                    T a2;
+                    if constexpr (sizeof(T) == 8)
+                        a2 = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, vc, so, 0));
+                    else
+                        a2 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, vc, so, 0));
+                    if constexpr (sizeof(T) == 8) {
+                        accc.x = fma(a2, p.x, accc.x);
+                        accc.y = fma(a2, p.y, accc.y);
+                    } else {
+                        cr = fmaf(a2, p.x, cr);
+                        ci = fmaf(a2, p.y, ci);
+                    }
                 }
             }
             if constexpr (sizeof(T) == 4) {
@@ -224,22 +236,109 @@ __global__ __launch_bounds__(256) void pairs_kernel(Geo g, const Inst *D, IOs io
             }
         }
     }
-    if (!valid) return;
-    if (want_w) st2(I.W, idx_E(g, s0, s1, s2), accw);
-    if (do_c) st2(I.Qc, idx_I(g, s0, s1, s2), accc);
 }
 
-void launch_pairs(const Geo &g, int prec, const Inst *D, const IOs &io, const void *wc, const void *wq,
+template <typename T>
+__global__ __launch_bounds__(256) void pairs_kernel(Geo g, const Inst *D, IOs io, const T *wc, const T *wq,
+                                                    int ext) {
+    extern __shared__ unsigned char pairs_lds[];
+    const Inst &I = D[io.inst[blockIdx.z]];
+    const int want_c = (I.terms & 1) != 0, want_w = (I.terms & 2) != 0;
+    if (!want_c && !want_w) return;
+    using T2 = typename V2<T>::type;
+    const T2 *G;
+    if constexpr (sizeof(T) == 8)
+        G = I.Ghat;
+    else
+        G = I.G32;
+    const int N = g.N, h = g.h;
+    const int lo = ext == N ? -h : -N;
+    const int rows = 256 / ext;  // s1 rows per workgroup
+    const int tid = threadIdx.x;
+    const int s2 = tid % ext + lo;
+    const int r = tid / ext;
+    const int s1 = blockIdx.x * rows + r + lo;
+    const int K = pair_split(g);
+    const int c = (int)blockIdx.y % K;  // slice of the split l axis
+    const int s0 = g.d == 3 ? (int)blockIdx.y / K + lo : 0;
+    const bool valid = r < rows && s1 < lo + ext;
+    const bool inI = valid && s2 >= -h && s2 < h && s1 >= -h && s1 < h && (g.d == 2 || (s0 >= -h && s0 < h));
+    // reachable box of l: l and s - l in I_N for some s of the workgroup
+    const int s1min = blockIdx.x * rows + lo, s1max = min(s1min + rows - 1, lo + ext - 1);
+    // an instance without W sums has nothing to do outside I_N
+    if (!want_w && (s1max < -h || s1min >= h || (g.d == 3 && (s0 < -h || s0 >= h)))) return;
+    int l0lo = g.d == 3 ? max(-h, s0 - (h - 1)) : 0, l0hi = g.d == 3 ? min(h - 1, s0 + h) : 0;
+    int l1lo = max(-h, s1min - (h - 1)), l1hi = min(h - 1, s1max + h);
+    {
+        // this workgroup's slice [-h + c w, -h + (c + 1) w) of the split axis
+        const int wsl = (N + K - 1) / K, clo = -h + c * wsl, chi = clo + wsl - 1;  // the last slices may be empty
+        if (g.d == 3) {
+            l0lo = max(l0lo, clo);
+            l0hi = min(l0hi, chi);
+        } else {
+            l1lo = max(l1lo, clo);
+            l1hi = min(l1hi, chi);
+        }
+    }
+    double2 accw = make_double2(0.0, 0.0), accc = make_double2(0.0, 0.0);
+    const bool do_c = want_c && inI;
+    T2 *gp = (T2 *)pairs_lds;
+    // a wave whose lanes all lie outside I_N issues no classical-weight loads
+    const bool wave_c = __builtin_amdgcn_ballot_w64(do_c) != 0;
+    if (want_w && wave_c)
+        pairs_body<T, true, true>(g, G, wc, wq, gp, s0, s1, s2, valid, do_c, l0lo, l0hi, l1lo, l1hi, accw, accc);
+    else if (want_w)
+        pairs_body<T, true, false>(g, G, wc, wq, gp, s0, s1, s2, valid, do_c, l0lo, l0hi, l1lo, l1hi, accw, accc);
+    else
+        pairs_body<T, false, true>(g, G, wc, wq, gp, s0, s1, s2, valid, do_c, l0lo, l0hi, l1lo, l1hi, accw, accc);
+    if (!valid) return;
+    if (want_w) st2(I.ppart + (int64_t)c * g.neg, idx_E(g, s0, s1, s2), accw);
+    if (do_c) st2(I.ppart + (int64_t)K * g.neg + (int64_t)c * g.nm, idx_I(g, s0, s1, s2), accc);
+}
+
+// W and Qc as the sums of the slices, in slice order.
+__global__ void pairs_reduce_kernel(Geo g, const Inst *D, IOs io) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const Inst &I = D[io.inst[blockIdx.z]];
+    const int K = pair_split(g);
+    if ((I.terms & 2) && i < g.neg) {
+        double2 a = make_double2(0.0, 0.0);
+        for (int c = 0; c < K; ++c) {
+            const double2 v = ld2(I.ppart + (int64_t)c * g.neg, i);
+            a.x += v.x;
+            a.y += v.y;
+        }
+        st2(I.W, i, a);
+    }
+    if ((I.terms & 1) && i < g.nm) {
+        double2 a = make_double2(0.0, 0.0);
+        for (int c = 0; c < K; ++c) {
+            const double2 v = ld2(I.ppart + (int64_t)K * g.neg + (int64_t)c * g.nm, i);
+            a.x += v.x;
+            a.y += v.y;
+        }
+        st2(I.Qc, i, a);
+    }
+}
+
+void launch_pairs_reduce(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
+    hipLaunchKernelGGL(pairs_reduce_kernel, dim3((unsigned)((g.neg + 255) / 256), 1, (unsigned)io.n), dim3(256), 0,
+                       s, g, D, io);
+}
+
+void launch_pairs(const Geo &g, int prec, const Inst *D, const IOs &io, const void *wc, const void *wq, int w_any,
                   hipStream_t s) {
     const int N = g.N;
-    const int rows = 256 / (2 * N);
-    dim3 grid((unsigned)((2 * N + rows - 1) / rows), (unsigned)(g.d == 3 ? 2 * N : 1), (unsigned)io.n);
+    const int ext = w_any ? 2 * N : N;
+    const int rows = 256 / ext;
+    dim3 grid((unsigned)((ext + rows - 1) / rows), (unsigned)((g.d == 3 ? ext : 1) * pair_split(g)), (unsigned)io.n);
+    const size_t lds = (size_t)N * N * (prec == 0 ? sizeof(double2) : sizeof(float2));  // one m_0 plane of G
     if (prec == 0)
-        hipLaunchKernelGGL(pairs_kernel<double>, grid, dim3(256), 0, s, g, D, io, (const double *)wc,
-                           (const double *)wq);
+        hipLaunchKernelGGL(pairs_kernel<double>, grid, dim3(256), lds, s, g, D, io, (const double *)wc,
+                           (const double *)wq, ext);
     else
-        hipLaunchKernelGGL(pairs_kernel<float>, grid, dim3(256), 0, s, g, D, io, (const float *)wc,
-                           (const float *)wq);
+        hipLaunchKernelGGL(pairs_kernel<float>, grid, dim3(256), lds, s, g, D, io, (const float *)wc,
+                           (const float *)wq, ext);
 }
 
 // ---------------------------------------------------------------------------
