@@ -137,3 +137,30 @@ def test_dynamic_schedule_batch_matches_solo():
         assert r <= 1e-12, f"instance {i}: {r}"
     for pl in plans:
         pl.close()
+
+
+def test_pair_sums_at_the_largest_n_batched_and_solo():
+    # 2-D N = 64, the largest N: the spectrum plane staged by the pair sums is
+    # 64 KiB.  A classical-only instance alone covers I_N; batched with an
+    # instance that needs the W sums it runs in the E_g launch shape.  Both
+    # must give the same modes bitwise, with exact mass conservation.
+    dev = torch.device("cuda:0")
+    d, N, L = 2, 64, 6.0
+    f = torch.tensor(inp.gaussian_mixture(d, N, L, seed=91, kmin=2), device=dev)
+    g = torch.tensor(inp.gaussian_mixture(d, N, L, seed=92, kmin=2), device=dev)
+    pa = bnq.Plan(bnq.Params(d=d, N=N, eps=0, L=L))
+    pb = bnq.Plan(bnq.Params(d=d, N=N, eps=1, L=L, terms=bnq.T_CLASSICAL | bnq.T_QMULT))
+    Qa = torch.empty_like(f)
+    Qha = torch.empty(f.shape, dtype=torch.complex128, device=dev)
+    pa.collide(f, Qa, Qha)
+    torch.cuda.synchronize()
+    with bnq.Batch([pa, pb], [f, g]) as B:
+        Qs = [torch.empty_like(f), torch.empty_like(g)]
+        Qhs = [torch.empty(f.shape, dtype=torch.complex128, device=dev) for _ in range(2)]
+        B.collide(Qs, Qhs)
+        torch.cuda.synchronize()
+    assert torch.equal(Qha, Qhs[0])
+    qh = Qha.cpu().numpy()
+    assert abs(qh[N // 2, N // 2]) <= 1e-12 * np.abs(qh).max()
+    pa.close()
+    pb.close()
