@@ -432,7 +432,8 @@ struct bnq_plan_s {
     Rot *rots_d = nullptr;
     double2 *tw = nullptr;
     double2 *Ghat = nullptr, *tmp = nullptr, *tmp2 = nullptr, *Gr = nullptr, *W = nullptr, *Qc = nullptr,
-            *T1 = nullptr, *X = nullptr, *Qh = nullptr, *part = nullptr, *ppart = nullptr;
+            *T1 = nullptr, *X = nullptr, *Qh = nullptr, *part = nullptr, *ppart = nullptr,
+            *xpart = nullptr;
     float2 *G32 = nullptr, *Gr32 = nullptr;  // FP32c spectra
     int nbdesc = 0;
     double *kbuf[4] = {nullptr, nullptr, nullptr, nullptr}, *ybuf = nullptr;
@@ -524,7 +525,7 @@ size_t plan_workspace_bytes(const bnq_params *p, int nslots_est) {
     const size_t nrot = p->d == 3 ? 48 : 8;
     const size_t f32 = p->precision == BNQ_FP32C ? sizeof(float2) * ((size_t)g.nm + nrot * g.next) : 0;
     return c * (6 * (size_t)g.nm + g.neg + nrot * g.next + (size_t)nslots_est * g.nm +
-                (size_t)pair_split(g) * ((size_t)g.neg + g.nm)) +
+                (size_t)pair_split(g) * ((size_t)g.neg + g.nm) + (size_t)outer_split(g) * g.nm) +
            r * 5 * (size_t)g.nm + f32;
 }
 
@@ -753,6 +754,7 @@ void destroy_plan(bnq_plan_s *P) {
     hipFree(P->Gr);
     hipFree(P->W);
     hipFree(P->ppart);
+    hipFree(P->xpart);
     hipFree(P->Qc);
     hipFree(P->T1);
     hipFree(P->X);
@@ -1053,6 +1055,7 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         (st = dalloc(&P->tmp2, nm, "dft scratch")) || (st = dalloc(&P->Gr, P->grp.size() * (size_t)g.next, "rotated spectra")) ||
         (st = dalloc(&P->W, (size_t)g.neg, "pair sum W")) || (st = dalloc(&P->Qc, nm, "classical modes")) ||
         (st = dalloc(&P->ppart, (size_t)pair_split(g) * ((size_t)g.neg + nm), "pair sum slices")) ||
+        (st = dalloc(&P->xpart, (size_t)outer_split(g) * nm, "outer sum slices")) ||
         (st = dalloc(&P->T1, nm, "trilinear modes")) || (st = dalloc(&P->X, nm, "outer modes")) ||
         (st = dalloc(&P->Qh, nm, "modes")) || (st = dalloc(&P->ybuf, nm, "stage")) ||
         (st = dalloc(&P->mom_part, (size_t)MOM_BLOCKS * MOM_FIELDS, "moment partials")) ||
@@ -1090,6 +1093,7 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         I.Gr = P->Gr;
         I.W = P->W;
         I.ppart = P->ppart;
+        I.xpart = P->xpart;
         I.Qc = P->Qc;
         I.T1 = P->T1;
         I.X = P->X;

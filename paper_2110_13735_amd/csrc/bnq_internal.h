@@ -164,8 +164,13 @@ constexpr int BNQ_MAXB = 64;  // instances per launch
 // add the slices in a fixed order afterwards.
 __host__ __device__ inline int pair_split(const Geo &g) { return g.N < (g.d == 3 ? 8 : 16) ? g.N : (g.d == 3 ? 8 : 16); }
 
+// The outer sum likewise splits its k box into this many slices (k_0 in 3-D,
+// k_1 in 2-D).
+__host__ __device__ inline int outer_split(const Geo &g) { return g.N < 16 ? g.N : 16; }
+
 struct Inst {
     double2 *Ghat, *tmp, *tmp2, *Gr, *W, *Qc, *T1, *X, *Qh, *part;
+    double2 *xpart;  // outer-sum partials: outer_split(g) arrays over I_N
     double2 *ppart;  // pair-sum partials: pair_split(g) arrays over E_g (W), then as many over I_N (Qc)
     float2 *G32, *Gr32;  // FP32c: rounded spectrum and rotated spectra
     double *ybuf, *k[4];

@@ -342,33 +342,110 @@ void launch_pairs(const Geo &g, int prec, const Inst *D, const IOs &io, const vo
 }
 
 // ---------------------------------------------------------------------------
-// Outer sum X_n = sum_k G_k W_{n-k}; n - k always lies in Eg.
+// Outer sum X_n = sum_k G_k W_{n-k}; n - k always lies in Eg.  A lane owns 4
+// consecutive outputs along x and walks k_2 in blocks of 4: block b needs
+// W at x-offsets c_b - 4 .. c_b + 3 (c_b = n_2 + N/2 - 4b), of which the upper
+// half is the previous block's lower half, so each loaded W value serves 4
+// outputs.  G_k is uniform across the wave (scalar loads).  The k box is split
+// into slices along k_0 (3-D) or k_1 (2-D), one workgroup per slice and
+// partial array, added in slice order by outer_reduce_kernel.
+__device__ __forceinline__ void outer_macs(double2 (&acc)[4], double2 gk, const double2 (&lo)[4],
+                                           const double2 (&hi)[4], int jj) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double2 w = i - jj >= 0 ? hi[i - jj] : lo[i - jj + 4];
+        acc[i].x = fma(gk.x, w.x, fma(-gk.y, w.y, acc[i].x));
+        acc[i].y = fma(gk.x, w.y, fma(gk.y, w.x, acc[i].y));
+    }
+}
+
 __global__ __launch_bounds__(256) void outer_kernel(Geo g, const Inst *D, IOs io) {
+    const Inst &I = D[io.inst[blockIdx.z]];
+    if (!(I.terms & 2)) return;
+    const int N = g.N, h = g.h, nq = (N + 3) / 4;  // x-quads per row
+    const int64_t rowsq = (int64_t)(g.d == 3 ? N : 1) * N * nq;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int K = outer_split(g), c = blockIdx.y;
+    const int wsl = (N + K - 1) / K;
+    const bool valid = q < rowsq;
+    const int64_t qq = valid ? q : 0;
+    const int n2a = (int)(qq % nq) * 4 - h, n1 = (int)((qq / nq) % N) - h;
+    const int n0 = g.d == 3 ? (int)(qq / ((int64_t)nq * N)) - h : 0;
+    const double2 *G = I.Ghat, *W = I.W;
+    double2 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = make_double2(0.0, 0.0);
+    // slice of the split axis
+    int k0lo = g.d == 3 ? -h : 0, k0hi = g.d == 3 ? h - 1 : 0, k1lo = -h, k1hi = h - 1;
+    if (g.d == 3) {
+        k0lo = -h + c * wsl;
+        k0hi = min(h - 1, k0lo + wsl - 1);
+    } else {
+        k1lo = -h + c * wsl;
+        k1hi = min(h - 1, k1lo + wsl - 1);
+    }
+    const int E = 2 * N;
+    const int nb = N / 4;  // full blocks of 4 k_2
+    for (int k0 = k0lo; k0 <= k0hi; ++k0)
+        for (int k1 = k1lo; k1 <= k1hi; ++k1) {
+            const double2 *Grow = G + idx_I(g, k0, k1, -h);
+            const double2 *Wrow = W + idx_E(g, n0 - k0, n1 - k1, -N);  // x-offset x at Wrow[x + N]
+            // W at x-offset c_b + e, clamped into the row (clamped values only
+            // reach outputs past the window, which are not stored)
+            auto wat = [&](int x) { return ld2(Wrow, min(max(x, -N), N - 1) + N); };
+            const int c0 = n2a + h;
+            double2 A[4], B[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) A[e] = wat(c0 + e);
+            int b = 0;
+            for (; b + 1 < nb; b += 2) {
+                const int cb = c0 - 4 * b;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) B[e] = wat(cb - 4 + e);
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) outer_macs(acc, ld2(Grow, 4 * b + jj), B, A, jj);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) A[e] = wat(cb - 8 + e);
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) outer_macs(acc, ld2(Grow, 4 * b + 4 + jj), A, B, jj);
+            }
+            // an odd last block and the last N mod 4 values of k_2
+            for (int t = 4 * b; t < N; ++t) {
+                const double2 gk = ld2(Grow, t);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const double2 w = wat(c0 + i - t);
+                    acc[i].x = fma(gk.x, w.x, fma(-gk.y, w.y, acc[i].x));
+                    acc[i].y = fma(gk.x, w.y, fma(gk.y, w.x, acc[i].y));
+                }
+            }
+            (void)E;
+        }
+    if (!valid) return;
+    double2 *part = I.xpart + (int64_t)c * g.nm;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (n2a + i < h) st2(part, idx_I(g, n0, n1, n2a + i), acc[i]);
+}
+
+__global__ void outer_reduce_kernel(Geo g, const Inst *D, IOs io) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const Inst &I = D[io.inst[blockIdx.z]];
     if (i >= g.nm || !(I.terms & 2)) return;
-    const double2 *G = I.Ghat, *W = I.W;
-    const int N = g.N, h = g.h;
-    const int n2 = (int)(i % N) - h, n1 = (int)((i / N) % N) - h;
-    const int n0 = g.d == 3 ? (int)(i / ((int64_t)N * N)) - h : 0;
-    double2 acc = make_double2(0.0, 0.0);
-    const int k0lo = g.d == 3 ? -h : 0, k0hi = g.d == 3 ? h - 1 : 0;
-    for (int k0 = k0lo; k0 <= k0hi; ++k0)
-        for (int k1 = -h; k1 < h; ++k1) {
-            const double2 *Grow = G + idx_I(g, k0, k1, -h);
-            const double2 *Wrow = W + idx_E(g, n0 - k0, n1 - k1, n2 + h);
-#pragma unroll 8
-            for (int k2 = 0; k2 < N; ++k2) {
-                const double2 a = ld2(Grow, k2), b = ld2(Wrow, -k2);
-                acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
-                acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
-            }
-        }
-    st2(I.X, i, acc);
+    double2 a = make_double2(0.0, 0.0);
+    for (int c = 0; c < outer_split(g); ++c) {
+        const double2 v = ld2(I.xpart + (int64_t)c * g.nm, i);
+        a.x += v.x;
+        a.y += v.y;
+    }
+    st2(I.X, i, a);
 }
 
 void launch_outer(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
-    hipLaunchKernelGGL(outer_kernel, grid_nm(g, io), dim3(256), 0, s, g, D, io);
+    const int64_t rowsq = (int64_t)(g.d == 3 ? g.N : 1) * g.N * ((g.N + 3) / 4);
+    hipLaunchKernelGGL(outer_kernel, dim3((unsigned)((rowsq + 255) / 256), (unsigned)outer_split(g), (unsigned)io.n),
+                       dim3(256), 0, s, g, D, io);
+    hipLaunchKernelGGL(outer_reduce_kernel, grid_nm(g, io), dim3(256), 0, s, g, D, io);
 }
 
 // ---------------------------------------------------------------------------
