@@ -354,3 +354,34 @@ def test_dynamic_schedule_matches_oracle(d, N, eps):
     Qo, Qho, g, qg = _oracle_collide(d, N, f, eps, L)
     _check(Qh, Qho, g)
     _check(Q, Qo, qg)
+
+
+@pytest.mark.parametrize("species", ["fermions", "bosons"])
+def test_quantum_maxwellian_residual_decays_beyond_oracle_sizes(species):
+    # The quantum Maxwellian is an equilibrium of the continuous operator: on
+    # the grid the GPU operator's residual must decay spectrally with N, here
+    # up to 2-D N = 64, beyond the sizes the oracle is run at (protocol of
+    # section 'Validation of spectral accuracy': hbar = 3, rho = 1, L = 4,
+    # u0 = 0; T = 0.5 for Fermi-Dirac, T = 1 for Bose-Einstein).  The datum is
+    # far from stationary under the other statistics.
+    hbar, rho, L = 3.0, 1.0, 4.0
+    alpha = hbar ** 2
+    if species == "fermions":
+        T, eps, sgn = 0.5, -1, 1.0
+        z = np.exp(rho * alpha / (2 * np.pi * T)) - 1.0
+    else:
+        T, eps, sgn = 1.0, 1, -1.0
+        z = 1.0 - np.exp(-rho * alpha / (2 * np.pi * T))
+    res, wrong = [], []
+    for N in (16, 32, 64):
+        f = inp.quantum_maxwellian(2, N, L, z=z, T=T, alpha=sgn * alpha)
+        Q, _ = _gpu_collide(bnq.Params(d=2, N=N, eps=eps, L=L, hbar=hbar), f)
+        Qw, _ = _gpu_collide(bnq.Params(d=2, N=N, eps=-eps, L=L, hbar=hbar), f)
+        res.append(np.max(np.abs(Q)))
+        wrong.append(np.max(np.abs(Qw)))
+    # measured: FD 2.4e-4, 1.5e-6, 1.7e-7 (the box edge starts to dominate);
+    # BE 3.8e-2, 6.0e-4, 3.3e-6
+    assert res[1] < res[0] / 50
+    assert res[2] < res[1] / 5
+    assert res[2] < 1e-5
+    assert min(wrong) > 1e4 * res[2]
