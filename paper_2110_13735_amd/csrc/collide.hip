@@ -296,6 +296,167 @@ __global__ __launch_bounds__(256) void pairs_kernel(Geo g, const Inst *D, IOs io
     if (do_c) st2(I.ppart + (int64_t)K * g.neg + (int64_t)c * g.nm, idx_I(g, s0, s1, s2), accc);
 }
 
+// Pair sums for launches with W sums (outputs over E_g), folded along x: lane
+// k (0 <= k < N) of an output row owns s_2 = k - N (A) and s_2 = k (B).  At
+// step t of the l_2 walk (l_2 = t - N/2) exactly one of them has m_2 = s_2 -
+// l_2 in I_N: A while t <= k, B after; in both cases m_2 + N/2 = (k - t) mod
+// N.  So every lane of every weight load carries a useful term, where the
+// unfolded walk over 2N outputs wastes half of them.  The l_1 range is the
+// wave's own (its output rows), the l_0 range the workgroup's.
+template <typename T, bool WW, bool CC>
+__device__ __forceinline__ void pairs_w_body(const Geo &g, const typename V2<T>::type *G, const T *wc, const T *wq,
+                                             typename V2<T>::type *gp, int s0, int s1, int k, bool valid, bool dcA,
+                                             bool dcB, int l0lo, int l0hi, int l1lo, int l1hi, double2 (&aw)[2],
+                                             double2 (&ac)[2]) {
+    using T2 = typename V2<T>::type;
+    const int N = g.N, h = g.h;
+    const int64_t nm = g.nm;
+    const uint32_t OOB = 0x80000000u;
+    for (int l0 = l0lo; l0 <= l0hi; ++l0) {
+        const int m0 = s0 - l0;
+        __syncthreads();  // the previous plane is no longer read
+        {
+            const T2 *Gm = G + idx_I(g, m0, -h, -h);
+            for (int i = threadIdx.x; i < N * N; i += blockDim.x) gp[i] = ldT2(Gm, i);
+        }
+        __syncthreads();
+        for (int l1 = l1lo; l1 <= l1hi; ++l1) {
+            const int m1 = s1 - l1;
+            const bool ok1 = valid && m1 >= -h && m1 < h;
+            const int64_t il0 = idx_I(g, l0, l1, -h);
+            const int mrow = (int)idx_I(g, m0, ok1 ? m1 : -h, -h);
+            const int grow = ((ok1 ? m1 : -h) + h) * N;
+            const T2 *Gl = G + il0;
+            __amdgpu_buffer_rsrc_t rq, rc;
+            if constexpr (WW)
+                rq = __builtin_amdgcn_make_buffer_rsrc((void *)(wq + il0 * nm), (short)0,
+                                                       (int)((int64_t)N * nm * sizeof(T)), 0x00020000);
+            if constexpr (CC)
+                rc = __builtin_amdgcn_make_buffer_rsrc((void *)(wc + il0 * nm), (short)0,
+                                                       (int)((int64_t)N * nm * sizeof(T)), 0x00020000);
+            // FP32c: the N terms of one l-row in FP32, row sums in FP64
+            T wr[2] = {0, 0}, wi[2] = {0, 0}, cr[2] = {0, 0}, ci[2] = {0, 0};
+#pragma unroll 8
+            for (int t = 0; t < N; ++t) {
+                const bool isA = t <= k;
+                const int mi = isA ? k - t : k - t + N;
+                const T2 gl = Gl[t];
+                const T2 gm = gp[grow + mi];
+                const uint32_t vo = ok1 ? (uint32_t)((mrow + mi) * (int)sizeof(T)) : OOB;
+                const int so = (int)((int64_t)t * nm * sizeof(T));
+                const T2 p = cmulT(gl, gm);
+                if constexpr (WW) {
+                    T a;
+                    if constexpr (sizeof(T) == 8)
+                        a = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rq, vo, so, 0));
+                    else
+                        a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rq, vo, so, 0));
+                    const T aA = isA ? a : (T)0, aB = isA ? (T)0 : a;
+                    if constexpr (sizeof(T) == 8) {
+                        aw[0].x = fma(aA, p.x, aw[0].x);
+                        aw[0].y = fma(aA, p.y, aw[0].y);
+                        aw[1].x = fma(aB, p.x, aw[1].x);
+                        aw[1].y = fma(aB, p.y, aw[1].y);
+                    } else {
+                        wr[0] = fmaf(aA, p.x, wr[0]);
+                        wi[0] = fmaf(aA, p.y, wi[0]);
+                        wr[1] = fmaf(aB, p.x, wr[1]);
+                        wi[1] = fmaf(aB, p.y, wi[1]);
+                    }
+                }
+                if constexpr (CC) {
+                    const uint32_t vc = (isA ? dcA : dcB) ? vo : OOB;
+                    T a;
+                    if constexpr (sizeof(T) == 8)
+                        a = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, vc, so, 0));
+                    else
+                        a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, vc, so, 0));
+                    const T aA = isA ? a : (T)0, aB = isA ? (T)0 : a;
+                    if constexpr (sizeof(T) == 8) {
+                        ac[0].x = fma(aA, p.x, ac[0].x);
+                        ac[0].y = fma(aA, p.y, ac[0].y);
+                        ac[1].x = fma(aB, p.x, ac[1].x);
+                        ac[1].y = fma(aB, p.y, ac[1].y);
+                    } else {
+                        cr[0] = fmaf(aA, p.x, cr[0]);
+                        ci[0] = fmaf(aA, p.y, ci[0]);
+                        cr[1] = fmaf(aB, p.x, cr[1]);
+                        ci[1] = fmaf(aB, p.y, ci[1]);
+                    }
+                }
+            }
+            if constexpr (sizeof(T) == 4) {
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    aw[e].x += wr[e];
+                    aw[e].y += wi[e];
+                    ac[e].x += cr[e];
+                    ac[e].y += ci[e];
+                }
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void pairs_w_kernel(Geo g, const Inst *D, IOs io, const T *wc, const T *wq) {
+    extern __shared__ unsigned char pairs_lds[];
+    const Inst &I = D[io.inst[blockIdx.z]];
+    const int want_c = (I.terms & 1) != 0, want_w = (I.terms & 2) != 0;
+    if (!want_c && !want_w) return;
+    using T2 = typename V2<T>::type;
+    const T2 *G;
+    if constexpr (sizeof(T) == 8)
+        G = I.Ghat;
+    else
+        G = I.G32;
+    const int N = g.N, h = g.h;
+    const int rows = 256 / N;  // output rows per workgroup, N lanes each
+    const int tid = threadIdx.x;
+    const int k = tid % N, r = tid / N;
+    const int s1 = blockIdx.x * rows + r - N;
+    const int K = pair_split(g);
+    const int c = (int)blockIdx.y % K;
+    const int s0 = g.d == 3 ? (int)blockIdx.y / K - N : 0;
+    const bool valid = r < rows && s1 < N;
+    const bool rowI = valid && s1 >= -h && s1 < h && (g.d == 2 || (s0 >= -h && s0 < h));
+    const bool dcA = want_c && rowI && k >= h, dcB = want_c && rowI && k < h;  // output in I_N
+    const int s1min = blockIdx.x * rows - N, s1max = min(s1min + rows - 1, N - 1);
+    if (!want_w && (s1max < -h || s1min >= h || (g.d == 3 && (s0 < -h || s0 >= h)))) return;
+    int l0lo = g.d == 3 ? max(-h, s0 - (h - 1)) : 0, l0hi = g.d == 3 ? min(h - 1, s0 + h) : 0;
+    // the wave's own output rows
+    const int wv = __builtin_amdgcn_readfirstlane(tid / 64);
+    const int ws1min = s1min + wv * 64 / N, ws1max = min(s1min + (wv * 64 + 63) / N, s1max);
+    int l1lo = max(-h, ws1min - (h - 1)), l1hi = min(h - 1, ws1max + h);
+    {
+        const int wsl = (N + K - 1) / K, clo = -h + c * wsl, chi = clo + wsl - 1;
+        if (g.d == 3) {
+            l0lo = max(l0lo, clo);
+            l0hi = min(l0hi, chi);
+        } else {
+            l1lo = max(l1lo, clo);
+            l1hi = min(l1hi, chi);
+        }
+    }
+    double2 aw[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    double2 ac[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    T2 *gp = (T2 *)pairs_lds;
+    const bool wave_c = __builtin_amdgcn_ballot_w64(dcA || dcB) != 0;
+    if (want_w && wave_c)
+        pairs_w_body<T, true, true>(g, G, wc, wq, gp, s0, s1, k, valid, dcA, dcB, l0lo, l0hi, l1lo, l1hi, aw, ac);
+    else if (want_w)
+        pairs_w_body<T, true, false>(g, G, wc, wq, gp, s0, s1, k, valid, dcA, dcB, l0lo, l0hi, l1lo, l1hi, aw, ac);
+    else
+        pairs_w_body<T, false, true>(g, G, wc, wq, gp, s0, s1, k, valid, dcA, dcB, l0lo, l0hi, l1lo, l1hi, aw, ac);
+    if (!valid) return;
+    const int s2[2] = {k - N, k};
+    if (want_w)
+        for (int e = 0; e < 2; ++e) st2(I.ppart + (int64_t)c * g.neg, idx_E(g, s0, s1, s2[e]), aw[e]);
+    double2 *qp = I.ppart + (int64_t)K * g.neg + (int64_t)c * g.nm;
+    if (dcA) st2(qp, idx_I(g, s0, s1, s2[0]), ac[0]);
+    if (dcB) st2(qp, idx_I(g, s0, s1, s2[1]), ac[1]);
+}
+
 // W and Qc as the sums of the slices, in slice order.
 __global__ void pairs_reduce_kernel(Geo g, const Inst *D, IOs io) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -329,10 +490,23 @@ void launch_pairs_reduce(const Geo &g, const Inst *D, const IOs &io, hipStream_t
 void launch_pairs(const Geo &g, int prec, const Inst *D, const IOs &io, const void *wc, const void *wq, int w_any,
                   hipStream_t s) {
     const int N = g.N;
-    const int ext = w_any ? 2 * N : N;
+    const size_t lds = (size_t)N * N * (prec == 0 ? sizeof(double2) : sizeof(float2));  // one m_0 plane of G
+    if (w_any) {
+        // outputs over E_g, x folded: N lanes per output row
+        const int rows = 256 / N;
+        dim3 grid((unsigned)((2 * N + rows - 1) / rows), (unsigned)((g.d == 3 ? 2 * N : 1) * pair_split(g)),
+                  (unsigned)io.n);
+        if (prec == 0)
+            hipLaunchKernelGGL(pairs_w_kernel<double>, grid, dim3(256), lds, s, g, D, io, (const double *)wc,
+                               (const double *)wq);
+        else
+            hipLaunchKernelGGL(pairs_w_kernel<float>, grid, dim3(256), lds, s, g, D, io, (const float *)wc,
+                               (const float *)wq);
+        return;
+    }
+    const int ext = N;
     const int rows = 256 / ext;
     dim3 grid((unsigned)((ext + rows - 1) / rows), (unsigned)((g.d == 3 ? ext : 1) * pair_split(g)), (unsigned)io.n);
-    const size_t lds = (size_t)N * N * (prec == 0 ? sizeof(double2) : sizeof(float2));  // one m_0 plane of G
     if (prec == 0)
         hipLaunchKernelGGL(pairs_kernel<double>, grid, dim3(256), lds, s, g, D, io, (const double *)wc,
                            (const double *)wq, ext);
