@@ -112,11 +112,15 @@ typedef struct {
  * correction, hbar = C_phi = c = 1, L = 8. */
 void bnq_params_default(bnq_params *p);
 
-/* Build a plan: validates *p, attaches (building on first use, in FP64 on
- * the device) the kernel-mode tables shared by every plan with the same
- * (d, N, C_phi), and allocates the plan's workspace on the current device.
- * Tables are built on `stream` and the call synchronises it.  Errors:
- * EINVAL, ENOTSUP, ENOMEM, EHIP.  On error *out is NULL. */
+/* Build a plan: validates *p, attaches the kernel-mode tables shared by
+ * every plan with the same (d, N, C_phi), and allocates the plan's workspace
+ * on the current device.  The tables of the plan's precision are built on
+ * first use: every value is computed in FP64 on the device and stored in
+ * FP64 (BNQ_FP64) or rounded to FP32 (BNQ_FP32C), so an FP32c plan never
+ * needs the FP64 tables (at 3-D N = 48 they take 364 GB, the FP32 ones
+ * 182 GB).  Tables are built on `stream` and the call synchronises it.
+ * Errors: EINVAL, ENOTSUP, ENOMEM (also when the tables do not fit the free
+ * device memory), EHIP.  On error *out is NULL. */
 bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out);
 
 /* Release the plan (waits for its stream work); drops its reference to the
@@ -124,7 +128,8 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out);
 bnq_status bnq_plan_destroy(bnq_plan_t plan);
 
 /* Device bytes the plan would need: *plan_bytes for its own workspace,
- * *table_bytes for the shared tables (0 if already resident).  Host only. */
+ * *table_bytes for the shared tables of its precision (0 if already
+ * resident).  Host only. */
 bnq_status bnq_plan_footprint(const bnq_params *p, size_t *plan_bytes, size_t *table_bytes);
 
 /* Q = c (L/pi)^(d+gamma) Re IDFT(Qhat) for the grid distribution f (the right
@@ -158,7 +163,9 @@ bnq_status bnq_moments(bnq_plan_t plan, const double *f, double *out_host, bnq_s
  * |b|_inf <= N-1 (the trilinear table) -- or, with table = 1, a and b in
  * I_N (the classical weight table: returns beta(a,b) - beta(b,b)), table = 2
  * (the quantum pair weight: beta(a,b) - beta(a+b,a) - beta(a,a+b)).
- * Synchronous; for tests and diagnostics.  Errors: EINVAL (out of range). */
+ * Values come from the FP64 tables if the table set holds them, else from
+ * the FP32 ones (rounded to nearest).  Synchronous; for tests and
+ * diagnostics.  Errors: EINVAL (out of range). */
 bnq_status bnq_table_lookup(bnq_plan_t plan, int32_t table, int64_t n, const int32_t *a_host,
                             const int32_t *b_host, double *out_host);
 

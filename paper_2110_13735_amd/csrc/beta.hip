@@ -125,8 +125,10 @@ __device__ static double beta_series(const Radial &rad, int qa, int qb, double d
 }
 
 // K[kc][a] = beta(a, b_c[kc]) for a in A, stored as [a0][a2 (padded)][a1];
-// the x padding holds zeros.
-__global__ void beta_rows_kernel(Geo g, Radial rad, const int *canon, double *K) {
+// the x padding holds zeros.  Every value is formed in FP64; an FP32 table
+// holds it rounded to nearest.
+template <typename T>
+__global__ void beta_rows_kernel(Geo g, Radial rad, const int *canon, T *K) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int kc = blockIdx.y;
     if (i >= g.nak) return;
@@ -142,12 +144,17 @@ __global__ void beta_rows_kernel(Geo g, Radial rad, const int *canon, double *K)
         const int dab = abs(a0 * b0 + a1 * b1 + a2 * b2);
         v = beta_series(rad, qa, qb, (double)dab);
     }
-    K[(int64_t)kc * g.nak + i] = v;
+    K[(int64_t)kc * g.nak + i] = (T)v;
 }
 
 void launch_beta_rows(const Geo &g, const Radial &rad, const int *canon, int ncanon, double *K, hipStream_t s) {
     dim3 grid((unsigned)((g.nak + 255) / 256), (unsigned)ncanon);
-    hipLaunchKernelGGL(beta_rows_kernel, grid, dim3(256), 0, s, g, rad, canon, K);
+    hipLaunchKernelGGL(beta_rows_kernel<double>, grid, dim3(256), 0, s, g, rad, canon, K);
+}
+
+void launch_beta_rows(const Geo &g, const Radial &rad, const int *canon, int ncanon, float *K, hipStream_t s) {
+    dim3 grid((unsigned)((g.nak + 255) / 256), (unsigned)ncanon);
+    hipLaunchKernelGGL(beta_rows_kernel<float>, grid, dim3(256), 0, s, g, rad, canon, K);
 }
 
 __device__ static inline void mode_of(const Geo &g, int64_t i, int &k0, int &k1, int &k2) {
@@ -159,7 +166,8 @@ __device__ static inline void mode_of(const Geo &g, int64_t i, int &k0, int &k1,
 // Pair weights on I_N x I_N, [l][m] order:
 //   wc = beta(l,m) - beta(m,m)                      (only where l+m in I_N; 0 elsewhere)
 //   wq = beta(l,m) - beta(l+m,l) - beta(l,l+m)
-__global__ void weights_kernel(Geo g, Radial rad, double *wc, double *wq) {
+template <typename T>
+__global__ void weights_kernel(Geo g, Radial rad, T *wc, T *wq) {
     const int64_t im = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t il = blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
     if (im >= g.nm || il >= g.nm) return;
@@ -179,24 +187,38 @@ __global__ void weights_kernel(Geo g, Radial rad, double *wc, double *wq) {
     const bool inI = s1 >= lo && s1 <= hi && s2 >= lo && s2 <= hi &&
                      (g.d == 2 || (s0 >= lo && s0 <= hi));
     const int64_t o = il * g.nm + im;
-    wc[o] = inI ? blm - bmm : 0.0;
-    wq[o] = blm - bsl - bls;
+    wc[o] = (T)(inI ? blm - bmm : 0.0);
+    wq[o] = (T)(blm - bsl - bls);
 }
 
-void launch_weights(const Geo &g, const Radial &rad, double *wc, double *wq, hipStream_t s) {
+template <typename T>
+static void launch_weights_t(const Geo &g, const Radial &rad, T *wc, T *wq, hipStream_t s) {
     unsigned gy = (unsigned)(g.nm < 65535 ? g.nm : 32768);
     unsigned gz = (unsigned)((g.nm + gy - 1) / gy);
     dim3 grid((unsigned)((g.nm + 255) / 256), gy, gz);
-    hipLaunchKernelGGL(weights_kernel, grid, dim3(256), 0, s, g, rad, wc, wq);
+    hipLaunchKernelGGL(weights_kernel<T>, grid, dim3(256), 0, s, g, rad, wc, wq);
 }
 
-__global__ void gather_kernel(const double *base, const int64_t *idx, int64_t n, double *out) {
+void launch_weights(const Geo &g, const Radial &rad, double *wc, double *wq, hipStream_t s) {
+    launch_weights_t(g, rad, wc, wq, s);
+}
+
+void launch_weights(const Geo &g, const Radial &rad, float *wc, float *wq, hipStream_t s) {
+    launch_weights_t(g, rad, wc, wq, s);
+}
+
+template <typename T>
+__global__ void gather_kernel(const T *base, const int64_t *idx, int64_t n, double *out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = base[idx[i]];
+    if (i < n) out[i] = (double)base[idx[i]];
 }
 
 void launch_gather(const double *base, const int64_t *idx, int64_t n, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, base, idx, n, out);
+    hipLaunchKernelGGL(gather_kernel<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, base, idx, n, out);
+}
+
+void launch_gather(const float *base, const int64_t *idx, int64_t n, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(gather_kernel<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, base, idx, n, out);
 }
 
 }  // namespace bnq

@@ -17,10 +17,6 @@
 #include "../../include/bnq.h"
 #include "bnq_internal.h"
 
-namespace bnq {
-void launch_gather(const double *base, const int64_t *idx, int64_t n, double *out, hipStream_t s);
-}
-
 using namespace bnq;
 
 namespace {
@@ -157,8 +153,9 @@ struct TableSet {
     std::vector<int> canon_row;  // [N][N][N] -> row or -1
     int ncanon = 0;
     int *canon_d = nullptr;
+    // kernel-mode tables, each precision built when a plan first needs it
     double *K = nullptr, *wc = nullptr, *wq = nullptr;
-    float *K32 = nullptr, *wc32 = nullptr, *wq32 = nullptr;  // FP32c copies, made on first use
+    float *K32 = nullptr, *wc32 = nullptr, *wq32 = nullptr;
     size_t bytes = 0;
     Radial radial() const {
         Radial r;
@@ -196,16 +193,23 @@ void canon_list(int d, int N, std::vector<int> &canon, std::vector<int> &row) {
     }
 }
 
-size_t table_bytes(int d, int N) {
+// Bytes of the radial tables of a table set, and of its kernel-mode tables
+// (trilinear rows plus the two pair-weight tables) in FP64 and in FP32.
+size_t table_bytes_radial(int d, int N) {
+    const int qmax = d * N * N;
+    const int M = mcut_of(qmax) + 1;
+    return sizeof(double) * ((size_t)(qmax + 1) * M) + sizeof(int) * (qmax + 1);
+}
+
+size_t table_values(int d, int N) {
     Geo g = make_geo(d, N);
     std::vector<int> canon, row;
     canon_list(d, N, canon, row);
-    const size_t ncanon = canon.size() / 3;
-    const int qmax = d * N * N;
-    const int M = mcut_of(qmax) + 1;
-    return sizeof(double) * (ncanon * (size_t)g.nak + 2 * (size_t)g.nm * g.nm + (size_t)(qmax + 1) * M) +
-           sizeof(int) * (qmax + 1);
+    return (canon.size() / 3) * (size_t)g.nak + 2 * (size_t)g.nm * g.nm;
 }
+
+size_t table_bytes_f64(int d, int N) { return sizeof(double) * table_values(d, N); }
+size_t table_bytes_f32(int d, int N) { return sizeof(float) * table_values(d, N); }
 
 void free_tables(TableSet *t) {
     hipFree(t->J);
@@ -248,7 +252,6 @@ bnq_status upload(T **p, const std::vector<T> &v, const char *what) {
 bnq_status build_tables(TableSet *t, hipStream_t s) {
     const int d = t->d, N = t->N;
     t->g = make_geo(d, N);
-    const Geo &g = t->g;
     t->qmax = d * N * N;
     t->M = mcut_of(t->qmax) + 1;
     bnq_status st;
@@ -294,50 +297,84 @@ bnq_status build_tables(TableSet *t, hipStream_t s) {
     hipFree(scratch);
     hipFree(glx_d);
     hipFree(glw_d);
-    // trilinear rows
     canon_list(d, N, t->canon, t->canon_row);
     t->ncanon = (int)(t->canon.size() / 3);
     if ((st = upload(&t->canon_d, t->canon, "canonical list"))) return st;
-    if ((st = dalloc(&t->K, (size_t)t->ncanon * g.nak, "trilinear kernel-mode table"))) return st;
-    if ((st = dalloc(&t->wc, (size_t)g.nm * g.nm, "classical weight table"))) return st;
-    if ((st = dalloc(&t->wq, (size_t)g.nm * g.nm, "quantum pair weight table"))) return st;
-    const Radial rad = t->radial();
-    launch_beta_rows(g, rad, t->canon_d, t->ncanon, t->K, s);
-    LAUNCHCHK();
-    launch_weights(g, rad, t->wc, t->wq, s);
-    LAUNCHCHK();
-    HIPCHK(hipStreamSynchronize(s));
-    t->bytes = table_bytes(d, N);
+    t->bytes = table_bytes_radial(d, N);
     return BNQ_OK;
 }
 
-bnq_status acquire_tables(int d, int N, double Cphi, hipStream_t s, TableSet **out) {
+// Kernel-mode tables of one precision (T = double: FP64 plans; T = float:
+// FP32c plans), built on first need.  Each value is formed in FP64 from the
+// radial table; the FP32 tables hold it rounded to nearest, so they never
+// need the FP64 ones (at 3-D N = 48 only the FP32 set fits one GPU).
+template <typename T>
+bnq_status build_kernel_mode(TableSet *t, T **K, T **wc, T **wq, hipStream_t s) {
+    if (*K) return BNQ_OK;
+    const Geo &g = t->g;
+    const size_t nk = (size_t)t->ncanon * g.nak, nw = (size_t)g.nm * g.nm;
+    const size_t need = sizeof(T) * (nk + 2 * nw);
+    size_t freeb = 0, totalb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totalb));
+    if (need > freeb)
+        return fail(BNQ_ENOMEM, "%s kernel-mode tables need %zu bytes, %zu free",
+                    sizeof(T) == 8 ? "FP64" : "FP32", need, freeb);
+    T *k = nullptr, *c = nullptr, *q = nullptr;
+    bnq_status st;
+    if ((st = dalloc(&k, nk, "trilinear kernel-mode table")) || (st = dalloc(&c, nw, "classical weight table")) ||
+        (st = dalloc(&q, nw, "quantum pair weight table"))) {
+        hipFree(k);
+        hipFree(c);
+        return st;
+    }
+    const Radial rad = t->radial();
+    launch_beta_rows(g, rad, t->canon_d, t->ncanon, k, s);
+    launch_weights(g, rad, c, q, s);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        hipFree(k);
+        hipFree(c);
+        hipFree(q);
+        return fail(BNQ_EHIP, "kernel-mode table build failed: %s", hipGetErrorString(e));
+    }
+    *K = k;
+    *wc = c;
+    *wq = q;
+    t->bytes += need;
+    return BNQ_OK;
+}
+
+// The table set of (d, N, C_phi) on the current device, with the kernel-mode
+// tables of precision prec, shared by every plan that uses it (refcounted).
+bnq_status acquire_tables(int d, int N, double Cphi, int prec, hipStream_t s, TableSet **out) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
-    for (TableSet *t : g_cache)
-        if (t->d == d && t->N == N && t->Cphi == Cphi && t->device == dev) {
-            t->refs++;
-            *out = t;
-            return BNQ_OK;
+    TableSet *t = nullptr;
+    for (TableSet *c : g_cache)
+        if (c->d == d && c->N == N && c->Cphi == Cphi && c->device == dev) t = c;
+    bnq_status st;
+    const bool fresh = t == nullptr;
+    if (fresh) {
+        t = new TableSet;
+        t->d = d;
+        t->N = N;
+        t->Cphi = Cphi;
+        t->device = dev;
+        if ((st = build_tables(t, s))) {
+            free_tables(t);
+            return st;
         }
-    size_t freeb = 0, totalb = 0;
-    HIPCHK(hipMemGetInfo(&freeb, &totalb));
-    const size_t need = table_bytes(d, N);
-    if (need > freeb)
-        return fail(BNQ_ENOMEM, "kernel-mode tables need %zu bytes, %zu free", need, freeb);
-    TableSet *t = new TableSet;
-    t->d = d;
-    t->N = N;
-    t->Cphi = Cphi;
-    t->device = dev;
-    bnq_status st = build_tables(t, s);
+    }
+    st = prec == BNQ_FP32C ? build_kernel_mode(t, &t->K32, &t->wc32, &t->wq32, s)
+                           : build_kernel_mode(t, &t->K, &t->wc, &t->wq, s);
     if (st) {
-        free_tables(t);
+        if (fresh) free_tables(t);
         return st;
     }
-    t->refs = 1;
-    g_cache.push_back(t);
+    if (fresh) g_cache.push_back(t);
+    t->refs++;
     *out = t;
     return BNQ_OK;
 }
@@ -347,44 +384,6 @@ void release_tables(TableSet *t) {
     if (--t->refs > 0) return;
     g_cache.erase(std::remove(g_cache.begin(), g_cache.end(), t), g_cache.end());
     free_tables(t);
-}
-
-// FP32c copies of the tables (round to nearest), made once per table set.
-size_t table_bytes_f32(int d, int N) {
-    Geo g = make_geo(d, N);
-    std::vector<int> canon, row;
-    canon_list(d, N, canon, row);
-    return sizeof(float) * ((canon.size() / 3) * (size_t)g.nak + 2 * (size_t)g.nm * g.nm);
-}
-
-bnq_status ensure_f32(TableSet *t, hipStream_t s) {
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    if (t->K32) return BNQ_OK;
-    const size_t nk = (size_t)t->ncanon * t->g.nak, nw = (size_t)t->g.nm * t->g.nm;
-    float *K32 = nullptr, *wc32 = nullptr, *wq32 = nullptr;
-    bnq_status st;
-    if ((st = dalloc(&K32, nk, "FP32 trilinear table")) || (st = dalloc(&wc32, nw, "FP32 weights")) ||
-        (st = dalloc(&wq32, nw, "FP32 weights"))) {
-        hipFree(K32);
-        hipFree(wc32);
-        return st;
-    }
-    launch_to_f32(t->K, K32, (int64_t)nk, s);
-    launch_to_f32(t->wc, wc32, (int64_t)nw, s);
-    launch_to_f32(t->wq, wq32, (int64_t)nw, s);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-        hipFree(K32);
-        hipFree(wc32);
-        hipFree(wq32);
-        return fail(BNQ_EHIP, "FP32 table conversion failed: %s", hipGetErrorString(e));
-    }
-    t->K32 = K32;
-    t->wc32 = wc32;
-    t->wq32 = wq32;
-    t->bytes += sizeof(float) * (nk + 2 * nw);
-    return BNQ_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -440,13 +439,14 @@ struct bnq_plan_s {
     double *mom_part = nullptr, *mom_out = nullptr;
     double *ginv = nullptr;  // inverse Gram matrix for BNQ_CORR_MOMENTS
     int nslots = 0;
-    int *slot_off = nullptr;
     T1Item *items = nullptr;
     T1B *bdesc = nullptr;
     std::vector<T1Item> items_h;  // per-slot item lists (host copy), slot offsets
     std::vector<int> off_h;       // (dynamic schedule: queue offsets)
     int nq = 0;                   // dynamic schedule: queues (0 = static)
-    int *qoff = nullptr, *qctr = nullptr;
+    int *qctr = nullptr;
+    int nchunk = 1;               // trilinear launches per evaluation
+    int *t1cut = nullptr;         // their item ranges (t1_cuts)
     T1Tune tune;                  // trilinear work distribution
     Inst ih{};                    // workspace pointers and scalars (host copy)
     Inst *inst_d = nullptr;       // device copy, one entry
@@ -570,6 +570,29 @@ bnq_status gram_inverse(int d, int N, double hstep, std::vector<double> &out) {
     return BNQ_OK;
 }
 
+// Trilinear terms of one evaluation, and the number of launches it is cut
+// into: at most about 2e13 terms (one to two seconds) per launch, so that no
+// single kernel runs for tens of seconds at 3-D N = 48.
+double t1_terms(int d, int N) {
+    double c1, w1, o1, t1;
+    counts_1d(N, c1, w1, o1, t1);
+    return std::pow(t1, d);
+}
+
+int t1_chunks(double terms) { return std::max(1, (int)std::ceil(terms / 2e13)); }
+
+// Item ranges of the launches: off holds the nl + 1 boundaries of the nl
+// slot lists (or queues); launch r covers [cut[r nl + i], cut[(r + 1) nl + i])
+// of list i, so the launches together walk every list once, in order.
+std::vector<int> t1_cuts(const std::vector<int> &off, int nchunk) {
+    const size_t nl = off.size() - 1;
+    std::vector<int> cut((nchunk + 1) * nl);
+    for (int r = 0; r <= nchunk; ++r)
+        for (size_t i = 0; i < nl; ++i)
+            cut[r * nl + i] = off[i] + (int)((int64_t)(off[i + 1] - off[i]) * r / nchunk);
+    return cut;
+}
+
 bnq_status build_t1_work(bnq_plan_s *P) {
     const Geo &g = P->g;
     const TableSet *t = P->tabs;
@@ -674,9 +697,10 @@ bnq_status build_t1_work(bnq_plan_s *P) {
         P->items_h = flat;
         P->off_h = qoff;
         bnq_status st;
+        P->nchunk = t1_chunks(t1_terms(d, N));
         if ((st = upload(&P->bdesc, bd, "trilinear b descriptors")) ||
             (!flat.empty() && (st = upload(&P->items, flat, "trilinear items"))) ||
-            (st = upload(&P->qoff, qoff, "trilinear queues")) ||
+            (st = upload(&P->t1cut, t1_cuts(qoff, P->nchunk), "trilinear queues")) ||
             (st = dalloc(&P->qctr, (size_t)((nx + 1) & ~1), "trilinear queue tickets")))
             return st;
         return dalloc(&P->part, (size_t)ns_want * g.nm, "trilinear partial sums");
@@ -714,9 +738,10 @@ bnq_status build_t1_work(bnq_plan_s *P) {
     P->nbdesc = (int)bd.size();
     P->items_h = flat;
     P->off_h = off;
+    P->nchunk = t1_chunks(t1_terms(d, N));
     bnq_status st;
     if ((st = upload(&P->bdesc, bd, "trilinear b descriptors")) || (st = upload(&P->items, flat, "trilinear items")) ||
-        (st = upload(&P->slot_off, off, "trilinear slot offsets")))
+        (st = upload(&P->t1cut, t1_cuts(off, P->nchunk), "trilinear slot ranges")))
         return st;
     return dalloc(&P->part, (size_t)ns * g.nm, "trilinear partial sums");
 }
@@ -726,15 +751,14 @@ bnq_status rebuild_t1(bnq_plan_s *P, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
     hipFree(P->bdesc);
     hipFree(P->items);
-    hipFree(P->slot_off);
+    hipFree(P->t1cut);
     hipFree(P->part);
-    hipFree(P->qoff);
     hipFree(P->qctr);
-    P->qoff = P->qctr = nullptr;
+    P->qctr = nullptr;
     P->nq = 0;
     P->bdesc = nullptr;
     P->items = nullptr;
-    P->slot_off = nullptr;
+    P->t1cut = nullptr;
     P->part = nullptr;
     bnq_status st = build_t1_work(P);
     if (st) return st;
@@ -767,11 +791,10 @@ void destroy_plan(bnq_plan_s *P) {
     hipFree(P->mom_part);
     hipFree(P->mom_out);
     hipFree(P->ginv);
-    hipFree(P->slot_off);
+    hipFree(P->t1cut);
     hipFree(P->items);
     hipFree(P->bdesc);
     hipFree(P->inst_d);
-    hipFree(P->qoff);
     hipFree(P->qctr);
     for (auto &e : P->evs) {
         hipEventDestroy(e.a);
@@ -793,13 +816,13 @@ struct Exec {
     const double2 *tw = nullptr;
     const Rot *rots = nullptr;
     int nrot = 0, nslots = 0;
-    const int *slot_off = nullptr;
+    int nchunk = 1;                // trilinear launches
+    const int *t1cut = nullptr;    // their item ranges, (nchunk + 1) x (nq or nslots)
     const T1Item *items = nullptr;
     const T1B *bdesc = nullptr;
     const Inst *D = nullptr;
     int prec = 0;               // 0 FP64, 1 FP32c
     int nq = 0;                 // dynamic schedule: queues (0 = static)
-    const int *qoff = nullptr;
     int *qctr = nullptr;
     std::vector<Inst> Dh;       // host copies of D
     bnq_plan_s *timer = nullptr;  // plan whose timing spans record this run
@@ -813,13 +836,13 @@ Exec exec_of(bnq_plan_s *P) {
     E.rots = P->rots_d;
     E.nrot = (int)P->grp.size();
     E.nslots = P->nslots;
-    E.slot_off = P->slot_off;
+    E.nchunk = P->nchunk;
+    E.t1cut = P->t1cut;
     E.items = P->items;
     E.bdesc = P->bdesc;
     E.D = P->inst_d;
     E.prec = P->p.precision == BNQ_FP32C ? 1 : 0;
     E.nq = P->nq;
-    E.qoff = P->qoff;
     E.qctr = P->qctr;
     E.Dh.assign(1, P->ih);
     E.timer = P;
@@ -889,14 +912,15 @@ bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s
                 LAUNCHCHK();
             }
         }
-        if (E.nq) {
-            launch_zero(E.qctr, (int64_t)((E.nq + 1) & ~1) * (int64_t)sizeof(int), s);  // whole 8-byte words
-            LAUNCHCHK();
-        }
-        {
+        const int nl = E.nq ? E.nq : E.nslots;
+        for (int r = 0; r < E.nchunk; ++r) {
+            if (E.nq) {
+                launch_zero(E.qctr, (int64_t)((E.nq + 1) & ~1) * (int64_t)sizeof(int), s);  // whole 8-byte words
+                LAUNCHCHK();
+            }
             Span sp(E.timer, 3, s);
-            launch_trilinear(g, E.prec, E.nslots, E.slot_off, E.items, E.bdesc,
-                             E.prec ? (const void *)E.t->K32 : (const void *)E.t->K, E.D, E.rots, E.nq, E.qoff,
+            launch_trilinear(g, E.prec, E.nslots, E.t1cut + (size_t)r * nl, E.t1cut + (size_t)(r + 1) * nl, E.items,
+                             E.bdesc, E.prec ? (const void *)E.t->K32 : (const void *)E.t->K, E.D, E.rots, E.nq,
                              E.qctr, s);
             LAUNCHCHK();
         }
@@ -1013,14 +1037,17 @@ bnq_status bnq_plan_footprint(const bnq_params *p, size_t *plan_bytes, size_t *t
     if (st) return st;
     if (plan_bytes) *plan_bytes = plan_workspace_bytes(p, kMaxSlots);
     if (table_bytes_out) {
+        // the radial tables of a new table set, plus the kernel-mode tables
+        // of the plan's precision unless the cached set already has them
         const bool f32 = p->precision == BNQ_FP32C;
-        size_t tb = table_bytes(p->d, p->N) + (f32 ? table_bytes_f32(p->d, p->N) : 0);
+        const size_t km = f32 ? table_bytes_f32(p->d, p->N) : table_bytes_f64(p->d, p->N);
+        size_t tb = table_bytes_radial(p->d, p->N) + km;
         std::lock_guard<std::mutex> lk(g_cache_mu);
         int dev = 0;
         hipGetDevice(&dev);
         for (TableSet *t : g_cache)
             if (t->d == p->d && t->N == p->N && t->Cphi == p->C_phi && t->device == dev)
-                tb = (f32 && !t->K32) ? table_bytes_f32(p->d, p->N) : 0;
+                tb = (f32 ? t->K32 != nullptr : t->K != nullptr) ? 0 : km;
         *table_bytes_out = tb;
     }
     return BNQ_OK;
@@ -1040,7 +1067,7 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
     P->pref = p->c * std::pow(p->L / M_PI, p->d + (p->d == 3 ? 1 : 0));
     P->grp = make_group(p->d);
     P->last = s;
-    if ((st = acquire_tables(p->d, p->N, p->C_phi, s, &P->tabs))) {
+    if ((st = acquire_tables(p->d, p->N, p->C_phi, p->precision, s, &P->tabs))) {
         destroy_plan(P);
         return st;
     }
@@ -1069,7 +1096,7 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
             return st;
         }
     if (p->precision == BNQ_FP32C &&
-        ((st = ensure_f32(P->tabs, s)) || (st = dalloc(&P->G32, nm, "FP32 spectrum")) ||
+        ((st = dalloc(&P->G32, nm, "FP32 spectrum")) ||
          (st = dalloc(&P->Gr32, P->grp.size() * (size_t)g.next, "FP32 rotated spectra")))) {
         destroy_plan(P);
         return st;
@@ -1240,8 +1267,11 @@ bnq_status bnq_table_lookup(bnq_plan_t P, int32_t table, int64_t n, const int32_
         hipFree(idx_d);
         return st;
     }
-    const double *base = table == 0 ? t->K : (table == 1 ? t->wc : t->wq);
-    launch_gather(base, idx_d, n, out_d, nullptr);
+    // the FP64 tables if the set has them, else the FP32 ones
+    if (t->K)
+        launch_gather(table == 0 ? t->K : (table == 1 ? t->wc : t->wq), idx_d, n, out_d, nullptr);
+    else
+        launch_gather(table == 0 ? t->K32 : (table == 1 ? t->wc32 : t->wq32), idx_d, n, out_d, nullptr);
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipMemcpy(out, out_d, sizeof(double) * n, hipMemcpyDeviceToHost);
     hipFree(idx_d);
@@ -1361,9 +1391,9 @@ struct bnq_batch_s {
         Exec E;
         std::vector<int> members;  // positions in the batch
         Inst *D = nullptr;
-        int *slot_off = nullptr;
+        int *t1cut = nullptr;
         T1Item *items = nullptr;
-        int *qoff = nullptr, *qctr = nullptr;
+        int *qctr = nullptr;
     };
     std::vector<bnq_plan_s *> plans;
     std::vector<double *> f;
@@ -1381,9 +1411,8 @@ void destroy_batch(bnq_batch_s *B) {
     if (B->gexec) hipGraphExecDestroy(B->gexec);
     for (auto &G : B->groups) {
         hipFree(G.D);
-        hipFree(G.slot_off);
+        hipFree(G.t1cut);
         hipFree(G.items);
-        hipFree(G.qoff);
         hipFree(G.qctr);
     }
     delete B;
@@ -1484,21 +1513,24 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
             }
             off[ns] = (int)items.size();
         }
+        // launches per evaluation: by the trilinear terms of the whole group
+        double terms = 0;
+        for (int m : G.members)
+            if (plans[m]->ih.terms & BNQ_T_QTRI) terms += t1_terms(plans[m]->g.d, plans[m]->g.N);
+        G.E.nchunk = t1_chunks(terms);
         bnq_status st;
         if ((st = upload(&G.D, G.E.Dh, "batch instance descriptors")) ||
-            (!nq && (st = upload(&G.slot_off, off, "batch slot offsets"))) ||
-            (nq && (st = upload(&G.qoff, off, "batch queues"))) ||
+            (st = upload(&G.t1cut, t1_cuts(off, G.E.nchunk), nq ? "batch queues" : "batch slot ranges")) ||
             (nq && (st = dalloc(&G.qctr, (size_t)((nq + 1) & ~1), "batch queue tickets"))) ||
             (!items.empty() && (st = upload(&G.items, items, "batch trilinear items")))) {
             destroy_batch(B);
             return st;
         }
         G.E.nq = nq;
-        G.E.qoff = G.qoff;
         G.E.qctr = G.qctr;
         G.E.D = G.D;
         G.E.nslots = ns;
-        G.E.slot_off = G.slot_off;
+        G.E.t1cut = G.t1cut;
         G.E.items = G.items;
     }
     *out = B;

@@ -201,10 +201,14 @@ struct IOs {
 // ---- launchers (defined in the .hip files) --------------------------------
 void launch_radial(int d, double R, int qmax, int M, int nq, const double *glx, const double *glw,
                    double *S, double *J, hipStream_t s);
+// tables in FP64 or FP32 (values formed in FP64, rounded to nearest)
 void launch_beta_rows(const Geo &g, const Radial &rad, const int *canon, int ncanon, double *K,
                       hipStream_t s);
+void launch_beta_rows(const Geo &g, const Radial &rad, const int *canon, int ncanon, float *K, hipStream_t s);
 void launch_weights(const Geo &g, const Radial &rad, double *wc, double *wq, hipStream_t s);
+void launch_weights(const Geo &g, const Radial &rad, float *wc, float *wq, hipStream_t s);
 void launch_gather(const double *base, const int64_t *idx, int64_t n, double *out, hipStream_t s);
+void launch_gather(const float *base, const int64_t *idx, int64_t n, double *out, hipStream_t s);
 
 // DFT of grid values io.in -> Ghat (forward, scale N^-d) and Qh -> io.out
 // (inverse, real part, scale Inst::pref).
@@ -216,19 +220,21 @@ void launch_rotate(const Geo &g, int prec, const Inst *D, const IOs &io, const R
 void launch_pairs_reduce(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 void launch_pairs(const Geo &g, int prec, const Inst *D, const IOs &io, const void *wc, const void *wq, int w_any,
                   hipStream_t s);  // w_any: some instance of the launch needs the W pair sums
-void launch_to_f32(const double *in, float *out, int64_t n, hipStream_t s);
 void launch_outer(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 void launch_zero_part(const Geo &g, const Inst *D, const IOs &io, int max_slots, hipStream_t s);
 // prec 0: FP64 (K is double), 1: FP32c (K is float, spectra Inst::Gr32)
 // nq = 0: static per-slot lists; nq > 0: dynamic tickets over nq queues
-void launch_trilinear(const Geo &g, int prec, int nslots, const int *slot_off, const T1Item *items,
-                      const T1B *bdesc, const void *K, const Inst *D, const Rot *rots, int nq, const int *qoff,
-                      int *qctr, hipStream_t s);
-void launch_t1_pairs(const Geo &g, int nslots, const int *slot_off, const T1Item *items, const T1B *bdesc,
-                     const double *K, const Inst *D, const Rot *rots, int nq, const int *qoff, int *qctr,
+// Trilinear sum over the item ranges [lo[i], hi[i]) of the nslots slots
+// (static) or nq queues (dynamic).
+void launch_trilinear(const Geo &g, int prec, int nslots, const int *lo, const int *hi, const T1Item *items,
+                      const T1B *bdesc, const void *K, const Inst *D, const Rot *rots, int nq, int *qctr,
+                      hipStream_t s);
+void launch_t1_pairs(const Geo &g, int nslots, const int *lo, const int *hi, const T1Item *items,
+                     const T1B *bdesc, const double *K, const Inst *D, const Rot *rots, int nq, int *qctr,
                      hipStream_t s);
-void launch_t1_rows(const Geo &g, int nslots, const int *slot_off, const T1Item *items, const T1B *bdesc,
-                    const float *K, const Inst *D, const Rot *rots, int nq, const int *qoff, int *qctr, hipStream_t s);
+void launch_t1_rows(const Geo &g, int nslots, const int *lo, const int *hi, const T1Item *items,
+                    const T1B *bdesc, const float *K, const Inst *D, const Rot *rots, int nq, int *qctr,
+                    hipStream_t s);
 int t1_pairs_blocks_per_cu();
 int t1_rows_blocks_per_cu();
 int trilinear_blocks_per_cu(int prec);  // resident 64-lane trilinear workgroups per CU (0 on error)

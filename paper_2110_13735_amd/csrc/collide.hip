@@ -624,26 +624,16 @@ void launch_outer(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Trilinear sum: FP64 in t1_pairs.hip, FP32c in t1_rows.hip.
-void launch_trilinear(const Geo &g, int prec, int nslots, const int *slot_off, const T1Item *items,
-                      const T1B *bdesc, const void *K, const Inst *D, const Rot *rots, int nq, const int *qoff,
-                      int *qctr, hipStream_t s) {
+void launch_trilinear(const Geo &g, int prec, int nslots, const int *lo, const int *hi, const T1Item *items,
+                      const T1B *bdesc, const void *K, const Inst *D, const Rot *rots, int nq, int *qctr,
+                      hipStream_t s) {
     if (prec == 0)
-        launch_t1_pairs(g, nslots, slot_off, items, bdesc, (const double *)K, D, rots, nq, qoff, qctr, s);
+        launch_t1_pairs(g, nslots, lo, hi, items, bdesc, (const double *)K, D, rots, nq, qctr, s);
     else
-        launch_t1_rows(g, nslots, slot_off, items, bdesc, (const float *)K, D, rots, nq, qoff, qctr, s);
+        launch_t1_rows(g, nslots, lo, hi, items, bdesc, (const float *)K, D, rots, nq, qctr, s);
 }
 
 int trilinear_blocks_per_cu(int prec) { return prec == 0 ? t1_pairs_blocks_per_cu() : t1_rows_blocks_per_cu(); }
-
-__global__ void to_f32_kernel(const double *in, float *out, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = (float)in[i];
-}
-
-void launch_to_f32(const double *in, float *out, int64_t n, hipStream_t s) {
-    const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 16384);
-    hipLaunchKernelGGL(to_f32_kernel, dim3(nb), dim3(256), 0, s, in, out, n);
-}
 
 __global__ void zero_kernel(double *p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)

@@ -228,22 +228,24 @@ __device__ __forceinline__ const typename V2<T>::type *rotated_of(const Inst &I)
         return I.Gr32;
 }
 
-// Static schedule (nq = 0): slot blockIdx.x walks items[slot_off[slot] ..
-// slot_off[slot + 1]).  Dynamic schedule (nq > 0): the items are nq queues
-// (qoff), one per XCD; a wave takes the next item of its XCD's queue by
-// ticket (qctr, zeroed before the launch), then of the other queues.  Either
-// way a wave adds into partial array blockIdx.x of the item's instance.
+// Static schedule (nq = 0): slot blockIdx.x walks items[lo[slot] ..
+// hi[slot]).  Dynamic schedule (nq > 0): the items are nq queues, queue q
+// being items[lo[q] .. hi[q]), one per XCD; a wave takes the next item of its
+// XCD's queue by ticket (qctr, zeroed before the launch), then of the other
+// queues.  Either way a wave adds into partial array blockIdx.x of the item's
+// instance.  A long evaluation is cut into several launches, each over its
+// own ranges, which continue the same partial sums.
 template <typename T>
-__global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_off, const T1Item *items,
+__global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *lo, const int *hi, const T1Item *items,
                                                        const T1B *bdesc, const T *K, const Inst *D,
-                                                       const Rot *rots, int nq, const int *qoff, int *qctr) {
+                                                       const Rot *rots, int nq, int *qctr) {
     using T2 = typename V2<T>::type;
     __shared__ T2 ps[2][64];
     const int slot = blockIdx.x;
     const int lane = threadIdx.x;
     const int A = 2 * g.N - 1;
-    int it = nq ? -1 : slot_off[slot] - 1;
-    const int it_end = nq ? 0 : slot_off[slot + 1];
+    int it = nq ? -1 : lo[slot] - 1;
+    const int it_end = nq ? 0 : hi[slot];
     int q = nq ? (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) % (unsigned)nq) : 0;
     int qseen = 0;
     for (;;) {
@@ -255,8 +257,8 @@ __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_of
                 int tk = 0;
                 if (lane == 0) tk = atomicAdd(qctr + q, 1);
                 tk = __builtin_amdgcn_readfirstlane(tk);
-                if (tk < qoff[q + 1] - qoff[q]) {
-                    got = qoff[q] + tk;
+                if (tk < hi[q] - lo[q]) {
+                    got = lo[q] + tk;
                     break;
                 }
                 ++qseen;
@@ -345,10 +347,11 @@ __global__ __launch_bounds__(64) void trilinear_kernel(Geo g, const int *slot_of
 
 }  // namespace
 
-void launch_t1_rows(const Geo &g, int nslots, const int *slot_off, const T1Item *items, const T1B *bdesc,
-                     const float *K, const Inst *D, const Rot *rots, int nq, const int *qoff, int *qctr, hipStream_t s) {
-    hipLaunchKernelGGL(trilinear_kernel<float>, dim3(nslots), dim3(64), 0, s, g, slot_off, items, bdesc, K, D, rots,
-                       nq, qoff, qctr);
+void launch_t1_rows(const Geo &g, int nslots, const int *lo, const int *hi, const T1Item *items,
+                     const T1B *bdesc, const float *K, const Inst *D, const Rot *rots, int nq, int *qctr,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(trilinear_kernel<float>, dim3(nslots), dim3(64), 0, s, g, lo, hi, items, bdesc, K, D,
+                       rots, nq, qctr);
 }
 
 int t1_rows_blocks_per_cu() {

@@ -66,6 +66,24 @@ def test_footprint_sizes():
     assert plan_b > 0
 
 
+def test_footprint_3d48_fp32_tables_fit_one_gpu():
+    # 3-D N = 48: 19600 canonical trilinear rows of (2N-1)^2 (2N-1 + pad)
+    # values plus two N^6 pair-weight tables.  Only the FP32 set fits the
+    # 288 GB of one MI355X.
+    if not os.path.exists(bnq.LIBPATH):
+        pytest.skip("libbnq.so not built")
+    N = 48
+    plan32, tab32 = bnq.footprint(bnq.Params(d=3, N=N, L=8.0, precision=bnq.FP32C))
+    plan64, tab64 = bnq.footprint(bnq.Params(d=3, N=N, L=8.0))
+    vals_lo = 19600 * (2 * N - 1) ** 3 + 2 * N ** 6
+    vals_hi = 19600 * (2 * N - 1) ** 2 * (2 * N - 1 + 32) + 2 * N ** 6
+    radial = tab64 - 2 * (tab64 - tab32)  # bytes shared by both precisions
+    assert 0 < radial < 1e8
+    assert 4 * vals_lo <= tab32 - radial <= 4 * vals_hi
+    assert tab64 - radial == 2 * (tab32 - radial)
+    assert tab32 + plan32 < 250e9 < 288e9 < tab64
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(bnq, "LIBPATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(bnq, "_lib", None)
