@@ -98,7 +98,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=32)
-    ap.add_argument("--dt", type=float, default=0.01)
+    ap.add_argument("--dt", type=float, default=None,
+                    help="time step (default 0.01; c3: 0.001, since the condensing boson datum blows up near "
+                         "t = 0.15 at dt = 0.01)")
     ap.add_argument("--precision", choices=("fp64", "fp32c"), default="fp64")
     ap.add_argument("--eps", type=int, choices=(-1, 0, 1), default=-1,
                     help="statistics: -1 fermions (default, the trilinear-bound workload), +1 bosons, "
@@ -108,8 +110,10 @@ def main():
                          "between runs) or static (the library default, bitwise reproducible)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-N", type=int, default=10)
-    ap.add_argument("--workload", choices=("c2", "batch", "serve"), default="c2",
-                    help="c2: the 3-D N=32 fermion RK4 step (default); batch: mixed instances stepped together")
+    ap.add_argument("--workload", choices=("c2", "c3", "batch", "serve"), default="c2",
+                    help="c2: the 3-D N=32 fermion RK4 step (default); c3: 3-D bosons near condensation in "
+                         "FP32c (--N 32 or 48) with the error against FP64 every 10 steps; batch: mixed "
+                         "instances stepped together; serve: Poisson arrivals")
     ap.add_argument("--instances", type=int, default=60, help="batch workload: number of instances")
     ap.add_argument("--cells", choices=("mixed", "small"), default="mixed", help="batch workload: cell set")
     ap.add_argument("--rate", type=float, default=10.0, help="serve workload: mean arrivals per second")
@@ -130,10 +134,14 @@ def main():
     if not os.path.exists(bnq.LIBPATH):
         import __graft_entry__
         __graft_entry__.build()
+    if args.dt is None:
+        args.dt = 0.001 if args.workload == "c3" else 0.01
     if args.workload == "batch":
         return run_batch(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "c3":
+        return run_c3(args)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -266,6 +274,109 @@ def measured_peaks(torch, dev):
     del x, y, z
     torch.cuda.empty_cache()
     return {"hbm_copy_GB_s": round(copy_gbs, 1), "fp64_gemm_tflops": round(gemm_tf, 2)}
+
+
+def run_c3(args):
+    """3-D bosons (eps = +1) near condensation, f0 = a exp(-|v|^2 / T) with
+    T = 0.2, a = 10.6, L = 3: RK4 steps with the pair sums and the trilinear
+    sum in FP32c (FP32 spectra and tables, FP32 sums of at most two inner
+    rows, FP64 totals), the tables computed in FP64 and rounded, the moments
+    and stage updates in FP64.  Only the FP32c steps are timed.  At N = 32 an
+    FP64 trajectory runs beside it (untimed), and every 10 steps the bench
+    records the relative error of the FP32c Qhat on the current state and of
+    the moments of the FP32c trajectory against it; at N = 48 the FP64 tables
+    (364 GB) do not fit one GPU and only the FP32c run is made."""
+    import numpy as np
+    import torch
+
+    import bnq_inputs as inp
+    import paper_2110_13735_amd as bnq
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    N, L, eps = args.N, 3.0, 1
+    sched = bnq.SCHED_DYNAMIC if args.schedule == "dynamic" else bnq.SCHED_STATIC
+    p32 = bnq.Params(d=3, N=N, eps=eps, L=L, precision=bnq.FP32C, schedule=sched)
+    f0 = inp.boson_condensing_3d(N=N, L=L)
+    t_plan = time.perf_counter()
+    plan = bnq.Plan(p32)
+    t_plan = time.perf_counter() - t_plan
+    terms_step = 4.0 * bnq.terms_per_eval(p32, plan.counts())
+    ref = None
+    if N <= 32:
+        ref = bnq.Plan(bnq.Params(d=3, N=N, eps=eps, L=L, schedule=sched))
+    f = torch.tensor(f0, device=dev)
+    g = torch.tensor(f0, device=dev)
+    Q32 = torch.empty_like(f)
+    Q64 = torch.empty_like(f)
+    Qh32 = torch.empty(f.shape, dtype=torch.complex128, device=dev)
+    Qh64 = torch.empty_like(Qh32)
+    checks = []
+
+    def check(step):
+        if ref is None:
+            return
+        plan.collide(f, Q32, Qh32)
+        ref.collide(f, Q64, Qh64)
+        m32, m64 = plan.moments(f, check=False), ref.moments(g, check=False)
+        torch.cuda.synchronize()
+        eq = (torch.linalg.norm(Qh32 - Qh64) / torch.linalg.norm(Qh64)).item()
+        em = {k: abs(m32[k] - m64[k]) / max(abs(m64[k]), 1e-300) for k in ("rho", "e", "H", "fmax")}
+        checks.append({"step": step, "qhat_rel_err": eq, "moments_rel_err": em})
+        print(f"c3 N={N} step {step}: FP32c Qhat error {eq:.2e}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):  # warm-up steps act on copies of the start state
+        h = f.clone()
+        plan.step(h, args.dt, bnq.RK4)
+    torch.cuda.synchronize()
+    check(0)
+    elapsed = 0.0
+    blow_up = None
+    for k in range(1, args.steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step(f, args.dt, bnq.RK4)
+        m = plan.moments(f, check=False)
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        if m["status"] == bnq.BNQ_ENONFINITE:
+            blow_up = k
+            break
+        print(f"c3 N={N} step {k}: {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
+        if ref is not None:
+            ref.step(g, args.dt, bnq.RK4)
+        if k % 10 == 0 or k == args.steps:
+            check(k)
+    if blow_up:
+        print(f"c3: non-finite state after step {blow_up}", file=sys.stderr, flush=True)
+    mom = plan.moments(f, check=False)
+    out = {
+        "metric": METRIC,
+        "value": terms_step * (blow_up or args.steps) / elapsed,
+        "unit": "pair-terms/s",
+        "n_gpus": 1,
+        "steps": blow_up or args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / (blow_up or args.steps),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32c",
+        "data": "synthetic",
+        "config": {"workload": f"3-D bosons eps=+1 near condensation, N={N}^3, FP32c pair and trilinear sums, "
+                               f"FP64 tables precompute, moments and RK4 stages (dt={args.dt}); "
+                               f"f0 = 10.6 exp(-|v|^2/0.2), L=3, hard spheres",
+                   "d": 3, "N": N, "eps": eps, "precision": "fp32c", "schedule": args.schedule,
+                   "terms_per_eval": terms_step / 4, "plan_build_s": round(t_plan, 3)},
+        "error_vs_fp64": checks if ref is not None else
+        "FP64 tables (364 GB) do not fit one GPU at N=48; FP32c parity is checked on sparse spectra",
+        "moments_last": {k: mom[k] for k in ("rho", "e", "H", "fmax")},
+        "blow_up_step": blow_up,
+    }
+    plan.close()
+    if ref is not None:
+        ref.close()
+    print(json.dumps(out))
 
 
 BATCH_CELLS = {"mixed": [(2, 16), (2, 24), (2, 32), (3, 16), (3, 24)],
