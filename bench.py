@@ -99,8 +99,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=32)
     ap.add_argument("--dt", type=float, default=None,
-                    help="time step (default 0.01; c3: 0.001, since the condensing boson datum blows up near "
-                         "t = 0.15 at dt = 0.01)")
+                    help="time step (default 0.01; c3 and relax: 0.001, since those trajectories leave RK4's "
+                         "stability region at dt = 0.01)")
     ap.add_argument("--precision", choices=("fp64", "fp32c"), default="fp64")
     ap.add_argument("--eps", type=int, choices=(-1, 0, 1), default=-1,
                     help="statistics: -1 fermions (default, the trilinear-bound workload), +1 bosons, "
@@ -110,9 +110,10 @@ def main():
                          "between runs) or static (the library default, bitwise reproducible)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-N", type=int, default=10)
-    ap.add_argument("--workload", choices=("c2", "c3", "batch", "serve"), default="c2",
+    ap.add_argument("--workload", choices=("c2", "c3", "relax", "batch", "serve"), default="c2",
                     help="c2: the 3-D N=32 fermion RK4 step (default); c3: 3-D bosons near condensation in "
-                         "FP32c (--N 32 or 48) with the error against FP64 every 10 steps; batch: mixed "
+                         "FP32c (--N 32 or 48) with the error against FP64 every 10 steps; relax: the c2 "
+                         "trajectory with entropy and distance to its Fermi-Dirac limit every 10 steps; batch: mixed "
                          "instances stepped together; serve: Poisson arrivals")
     ap.add_argument("--instances", type=int, default=60, help="batch workload: number of instances")
     ap.add_argument("--cells", choices=("mixed", "small"), default="mixed", help="batch workload: cell set")
@@ -135,13 +136,15 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     if args.dt is None:
-        args.dt = 0.001 if args.workload == "c3" else 0.01
+        args.dt = 0.001 if args.workload in ("c3", "relax") else 0.01
     if args.workload == "batch":
         return run_batch(args)
     if args.workload == "serve":
         return run_serve(args)
     if args.workload == "c3":
         return run_c3(args)
+    if args.workload == "relax":
+        return run_relax(args)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -274,6 +277,72 @@ def measured_peaks(torch, dev):
     del x, y, z
     torch.cuda.empty_cache()
     return {"hbm_copy_GB_s": round(copy_gbs, 1), "fp64_gemm_tflops": round(gemm_tf, 2)}
+
+
+def run_relax(args):
+    """The c2 trajectory (3-D fermions, N = 32, three-Gaussian f0, RK4) with
+    its limit state: the Fermi-Dirac distribution of the same mass, velocity
+    and energy (fugacity by Brent's method on eq. eq_fugacity, in the
+    library), and every 10 steps the entropy H, the L1 distance and the
+    largest pointwise gap to it.  Only the steps are timed."""
+    import numpy as np
+    import torch
+
+    import bnq_inputs as inp
+    import paper_2110_13735_amd as bnq
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    N, L, eps = args.N, 8.0, -1
+    prec = bnq.FP32C if args.precision == "fp32c" else bnq.FP64
+    sched = bnq.SCHED_DYNAMIC if args.schedule == "dynamic" else bnq.SCHED_STATIC
+    p = bnq.Params(d=3, N=N, eps=eps, L=L, precision=prec, schedule=sched)
+    plan = bnq.Plan(p)
+    terms_step = 4.0 * bnq.terms_per_eval(p, plan.counts())
+    f = torch.tensor(inp.fermion_mixture_3d(N=N, L=L, seed=0), device=dev)
+    m = plan.moments(f)
+    st = bnq.equilibrium(3, eps, 1.0, m["rho"], [m["u0"], m["u1"], m["u2"]], m["e"])
+    track = []
+
+    def record(k):
+        mk = plan.moments(f, check=False)
+        dk = plan.equilibrium_distance(f, st)
+        track.append({"step": k, "t": round(k * args.dt, 6), "H": mk["H"], "l1": dk["l1"], "max_abs": dk["max_abs"],
+                      "fmax": mk["fmax"], "rho": mk["rho"], "e": mk["e"]})
+        print(f"relax step {k}: H {mk['H']:.8f} L1 {dk['l1']:.4e}", file=sys.stderr, flush=True)
+
+    record(0)
+    elapsed = 0.0
+    for k in range(1, args.steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step(f, args.dt, bnq.RK4)
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        if k % 10 == 0 or k == args.steps:
+            record(k)
+    out = {
+        "metric": METRIC,
+        "value": terms_step * args.steps / elapsed,
+        "unit": "pair-terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 0,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32c" if prec == bnq.FP32C else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3-D fermions eps=-1, N={N}^3, {args.precision.upper()}, hard spheres, hbar=1, L=8, "
+                               f"three-Gaussian f0 (seed 0), RK4 dt={args.dt} to t={args.steps * args.dt:g}, "
+                               f"relaxation to the Fermi-Dirac limit tracked every 10 steps",
+                   "d": 3, "N": N, "eps": eps, "precision": args.precision, "dt": args.dt},
+        "limit_state": st.as_dict(),
+        "relaxation": track,
+    }
+    plan.close()
+    print(json.dumps(out))
 
 
 def run_c3(args):

@@ -157,6 +157,76 @@ bnq_status bnq_step(bnq_plan_t plan, double *f, double dt, int32_t scheme, bnq_s
 #define BNQ_MOMENTS_LEN 10
 bnq_status bnq_moments(bnq_plan_t plan, const double *f, double *out_host, bnq_stream_t stream);
 
+/* ---- limit states (section 'Convergence towards a steady state') --------
+ * The state a solution relaxes to, for given mass rho, mean velocity u and
+ * internal energy e = (1/rho) int |v - u|^2 / 2 f dv.  With alpha = -eps
+ * hbar^d (the paper's alpha: > 0 Fermi-Dirac, < 0 Bose-Einstein) and
+ * ratio = |alpha| rho (d / (4 pi e))^(d/2):
+ *  BNQ_EQ_MAXWELL     alpha = 0: rho (2 pi T)^(-d/2) exp(-|v - u|^2 / 2T),
+ *                     T = 2e/d;
+ *  BNQ_EQ_QUANTUM     ratio inside I_eq: the quantum Maxwellian
+ *                     (1/|alpha|) / (z^-1 exp(|v - u|^2 / 2T) + sgn alpha),
+ *                     z from eq. eq_fugacity by Brent's method (in ln z for
+ *                     Fermi-Dirac), T from eq. mom2_qmaxwell;
+ *  BNQ_EQ_CONDENSATE  3-D Bose-Einstein with ratio at or beyond the end of
+ *                     I_eq: z = 1, the condensed mass m0 at v = u from eq.
+ *                     m0critical_bosons_3d, and T such that the z = 1 part
+ *                     carries the internal energy rho e (eq.
+ *                     Tcritical_bosons_3d as printed conserves the energy
+ *                     only at the critical ratio, where both agree);
+ *  BNQ_EQ_SATURATED   Fermi-Dirac at the end of I_eq (the equality
+ *                     critical_FD, to a relative 1e-9): rho / |D(u, A)| on
+ *                     the ball D(u, A), A = sqrt(2 e (d + 2) / d);
+ *  BNQ_EQ_UNKNOWN     Fermi-Dirac beyond it: no limit state is identified.
+ * The complete Fermi-Dirac / Bose-Einstein integrals K_nu are evaluated by
+ * composite Gauss-Legendre quadrature to about 1e-15 relative. */
+#define BNQ_EQ_MAXWELL 0
+#define BNQ_EQ_QUANTUM 1
+#define BNQ_EQ_CONDENSATE 2
+#define BNQ_EQ_SATURATED 3
+#define BNQ_EQ_UNKNOWN 4
+typedef struct {
+    int32_t kind;   /* BNQ_EQ_* */
+    int32_t d;
+    double alpha;   /* -eps hbar^d */
+    double rho;
+    double u[3];    /* components in the order of the moments' u (d = 2: u[0], u[1]) */
+    double e;
+    double z;       /* fugacity (1 for a condensate; may overflow for degenerate FD) */
+    double log_z;   /* ln z, always finite */
+    double T;
+    double m0;      /* condensed mass (BNQ_EQ_CONDENSATE), else 0 */
+    double A;       /* radius of the saturated ball (Fermi-Dirac), else 0 */
+    double ratio;   /* |alpha| rho (d / (4 pi e))^(d/2); 0 when alpha = 0 */
+} bnq_equilibrium;
+
+/* Limit state for (d, eps, hbar, rho, u[d], e).  Host only.  Errors: EINVAL
+ * (d not 2 or 3, rho or e not positive and finite, no root bracketed). */
+bnq_status bnq_equilibrium_solve(int32_t d, int32_t eps, double hbar, double rho, const double *u_host, double e,
+                                 bnq_equilibrium *out_host);
+
+/* ln K_nu of the complete Fermi-Dirac (fermi = 1, p = ln z) or Bose-Einstein
+ * (fermi = 0, p = -ln z >= 0) integral K_nu(z) = Gamma(nu)^-1 int_0^inf
+ * x^(nu-1) / (z^-1 e^x +- 1) dx, the quadrature the solver uses.  Host only;
+ * for tests.  Errors: EINVAL (nu < 1, or p < 0 with fermi = 0). */
+bnq_status bnq_fd_be_log(double nu, int32_t fermi, double p, double *out_host);
+
+/* The limit state on the plan's grid (v_j = 2 L j / N), FP64, on `stream`:
+ * out[j] = its value at v_j, with 0 written at the nodes where it is not a
+ * finite function (v_j = u for a condensate, and for BNQ_EQ_QUANTUM
+ * Bose-Einstein only if z = 1 exactly).  The plan's d must match.  Errors:
+ * EINVAL (null pointers, d mismatch, BNQ_EQ_UNKNOWN), EHIP. */
+bnq_status bnq_equilibrium_fill(bnq_plan_t plan, const bnq_equilibrium *eq_host, double *out, bnq_stream_t stream);
+
+/* Distance of grid data f to the limit state, over the nodes where the state
+ * is finite: out_host[0] = Delta v sum |f - M|, [1] = max |f - M|,
+ * [2] = Delta v sum M, [3] = number of excluded nodes (where M is infinite),
+ * [4] = Delta v sum f over them (to compare with a condensate's m0).
+ * Synchronises `stream`.  Errors as bnq_equilibrium_fill. */
+#define BNQ_EQDIST_LEN 5
+bnq_status bnq_equilibrium_distance(bnq_plan_t plan, const double *f, const bnq_equilibrium *eq_host,
+                                    double *out_host, bnq_stream_t stream);
+
 /* Kernel modes beta(a_i, b_i) read back from the plan's device tables, for
  * n integer vector pairs a_host[3*i..], b_host[3*i..] (d = 2 uses components
  * 1 and 2; component 0 must be 0).  Requires |a|_inf <= N-1 and

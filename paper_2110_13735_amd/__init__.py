@@ -61,6 +61,41 @@ class Params:
                        self.hbar, self.C_phi, self.c, self.L, self.schedule, 0)
 
 
+EQ_MAXWELL, EQ_QUANTUM, EQ_CONDENSATE, EQ_SATURATED, EQ_UNKNOWN = 0, 1, 2, 3, 4
+EQDIST_NAMES = ("l1", "max_abs", "mass_of_state", "n_excluded", "mass_excluded")
+
+
+class Equilibrium(ctypes.Structure):
+    """bnq_equilibrium: a limit state (kind EQ_*) and its parameters."""
+    _fields_ = [("kind", ctypes.c_int32), ("d", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("rho", ctypes.c_double), ("u", ctypes.c_double * 3), ("e", ctypes.c_double),
+                ("z", ctypes.c_double), ("log_z", ctypes.c_double), ("T", ctypes.c_double),
+                ("m0", ctypes.c_double), ("A", ctypes.c_double), ("ratio", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: (list(getattr(self, k)) if k == "u" else getattr(self, k)) for k, _ in self._fields_}
+
+
+def equilibrium(d: int, eps: int, hbar: float, rho: float, u, e: float) -> Equilibrium:
+    """Limit state for mass rho, mean velocity u (d components) and internal
+    energy e (bnq_equilibrium_solve)."""
+    uu = np.zeros(3)
+    uv = np.asarray(u, dtype=np.float64).ravel()[:3]
+    uu[:uv.size] = uv
+    out = Equilibrium()
+    _check(lib().bnq_equilibrium_solve(int(d), int(eps), float(hbar), float(rho), uu.ctypes.data, float(e),
+                                       ctypes.byref(out)))
+    return out
+
+
+def fd_be_log(nu: float, fermi: bool, p: float) -> float:
+    """ln of the complete Fermi-Dirac (p = ln z) or Bose-Einstein (p = -ln z)
+    integral K_nu (bnq_fd_be_log)."""
+    out = ctypes.c_double()
+    _check(lib().bnq_fd_be_log(float(nu), 1 if fermi else 0, float(p), ctypes.byref(out)))
+    return out.value
+
+
 _lib = None
 
 
@@ -90,10 +125,16 @@ def lib():
         L.bnq_batch_destroy.argtypes = [vp]
         L.bnq_batch_collide.argtypes = [vp, vp, vp, vp]
         L.bnq_batch_step.argtypes = [vp, vp, i32, i32, vp]
+        EQ = ctypes.POINTER(Equilibrium)
+        L.bnq_equilibrium_solve.argtypes = [i32, i32, f64, f64, vp, f64, EQ]
+        L.bnq_fd_be_log.argtypes = [f64, i32, f64, ctypes.POINTER(f64)]
+        L.bnq_equilibrium_fill.argtypes = [vp, EQ, vp, vp]
+        L.bnq_equilibrium_distance.argtypes = [vp, vp, EQ, vp, vp]
         for fn in ("bnq_plan", "bnq_plan_destroy", "bnq_plan_footprint", "bnq_collide", "bnq_step",
                    "bnq_moments", "bnq_table_lookup", "bnq_plan_counts", "bnq_plan_set_timing",
                    "bnq_plan_timing", "bnq_plan_autotune", "bnq_batch_create", "bnq_batch_destroy", "bnq_batch_collide",
-                   "bnq_batch_step"):
+                   "bnq_batch_step", "bnq_equilibrium_solve", "bnq_fd_be_log", "bnq_equilibrium_fill",
+                   "bnq_equilibrium_distance"):
             getattr(L, fn).restype = ctypes.c_int
         L.bnq_status_string.argtypes = [ctypes.c_int]
         L.bnq_status_string.restype = ctypes.c_char_p
@@ -173,6 +214,15 @@ class Plan:
         res = dict(zip(MOMENT_NAMES, out.tolist()))
         res["status"] = st
         return res
+
+    def equilibrium_fill(self, eq: Equilibrium, out, stream=None):
+        _check(lib().bnq_equilibrium_fill(self._h, ctypes.byref(eq), _ptr(out), _stream(stream)))
+
+    def equilibrium_distance(self, f, eq: Equilibrium, stream=None) -> dict:
+        out = np.zeros(len(EQDIST_NAMES))
+        _check(lib().bnq_equilibrium_distance(self._h, _ptr(f), ctypes.byref(eq), out.ctypes.data,
+                                              _stream(stream)))
+        return dict(zip(EQDIST_NAMES, out.tolist()))
 
     def lookup(self, table: int, a, b) -> np.ndarray:
         a = np.ascontiguousarray(a, dtype=np.int32).reshape(-1, 3)

@@ -1229,6 +1229,100 @@ bnq_status bnq_moments(bnq_plan_t P, const double *f, double *out_host, bnq_stre
     return BNQ_OK;
 }
 
+bnq_status bnq_equilibrium_solve(int32_t d, int32_t eps, double hbar, double rho, const double *u, double e,
+                                 bnq_equilibrium *out) {
+    if (!out) return fail(BNQ_EINVAL, "out is NULL");
+    if (eps < -1 || eps > 1) return fail(BNQ_EINVAL, "eps must be -1, 0 or 1 (got %d)", eps);
+    if (!(hbar > 0) || !std::isfinite(hbar)) return fail(BNQ_EINVAL, "hbar must be positive and finite");
+    const double alpha = -(double)eps * std::pow(hbar, d == 3 ? 3 : 2);
+    char err[256] = "";
+    const int st = solve_equilibrium(d, alpha, rho, u, e, out, err, sizeof err);
+    if (st) return fail((bnq_status)st, "%s", err);
+    return BNQ_OK;
+}
+
+bnq_status bnq_fd_be_log(double nu, int32_t fermi, double p, double *out) {
+    if (!out) return fail(BNQ_EINVAL, "out is NULL");
+    if (!(nu >= 1.0) || !std::isfinite(nu) || !std::isfinite(p) || (!fermi && !(p >= 0.0)) ||
+        (!fermi && nu <= 1.0 && p == 0.0))
+        return fail(BNQ_EINVAL, "need nu >= 1, finite p, and p >= 0 (p > 0 for nu = 1) for Bose-Einstein");
+    *out = complete_fd_be_log(nu, fermi ? 1 : 0, p);
+    return BNQ_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// device form of a limit state for the plan's grid
+bnq_status eq_dev(const bnq_plan_s *P, const bnq_equilibrium *q, EqDev &E) {
+    if (!q) return fail(BNQ_EINVAL, "equilibrium is NULL");
+    if (q->d != P->g.d) return fail(BNQ_EINVAL, "equilibrium of d = %d for a plan of d = %d", q->d, P->g.d);
+    const int d = q->d;
+    E.kind = q->kind;
+    E.d = d;
+    E.bose = q->alpha < 0;
+    for (int i = 0; i < 3; ++i) E.u[i] = q->u[i];
+    E.log_z = q->log_z;
+    E.T = q->T;
+    E.A2 = 0;
+    switch (q->kind) {
+        case BNQ_EQ_MAXWELL: E.c0 = q->rho * std::pow(2.0 * M_PI * q->T, -0.5 * d); break;
+        case BNQ_EQ_QUANTUM: E.c0 = 1.0 / std::fabs(q->alpha); break;
+        case BNQ_EQ_CONDENSATE:
+            E.c0 = 1.0 / std::fabs(q->alpha);
+            E.bose = 1;
+            E.log_z = 0.0;
+            break;
+        case BNQ_EQ_SATURATED:
+            E.A2 = q->A * q->A;
+            E.c0 = q->rho / (std::pow(M_PI, 0.5 * d) * std::pow(q->A, d) / std::tgamma(0.5 * d + 1.0));
+            break;
+        default: return fail(BNQ_EINVAL, "no limit state identified (kind %d)", q->kind);
+    }
+    if (q->kind != BNQ_EQ_SATURATED && !(E.T > 0)) return fail(BNQ_EINVAL, "temperature must be positive");
+    return BNQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bnq_status bnq_equilibrium_fill(bnq_plan_t P, const bnq_equilibrium *q, double *out, bnq_stream_t stream) {
+    if (!P || !out) return fail(BNQ_EINVAL, "plan and out must be non-NULL");
+    EqDev E;
+    bnq_status st = eq_dev(P, q, E);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    P->last = s;
+    launch_equilibrium(P->g, P->p.L, E, nullptr, out, nullptr, MOM_BLOCKS, nullptr, s);
+    LAUNCHCHK();
+    return BNQ_OK;
+}
+
+bnq_status bnq_equilibrium_distance(bnq_plan_t P, const double *f, const bnq_equilibrium *q, double *out_host,
+                                    bnq_stream_t stream) {
+    if (!P || !f || !out_host) return fail(BNQ_EINVAL, "plan, f and out_host must be non-NULL");
+    EqDev E;
+    bnq_status st = eq_dev(P, q, E);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    P->last = s;
+    static_assert(EQ_FIELDS <= MOM_FIELDS, "moment buffers hold the distance partials");
+    launch_equilibrium(P->g, P->p.L, E, f, nullptr, P->mom_part, MOM_BLOCKS, P->mom_out, s);
+    LAUNCHCHK();
+    double r[EQ_FIELDS];
+    HIPCHK(hipMemcpyAsync(r, P->mom_out, sizeof r, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double dv = std::pow(2.0 * P->p.L / P->p.N, P->p.d);
+    out_host[0] = dv * r[0];
+    out_host[1] = r[1];
+    out_host[2] = dv * r[2];
+    out_host[3] = r[3];
+    out_host[4] = dv * r[4];
+    return BNQ_OK;
+}
+
 bnq_status bnq_table_lookup(bnq_plan_t P, int32_t table, int64_t n, const int32_t *a, const int32_t *b,
                             double *out) {
     if (!P) return fail(BNQ_EINVAL, "plan is NULL");

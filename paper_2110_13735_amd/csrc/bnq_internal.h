@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/bnq.h"
+
 namespace bnq {
 
 struct Geo {
@@ -252,5 +254,26 @@ void launch_moments(const Geo &g, const double *f, double L, double alpha, doubl
                     double *out, hipStream_t s);
 constexpr int MOM_BLOCKS = 256;
 constexpr int MOM_FIELDS = 12;
+
+// A limit state on the grid (kinds as BNQ_EQ_*): M(v) with r2 = |v - u|^2
+//   kind 0: c0 exp(-r2 / 2T)                       (c0 = rho (2 pi T)^(-d/2))
+//   kind 1, 2: c0 / (exp(r2 / 2T - log_z) + sgn)   (c0 = 1/|alpha|; sgn = -1
+//              uses expm1, and a zero denominator marks the node excluded)
+//   kind 3: c0 for r2 <= A2, else 0                (c0 = rho / |D(u, A)|)
+struct EqDev {
+    int kind, d, bose;
+    double c0, u[3], log_z, T, A2;
+};
+// out_fill (if non-NULL) <- M on the grid (0 at excluded nodes); if f is
+// non-NULL, part/out receive sum |f - M|, max |f - M|, sum M, excluded
+// nodes, sum f over them (unscaled sums)
+void launch_equilibrium(const Geo &g, double L, const EqDev &q, const double *f, double *out_fill, double *part,
+                        int nblk, double *out, hipStream_t s);
+constexpr int EQ_FIELDS = 5;
+
+// host: ln K_nu (FD p = ln z, BE p = -ln z) and the limit-state solve
+double complete_fd_be_log(double nu, int fermi, double p);
+int solve_equilibrium(int d, double alpha, double rho, const double *u, double e, bnq_equilibrium *out, char *err,
+                      size_t errlen);
 
 }  // namespace bnq

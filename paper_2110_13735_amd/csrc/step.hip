@@ -186,4 +186,82 @@ void launch_moments(const Geo &g, const double *f, double L, double alpha, doubl
     hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(64), 0, s, nblk, part, out);
 }
 
+// ---------------------------------------------------------------------------
+// Limit state on the grid: value at node i, or excluded (not finite there).
+__device__ static double eq_value(const Geo &g, const EqDev &q, double hstep, int64_t i, bool &excl) {
+    const double x2 = (double)((int)(i % g.N) - g.h) * hstep;
+    const double x1 = (double)((int)((i / g.N) % g.N) - g.h) * hstep;
+    const double x0 = g.d == 3 ? (double)((int)(i / ((int64_t)g.N * g.N)) - g.h) * hstep : 0.0;
+    // u holds the velocity components in the order of the used axes
+    const double w0 = g.d == 3 ? x0 - q.u[0] : 0.0;
+    const double w1 = x1 - q.u[g.d == 3 ? 1 : 0];
+    const double w2 = x2 - q.u[g.d == 3 ? 2 : 1];
+    const double r2 = w0 * w0 + w1 * w1 + w2 * w2;
+    excl = false;
+    switch (q.kind) {
+        case BNQ_EQ_MAXWELL: return q.c0 * exp(-r2 / (2.0 * q.T));
+        case BNQ_EQ_SATURATED: return r2 <= q.A2 ? q.c0 : 0.0;
+        default: {
+            const double a = r2 / (2.0 * q.T) - q.log_z;
+            const double den = q.bose ? expm1(a) : exp(a) + 1.0;
+            if (!(den > 0.0)) {
+                excl = true;
+                return 0.0;
+            }
+            return q.c0 / den;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void equilibrium_kernel(Geo g, double hstep, EqDev q, const double *f,
+                                                          double *out_fill, double *part) {
+    __shared__ double red[256][EQ_FIELDS];
+    double acc[EQ_FIELDS] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.nm;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        bool excl;
+        const double m = eq_value(g, q, hstep, i, excl);
+        if (out_fill) out_fill[i] = m;
+        if (!f) continue;
+        if (excl) {
+            acc[3] += 1.0;
+            acc[4] += f[i];
+        } else {
+            const double dlt = fabs(f[i] - m);
+            acc[0] += dlt;
+            acc[1] = fmax(acc[1], dlt);
+            acc[2] += m;
+        }
+    }
+    if (!f) return;
+    for (int k = 0; k < EQ_FIELDS; ++k) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < EQ_FIELDS; ++k) {
+                const double a = red[threadIdx.x][k], b = red[threadIdx.x + w][k];
+                red[threadIdx.x][k] = k == 1 ? fmax(a, b) : a + b;
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < EQ_FIELDS) part[(int64_t)blockIdx.x * EQ_FIELDS + threadIdx.x] = red[0][threadIdx.x];
+}
+
+__global__ void equilibrium_final_kernel(int nblk, const double *part, double *out) {
+    const int k = threadIdx.x;
+    if (k >= EQ_FIELDS) return;
+    double a = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        const double v = part[(int64_t)b * EQ_FIELDS + k];
+        a = k == 1 ? fmax(a, v) : a + v;
+    }
+    out[k] = a;
+}
+
+void launch_equilibrium(const Geo &g, double L, const EqDev &q, const double *f, double *out_fill, double *part,
+                        int nblk, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(equilibrium_kernel, dim3(nblk), dim3(256), 0, s, g, 2.0 * L / g.N, q, f, out_fill, part);
+    if (f) hipLaunchKernelGGL(equilibrium_final_kernel, dim3(1), dim3(64), 0, s, nblk, part, out);
+}
+
 }  // namespace bnq
