@@ -223,6 +223,44 @@ bnq_status bnq_equilibrium_fill(bnq_plan_t plan, const bnq_equilibrium *eq_host,
  * [2] = Delta v sum M, [3] = number of excluded nodes (where M is infinite),
  * [4] = Delta v sum f over them (to compare with a condensate's m0).
  * Synchronises `stream`.  Errors as bnq_equilibrium_fill. */
+/* ---- velocity-rescaled scheme (sections 'A rescaling velocity model of the
+ * BNE' and 'Numerical scheme for the velocity rescaled BNE', lambda = 1,
+ * mu = 1) ------------------------------------------------------------------
+ * The distribution is held as G on the plan's grid read as xi_j = 2 pi j / N
+ * (j in I_N): f(v) = s^d G(xi) with xi = s (v - u) and s = pi omega / L, so
+ * f lives on u + [-L/omega, L/omega)^d, a box that follows the mean velocity
+ * and the temperature.  The state carries the moments the scheme advances. */
+typedef struct {
+    double rho, u[3], e;  /* mass, mean velocity (order of the moments' u), internal energy */
+    double omega;         /* velocity scale */
+    double T, log_z;      /* temperature and ln fugacity of the last limit-state solve */
+    int32_t kind;         /* its BNQ_EQ_* kind */
+    int32_t reserved;
+} bnq_rescaled_state;
+
+/* State for G (device, N^d FP64) at velocity scale omega > 0 around u_ref
+ * (host, d components): rho, u, e of f = s^d G on u_ref + [-L/omega,
+ * L/omega)^d, and the limit state of those moments.  Synchronises `stream`.
+ * Errors: EINVAL, EHIP. */
+bnq_status bnq_rescaled_init(bnq_plan_t plan, const double *G, double omega, const double *u_ref_host,
+                             bnq_rescaled_state *st_host, bnq_stream_t stream);
+
+/* One forward Euler step of the rescaled scheme (its steps 2-5), G in place:
+ *  K = c s^-gamma Q^R_{alpha s^d}(G) (the plan's operator with the quantum
+ *      parameter alpha s^d: the same tables);
+ *  rho, rho u, rho e advanced by dt Delta xi times the sums of K against 1,
+ *      L xi / (pi omega) + u and |L xi / (pi omega)|^2 / 2;
+ *  T from the limit state of the new moments (bnq_equilibrium_solve's
+ *      rules), omega' = sqrt(T) (alpha != 0) or sqrt(T + |u'|^2 / d);
+ *  G' = G + dt (K - div_xi((a xi - b) G)), a = (omega' - omega) / (dt
+ *      omega), b = s (u' - u) / dt, the divergence by spectral
+ *      differentiation (Re of the inverse DFT of i k times the DFT, k in I_N).
+ * Synchronises `stream` (the temperature solve is host code).  Errors: EINVAL
+ * (dt or the state not positive, or new moments with no finite temperature:
+ * a degenerate Fermi-Dirac state; G is then unchanged), EHIP. */
+bnq_status bnq_step_rescaled(bnq_plan_t plan, double *G, bnq_rescaled_state *st_host, double dt,
+                             bnq_stream_t stream);
+
 #define BNQ_EQDIST_LEN 5
 bnq_status bnq_equilibrium_distance(bnq_plan_t plan, const double *f, const bnq_equilibrium *eq_host,
                                     double *out_host, bnq_stream_t stream);

@@ -76,6 +76,16 @@ class Equilibrium(ctypes.Structure):
         return {k: (list(getattr(self, k)) if k == "u" else getattr(self, k)) for k, _ in self._fields_}
 
 
+class RescaledState(ctypes.Structure):
+    """bnq_rescaled_state: moments and velocity scale of the rescaled scheme."""
+    _fields_ = [("rho", ctypes.c_double), ("u", ctypes.c_double * 3), ("e", ctypes.c_double),
+                ("omega", ctypes.c_double), ("T", ctypes.c_double), ("log_z", ctypes.c_double),
+                ("kind", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: (list(getattr(self, k)) if k == "u" else getattr(self, k)) for k, _ in self._fields_}
+
+
 def equilibrium(d: int, eps: int, hbar: float, rho: float, u, e: float) -> Equilibrium:
     """Limit state for mass rho, mean velocity u (d components) and internal
     energy e (bnq_equilibrium_solve)."""
@@ -130,11 +140,14 @@ def lib():
         L.bnq_fd_be_log.argtypes = [f64, i32, f64, ctypes.POINTER(f64)]
         L.bnq_equilibrium_fill.argtypes = [vp, EQ, vp, vp]
         L.bnq_equilibrium_distance.argtypes = [vp, vp, EQ, vp, vp]
+        RS = ctypes.POINTER(RescaledState)
+        L.bnq_rescaled_init.argtypes = [vp, vp, f64, vp, RS, vp]
+        L.bnq_step_rescaled.argtypes = [vp, vp, RS, f64, vp]
         for fn in ("bnq_plan", "bnq_plan_destroy", "bnq_plan_footprint", "bnq_collide", "bnq_step",
                    "bnq_moments", "bnq_table_lookup", "bnq_plan_counts", "bnq_plan_set_timing",
                    "bnq_plan_timing", "bnq_plan_autotune", "bnq_batch_create", "bnq_batch_destroy", "bnq_batch_collide",
                    "bnq_batch_step", "bnq_equilibrium_solve", "bnq_fd_be_log", "bnq_equilibrium_fill",
-                   "bnq_equilibrium_distance"):
+                   "bnq_equilibrium_distance", "bnq_rescaled_init", "bnq_step_rescaled"):
             getattr(L, fn).restype = ctypes.c_int
         L.bnq_status_string.argtypes = [ctypes.c_int]
         L.bnq_status_string.restype = ctypes.c_char_p
@@ -223,6 +236,19 @@ class Plan:
         _check(lib().bnq_equilibrium_distance(self._h, _ptr(f), ctypes.byref(eq), out.ctypes.data,
                                               _stream(stream)))
         return dict(zip(EQDIST_NAMES, out.tolist()))
+
+    def rescaled_init(self, G, omega: float, u_ref, stream=None) -> RescaledState:
+        uu = np.zeros(3)
+        uv = np.asarray(u_ref, dtype=np.float64).ravel()[:3]
+        uu[:uv.size] = uv
+        st = RescaledState()
+        _check(lib().bnq_rescaled_init(self._h, _ptr(G), float(omega), uu.ctypes.data, ctypes.byref(st),
+                                       _stream(stream)))
+        return st
+
+    def step_rescaled(self, G, st: RescaledState, dt: float, stream=None) -> RescaledState:
+        _check(lib().bnq_step_rescaled(self._h, _ptr(G), ctypes.byref(st), float(dt), _stream(stream)))
+        return st
 
     def lookup(self, table: int, a, b) -> np.ndarray:
         a = np.ascontiguousarray(a, dtype=np.int32).reshape(-1, 3)

@@ -438,6 +438,7 @@ struct bnq_plan_s {
     double *kbuf[4] = {nullptr, nullptr, nullptr, nullptr}, *ybuf = nullptr;
     double *mom_part = nullptr, *mom_out = nullptr;
     double *ginv = nullptr;  // inverse Gram matrix for BNQ_CORR_MOMENTS
+    double *dmat = nullptr;  // N x N spectral differentiation matrix (rescaled scheme)
     int nslots = 0;
     T1Item *items = nullptr;
     T1B *bdesc = nullptr;
@@ -791,6 +792,7 @@ void destroy_plan(bnq_plan_s *P) {
     hipFree(P->mom_part);
     hipFree(P->mom_out);
     hipFree(P->ginv);
+    hipFree(P->dmat);
     hipFree(P->t1cut);
     hipFree(P->items);
     hipFree(P->bdesc);
@@ -1076,8 +1078,19 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         const long double a = 2.0L * (long double)M_PI * t / p->N;
         tw[t] = make_double2((double)std::cos(a), (double)-std::sin(a));
     }
+    // D[j][m] = Re of (inverse DFT . i k . DFT) along one axis, k in I_N:
+    // -(1/N) sum_k k sin(2 pi k (j - m) / N)
+    std::vector<double> dm((size_t)p->N * p->N);
+    for (int j = 0; j < p->N; ++j)
+        for (int m = 0; m < p->N; ++m) {
+            long double acc = 0;
+            for (int k = -p->N / 2; k < p->N / 2; ++k)
+                acc -= k * std::sin(2.0L * (long double)M_PI * k * (j - m) / p->N);
+            dm[(size_t)j * p->N + m] = (double)(acc / p->N);
+        }
     const size_t nm = g.nm;
     if ((st = upload(&P->rots_d, P->grp, "rotations")) || (st = upload(&P->tw, tw, "twiddles")) ||
+        (st = upload(&P->dmat, dm, "differentiation matrix")) ||
         (st = dalloc(&P->Ghat, nm, "spectrum")) || (st = dalloc(&P->tmp, nm, "dft scratch")) ||
         (st = dalloc(&P->tmp2, nm, "dft scratch")) || (st = dalloc(&P->Gr, P->grp.size() * (size_t)g.next, "rotated spectra")) ||
         (st = dalloc(&P->W, (size_t)g.neg, "pair sum W")) || (st = dalloc(&P->Qc, nm, "classical modes")) ||
@@ -1320,6 +1333,123 @@ bnq_status bnq_equilibrium_distance(bnq_plan_t P, const double *f, const bnq_equ
     out_host[2] = dv * r[2];
     out_host[3] = r[3];
     out_host[4] = dv * r[4];
+    return BNQ_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Sums of x over the xi grid (xi_j = 2 pi j / N): r[0] = sum x, r[1..3] =
+// sum xi x per storage axis, r[4] = sum |xi|^2 x (the moment kernel on a box
+// of half-width pi).
+bnq_status xi_sums(bnq_plan_s *P, const double *x, hipStream_t s, double r[5]) {
+    launch_moments(P->g, x, M_PI, 0.0, P->mom_part, MOM_BLOCKS, P->mom_out, s);
+    LAUNCHCHK();
+    double buf[MOM_FIELDS];
+    HIPCHK(hipMemcpyAsync(buf, P->mom_out, sizeof buf, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (buf[9] > 0) return fail(BNQ_ENONFINITE, "%.0f non-finite values", buf[9]);
+    for (int k = 0; k < 5; ++k) r[k] = buf[k];
+    return BNQ_OK;
+}
+
+// limit state of (rho, u, e) into st (T, log_z, kind); EINVAL when it has no
+// finite temperature
+bnq_status rescaled_limit(const bnq_plan_s *P, bnq_rescaled_state *st) {
+    bnq_equilibrium q;
+    char err[256] = "";
+    const int rc = solve_equilibrium(P->g.d, P->alpha, st->rho, st->u, st->e, &q, err, sizeof err);
+    if (rc) return fail((bnq_status)rc, "%s", err);
+    if (q.kind == BNQ_EQ_SATURATED || q.kind == BNQ_EQ_UNKNOWN)
+        return fail(BNQ_EINVAL, "degenerate Fermi-Dirac moments (ratio %.17g): no finite temperature", q.ratio);
+    st->T = q.T;
+    st->log_z = q.log_z;
+    st->kind = q.kind;
+    return BNQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bnq_status bnq_rescaled_init(bnq_plan_t P, const double *G, double omega, const double *u_ref,
+                             bnq_rescaled_state *st, bnq_stream_t stream) {
+    if (!P || !G || !u_ref || !st) return fail(BNQ_EINVAL, "plan, G, u_ref and st must be non-NULL");
+    if (!(omega > 0) || !std::isfinite(omega)) return fail(BNQ_EINVAL, "omega must be positive and finite");
+    hipStream_t s = (hipStream_t)stream;
+    P->last = s;
+    const int d = P->g.d, off = d == 3 ? 0 : 1;  // storage axis of u[0]
+    double r[5];
+    bnq_status rc = xi_sums(P, G, s, r);
+    if (rc) return rc;
+    const double dxi = std::pow(2.0 * M_PI / P->g.N, d), a = P->p.L / (M_PI * omega);
+    bnq_rescaled_state n{};
+    n.omega = omega;
+    n.rho = dxi * r[0];
+    if (!(n.rho > 0)) return fail(BNQ_EINVAL, "G has no positive mass");
+    double cr = 0, c2 = 0;  // (u_ref - u) . sum xi G and |u_ref - u|^2
+    for (int i = 0; i < d; ++i) {
+        n.u[i] = a * dxi * r[1 + off + i] / n.rho + u_ref[i];
+        cr += (u_ref[i] - n.u[i]) * r[1 + off + i];
+        c2 += (u_ref[i] - n.u[i]) * (u_ref[i] - n.u[i]);
+    }
+    n.e = 0.5 * dxi * (a * a * r[4] + 2.0 * a * cr + c2 * r[0]) / n.rho;
+    if ((rc = rescaled_limit(P, &n))) return rc;
+    *st = n;
+    return BNQ_OK;
+}
+
+bnq_status bnq_step_rescaled(bnq_plan_t P, double *G, bnq_rescaled_state *st, double dt, bnq_stream_t stream) {
+    if (!P || !G || !st) return fail(BNQ_EINVAL, "plan, G and st must be non-NULL");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(BNQ_EINVAL, "dt must be positive and finite");
+    if (!(st->omega > 0) || !(st->rho > 0) || !(st->e > 0))
+        return fail(BNQ_EINVAL, "state needs omega, rho and e positive");
+    hipStream_t s = (hipStream_t)stream;
+    P->last = s;
+    const Geo &g = P->g;
+    const int d = g.d, off = d == 3 ? 0 : 1;
+    const double L = P->p.L, om = st->omega, sc = M_PI * om / L;
+    // the plan's operator with the quantum parameter alpha s^d and the
+    // prefactor c s^-gamma, for this evaluation only
+    Inst I = P->ih;
+    I.alpha = P->alpha * std::pow(sc, d);
+    I.pref = P->p.c * std::pow(sc, -(double)(d == 3 ? 1 : 0));
+    HIPCHK(hipMemcpyAsync(P->inst_d, &I, sizeof I, hipMemcpyHostToDevice, s));
+    Exec E = exec_of(P);
+    E.Dh[0] = I;
+    double *K = P->kbuf[0];
+    const std::vector<IOs> io = make_ios(1, nullptr, [&](IOs &x, int z, int) {
+        x.in[z] = G;
+        x.out[z] = K;
+    });
+    bnq_status rc = run_collide(E, io, s);
+    HIPCHK(hipMemcpyAsync(P->inst_d, &P->ih, sizeof(Inst), hipMemcpyHostToDevice, s));
+    if (rc) {
+        hipStreamSynchronize(s);  // I is read by the copy above
+        return rc;
+    }
+    double r[5];
+    if ((rc = xi_sums(P, K, s, r))) return rc;
+    const double dxi = std::pow(2.0 * M_PI / g.N, d), a = L / (M_PI * om);
+    bnq_rescaled_state n = *st;
+    n.rho = st->rho + dt * dxi * r[0];
+    double u2 = 0;
+    for (int i = 0; i < d; ++i) {
+        n.u[i] = (st->rho * st->u[i] + dt * dxi * (a * r[1 + off + i] + st->u[i] * r[0])) / n.rho;
+        u2 += n.u[i] * n.u[i];
+    }
+    n.e = (st->rho * st->e + dt * 0.5 * dxi * a * a * r[4]) / n.rho;
+    if ((rc = rescaled_limit(P, &n))) return rc;
+    n.omega = P->alpha != 0.0 ? std::sqrt(n.T) : std::sqrt(n.T + u2 / d);
+    const double A = (n.omega - om) / (dt * om);
+    double B3[3] = {0, 0, 0};
+    for (int i = 0; i < d; ++i) B3[off + i] = sc * (n.u[i] - st->u[i]) / dt;
+    launch_drift_update(g, G, K, P->dmat, A, B3, dt, P->ybuf, s);
+    LAUNCHCHK();
+    launch_copy(G, P->ybuf, g.nm, s);
+    LAUNCHCHK();
+    *st = n;
     return BNQ_OK;
 }
 

@@ -271,6 +271,12 @@ void launch_equilibrium(const Geo &g, double L, const EqDev &q, const double *f,
                         int nblk, double *out, hipStream_t s);
 constexpr int EQ_FIELDS = 5;
 
+// out = G + dt (K - div_xi((A xi - B) G)) on the xi grid (B per storage axis),
+// the divergence through the N x N real spectral differentiation matrix D
+void launch_drift_update(const Geo &g, const double *G, const double *K, const double *D, double A,
+                         const double *B3, double dt, double *out, hipStream_t s);
+void launch_copy(double *dst, const double *src, int64_t n, hipStream_t s);
+
 // host: ln K_nu (FD p = ln z, BE p = -ln z) and the limit-state solve
 double complete_fd_be_log(double nu, int fermi, double p);
 int solve_equilibrium(int d, double alpha, double rho, const double *u, double e, bnq_equilibrium *out, char *err,

@@ -249,8 +249,9 @@ int solve_equilibrium(int d, double alpha, double rho, const double *u, double e
             out->z = 1.0;
             out->log_z = 0.0;
             // the z = 1 part carries all the internal energy rho e (the
-            // condensate sits at v = u); this T equals that of eq.
-            // Tcritical_bosons_3d at the critical ratio, where m0 = 0
+            // condensate sits at v = u), as in step 3(b) of the rescaled
+            // Euler scheme; eq. Tcritical_bosons_3d gives the same T only at
+            // the critical ratio, where m0 = 0
             out->T = std::pow(std::fabs(alpha) * rho * e / (std::pow(2.0 * M_PI, 1.5) * 1.5 * z52), 0.4);
             out->m0 = rho - std::pow(2.0 * M_PI * out->T, 1.5) * z32 / std::fabs(alpha);
             return BNQ_OK;

@@ -10,6 +10,8 @@
 // over nodes with f > 0 and 1 - alpha f > 0.  Reductions use a fixed
 // assignment of nodes to blocks and a fixed tree, so results are
 // bit-reproducible.
+#include <algorithm>
+
 #include "bnq_internal.h"
 
 namespace bnq {
@@ -184,6 +186,44 @@ void launch_moments(const Geo &g, const double *f, double L, double alpha, doubl
                     hipStream_t s) {
     hipLaunchKernelGGL(moments_part_kernel, dim3(nblk), dim3(256), 0, s, g, f, L, alpha, part);
     hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(64), 0, s, nblk, part, out);
+}
+
+// ---------------------------------------------------------------------------
+// Rescaled scheme: G + dt (K - div((A xi - B) G)); each axis's derivative is
+// the N-term row of D along that axis's line.
+__global__ __launch_bounds__(256) void drift_update_kernel(Geo g, const double *G, const double *K, const double *D,
+                                                           double A, double B0, double B1, double B2, double dt,
+                                                           double *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.nm) return;
+    const int N = g.N;
+    const int j2 = (int)(i % N), j1 = (int)((i / N) % N), j0 = g.d == 3 ? (int)(i / ((int64_t)N * N)) : 0;
+    const double h = 2.0 * M_PI / N;
+    const int64_t base2 = i - j2, base1 = i - (int64_t)j1 * N, base0 = i - (int64_t)j0 * N * N;
+    double div = 0.0;
+    for (int m = 0; m < N; ++m) {
+        const double xi = (m - g.h) * h;
+        div += D[j2 * N + m] * ((A * xi - B2) * G[base2 + m]);
+        div += D[j1 * N + m] * ((A * xi - B1) * G[base1 + (int64_t)m * N]);
+        if (g.d == 3) div += D[j0 * N + m] * ((A * xi - B0) * G[base0 + (int64_t)m * N * N]);
+    }
+    out[i] = G[i] + dt * (K[i] - div);
+}
+
+void launch_drift_update(const Geo &g, const double *G, const double *K, const double *D, double A,
+                         const double *B3, double dt, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(drift_update_kernel, dim3((unsigned)((g.nm + 255) / 256)), dim3(256), 0, s, g, G, K, D, A,
+                       B3[0], B3[1], B3[2], dt, out);
+}
+
+__global__ void copy_kernel(double *dst, const double *src, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+void launch_copy(double *dst, const double *src, int64_t n, hipStream_t s) {
+    const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(copy_kernel, dim3(nb), dim3(256), 0, s, dst, src, n);
 }
 
 // ---------------------------------------------------------------------------

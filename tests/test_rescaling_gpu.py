@@ -1,0 +1,82 @@
+"""Velocity-rescaled scheme on the GPU (bnq_rescaled_init, bnq_step_rescaled)
+against the oracle's step-by-step transcription of the scheme."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import rescaling as rs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+bnq = pytest.importorskip("paper_2110_13735_amd")
+
+DEV = "cuda:0"
+TOL = 1e-12
+
+
+def _datum(d, N, seed):
+    # two Gaussians in xi, decayed well inside [-pi, pi)
+    rng = np.random.default_rng(seed)
+    xi = rs.xi_grid(d, N)
+    G = np.zeros((N,) * d)
+    for _ in range(2):
+        c = rng.uniform(-0.6, 0.6, d)
+        G += rng.uniform(0.1, 0.3) * np.exp(-np.sum((xi - c) ** 2, axis=-1) / (2 * rng.uniform(0.3, 0.6) ** 2))
+    return G
+
+
+@pytest.mark.parametrize("d,N,eps", [(2, 8, 1), (2, 16, -1), (2, 12, 0), (3, 6, -1), (3, 6, 0)])
+def test_rescaled_steps_match_oracle(d, N, eps):
+    L, omega0, hbar = 5.0, 1.3, 1.0
+    u_ref = [0.3, -0.2, 0.1][:d]
+    G = _datum(d, N, 10 * d + N)
+    plan = bnq.Plan(bnq.Params(d=d, N=N, eps=eps, L=L, hbar=hbar))
+    Gt = torch.tensor(G, device=DEV)
+    st = plan.rescaled_init(Gt, omega0, u_ref)
+    m = rs.moments_of(G, L, omega0, u_ref)
+    assert st.rho == pytest.approx(m["rho"], rel=TOL)
+    assert list(st.u)[:d] == pytest.approx(list(m["u"]), rel=TOL, abs=TOL)
+    assert st.e == pytest.approx(m["e"], rel=TOL)
+    ref = {"rho": m["rho"], "u": m["u"], "e": m["e"], "omega": omega0}
+    o = oracle.Oracle(d, N)
+    Gr = G.copy()
+    for k in range(3):
+        plan.step_rescaled(Gt, st, 0.01)
+        Gr, ref = rs.euler_step(o, Gr, ref, 0.01, eps, L, hbar)
+        got = Gt.cpu().numpy()
+        err = np.linalg.norm(got - Gr) / np.linalg.norm(Gr)
+        assert err <= TOL, f"step {k}: G error {err:.2e}"
+        for key in ("rho", "e", "omega", "T"):
+            assert getattr(st, key) == pytest.approx(ref[key], rel=TOL), (k, key)
+        assert list(st.u)[:d] == pytest.approx(list(ref["u"]), rel=1e-11, abs=1e-13)
+        assert st.kind == ref["kind"]
+    plan.close()
+
+
+def test_rescaled_scheme_follows_a_shifted_equilibrium():
+    # a Fermi-Dirac state written in the moving frame stays put: the box is
+    # centred on u and scaled by sqrt(T), so nothing moves but rounding and
+    # the operator's residual (N and L resolve the state: about 4 nodes per
+    # thermal width, 1e-13 of its peak at the box edge)
+    d, N, L, eps, hbar = 2, 64, 3.5, -1, 1.0
+    rho, u, e = 1.0, np.array([1.2, -0.7]), 0.5
+    lim = bnq.equilibrium(d, eps, hbar, rho, u, e)
+    omega = math.sqrt(lim.T)
+    s = math.pi * omega / L
+    xi = rs.xi_grid(d, N)
+    r2 = np.sum((xi / s) ** 2, axis=-1)
+    G = (1.0 / (np.exp(r2 / (2 * lim.T) - lim.log_z) + 1.0)) / s ** d
+    plan = bnq.Plan(bnq.Params(d=d, N=N, eps=eps, L=L, hbar=hbar))
+    Gt = torch.tensor(G, device=DEV)
+    st = plan.rescaled_init(Gt, omega, u)
+    for _ in range(20):
+        plan.step_rescaled(Gt, st, 0.02)
+    got = Gt.cpu().numpy()
+    print(f"max |G - G0| / max G0 = {np.max(np.abs(got - G)) / G.max():.2e}, omega {omega:.6f} -> {st.omega:.6f}")
+    assert np.max(np.abs(got - G)) <= 1e-4 * G.max()
+    assert st.omega == pytest.approx(omega, rel=1e-5)
+    assert list(st.u)[:d] == pytest.approx(list(u), abs=1e-8)
+    plan.close()
