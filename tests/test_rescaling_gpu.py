@@ -80,3 +80,16 @@ def test_rescaled_scheme_follows_a_shifted_equilibrium():
     assert st.omega == pytest.approx(omega, rel=1e-5)
     assert list(st.u)[:d] == pytest.approx(list(u), abs=1e-8)
     plan.close()
+
+
+def test_spectral_accuracy_residual_decays_in_a_fitted_box():
+    # the experiment of section 'Validation of spectral accuracy' (2-D
+    # Fermi-Dirac, hbar = 3, rho = 1, sigma = 1, L = 6): the residual of the
+    # discrete limit state falls spectrally with N (measured 1.8e-4, 5.5e-7,
+    # 1.7e-9)
+    from paper_2110_13735_amd import spectral_accuracy as sa
+
+    res = [sa.residual(2, N, 6.0, -1, 1.0, False, False)["residual"] for N in (16, 32, 64)]
+    assert res[1] < res[0] / 100
+    assert res[2] < res[1] / 100
+    assert math.exp(sa.fugacity(2, -1, 1.0, 1.0)) == pytest.approx(3.1887, abs=1e-4)  # printed in the table caption
