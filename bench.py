@@ -471,7 +471,7 @@ def run_batch(args):
     for i in range(args.instances):
         d, N, eps = cells[i % len(cells)]
         f0, L = inp.mixed_instance(d, N, eps, seed=i)
-        p = bnq.Params(d=d, N=N, eps=eps, L=L)
+        p = bnq.Params(d=d, N=N, eps=eps, L=L, precision=bnq.FP32C if args.precision == "fp32c" else bnq.FP64)
         pl = bnq.Plan(p)
         plans.append(pl)
         terms += 4.0 * bnq.terms_per_eval(p, pl.counts())
@@ -517,7 +517,7 @@ def run_batch(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32c" if args.precision == "fp32c" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.instances} instances over cells (d, N) in {cell_set} x eps in (-1, 0, 1), "
                                f"Gaussian-mixture data (seed = instance), RK4 dt={dt}, one HIP-graph replay per step",
@@ -538,7 +538,11 @@ def run_serve(args):
 
     reqs = serve.poisson_requests(args.instances, rate=args.rate, seed=0,
                                   cells=[((3, 8), 4), ((3, 12), 3), ((3, 16), 2)], t_end=(0.05, 0.5))
-    srv = serve.Server(lambda r: inp.mixed_instance(r.d, r.N, r.eps, r.seed), budget_bytes=int(64e9), dt=args.dt)
+    import paper_2110_13735_amd as bnq
+
+    prec = bnq.FP32C if args.precision == "fp32c" else bnq.FP64
+    srv = serve.Server(lambda r: inp.mixed_instance(r.d, r.N, r.eps, r.seed), budget_bytes=int(64e9), dt=args.dt,
+                       precision=prec)
     try:
         st = srv.run(reqs)
     finally:
@@ -547,7 +551,7 @@ def run_serve(args):
         "metric": "served collision pair-terms/s; p50/p99 solve latency",
         "value": st["terms_per_s"], "unit": "pair-terms/s", "n_gpus": 1, "steps": st["ticks"], "warmup": 0,
         "ms_per_step": 1e3 * st["busy_s"] / max(1, st["ticks"]), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32c" if prec == bnq.FP32C else "f64", "data": "synthetic",
         "config": {"workload": f"{args.instances} Poisson arrivals at {args.rate} req/s, 3-D N in (8, 12, 16) "
                                f"weights 4:3:2, eps +-1, t_end U[0.05, 0.5], RK4 dt={args.dt}",
                    "rate_per_s": args.rate},

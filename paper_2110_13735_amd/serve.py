@@ -75,7 +75,7 @@ class Server:
     """Continuous-batching server.  make_input(req) -> (f0 ndarray, L)."""
 
     def __init__(self, make_input, budget_bytes: int, dt: float = 0.01, keep_results: bool = False,
-                 max_active: int = 256):
+                 max_active: int = 256, precision: int = 0):
         import torch
         self.torch = torch
         self.make_input = make_input
@@ -83,6 +83,7 @@ class Server:
         self.dt = float(dt)
         self.keep = keep_results
         self.max_active = max_active
+        self.precision = int(precision)  # FP64 (0) or FP32C (1) for every request
         self.dev = torch.device("cuda:0")
         self.stream = torch.cuda.Stream()
         self.anchors = {}  # (d, N) -> plan that keeps the shared tables resident
@@ -90,14 +91,14 @@ class Server:
 
     def _admit(self, req: Request, used: int):
         f0, L = self.make_input(req)
-        p = Params(d=req.d, N=req.N, eps=req.eps, L=L)
+        p = Params(d=req.d, N=req.N, eps=req.eps, L=L, precision=self.precision)
         plan_b, table_b = footprint(p)
         state_b = f0.nbytes
         need = plan_b + state_b + (table_b if (req.d, req.N) not in self.anchors else 0)
         if used + need > self.budget:
             return None
         if (req.d, req.N) not in self.anchors:
-            self.anchors[(req.d, req.N)] = Plan(Params(d=req.d, N=req.N, eps=0, L=L))
+            self.anchors[(req.d, req.N)] = Plan(Params(d=req.d, N=req.N, eps=0, L=L, precision=self.precision))
             self.table_bytes += table_b
             need -= table_b
         plan = Plan(p)
