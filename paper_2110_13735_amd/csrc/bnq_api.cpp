@@ -634,12 +634,19 @@ bnq_status build_t1_work(bnq_plan_s *P) {
                 }
                 if (empty) continue;
                 const int wnx = B.wnhi[2] - B.wnlo[2] + 1;
-                B.nxb = (wnx + T1_RB - 1) / T1_RB;
-                B.pad = 0;
+                // FP64: the block width among 8, 7, 6 whose blocks overhang the
+                // output row least (the kernel's time per block scales with its
+                // width); FP32c items keep 8
+                int rb = T1_RB;
+                if (P->p.precision != BNQ_FP32C)
+                    for (int w = T1_RB - 1; w >= 6; --w)
+                        if ((wnx + w - 1) / w * w < (wnx + rb - 1) / rb * rb) rb = w;
+                B.nxb = (wnx + rb - 1) / rb;
+                B.pad = rb;
                 const int ntasks = B.nxb * (B.wnhi[1] - B.wnlo[1] + 1) * (B.wnhi[0] - B.wnlo[0] + 1);
                 const int wpx = B.wphi[2] - B.wplo[2] + 1;
                 const double rows = (double)(B.wphi[1] - B.wplo[1] + 1) * (B.wphi[0] - B.wplo[0] + 1);
-                const double cost = rows * ((wpx + 7) / 8 + 2) + 8;
+                const double cost = rows * ((wpx + 7) / 8 + 2) * rb / T1_RB + 8;
                 const int bi = (int)bd.size();
                 bd.push_back(B);
                 for (int t0 = 0; t0 < ntasks; t0 += 64) {

@@ -74,7 +74,7 @@ struct T1B {
     int wnlo[3], wnhi[3];  // output window in the rotated frame
     int wplo[3], wphi[3];  // inner window in the rotated frame
     int nxb;         // x-blocks of the output window
-    int pad;
+    int pad;         // outputs per x-block (6, 7 or 8; always 8 for FP32c)
 };
 
 struct T1Item {

@@ -10,7 +10,9 @@ namespace {
 // list of items (b, range of <= 64 tasks) and accumulates into its own
 // partial array (no atomics; the slots are summed in a fixed order later).
 //
-// A task is 8 consecutive outputs along x at one (y, z); tasks are numbered
+// A task is RB consecutive outputs along x at one (y, z), RB = 6, 7 or 8
+// chosen per b so that the blocks cover the output row with the least
+// overhang (the width is T1B::pad; FP32 items always have 8); tasks are numbered
 // y fastest so that the lanes of a wave read consecutive addresses of the
 // y-fastest kernel-mode rows.  The inner rows (pz, py) are taken in pairs of
 // one plane, A = (pz, py) and B = (pz, py + 1): B needs a_y = ny - py - 1,
@@ -53,54 +55,85 @@ __device__ __forceinline__ typename V2<T>::type t1_kload(const T1Ctx<T> &c, int 
 template <int NF>
 constexpr int t1_ncol() { return (8 * NF + 7) / 16 + 1 < 4 ? (8 * NF + 7) / 16 + 1 : 4; }
 
-// The 16 FMAs of one row at inner position u: zr[i] += k[i] P(u).x,
+// The FMAs of one row at inner position u: zr[i] += k[i] P(u).x,
 // zi[i] += k[i] P(u).y, P(u) taken from lane u % 16 of each 16-lane row of
 // (px, py) by a DPP row broadcast.  The leading s_nop 1 gives the two wait
 // states a DPP source needs after a VALU write of it; a VALU write of EXEC
 // would need five, and no instruction of this kernel makes one (the compiled
 // kernel is checked for v_cmpx by the test suite).  The statement is volatile
 // so that the loads placed between steps keep their places.
-#define T1_BC16(OP)                                                                 \
-    "s_nop 1\n\t"                                                                   \
-    OP " %0, %16, %18 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
-    OP " %8, %17, %18 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
-    OP " %1, %16, %19 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
-    OP " %9, %17, %19 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
-    OP " %2, %16, %20 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
-    OP " %10, %17, %20 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"             \
-    OP " %3, %16, %21 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
-    OP " %11, %17, %21 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"             \
-    OP " %4, %16, %22 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
-    OP " %12, %17, %22 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"             \
-    OP " %5, %16, %23 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
-    OP " %13, %17, %23 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"             \
-    OP " %6, %16, %24 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
-    OP " %14, %17, %24 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"             \
-    OP " %7, %16, %25 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"              \
+#define T1_BC16(OP)                                                      \
+    "s_nop 1\n\t"                                                        \
+    OP " %0, %16, %18 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %8, %17, %18 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %1, %16, %19 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %9, %17, %19 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %2, %16, %20 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %10, %17, %20 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %3, %16, %21 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %11, %17, %21 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %4, %16, %22 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %12, %17, %22 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %5, %16, %23 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %13, %17, %23 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %6, %16, %24 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %14, %17, %24 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %7, %16, %25 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
     OP " %15, %17, %25 row_newbcast:%26 row_mask:0xf bank_mask:0xf"
 
-template <typename T, int U>
-__device__ __forceinline__ void t1_fma16(T (&zr)[T1_RB], T (&zi)[T1_RB], T px, T py, T k0, T k1, T k2, T k3, T k4,
-                                         T k5, T k6, T k7) {
-    if constexpr (sizeof(T) == 8)
-        asm volatile(T1_BC16("v_fmac_f64_dpp")
-                     : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zr[6]),
-                       "+v"(zr[7]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]),
-                       "+v"(zi[6]), "+v"(zi[7])
-                     : "v"(px), "v"(py), "v"(k0), "v"(k1), "v"(k2), "v"(k3), "v"(k4), "v"(k5), "v"(k6), "v"(k7),
-                       "i"(U % 16));
-    else
-        asm volatile(T1_BC16("v_fmac_f32_dpp")
-                     : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zr[6]),
-                       "+v"(zr[7]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]),
-                       "+v"(zi[6]), "+v"(zi[7])
-                     : "v"(px), "v"(py), "v"(k0), "v"(k1), "v"(k2), "v"(k3), "v"(k4), "v"(k5), "v"(k6), "v"(k7),
-                       "i"(U % 16));
+#define T1_BC14(OP)                                                      \
+    "s_nop 1\n\t"                                                        \
+    OP " %0, %14, %16 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %7, %15, %16 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %1, %14, %17 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %8, %15, %17 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %2, %14, %18 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %9, %15, %18 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %3, %14, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %10, %15, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %4, %14, %20 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %11, %15, %20 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %5, %14, %21 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %12, %15, %21 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %6, %14, %22 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %13, %15, %22 row_newbcast:%23 row_mask:0xf bank_mask:0xf"
+
+#define T1_BC12(OP)                                                      \
+    "s_nop 1\n\t"                                                        \
+    OP " %0, %12, %14 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %6, %13, %14 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %1, %12, %15 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %7, %13, %15 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %2, %12, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %8, %13, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %3, %12, %17 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %9, %13, %17 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %4, %12, %18 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %10, %13, %18 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %5, %12, %19 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %11, %13, %19 row_newbcast:%20 row_mask:0xf bank_mask:0xf"
+
+// The 2 RB FMAs of one row at inner position u for the first RB outputs
+// (the block width of the item, 6, 7 or 8 outputs).
+template <typename T, int U, int RB>
+__device__ __forceinline__ void t1_fma(T (&zr)[T1_RB], T (&zi)[T1_RB], T px, T py, T k0, T k1, T k2, T k3, T k4,
+                                       T k5, T k6, T k7) {
+    if constexpr (sizeof(T) == 8) {
+        if constexpr (RB == 8)
+            asm volatile(T1_BC16("v_fmac_f64_dpp") : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zr[6]), "+v"(zr[7]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]), "+v"(zi[6]), "+v"(zi[7]) : "v"(px), "v"(py), "v"(k0), "v"(k1), "v"(k2), "v"(k3), "v"(k4), "v"(k5), "v"(k6), "v"(k7), "i"(U % 16));
+        else if constexpr (RB == 7)
+            asm volatile(T1_BC14("v_fmac_f64_dpp") : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zr[6]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]), "+v"(zi[6]) : "v"(px), "v"(py), "v"(k0), "v"(k1), "v"(k2), "v"(k3), "v"(k4), "v"(k5), "v"(k6), "i"(U % 16));
+        else
+            asm volatile(T1_BC12("v_fmac_f64_dpp") : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]) : "v"(px), "v"(py), "v"(k0), "v"(k1), "v"(k2), "v"(k3), "v"(k4), "v"(k5), "i"(U % 16));
+    } else {
+        static_assert(RB == 8, "FP32 items have 8-wide blocks");
+        asm volatile(T1_BC16("v_fmac_f32_dpp") : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zr[6]), "+v"(zr[7]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]), "+v"(zi[6]), "+v"(zi[7]) : "v"(px), "v"(py), "v"(k0), "v"(k1), "v"(k2), "v"(k3), "v"(k4), "v"(k5), "v"(k6), "v"(k7), "i"(U % 16));
+    }
 }
 
 // Inner position u = 8 K + jj of both rows of a pair: row A (the .y halves of
 // the window, pair products PA) then row B (.x halves, PB).
-template <typename T, int U, int JJ>
+template <typename T, int U, int JJ, int RB>
 __device__ __forceinline__ void t1_pos(const typename V2<T>::type (&lo)[8], const typename V2<T>::type (&hi)[8],
                                        const typename V2<T>::type (&PA)[4], const typename V2<T>::type (&PB)[4],
                                        T (&zr)[T1_RB], T (&zi)[T1_RB]) {
@@ -108,44 +141,44 @@ __device__ __forceinline__ void t1_pos(const typename V2<T>::type (&lo)[8], cons
     // clamp only keeps the never-taken tail of an 8-block row in bounds
     constexpr int C = U / 16 < 4 ? U / 16 : 3;
 #define T1_K(i, c) ((i) - JJ < 0 ? lo[(i) - JJ + 8].c : hi[(i) - JJ].c)
-    t1_fma16<T, U>(zr, zi, PA[C].x, PA[C].y, T1_K(0, y), T1_K(1, y), T1_K(2, y), T1_K(3, y), T1_K(4, y),
+    t1_fma<T, U, RB>(zr, zi, PA[C].x, PA[C].y, T1_K(0, y), T1_K(1, y), T1_K(2, y), T1_K(3, y), T1_K(4, y),
                    T1_K(5, y), T1_K(6, y), T1_K(7, y));
-    t1_fma16<T, U>(zr, zi, PB[C].x, PB[C].y, T1_K(0, x), T1_K(1, x), T1_K(2, x), T1_K(3, x), T1_K(4, x),
+    t1_fma<T, U, RB>(zr, zi, PB[C].x, PB[C].y, T1_K(0, x), T1_K(1, x), T1_K(2, x), T1_K(3, x), T1_K(4, x),
                    T1_K(5, x), T1_K(6, x), T1_K(7, x));
 #undef T1_K
 }
 
 // Block K of a pair: lo_K = K(base - 8K - 8 + s), hi_K = lo_{K-1}; issues the
 // loads of lo_{K+1} into nx first.
-template <typename T, int K>
+template <typename T, int K, int RB>
 __device__ __forceinline__ void t1_full(const T1Ctx<T> &c, const typename V2<T>::type (&lo)[8],
                                         const typename V2<T>::type (&hi)[8], typename V2<T>::type (&nx)[8],
                                         T (&zr)[T1_RB], T (&zi)[T1_RB]) {
     const int vq = c.voff - (8 * (K + 1) + 8) * c.sA;
 #pragma unroll
     for (int s = 0; s < 8; ++s) nx[s] = t1_kload(c, vq, s);
-    t1_pos<T, 8 * K + 0, 0>(lo, hi, *c.PA, *c.PB, zr, zi);
-    t1_pos<T, 8 * K + 1, 1>(lo, hi, *c.PA, *c.PB, zr, zi);
-    t1_pos<T, 8 * K + 2, 2>(lo, hi, *c.PA, *c.PB, zr, zi);
-    t1_pos<T, 8 * K + 3, 3>(lo, hi, *c.PA, *c.PB, zr, zi);
-    t1_pos<T, 8 * K + 4, 4>(lo, hi, *c.PA, *c.PB, zr, zi);
-    t1_pos<T, 8 * K + 5, 5>(lo, hi, *c.PA, *c.PB, zr, zi);
-    t1_pos<T, 8 * K + 6, 6>(lo, hi, *c.PA, *c.PB, zr, zi);
-    t1_pos<T, 8 * K + 7, 7>(lo, hi, *c.PA, *c.PB, zr, zi);
+    t1_pos<T, 8 * K + 0, 0, RB>(lo, hi, *c.PA, *c.PB, zr, zi);
+    t1_pos<T, 8 * K + 1, 1, RB>(lo, hi, *c.PA, *c.PB, zr, zi);
+    t1_pos<T, 8 * K + 2, 2, RB>(lo, hi, *c.PA, *c.PB, zr, zi);
+    t1_pos<T, 8 * K + 3, 3, RB>(lo, hi, *c.PA, *c.PB, zr, zi);
+    t1_pos<T, 8 * K + 4, 4, RB>(lo, hi, *c.PA, *c.PB, zr, zi);
+    t1_pos<T, 8 * K + 5, 5, RB>(lo, hi, *c.PA, *c.PB, zr, zi);
+    t1_pos<T, 8 * K + 6, 6, RB>(lo, hi, *c.PA, *c.PB, zr, zi);
+    t1_pos<T, 8 * K + 7, 7, RB>(lo, hi, *c.PA, *c.PB, zr, zi);
 }
 
 // the last rem (< 8) positions 8 NF + jj of a pair: uniform branches that
 // update the accumulators in place
-template <typename T, int NF>
+template <typename T, int NF, int RB>
 __device__ __forceinline__ void t1_tail(const T1Ctx<T> &c, int rem, const typename V2<T>::type (&lo)[8],
                                         const typename V2<T>::type (&hi)[8], T (&zr)[T1_RB], T (&zi)[T1_RB]) {
-    if (rem > 0) t1_pos<T, 8 * NF + 0, 0>(lo, hi, *c.PA, *c.PB, zr, zi);
-    if (rem > 1) t1_pos<T, 8 * NF + 1, 1>(lo, hi, *c.PA, *c.PB, zr, zi);
-    if (rem > 2) t1_pos<T, 8 * NF + 2, 2>(lo, hi, *c.PA, *c.PB, zr, zi);
-    if (rem > 3) t1_pos<T, 8 * NF + 3, 3>(lo, hi, *c.PA, *c.PB, zr, zi);
-    if (rem > 4) t1_pos<T, 8 * NF + 4, 4>(lo, hi, *c.PA, *c.PB, zr, zi);
-    if (rem > 5) t1_pos<T, 8 * NF + 5, 5>(lo, hi, *c.PA, *c.PB, zr, zi);
-    if (rem > 6) t1_pos<T, 8 * NF + 6, 6>(lo, hi, *c.PA, *c.PB, zr, zi);
+    if (rem > 0) t1_pos<T, 8 * NF + 0, 0, RB>(lo, hi, *c.PA, *c.PB, zr, zi);
+    if (rem > 1) t1_pos<T, 8 * NF + 1, 1, RB>(lo, hi, *c.PA, *c.PB, zr, zi);
+    if (rem > 2) t1_pos<T, 8 * NF + 2, 2, RB>(lo, hi, *c.PA, *c.PB, zr, zi);
+    if (rem > 3) t1_pos<T, 8 * NF + 3, 3, RB>(lo, hi, *c.PA, *c.PB, zr, zi);
+    if (rem > 4) t1_pos<T, 8 * NF + 4, 4, RB>(lo, hi, *c.PA, *c.PB, zr, zi);
+    if (rem > 5) t1_pos<T, 8 * NF + 5, 5, RB>(lo, hi, *c.PA, *c.PB, zr, zi);
+    if (rem > 6) t1_pos<T, 8 * NF + 6, 6, RB>(lo, hi, *c.PA, *c.PB, zr, zi);
 }
 
 // Steps K .. NF of a pair (K < NF: full block K, K = NF: the tail).  Slot
@@ -154,7 +187,7 @@ __device__ __forceinline__ void t1_tail(const T1Ctx<T> &c, int rem, const typena
 // S[K] (hi) while loading lo_{K+1} into S[K + 2]; the last steps load the
 // next pair's first two slot blocks (N0 at step max(NF - 1, 0), N1 at step
 // NF), so that at most four slot blocks are live at once.
-template <typename T, int NF, int K>
+template <typename T, int NF, int K, int RB>
 __device__ __forceinline__ void t1_steps(const T1Ctx<T> &c, int rem, int vn, typename V2<T>::type (&S)[NF + 2][8],
                                          typename V2<T>::type (&N0)[8], typename V2<T>::type (&N1)[8],
                                          T (&zr)[T1_RB], T (&zi)[T1_RB]) {
@@ -167,10 +200,10 @@ __device__ __forceinline__ void t1_steps(const T1Ctx<T> &c, int rem, int vn, typ
         for (int s = 0; s < 8; ++s) N1[s] = t1_kload(c, vn - 8 * c.sA, s);
     }
     if constexpr (K < NF) {
-        t1_full<T, K>(c, S[K + 1], S[K], S[K + 2], zr, zi);
-        t1_steps<T, NF, K + 1>(c, rem, vn, S, N0, N1, zr, zi);
+        t1_full<T, K, RB>(c, S[K + 1], S[K], S[K + 2], zr, zi);
+        t1_steps<T, NF, K + 1, RB>(c, rem, vn, S, N0, N1, zr, zi);
     } else {
-        t1_tail<T, NF>(c, rem, S[K + 1], S[K], zr, zi);
+        t1_tail<T, NF, RB>(c, rem, S[K + 1], S[K], zr, zi);
     }
 }
 
@@ -241,7 +274,7 @@ __device__ __forceinline__ void t1_exchange(typename V2<T>::type (*pl)[64], int 
 // N1 on entry; they are replaced by the next pair's) and its pair-product
 // columns (PA, PB; replaced by the next pair's).  Past the last pair the
 // fetches repeat the last pair's addresses and the pair products are zero.
-template <typename T, int NF>
+template <typename T, int NF, int RB>
 __device__ __forceinline__ void t1_pair(T1Ctx<T> &c, T1Rows &rw, int k, int npairs, int wpx, int lane,
                                         const T1Pairs<T> &pr, typename V2<T>::type (*pl)[64],
                                         typename V2<T>::type (&N0)[8], typename V2<T>::type (&N1)[8],
@@ -266,7 +299,7 @@ __device__ __forceinline__ void t1_pair(T1Ctx<T> &c, T1Rows &rw, int k, int npai
     c.voff = rw.voff;
     c.PA = &PA;
     c.PB = &PB;
-    t1_steps<T, NF, 0>(c, wpx - 8 * NF, vn, S, N0, N1, zr, zi);
+    t1_steps<T, NF, 0, RB>(c, wpx - 8 * NF, vn, S, N0, N1, zr, zi);
     const bool keepa = more && lane < wpx;
     t1_exchange<T, t1_ncol<NF>()>(pl, lane, keepa, keepa && hasb, pna, pnb, PA, PB);
     rw.pz = npz;
@@ -277,7 +310,7 @@ __device__ __forceinline__ void t1_pair(T1Ctx<T> &c, T1Rows &rw, int k, int npai
 // All row pairs of an item.  FP64 accumulates every pair in zr/zi; FP32
 // accumulates one pair (at most 128 terms per output) in FP32 and adds it to
 // the FP64 totals Zr/Zi.
-template <typename T, int NF>
+template <typename T, int NF, int RB>
 __device__ __forceinline__ void t1_rows(T1Ctx<T> &c, T1Rows rw, int npairs, int wpx, int lane, const T1Pairs<T> &pr,
                                         typename V2<T>::type (*pl)[64], double (&Zr)[T1_RB], double (&Zi)[T1_RB]) {
     typename V2<T>::type N0[8], N1[8], PA[4], PB[4];
@@ -291,7 +324,7 @@ __device__ __forceinline__ void t1_rows(T1Ctx<T> &c, T1Rows rw, int npairs, int 
         t1_exchange<T, t1_ncol<NF>()>(pl, lane, keepa, keepa && hasb, pr.at(0, 0), pr.at(0, hasb ? 1 : 0), PA, PB);
     }
     for (int k = 0; k < npairs; ++k) {
-        t1_pair<T, NF>(c, rw, k, npairs, wpx, lane, pr, pl, N0, N1, PA, PB, zr, zi);
+        t1_pair<T, NF, RB>(c, rw, k, npairs, wpx, lane, pr, pl, N0, N1, PA, PB, zr, zi);
         if constexpr (sizeof(T) == 4) {
 #pragma unroll
             for (int i = 0; i < T1_RB; ++i) {
@@ -307,6 +340,24 @@ __device__ __forceinline__ void t1_rows(T1Ctx<T> &c, T1Rows rw, int npairs, int 
             Zr[i] = zr[i];
             Zi[i] = zi[i];
         }
+    }
+}
+
+// rows of an item with NF = wpx / 8 full blocks (a compile-time constant)
+template <typename T, int RB>
+__device__ __forceinline__ void t1_rows_nf(T1Ctx<T> &c, T1Rows rw, int npairs, int wpx, int lane,
+                                           const T1Pairs<T> &pr, typename V2<T>::type (*pl)[64], double (&Zr)[T1_RB],
+                                           double (&Zi)[T1_RB]) {
+    switch (wpx >> 3) {
+        case 0: t1_rows<T, 0, RB>(c, rw, npairs, wpx, lane, pr, pl, Zr, Zi); break;
+        case 1: t1_rows<T, 1, RB>(c, rw, npairs, wpx, lane, pr, pl, Zr, Zi); break;
+        case 2: t1_rows<T, 2, RB>(c, rw, npairs, wpx, lane, pr, pl, Zr, Zi); break;
+        case 3: t1_rows<T, 3, RB>(c, rw, npairs, wpx, lane, pr, pl, Zr, Zi); break;
+        case 4: t1_rows<T, 4, RB>(c, rw, npairs, wpx, lane, pr, pl, Zr, Zi); break;
+        case 5: t1_rows<T, 5, RB>(c, rw, npairs, wpx, lane, pr, pl, Zr, Zi); break;
+        case 6: t1_rows<T, 6, RB>(c, rw, npairs, wpx, lane, pr, pl, Zr, Zi); break;
+        case 7: t1_rows<T, 7, RB>(c, rw, npairs, wpx, lane, pr, pl, Zr, Zi); break;
+        default: t1_rows<T, 8, RB>(c, rw, npairs, wpx, lane, pr, pl, Zr, Zi); break;
     }
 }
 
@@ -368,7 +419,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
         const int rest = t / wny;
         const int xb = rest % B.nxb;
         const int nz = B.wnlo[0] + rest / B.nxb;
-        const int x0 = B.wnlo[2] + xb * T1_RB;
+        // outputs per task along x: the item's block width (6, 7 or 8)
+        const int rb = __builtin_amdgcn_readfirstlane(B.pad);
+        const int x0 = B.wnlo[2] + xb * rb;
         const int base = x0 - B.wplo[2];  // a_x = base + i - u
         const int wpx = B.wphi[2] - B.wplo[2] + 1;
         T1Ctx<T> c;
@@ -402,23 +455,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
         double zr[T1_RB], zi[T1_RB];
 #pragma unroll
         for (int i = 0; i < T1_RB; ++i) zr[i] = zi[i] = 0.0;
-        switch (wpx >> 3) {
-            case 0: t1_rows<T, 0>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
-            case 1: t1_rows<T, 1>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
-            case 2: t1_rows<T, 2>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
-            case 3: t1_rows<T, 3>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
-            case 4: t1_rows<T, 4>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
-            case 5: t1_rows<T, 5>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
-            case 6: t1_rows<T, 6>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
-            case 7: t1_rows<T, 7>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
-            default: t1_rows<T, 8>(c, rw, npairs, wpx, lane, pr, pl, zr, zi); break;
+        if constexpr (sizeof(T) == 8) {
+            if (rb == 6)
+                t1_rows_nf<T, 6>(c, rw, npairs, wpx, lane, pr, pl, zr, zi);
+            else if (rb == 7)
+                t1_rows_nf<T, 7>(c, rw, npairs, wpx, lane, pr, pl, zr, zi);
+            else
+                t1_rows_nf<T, 8>(c, rw, npairs, wpx, lane, pr, pl, zr, zi);
+        } else {
+            t1_rows_nf<T, 8>(c, rw, npairs, wpx, lane, pr, pl, zr, zi);
         }
         if (active) {
             const Rot R = rots[B.rot];
 #pragma unroll
             for (int i = 0; i < T1_RB; ++i) {
                 const int nx = x0 + i;
-                if (nx <= B.wnhi[2]) {
+                if (i < rb && nx <= B.wnhi[2]) {
                     const T2 gq = ldT2(G, idx_X(g, nz - B.bc[0], ny - B.bc[1], nx - B.bc[2]));
                     const double2 cc = cmul(make_double2(gq.x, gq.y), make_double2(zr[i], zi[i]));
                     const int v[3] = {nz, ny, nx};
