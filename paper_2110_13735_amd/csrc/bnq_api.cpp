@@ -635,8 +635,9 @@ bnq_status build_t1_work(bnq_plan_s *P) {
                 if (empty) continue;
                 const int wnx = B.wnhi[2] - B.wnlo[2] + 1;
                 // FP64: the block width among 8, 7, 6 whose blocks overhang the
-                // output row least (the kernel's time per block scales with its
-                // width); FP32c items keep 8
+                // output row least (the kernel's time per block grows with its
+                // width).  FP32c keeps 8: measured, narrower blocks made its
+                // kernel slower
                 int rb = T1_RB;
                 if (P->p.precision != BNQ_FP32C)
                     for (int w = T1_RB - 1; w >= 6; --w)

@@ -12,7 +12,7 @@ namespace {
 //
 // A task is RB consecutive outputs along x at one (y, z), RB = 6, 7 or 8
 // chosen per b so that the blocks cover the output row with the least
-// overhang (the width is T1B::pad; FP32 items always have 8); tasks are numbered
+// overhang (the width is T1B::pad; FP32c items always have 8); tasks are numbered
 // y fastest so that the lanes of a wave read consecutive addresses of the
 // y-fastest kernel-mode rows.  The inner rows (pz, py) are taken in pairs of
 // one plane, A = (pz, py) and B = (pz, py + 1): B needs a_y = ny - py - 1,
