@@ -57,13 +57,14 @@ constexpr int t1_ncol() { return (8 * NF + 7) / 16 + 1 < 4 ? (8 * NF + 7) / 16 +
 
 // The FMAs of one row at inner position u: zr[i] += k[i] P(u).x,
 // zi[i] += k[i] P(u).y, P(u) taken from lane u % 16 of each 16-lane row of
-// (px, py) by a DPP row broadcast.  The leading s_nop 1 gives the two wait
-// states a DPP source needs after a VALU write of it; a VALU write of EXEC
-// would need five, and no instruction of this kernel makes one (the compiled
-// kernel is checked for v_cmpx by the test suite).  The statement is volatile
-// so that the loads placed between steps keep their places.
+// (px, py) by a DPP row broadcast.  A DPP source needs two wait states after
+// a VALU write of it (five after a VALU write of EXEC).  The sources here are
+// the pair-product columns, which only LDS loads write, so no wait is
+// written; the test suite checks the compiled kernel for both conditions (no
+// VALU write of a DPP source within two wait states of its read, no v_cmpx).
+// The statement is volatile so that the loads placed between steps keep
+// their places.
 #define T1_BC16(OP)                                                      \
-    "s_nop 1\n\t"                                                        \
     OP " %0, %16, %18 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
     OP " %8, %17, %18 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
     OP " %1, %16, %19 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
@@ -82,7 +83,6 @@ constexpr int t1_ncol() { return (8 * NF + 7) / 16 + 1 < 4 ? (8 * NF + 7) / 16 +
     OP " %15, %17, %25 row_newbcast:%26 row_mask:0xf bank_mask:0xf"
 
 #define T1_BC14(OP)                                                      \
-    "s_nop 1\n\t"                                                        \
     OP " %0, %14, %16 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
     OP " %7, %15, %16 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
     OP " %1, %14, %17 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
@@ -99,7 +99,6 @@ constexpr int t1_ncol() { return (8 * NF + 7) / 16 + 1 < 4 ? (8 * NF + 7) / 16 +
     OP " %13, %15, %22 row_newbcast:%23 row_mask:0xf bank_mask:0xf"
 
 #define T1_BC12(OP)                                                      \
-    "s_nop 1\n\t"                                                        \
     OP " %0, %12, %14 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
     OP " %6, %13, %14 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
     OP " %1, %12, %15 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
