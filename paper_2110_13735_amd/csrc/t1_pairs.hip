@@ -55,7 +55,7 @@ __device__ __forceinline__ typename V2<T>::type t1_kload(const T1Ctx<T> &c, int 
 template <int NF>
 constexpr int t1_ncol() { return (8 * NF + 7) / 16 + 1 < 4 ? (8 * NF + 7) / 16 + 1 : 4; }
 
-// The FMAs of one row at inner position u: zr[i] += k[i] P(u).x,
+// The FMAs at inner position u: zr[i] += k[i] P(u).x,
 // zi[i] += k[i] P(u).y, P(u) taken from lane u % 16 of each 16-lane row of
 // (px, py) by a DPP row broadcast.  A DPP source needs two wait states after
 // a VALU write of it (five after a VALU write of EXEC).  The sources here are
@@ -64,69 +64,112 @@ constexpr int t1_ncol() { return (8 * NF + 7) / 16 + 1 < 4 ? (8 * NF + 7) / 16 +
 // VALU write of a DPP source within two wait states of its read, no v_cmpx).
 // The statement is volatile so that the loads placed between steps keep
 // their places.
-#define T1_BC16(OP)                                                      \
-    OP " %0, %16, %18 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %8, %17, %18 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %1, %16, %19 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %9, %17, %19 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %2, %16, %20 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %10, %17, %20 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"  \
-    OP " %3, %16, %21 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %11, %17, %21 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"  \
-    OP " %4, %16, %22 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %12, %17, %22 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"  \
-    OP " %5, %16, %23 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %13, %17, %23 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"  \
-    OP " %6, %16, %24 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %14, %17, %24 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"  \
-    OP " %7, %16, %25 row_newbcast:%26 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %15, %17, %25 row_newbcast:%26 row_mask:0xf bank_mask:0xf"
+#define T1_BC32(OP)                                                      \
+    OP " %0, %16, %20 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %8, %17, %20 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %1, %16, %21 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %9, %17, %21 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %2, %16, %22 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %10, %17, %22 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %3, %16, %23 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %11, %17, %23 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %4, %16, %24 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %12, %17, %24 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %5, %16, %25 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %13, %17, %25 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %6, %16, %26 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %14, %17, %26 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %7, %16, %27 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %15, %17, %27 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %0, %18, %28 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %8, %19, %28 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %1, %18, %29 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %9, %19, %29 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %2, %18, %30 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %10, %19, %30 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %3, %18, %31 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %11, %19, %31 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %4, %18, %32 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %12, %19, %32 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %5, %18, %33 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %13, %19, %33 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %6, %18, %34 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %14, %19, %34 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %7, %18, %35 row_newbcast:%36 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %15, %19, %35 row_newbcast:%36 row_mask:0xf bank_mask:0xf"
 
-#define T1_BC14(OP)                                                      \
-    OP " %0, %14, %16 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %7, %15, %16 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %1, %14, %17 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %8, %15, %17 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %2, %14, %18 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %9, %15, %18 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %3, %14, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %10, %15, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"  \
-    OP " %4, %14, %20 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %11, %15, %20 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"  \
-    OP " %5, %14, %21 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %12, %15, %21 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"  \
-    OP " %6, %14, %22 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %13, %15, %22 row_newbcast:%23 row_mask:0xf bank_mask:0xf"
+#define T1_BC28(OP)                                                      \
+    OP " %0, %14, %18 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %7, %15, %18 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %1, %14, %19 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %8, %15, %19 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %2, %14, %20 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %9, %15, %20 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %3, %14, %21 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %10, %15, %21 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %4, %14, %22 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %11, %15, %22 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %5, %14, %23 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %12, %15, %23 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %6, %14, %24 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %13, %15, %24 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %0, %16, %25 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %7, %17, %25 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %1, %16, %26 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %8, %17, %26 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %2, %16, %27 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %9, %17, %27 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %3, %16, %28 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %10, %17, %28 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %4, %16, %29 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %11, %17, %29 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %5, %16, %30 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %12, %17, %30 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %6, %16, %31 row_newbcast:%32 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %13, %17, %31 row_newbcast:%32 row_mask:0xf bank_mask:0xf"
 
-#define T1_BC12(OP)                                                      \
-    OP " %0, %12, %14 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %6, %13, %14 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %1, %12, %15 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %7, %13, %15 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %2, %12, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %8, %13, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %3, %12, %17 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %9, %13, %17 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %4, %12, %18 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %10, %13, %18 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"  \
-    OP " %5, %12, %19 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n\t"   \
-    OP " %11, %13, %19 row_newbcast:%20 row_mask:0xf bank_mask:0xf"
+#define T1_BC24(OP)                                                      \
+    OP " %0, %12, %16 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %6, %13, %16 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %1, %12, %17 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %7, %13, %17 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %2, %12, %18 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %8, %13, %18 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %3, %12, %19 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %9, %13, %19 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %4, %12, %20 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %10, %13, %20 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %5, %12, %21 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %11, %13, %21 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %0, %14, %22 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %6, %15, %22 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %1, %14, %23 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %7, %15, %23 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %2, %14, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %8, %15, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %3, %14, %25 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %9, %15, %25 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %4, %14, %26 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %10, %15, %26 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"  \
+    OP " %5, %14, %27 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n\t"   \
+    OP " %11, %15, %27 row_newbcast:%28 row_mask:0xf bank_mask:0xf"
 
-// The 2 RB FMAs of one row at inner position u for the first RB outputs
-// (the block width of the item, 6, 7 or 8 outputs).
+// The 4 RB FMAs of both rows of a pair at inner position u for the first RB
+// outputs (the block width of the item, 6, 7 or 8): row A with its pair
+// product pa and window values ka, then row B with pb and kb.
 template <typename T, int U, int RB>
-__device__ __forceinline__ void t1_fma(T (&zr)[T1_RB], T (&zi)[T1_RB], T px, T py, T k0, T k1, T k2, T k3, T k4,
-                                       T k5, T k6, T k7) {
+__device__ __forceinline__ void t1_fma(T (&zr)[T1_RB], T (&zi)[T1_RB], const typename V2<T>::type &pa,
+                                       const typename V2<T>::type &pb, const T (&ka)[8], const T (&kb)[8]) {
     if constexpr (sizeof(T) == 8) {
         if constexpr (RB == 8)
-            asm volatile(T1_BC16("v_fmac_f64_dpp") : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zr[6]), "+v"(zr[7]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]), "+v"(zi[6]), "+v"(zi[7]) : "v"(px), "v"(py), "v"(k0), "v"(k1), "v"(k2), "v"(k3), "v"(k4), "v"(k5), "v"(k6), "v"(k7), "i"(U % 16));
+            asm volatile(T1_BC32("v_fmac_f64_dpp") : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zr[6]), "+v"(zr[7]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]), "+v"(zi[6]), "+v"(zi[7]) : "v"(pa.x), "v"(pa.y), "v"(pb.x), "v"(pb.y), "v"(ka[0]), "v"(ka[1]), "v"(ka[2]), "v"(ka[3]), "v"(ka[4]), "v"(ka[5]), "v"(ka[6]), "v"(ka[7]), "v"(kb[0]), "v"(kb[1]), "v"(kb[2]), "v"(kb[3]), "v"(kb[4]), "v"(kb[5]), "v"(kb[6]), "v"(kb[7]), "i"(U % 16));
         else if constexpr (RB == 7)
-            asm volatile(T1_BC14("v_fmac_f64_dpp") : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zr[6]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]), "+v"(zi[6]) : "v"(px), "v"(py), "v"(k0), "v"(k1), "v"(k2), "v"(k3), "v"(k4), "v"(k5), "v"(k6), "i"(U % 16));
+            asm volatile(T1_BC28("v_fmac_f64_dpp") : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zr[6]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]), "+v"(zi[6]) : "v"(pa.x), "v"(pa.y), "v"(pb.x), "v"(pb.y), "v"(ka[0]), "v"(ka[1]), "v"(ka[2]), "v"(ka[3]), "v"(ka[4]), "v"(ka[5]), "v"(ka[6]), "v"(kb[0]), "v"(kb[1]), "v"(kb[2]), "v"(kb[3]), "v"(kb[4]), "v"(kb[5]), "v"(kb[6]), "i"(U % 16));
         else
-            asm volatile(T1_BC12("v_fmac_f64_dpp") : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]) : "v"(px), "v"(py), "v"(k0), "v"(k1), "v"(k2), "v"(k3), "v"(k4), "v"(k5), "i"(U % 16));
+            asm volatile(T1_BC24("v_fmac_f64_dpp") : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]) : "v"(pa.x), "v"(pa.y), "v"(pb.x), "v"(pb.y), "v"(ka[0]), "v"(ka[1]), "v"(ka[2]), "v"(ka[3]), "v"(ka[4]), "v"(ka[5]), "v"(kb[0]), "v"(kb[1]), "v"(kb[2]), "v"(kb[3]), "v"(kb[4]), "v"(kb[5]), "i"(U % 16));
     } else {
         static_assert(RB == 8, "FP32 items have 8-wide blocks");
-        asm volatile(T1_BC16("v_fmac_f32_dpp") : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zr[6]), "+v"(zr[7]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]), "+v"(zi[6]), "+v"(zi[7]) : "v"(px), "v"(py), "v"(k0), "v"(k1), "v"(k2), "v"(k3), "v"(k4), "v"(k5), "v"(k6), "v"(k7), "i"(U % 16));
+        asm volatile(T1_BC32("v_fmac_f32_dpp") : "+v"(zr[0]), "+v"(zr[1]), "+v"(zr[2]), "+v"(zr[3]), "+v"(zr[4]), "+v"(zr[5]), "+v"(zr[6]), "+v"(zr[7]), "+v"(zi[0]), "+v"(zi[1]), "+v"(zi[2]), "+v"(zi[3]), "+v"(zi[4]), "+v"(zi[5]), "+v"(zi[6]), "+v"(zi[7]) : "v"(pa.x), "v"(pa.y), "v"(pb.x), "v"(pb.y), "v"(ka[0]), "v"(ka[1]), "v"(ka[2]), "v"(ka[3]), "v"(ka[4]), "v"(ka[5]), "v"(ka[6]), "v"(ka[7]), "v"(kb[0]), "v"(kb[1]), "v"(kb[2]), "v"(kb[3]), "v"(kb[4]), "v"(kb[5]), "v"(kb[6]), "v"(kb[7]), "i"(U % 16));
     }
 }
 
@@ -139,12 +182,13 @@ __device__ __forceinline__ void t1_pos(const typename V2<T>::type (&lo)[8], cons
     // positions stay below 64 (a row has at most N <= 64 inner values); the
     // clamp only keeps the never-taken tail of an 8-block row in bounds
     constexpr int C = U / 16 < 4 ? U / 16 : 3;
-#define T1_K(i, c) ((i) - JJ < 0 ? lo[(i) - JJ + 8].c : hi[(i) - JJ].c)
-    t1_fma<T, U, RB>(zr, zi, PA[C].x, PA[C].y, T1_K(0, y), T1_K(1, y), T1_K(2, y), T1_K(3, y), T1_K(4, y),
-                   T1_K(5, y), T1_K(6, y), T1_K(7, y));
-    t1_fma<T, U, RB>(zr, zi, PB[C].x, PB[C].y, T1_K(0, x), T1_K(1, x), T1_K(2, x), T1_K(3, x), T1_K(4, x),
-                   T1_K(5, x), T1_K(6, x), T1_K(7, x));
-#undef T1_K
+    T ka[8], kb[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        ka[i] = i - JJ < 0 ? lo[i - JJ + 8].y : hi[i - JJ].y;
+        kb[i] = i - JJ < 0 ? lo[i - JJ + 8].x : hi[i - JJ].x;
+    }
+    t1_fma<T, U, RB>(zr, zi, PA[C], PB[C], ka, kb);
 }
 
 // Block K of a pair: lo_K = K(base - 8K - 8 + s), hi_K = lo_{K-1}; issues the
