@@ -354,7 +354,10 @@ def run_c3(args):
     FP64 trajectory runs beside it (untimed), and every 10 steps the bench
     records the relative error of the FP32c Qhat on the current state and of
     the moments of the FP32c trajectory against it; at N = 48 the FP64 tables
-    (364 GB) do not fit one GPU and only the FP32c run is made."""
+    (364 GB) do not fit one GPU and only the FP32c run is made.  The datum's
+    limit state is a condensate (ratio beyond the end of I_eq); every 10 steps
+    the run also records the L1 distance to its z = 1 part and the mass at the
+    node v = u, where the condensed mass m0 gathers."""
     import numpy as np
     import torch
 
@@ -381,6 +384,16 @@ def run_c3(args):
     Qh32 = torch.empty(f.shape, dtype=torch.complex128, device=dev)
     Qh64 = torch.empty_like(Qh32)
     checks = []
+    # the limit state of the datum's moments: a condensate (z = 1 plus the
+    # mass m0 at v = u) for this supercritical ratio
+    m0 = plan.moments(f, check=False)
+    lim = bnq.equilibrium(3, eps, 1.0, m0["rho"], [m0["u0"], m0["u1"], m0["u2"]], m0["e"])
+    relax = []
+
+    def track(step):
+        dk = plan.equilibrium_distance(f, lim)
+        relax.append({"step": step, "l1_regular_part": dk["l1"], "mass_at_v_eq_u": dk["mass_excluded"],
+                      "fmax": plan.moments(f, check=False)["fmax"]})
 
     def check(step):
         if ref is None:
@@ -399,6 +412,7 @@ def run_c3(args):
         plan.step(h, args.dt, bnq.RK4)
     torch.cuda.synchronize()
     check(0)
+    track(0)
     elapsed = 0.0
     blow_up = None
     for k in range(1, args.steps + 1):
@@ -416,6 +430,7 @@ def run_c3(args):
             ref.step(g, args.dt, bnq.RK4)
         if k % 10 == 0 or k == args.steps:
             check(k)
+            track(k)
     if blow_up:
         print(f"c3: non-finite state after step {blow_up}", file=sys.stderr, flush=True)
     mom = plan.moments(f, check=False)
@@ -440,6 +455,8 @@ def run_c3(args):
         "error_vs_fp64": checks if ref is not None else
         "FP64 tables (364 GB) do not fit one GPU at N=48; FP32c parity is checked on sparse spectra",
         "moments_last": {k: mom[k] for k in ("rho", "e", "H", "fmax")},
+        "limit_state": lim.as_dict(),
+        "relaxation": relax,
         "blow_up_step": blow_up,
     }
     plan.close()

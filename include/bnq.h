@@ -213,8 +213,9 @@ bnq_status bnq_fd_be_log(double nu, int32_t fermi, double p, double *out_host);
 
 /* The limit state on the plan's grid (v_j = 2 L j / N), FP64, on `stream`:
  * out[j] = its value at v_j, with 0 written at the nodes where it is not a
- * finite function (v_j = u for a condensate, and for BNQ_EQ_QUANTUM
- * Bose-Einstein only if z = 1 exactly).  The plan's d must match.  Errors:
+ * finite function: for a condensate the node of the grid cell that holds u
+ * (|v_j - u|_inf < L / N), where the mass m0 sits, and for BNQ_EQ_QUANTUM
+ * Bose-Einstein only a node with v_j = u if z = 1 exactly.  The plan's d must match.  Errors:
  * EINVAL (null pointers, d mismatch, BNQ_EQ_UNKNOWN), EHIP. */
 bnq_status bnq_equilibrium_fill(bnq_plan_t plan, const bnq_equilibrium *eq_host, double *out, bnq_stream_t stream);
 

@@ -132,13 +132,16 @@ def solve(d: int, eps: int, hbar: float, rho: float, u, e: float) -> dict:
 
 def on_grid(d: int, N: int, L: float, st: dict):
     """The state at the nodes v_j = 2 L j / N (j in I_N, axis order of the
-    grid arrays) and a mask of the nodes where it is infinite (a condensate's
-    v = u)."""
+    grid arrays) and a mask of the nodes where it is not a finite function: for
+    a condensate the node of the grid cell holding u (|v - u|_inf < L / N),
+    where its mass m0 sits."""
     ax = 2.0 * L * (np.arange(N) - N // 2) / N
     v = np.stack(np.meshgrid(*([ax] * d), indexing="ij"), axis=-1)
-    r2 = np.sum((v - np.asarray(st["u"], dtype=np.float64)) ** 2, axis=-1)
-    excl = np.zeros(r2.shape, dtype=bool)
+    w = v - np.asarray(st["u"], dtype=np.float64)
+    r2 = np.sum(w ** 2, axis=-1)
     k = st["kind"]
+    # a condensate's mass sits at v = u: the node of the grid cell holding u
+    excl = (np.max(np.abs(w), axis=-1) < L / N) if k == CONDENSATE else np.zeros(r2.shape, dtype=bool)
     if k == MAXWELL:
         M = st["rho"] * (2 * math.pi * st["T"]) ** (-d / 2.0) * np.exp(-r2 / (2 * st["T"]))
     elif k == SATURATED:
@@ -150,7 +153,7 @@ def on_grid(d: int, N: int, L: float, st: dict):
             den = np.exp(a) + 1.0
         else:
             den = np.expm1(a)
-            excl = ~(den > 0)
+            excl = excl | ~(den > 0)
         with np.errstate(divide="ignore"):
             M = np.where(excl, 0.0, 1.0 / abs(st["alpha"]) / np.where(excl, 1.0, den))
     else:

@@ -237,7 +237,9 @@ __device__ static double eq_value(const Geo &g, const EqDev &q, double hstep, in
     const double w1 = x1 - q.u[g.d == 3 ? 1 : 0];
     const double w2 = x2 - q.u[g.d == 3 ? 2 : 1];
     const double r2 = w0 * w0 + w1 * w1 + w2 * w2;
-    excl = false;
+    // a condensate's mass sits at v = u: the node of the grid cell holding u
+    excl = q.kind == BNQ_EQ_CONDENSATE && fmax(fabs(w0), fmax(fabs(w1), fabs(w2))) < 0.5 * hstep;
+    if (excl) return 0.0;
     switch (q.kind) {
         case BNQ_EQ_MAXWELL: return q.c0 * exp(-r2 / (2.0 * q.T));
         case BNQ_EQ_SATURATED: return r2 <= q.A2 ? q.c0 : 0.0;

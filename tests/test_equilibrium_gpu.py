@@ -23,6 +23,7 @@ CASES = [
     (3, 12, 5.0, -1, 2.0, [0.2, 0.0, -0.3], 0.6),      # Fermi-Dirac
     (2, 24, 6.0, 1, 3.0, [0.0, 0.5], 0.5),             # Bose-Einstein
     (3, 10, 4.0, 1, 20.0, [0.0, 0.0, 0.0], 0.3),       # condensate (v = u is a node)
+    (3, 10, 4.0, 1, 20.0, [0.05, -0.02, 1e-17], 0.3),  # condensate, u inside the origin's cell
 ]
 
 
@@ -54,6 +55,8 @@ def test_fill_and_distance_match_oracle(case):
     f = Mref * (1.0 + 0.1 * rng.standard_normal(Mref.shape)) + np.where(excl, 0.7, 0.0)
     dist = plan.equilibrium_distance(torch.tensor(f, device=DEV), st)
     dref = oe.distance(f, L, ref)
+    if st.kind == bnq.EQ_CONDENSATE:
+        assert dref["n_excluded"] == 1
     for k in ("l1", "max_abs", "mass_of_state", "mass_excluded"):
         assert dist[k] == pytest.approx(dref[k], rel=1e-12, abs=1e-300), k
     assert dist["n_excluded"] == dref["n_excluded"]
