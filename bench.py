@@ -110,8 +110,9 @@ def main():
                          "between runs) or static (the library default, bitwise reproducible)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-N", type=int, default=10)
-    ap.add_argument("--workload", choices=("c2", "c3", "relax", "batch", "serve"), default="c2",
-                    help="c2: the 3-D N=32 fermion RK4 step (default); c3: 3-D bosons near condensation in "
+    ap.add_argument("--workload", choices=("c1", "c2", "c3", "relax", "batch", "serve"), default="c2",
+                    help="c2: the 3-D N=32 fermion RK4 step (default); c1: the 2-D N=32 boson RK4 step; "
+                         "c3: 3-D bosons near condensation in "
                          "FP32c (--N 32 or 48) with the error against FP64 every 10 steps; relax: the c2 "
                          "trajectory with entropy and distance to its Fermi-Dirac limit every 10 steps; batch: mixed "
                          "instances stepped together; serve: Poisson arrivals")
@@ -145,6 +146,8 @@ def main():
         return run_c3(args)
     if args.workload == "relax":
         return run_relax(args)
+    if args.workload == "c1":
+        return run_c1(args)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -277,6 +280,46 @@ def measured_peaks(torch, dev):
     del x, y, z
     torch.cuda.empty_cache()
     return {"hbm_copy_GB_s": round(copy_gbs, 1), "fp64_gemm_tflops": round(gemm_tf, 2)}
+
+
+def run_c1(args):
+    """2-D bosons (eps = +1), N = 32^2, FP64, Maxwell molecules (B = 1):
+    f0 = two isotropic Gaussians at (+-1.5, 0) of variance 0.5, cut at
+    |v| <= R = 4 and scaled to mass 1, on [-L, L)^2 with L = (3 + sqrt 2) R / 2;
+    one RK4 step of dt per step (four evaluations) plus the moments."""
+    import torch
+
+    import bnq_inputs as inp
+    import paper_2110_13735_amd as bnq
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    f0, L = inp.two_gaussians_2d(N=32, R_v=4.0)
+    p = bnq.Params(d=2, N=32, eps=1, L=L)
+    plan = bnq.Plan(p)
+    terms_step = 4.0 * bnq.terms_per_eval(p, plan.counts())
+    f = torch.tensor(f0, device=dev)
+    for _ in range(args.warmup):
+        g = f.clone()
+        plan.step(g, args.dt, bnq.RK4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.step(f, args.dt, bnq.RK4)
+        mom = plan.moments(f, check=False)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    out = {
+        "metric": METRIC, "value": terms_step * args.steps / elapsed, "unit": "pair-terms/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"2-D bosons eps=+1, N=32^2, FP64, Maxwell molecules, hbar=1, two-Gaussian f0 cut at "
+                               f"R=4, L={L:.4f}, RK4 dt={args.dt}", "d": 2, "N": 32, "eps": 1, "dt": args.dt,
+                   "terms_per_eval": terms_step / 4},
+        "moments_last": {k: mom[k] for k in ("rho", "e", "H", "fmax")},
+    }
+    plan.close()
+    print(json.dumps(out))
 
 
 def run_relax(args):
