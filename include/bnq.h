@@ -102,8 +102,17 @@ typedef struct {
                            their XCD's queue; balances waves that the hardware issues
                            at different rates; the summation order, hence the last
                            bits, may change from run to run) */
-    int32_t reserved;   /* 0 */
+    int32_t flags;      /* BNQ_FLAG_* bits, default 0 */
 } bnq_params;
+
+/* FP64 only: the pair sums form their weights w_c, w_q from the kernel-mode
+ * series on the fly instead of reading the two N^d x N^d tables (the same
+ * code forms both, so the results are bitwise those of the tables).  A plan
+ * gets this mode without the flag when its table set's FP64 weight tables do
+ * not fit the free device memory (3-D N = 48: the trilinear rows take 168 GB,
+ * the weights would take 196 GB more); the pair sums then cost about 1000
+ * flops per weight instead of 16 bytes of HBM traffic. */
+#define BNQ_FLAG_WEIGHTS_OTF 1
 
 #define BNQ_SCHED_STATIC 0
 #define BNQ_SCHED_DYNAMIC 1
@@ -118,7 +127,9 @@ void bnq_params_default(bnq_params *p);
  * first use: every value is computed in FP64 on the device and stored in
  * FP64 (BNQ_FP64) or rounded to FP32 (BNQ_FP32C), so an FP32c plan never
  * needs the FP64 tables (at 3-D N = 48 they take 364 GB, the FP32 ones
- * 182 GB).  Tables are built on `stream` and the call synchronises it.
+ * 182 GB; an FP64 plan there keeps the 168 GB of trilinear rows and forms
+ * its pair weights on the fly: BNQ_FLAG_WEIGHTS_OTF).  Tables are built on
+ * `stream` and the call synchronises it.
  * Errors: EINVAL, ENOTSUP, ENOMEM (also when the tables do not fit the free
  * device memory), EHIP.  On error *out is NULL. */
 bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out);
@@ -129,7 +140,8 @@ bnq_status bnq_plan_destroy(bnq_plan_t plan);
 
 /* Device bytes the plan would need: *plan_bytes for its own workspace,
  * *table_bytes for the shared tables of its precision (0 if already
- * resident).  Host only. */
+ * resident; with BNQ_FLAG_WEIGHTS_OTF the FP64 trilinear rows only).  Host
+ * only. */
 bnq_status bnq_plan_footprint(const bnq_params *p, size_t *plan_bytes, size_t *table_bytes);
 
 /* Q = c (L/pi)^(d+gamma) Re IDFT(Qhat) for the grid distribution f (the right

@@ -103,27 +103,6 @@ void launch_radial(int d, double R, int qmax, int M, int nq, const double *glx, 
     hipLaunchKernelGGL(radial_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, qmax, M, nq, S, J);
 }
 
-// Series value for |a|^2 = qa, |b|^2 = qb, |a.b| = dab.
-__device__ static double beta_series(const Radial &rad, int qa, int qb, double dab) {
-    const int mc = min(rad.mcut[qa], rad.mcut[qb]);
-    double x = 1.0;
-    if (qa > 0 && qb > 0) x = fmin(1.0, dab / sqrt((double)qa * (double)qb));
-    const double *Ja = rad.J + (int64_t)qa * rad.M;
-    const double *Jb = rad.J + (int64_t)qb * rad.M;
-    double sum = rad.coef[0] * (Ja[0] * Jb[0]);
-    // (pm, p) = (P_{2m-2}, P_{2m-1}); Legendre (3-D) or Chebyshev (2-D)
-    double pm = 1.0, p = x;
-    for (int m = 1; m <= mc; ++m) {
-        const int n = 2 * m - 1;
-        const double p2 = rad.d == 3 ? rad.lrA[n] * x * p - rad.lrB[n] * pm : 2.0 * x * p - pm;
-        sum += rad.coef[m] * (Ja[m] * Jb[m]) * p2;
-        const double p3 = rad.d == 3 ? rad.lrA[n + 1] * x * p2 - rad.lrB[n + 1] * p : 2.0 * x * p2 - p;
-        pm = p2;
-        p = p3;
-    }
-    return sum;
-}
-
 // K[kc][a] = beta(a, b_c[kc]) for a in A, stored as [a0][a2 (padded)][a1];
 // the x padding holds zeros.  Every value is formed in FP64; an FP32 table
 // holds it rounded to nearest.
@@ -174,21 +153,11 @@ __global__ void weights_kernel(Geo g, Radial rad, T *wc, T *wq) {
     int l0, l1, l2, m0, m1, m2;
     mode_of(g, il, l0, l1, l2);
     mode_of(g, im, m0, m1, m2);
-    const int s0 = l0 + m0, s1 = l1 + m1, s2 = l2 + m2;
-    const int ql = l0 * l0 + l1 * l1 + l2 * l2;
-    const int qm = m0 * m0 + m1 * m1 + m2 * m2;
-    const int qs = s0 * s0 + s1 * s1 + s2 * s2;
-    const double blm = beta_series(rad, ql, qm, (double)abs(l0 * m0 + l1 * m1 + l2 * m2));
-    const double bmm = beta_series(rad, qm, qm, (double)qm);
-    const int dsl = abs(s0 * l0 + s1 * l1 + s2 * l2);
-    const double bsl = beta_series(rad, qs, ql, (double)dsl);
-    const double bls = beta_series(rad, ql, qs, (double)dsl);
-    const int hi = g.h - 1, lo = -g.h;
-    const bool inI = s1 >= lo && s1 <= hi && s2 >= lo && s2 <= hi &&
-                     (g.d == 2 || (s0 >= lo && s0 <= hi));
+    double c, q;
+    pair_weights(rad, g, l0, l1, l2, m0, m1, m2, c, q);
     const int64_t o = il * g.nm + im;
-    wc[o] = (T)(inI ? blm - bmm : 0.0);
-    wq[o] = (T)(blm - bsl - bls);
+    wc[o] = (T)c;
+    wq[o] = (T)q;
 }
 
 template <typename T>
@@ -205,6 +174,25 @@ void launch_weights(const Geo &g, const Radial &rad, double *wc, double *wq, hip
 
 void launch_weights(const Geo &g, const Radial &rad, float *wc, float *wq, hipStream_t s) {
     launch_weights_t(g, rad, wc, wq, s);
+}
+
+// Pair weights at n index pairs (l, m) (flattened I_N indices): which = 1
+// gives wc, 2 gives wq; for table sets that hold no weight tables.
+__global__ void pair_weights_at_kernel(Geo g, Radial rad, const int64_t *idx, int64_t n, int which, double *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int l0, l1, l2, m0, m1, m2;
+    mode_of(g, idx[i] / g.nm, l0, l1, l2);
+    mode_of(g, idx[i] % g.nm, m0, m1, m2);
+    double c, q;
+    pair_weights(rad, g, l0, l1, l2, m0, m1, m2, c, q);
+    out[i] = which == 1 ? c : q;
+}
+
+void launch_pair_weights_at(const Geo &g, const Radial &rad, const int64_t *idx, int64_t n, int which, double *out,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(pair_weights_at_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, rad, idx, n,
+                       which, out);
 }
 
 template <typename T>

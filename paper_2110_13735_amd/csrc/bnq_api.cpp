@@ -307,47 +307,49 @@ bnq_status build_tables(TableSet *t, hipStream_t s) {
 // Kernel-mode tables of one precision (T = double: FP64 plans; T = float:
 // FP32c plans), built on first need.  Each value is formed in FP64 from the
 // radial table; the FP32 tables hold it rounded to nearest, so they never
-// need the FP64 ones (at 3-D N = 48 only the FP32 set fits one GPU).
+// need the FP64 ones.  The trilinear rows and the two pair-weight tables are
+// built separately: an FP64 set whose weights do not fit (3-D N = 48: rows
+// 168 GB, weights 196 GB) keeps the rows only, and its plans form the pair
+// weights on the fly.
 template <typename T>
-bnq_status build_kernel_mode(TableSet *t, T **K, T **wc, T **wq, hipStream_t s) {
-    if (*K) return BNQ_OK;
+bnq_status build_table(TableSet *t, T **out, size_t n, const char *what, bool rows, hipStream_t s) {
+    if (*out) return BNQ_OK;
     const Geo &g = t->g;
-    const size_t nk = (size_t)t->ncanon * g.nak, nw = (size_t)g.nm * g.nm;
-    const size_t need = sizeof(T) * (nk + 2 * nw);
     size_t freeb = 0, totalb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totalb));
-    if (need > freeb)
-        return fail(BNQ_ENOMEM, "%s kernel-mode tables need %zu bytes, %zu free",
-                    sizeof(T) == 8 ? "FP64" : "FP32", need, freeb);
-    T *k = nullptr, *c = nullptr, *q = nullptr;
+    const size_t need = sizeof(T) * n * (rows ? 1 : 2);
+    if (need > freeb) return fail(BNQ_ENOMEM, "%s %s need %zu bytes, %zu free", sizeof(T) == 8 ? "FP64" : "FP32",
+                                  what, need, freeb);
+    T *a = nullptr, *b = nullptr;
     bnq_status st;
-    if ((st = dalloc(&k, nk, "trilinear kernel-mode table")) || (st = dalloc(&c, nw, "classical weight table")) ||
-        (st = dalloc(&q, nw, "quantum pair weight table"))) {
-        hipFree(k);
-        hipFree(c);
+    if ((st = dalloc(&a, n, what)) || (!rows && (st = dalloc(&b, n, what)))) {
+        hipFree(a);
         return st;
     }
     const Radial rad = t->radial();
-    launch_beta_rows(g, rad, t->canon_d, t->ncanon, k, s);
-    launch_weights(g, rad, c, q, s);
+    if (rows)
+        launch_beta_rows(g, rad, t->canon_d, t->ncanon, a, s);
+    else
+        launch_weights(g, rad, a, b, s);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        hipFree(k);
-        hipFree(c);
-        hipFree(q);
-        return fail(BNQ_EHIP, "kernel-mode table build failed: %s", hipGetErrorString(e));
+        hipFree(a);
+        hipFree(b);
+        return fail(BNQ_EHIP, "%s build failed: %s", what, hipGetErrorString(e));
     }
-    *K = k;
-    *wc = c;
-    *wq = q;
+    out[0] = a;
+    if (!rows) out[1] = b;
     t->bytes += need;
     return BNQ_OK;
 }
 
 // The table set of (d, N, C_phi) on the current device, with the kernel-mode
 // tables of precision prec, shared by every plan that uses it (refcounted).
-bnq_status acquire_tables(int d, int N, double Cphi, int prec, hipStream_t s, TableSet **out) {
+// FP64 sets get their weight tables unless weights = false or they do not
+// fit; *weights_out says whether the set holds them.
+bnq_status acquire_tables(int d, int N, double Cphi, int prec, bool weights, hipStream_t s, TableSet **out,
+                          bool *weights_out) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
@@ -367,8 +369,28 @@ bnq_status acquire_tables(int d, int N, double Cphi, int prec, hipStream_t s, Ta
             return st;
         }
     }
-    st = prec == BNQ_FP32C ? build_kernel_mode(t, &t->K32, &t->wc32, &t->wq32, s)
-                           : build_kernel_mode(t, &t->K, &t->wc, &t->wq, s);
+    const size_t nk = (size_t)t->ncanon * t->g.nak, nw = (size_t)t->g.nm * t->g.nm;
+    if (prec == BNQ_FP32C) {
+        // both weight tables come in one call (wc32, wq32 are adjacent members)
+        float *w2[2] = {t->wc32, t->wq32};
+        st = build_table(t, &t->K32, nk, "trilinear kernel-mode table", true, s);
+        if (!st) st = build_table(t, w2, nw, "pair weight tables", false, s);
+        t->wc32 = w2[0];
+        t->wq32 = w2[1];
+    } else {
+        st = build_table(t, &t->K, nk, "trilinear kernel-mode table", true, s);
+        if (!st && weights && !t->wc) {
+            size_t freeb = 0, totalb = 0;
+            HIPCHK(hipMemGetInfo(&freeb, &totalb));
+            // keep 8 GB for plan workspaces; without room the weights are formed on the fly
+            if (2 * sizeof(double) * nw + ((size_t)8 << 30) <= freeb) {
+                double *w2[2] = {nullptr, nullptr};
+                st = build_table(t, w2, nw, "pair weight tables", false, s);
+                t->wc = w2[0];
+                t->wq = w2[1];
+            }
+        }
+    }
     if (st) {
         if (fresh) free_tables(t);
         return st;
@@ -376,6 +398,7 @@ bnq_status acquire_tables(int d, int N, double Cphi, int prec, hipStream_t s, Ta
     if (fresh) g_cache.push_back(t);
     t->refs++;
     *out = t;
+    if (weights_out) *weights_out = prec == BNQ_FP32C ? true : t->wc != nullptr;
     return BNQ_OK;
 }
 
@@ -439,6 +462,7 @@ struct bnq_plan_s {
     double *mom_part = nullptr, *mom_out = nullptr;
     double *ginv = nullptr;  // inverse Gram matrix for BNQ_CORR_MOMENTS
     double *dmat = nullptr;  // N x N spectral differentiation matrix (rescaled scheme)
+    bool otf = false;        // FP64 pair weights formed on the fly (no weight tables)
     int nslots = 0;
     T1Item *items = nullptr;
     T1B *bdesc = nullptr;
@@ -517,6 +541,9 @@ bnq_status validate(const bnq_params *p) {
         return fail(BNQ_EINVAL, "bad correction %d", p->correction);
     if (p->schedule != BNQ_SCHED_STATIC && p->schedule != BNQ_SCHED_DYNAMIC)
         return fail(BNQ_EINVAL, "bad schedule %d", p->schedule);
+    if (p->flags & ~BNQ_FLAG_WEIGHTS_OTF) return fail(BNQ_EINVAL, "unknown flags 0x%x", p->flags);
+    if ((p->flags & BNQ_FLAG_WEIGHTS_OTF) && p->precision != BNQ_FP64)
+        return fail(BNQ_ENOTSUP, "weights on the fly are an FP64 mode");
     return BNQ_OK;
 }
 
@@ -832,6 +859,7 @@ struct Exec {
     const T1B *bdesc = nullptr;
     const Inst *D = nullptr;
     int prec = 0;               // 0 FP64, 1 FP32c
+    bool otf = false;           // FP64: pair weights formed on the fly
     int nq = 0;                 // dynamic schedule: queues (0 = static)
     int *qctr = nullptr;
     std::vector<Inst> Dh;       // host copies of D
@@ -852,6 +880,7 @@ Exec exec_of(bnq_plan_s *P) {
     E.bdesc = P->bdesc;
     E.D = P->inst_d;
     E.prec = P->p.precision == BNQ_FP32C ? 1 : 0;
+    E.otf = P->otf;
     E.nq = P->nq;
     E.qctr = P->qctr;
     E.Dh.assign(1, P->ih);
@@ -898,8 +927,9 @@ bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s
     if (any & (BNQ_T_CLASSICAL | BNQ_T_QMULT)) {
         Span sp(E.timer, 1, s);
         for (const IOs &io : ios) {
+            const Radial rad = E.t->radial();
             launch_pairs(g, E.prec, E.D, io, E.prec ? (const void *)E.t->wc32 : (const void *)E.t->wc,
-                         E.prec ? (const void *)E.t->wq32 : (const void *)E.t->wq, (any & BNQ_T_QMULT) != 0, s);
+                         E.prec ? (const void *)E.t->wq32 : (const void *)E.t->wq, (any & BNQ_T_QMULT) != 0, E.otf ? &rad : nullptr, s);
             LAUNCHCHK();
             launch_pairs_reduce(g, E.D, io, s);
             LAUNCHCHK();
@@ -1039,7 +1069,7 @@ void bnq_params_default(bnq_params *p) {
     p->c = 1.0;
     p->L = 8.0;
     p->schedule = BNQ_SCHED_STATIC;
-    p->reserved = 0;
+    p->flags = 0;
 }
 
 bnq_status bnq_plan_footprint(const bnq_params *p, size_t *plan_bytes, size_t *table_bytes_out) {
@@ -1049,15 +1079,18 @@ bnq_status bnq_plan_footprint(const bnq_params *p, size_t *plan_bytes, size_t *t
     if (table_bytes_out) {
         // the radial tables of a new table set, plus the kernel-mode tables
         // of the plan's precision unless the cached set already has them
-        const bool f32 = p->precision == BNQ_FP32C;
-        const size_t km = f32 ? table_bytes_f32(p->d, p->N) : table_bytes_f64(p->d, p->N);
+        // (FP64 with weights on the fly: the trilinear rows only)
+        const bool f32 = p->precision == BNQ_FP32C, otf = (p->flags & BNQ_FLAG_WEIGHTS_OTF) != 0;
+        Geo g = make_geo(p->d, p->N);
+        const size_t wbytes = sizeof(double) * 2 * (size_t)g.nm * g.nm;
+        const size_t km = f32 ? table_bytes_f32(p->d, p->N) : table_bytes_f64(p->d, p->N) - (otf ? wbytes : 0);
         size_t tb = table_bytes_radial(p->d, p->N) + km;
         std::lock_guard<std::mutex> lk(g_cache_mu);
         int dev = 0;
         hipGetDevice(&dev);
         for (TableSet *t : g_cache)
             if (t->d == p->d && t->N == p->N && t->Cphi == p->C_phi && t->device == dev)
-                tb = (f32 ? t->K32 != nullptr : t->K != nullptr) ? 0 : km;
+                tb = f32 ? (t->K32 ? 0 : km) : (t->K ? (otf || t->wc ? 0 : wbytes) : km);
         *table_bytes_out = tb;
     }
     return BNQ_OK;
@@ -1077,10 +1110,13 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
     P->pref = p->c * std::pow(p->L / M_PI, p->d + (p->d == 3 ? 1 : 0));
     P->grp = make_group(p->d);
     P->last = s;
-    if ((st = acquire_tables(p->d, p->N, p->C_phi, p->precision, s, &P->tabs))) {
+    bool have_w = true;
+    if ((st = acquire_tables(p->d, p->N, p->C_phi, p->precision, !(p->flags & BNQ_FLAG_WEIGHTS_OTF), s, &P->tabs,
+                             &have_w))) {
         destroy_plan(P);
         return st;
     }
+    P->otf = p->precision == BNQ_FP64 && (!have_w || (p->flags & BNQ_FLAG_WEIGHTS_OTF));
     std::vector<double2> tw(p->N);
     for (int t = 0; t < p->N; ++t) {
         const long double a = 2.0L * (long double)M_PI * t / p->N;
@@ -1499,11 +1535,17 @@ bnq_status bnq_table_lookup(bnq_plan_t P, int32_t table, int64_t n, const int32_
         hipFree(idx_d);
         return st;
     }
-    // the FP64 tables if the set has them, else the FP32 ones
-    if (t->K)
-        launch_gather(table == 0 ? t->K : (table == 1 ? t->wc : t->wq), idx_d, n, out_d, nullptr);
+    // the FP64 tables if the set has them, else the FP32 ones; weights of a
+    // set that holds none are formed here by the code of the pair sums
+    const Radial rad = t->radial();
+    if (table == 0)
+        t->K ? launch_gather(t->K, idx_d, n, out_d, nullptr) : launch_gather(t->K32, idx_d, n, out_d, nullptr);
+    else if (t->wc)
+        launch_gather(table == 1 ? t->wc : t->wq, idx_d, n, out_d, nullptr);
+    else if (t->wc32 && !t->K)
+        launch_gather(table == 1 ? t->wc32 : t->wq32, idx_d, n, out_d, nullptr);
     else
-        launch_gather(table == 0 ? t->K32 : (table == 1 ? t->wc32 : t->wq32), idx_d, n, out_d, nullptr);
+        launch_pair_weights_at(g, rad, idx_d, n, table, out_d, nullptr);
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipMemcpy(out, out_d, sizeof(double) * n, hipMemcpyDeviceToHost);
     hipFree(idx_d);
@@ -1691,7 +1733,8 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
     for (int i = 0; i < n; ++i) {
         const bnq_plan_s *Pi = plans[i];
         const int dyn_slots = (Pi->nq && (Pi->ih.terms & BNQ_T_QTRI)) ? Pi->nslots : 0;
-        const auto key = std::make_tuple((const TableSet *)Pi->tabs, (int)Pi->p.precision, (int)Pi->p.schedule, dyn_slots);
+        const auto key = std::make_tuple((const TableSet *)Pi->tabs, (int)Pi->p.precision + 2 * (int)Pi->otf,
+                                         (int)Pi->p.schedule, dyn_slots);
         auto it = gidx.find(key);
         if (it == gidx.end()) {
             gidx[key] = (int)B->groups.size();

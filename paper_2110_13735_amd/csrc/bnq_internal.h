@@ -97,6 +97,49 @@ struct Radial {
     int d;
 };
 
+// Kernel-mode series value for |a|^2 = qa, |b|^2 = qb, |a.b| = dab.  Not
+// inlined, so that every kernel that forms kernel modes (the tables, and the
+// pair sums that form their weights on the fly) runs the same code.
+[[maybe_unused]] static __device__ __noinline__ double beta_series(const Radial &rad, int qa, int qb, double dab) {
+    const int mc = min(rad.mcut[qa], rad.mcut[qb]);
+    double x = 1.0;
+    if (qa > 0 && qb > 0) x = fmin(1.0, dab / sqrt((double)qa * (double)qb));
+    const double *Ja = rad.J + (int64_t)qa * rad.M;
+    const double *Jb = rad.J + (int64_t)qb * rad.M;
+    double sum = rad.coef[0] * (Ja[0] * Jb[0]);
+    // (pm, p) = (P_{2m-2}, P_{2m-1}); Legendre (3-D) or Chebyshev (2-D)
+    double pm = 1.0, p = x;
+    for (int m = 1; m <= mc; ++m) {
+        const int n = 2 * m - 1;
+        const double p2 = rad.d == 3 ? rad.lrA[n] * x * p - rad.lrB[n] * pm : 2.0 * x * p - pm;
+        sum += rad.coef[m] * (Ja[m] * Jb[m]) * p2;
+        const double p3 = rad.d == 3 ? rad.lrA[n + 1] * x * p2 - rad.lrB[n + 1] * p : 2.0 * x * p2 - p;
+        pm = p2;
+        p = p3;
+    }
+    return sum;
+}
+
+// Pair weights of modes l, m in I_N:
+//   wc = beta(l,m) - beta(m,m)  where l + m is in I_N, else 0
+//   wq = beta(l,m) - beta(l+m,l) - beta(l,l+m)
+[[maybe_unused]] static __device__ __noinline__ void pair_weights(const Radial &rad, const Geo &g, int l0, int l1, int l2, int m0,
+                                                 int m1, int m2, double &wc, double &wq) {
+    const int s0 = l0 + m0, s1 = l1 + m1, s2 = l2 + m2;
+    const int ql = l0 * l0 + l1 * l1 + l2 * l2;
+    const int qm = m0 * m0 + m1 * m1 + m2 * m2;
+    const int qs = s0 * s0 + s1 * s1 + s2 * s2;
+    const double blm = beta_series(rad, ql, qm, (double)abs(l0 * m0 + l1 * m1 + l2 * m2));
+    const double bmm = beta_series(rad, qm, qm, (double)qm);
+    const int dsl = abs(s0 * l0 + s1 * l1 + s2 * l2);
+    const double bsl = beta_series(rad, qs, ql, (double)dsl);
+    const double bls = beta_series(rad, ql, qs, (double)dsl);
+    const int hi = g.h - 1, lo = -g.h;
+    const bool inI = s1 >= lo && s1 <= hi && s2 >= lo && s2 <= hi && (g.d == 2 || (s0 >= lo && s0 <= hi));
+    wc = inI ? blm - bmm : 0.0;
+    wq = blm - bsl - bls;
+}
+
 // Pointers read from memory (the Inst and IOs tables) are generic; kernels
 // convert them to the global address space so that their accesses compile to
 // global (not flat) memory instructions.
@@ -211,6 +254,8 @@ void launch_weights(const Geo &g, const Radial &rad, double *wc, double *wq, hip
 void launch_weights(const Geo &g, const Radial &rad, float *wc, float *wq, hipStream_t s);
 void launch_gather(const double *base, const int64_t *idx, int64_t n, double *out, hipStream_t s);
 void launch_gather(const float *base, const int64_t *idx, int64_t n, double *out, hipStream_t s);
+void launch_pair_weights_at(const Geo &g, const Radial &rad, const int64_t *idx, int64_t n, int which, double *out,
+                            hipStream_t s);
 
 // DFT of grid values io.in -> Ghat (forward, scale N^-d) and Qh -> io.out
 // (inverse, real part, scale Inst::pref).
@@ -220,8 +265,10 @@ void launch_inverse_real(const Geo &g, const Inst *D, const IOs &io, const doubl
 void launch_spectrum_f32(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 void launch_rotate(const Geo &g, int prec, const Inst *D, const IOs &io, const Rot *rots, int nrot, hipStream_t s);
 void launch_pairs_reduce(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
+// w_any: some instance of the launch needs the W pair sums; otf (FP64 only):
+// form the pair weights from these radial tables instead of reading wc, wq
 void launch_pairs(const Geo &g, int prec, const Inst *D, const IOs &io, const void *wc, const void *wq, int w_any,
-                  hipStream_t s);  // w_any: some instance of the launch needs the W pair sums
+                  const Radial *otf, hipStream_t s);
 void launch_outer(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 void launch_zero_part(const Geo &g, const Inst *D, const IOs &io, int max_slots, hipStream_t s);
 // prec 0: FP64 (K is double), 1: FP32c (K is float, spectra Inst::Gr32)

@@ -156,10 +156,11 @@ void launch_spectrum_f32(const Geo &g, const Inst *D, const IOs &io, hipStream_t
 // serves.  Weights come through a buffer resource over the N table rows of
 // one (l_0, l_1): a lane whose m = s - l falls outside I_N gets an offset past
 // the end, so that its load returns zero without touching memory.
-template <typename T, bool WW, bool CC>
+template <typename T, bool WW, bool CC, bool OTF>
 __device__ __forceinline__ void pairs_body(const Geo &g, const typename V2<T>::type *G, const T *wc, const T *wq,
-                                           typename V2<T>::type *gp, int s0, int s1, int s2, bool valid, bool do_c,
-                                           int l0lo, int l0hi, int l1lo, int l1hi, double2 &accw, double2 &accc) {
+                                           const Radial &rad, typename V2<T>::type *gp, int s0, int s1, int s2,
+                                           bool valid, bool do_c, int l0lo, int l0hi, int l1lo, int l1hi,
+                                           double2 &accw, double2 &accc) {
     using T2 = typename V2<T>::type;
     const int N = g.N, h = g.h;
     const int64_t nm = g.nm;
@@ -180,10 +181,10 @@ __device__ __forceinline__ void pairs_body(const Geo &g, const typename V2<T>::t
             const int grow = ((ok1 ? m1 : -h) + h) * N;
             const T2 *Gl = G + il0;
             __amdgpu_buffer_rsrc_t rq, rc;
-            if constexpr (WW)
+            if constexpr (WW && !OTF)
                 rq = __builtin_amdgcn_make_buffer_rsrc((void *)(wq + il0 * nm), (short)0,
                                                        (int)((int64_t)N * nm * sizeof(T)), 0x00020000);
-            if constexpr (CC)
+            if constexpr (CC && !OTF)
                 rc = __builtin_amdgcn_make_buffer_rsrc((void *)(wc + il0 * nm), (short)0,
                                                        (int)((int64_t)N * nm * sizeof(T)), 0x00020000);
             // FP64: every term goes straight into the FP64 sums.  FP32c: the
@@ -198,9 +199,15 @@ __device__ __forceinline__ void pairs_body(const Geo &g, const typename V2<T>::t
                 const uint32_t vo = ok ? (uint32_t)((mrow + m2 + h) * (int)sizeof(T)) : OOB;
                 const int so = (int)((int64_t)j * nm * sizeof(T));
                 const T2 p = cmulT(gl, gm);
+                // weights formed here instead of read (FP64 only)
+                double owc = 0.0, owq = 0.0;
+                if constexpr (OTF)
+                    if (ok) pair_weights(rad, g, l0, l1, j - h, m0, m1, m2, owc, owq);
                 if constexpr (WW) {
                     T a1;
-                    if constexpr (sizeof(T) == 8)
+                    if constexpr (OTF)
+                        a1 = owq;
+                    else if constexpr (sizeof(T) == 8)
                         a1 = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rq, vo, so, 0));
                     else
                         a1 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rq, vo, so, 0));
@@ -215,7 +222,9 @@ __device__ __forceinline__ void pairs_body(const Geo &g, const typename V2<T>::t
                 if constexpr (CC) {
                     const uint32_t vc = do_c ? vo : OOB;
                     T a2;
-                    if constexpr (sizeof(T) == 8)
+                    if constexpr (OTF)
+                        a2 = do_c ? owc : 0.0;
+                    else if constexpr (sizeof(T) == 8)
                         a2 = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, vc, so, 0));
                     else
                         a2 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, vc, so, 0));
@@ -238,9 +247,9 @@ __device__ __forceinline__ void pairs_body(const Geo &g, const typename V2<T>::t
     }
 }
 
-template <typename T>
+template <typename T, bool OTF>
 __global__ __launch_bounds__(256) void pairs_kernel(Geo g, const Inst *D, IOs io, const T *wc, const T *wq,
-                                                    int ext) {
+                                                    Radial rad, int ext) {
     extern __shared__ unsigned char pairs_lds[];
     const Inst &I = D[io.inst[blockIdx.z]];
     const int want_c = (I.terms & 1) != 0, want_w = (I.terms & 2) != 0;
@@ -286,11 +295,11 @@ __global__ __launch_bounds__(256) void pairs_kernel(Geo g, const Inst *D, IOs io
     // a wave whose lanes all lie outside I_N issues no classical-weight loads
     const bool wave_c = __builtin_amdgcn_ballot_w64(do_c) != 0;
     if (want_w && wave_c)
-        pairs_body<T, true, true>(g, G, wc, wq, gp, s0, s1, s2, valid, do_c, l0lo, l0hi, l1lo, l1hi, accw, accc);
+        pairs_body<T, true, true, OTF>(g, G, wc, wq, rad, gp, s0, s1, s2, valid, do_c, l0lo, l0hi, l1lo, l1hi, accw, accc);
     else if (want_w)
-        pairs_body<T, true, false>(g, G, wc, wq, gp, s0, s1, s2, valid, do_c, l0lo, l0hi, l1lo, l1hi, accw, accc);
+        pairs_body<T, true, false, OTF>(g, G, wc, wq, rad, gp, s0, s1, s2, valid, do_c, l0lo, l0hi, l1lo, l1hi, accw, accc);
     else
-        pairs_body<T, false, true>(g, G, wc, wq, gp, s0, s1, s2, valid, do_c, l0lo, l0hi, l1lo, l1hi, accw, accc);
+        pairs_body<T, false, true, OTF>(g, G, wc, wq, rad, gp, s0, s1, s2, valid, do_c, l0lo, l0hi, l1lo, l1hi, accw, accc);
     if (!valid) return;
     if (want_w) st2(I.ppart + (int64_t)c * g.neg, idx_E(g, s0, s1, s2), accw);
     if (do_c) st2(I.ppart + (int64_t)K * g.neg + (int64_t)c * g.nm, idx_I(g, s0, s1, s2), accc);
@@ -303,11 +312,11 @@ __global__ __launch_bounds__(256) void pairs_kernel(Geo g, const Inst *D, IOs io
 // N.  So every lane of every weight load carries a useful term, where the
 // unfolded walk over 2N outputs wastes half of them.  The l_1 range is the
 // wave's own (its output rows), the l_0 range the workgroup's.
-template <typename T, bool WW, bool CC>
+template <typename T, bool WW, bool CC, bool OTF>
 __device__ __forceinline__ void pairs_w_body(const Geo &g, const typename V2<T>::type *G, const T *wc, const T *wq,
-                                             typename V2<T>::type *gp, int s0, int s1, int k, bool valid, bool dcA,
-                                             bool dcB, int l0lo, int l0hi, int l1lo, int l1hi, double2 (&aw)[2],
-                                             double2 (&ac)[2]) {
+                                             const Radial &rad, typename V2<T>::type *gp, int s0, int s1, int k,
+                                             bool valid, bool dcA, bool dcB, int l0lo, int l0hi, int l1lo, int l1hi,
+                                             double2 (&aw)[2], double2 (&ac)[2]) {
     using T2 = typename V2<T>::type;
     const int N = g.N, h = g.h;
     const int64_t nm = g.nm;
@@ -328,10 +337,10 @@ __device__ __forceinline__ void pairs_w_body(const Geo &g, const typename V2<T>:
             const int grow = ((ok1 ? m1 : -h) + h) * N;
             const T2 *Gl = G + il0;
             __amdgpu_buffer_rsrc_t rq, rc;
-            if constexpr (WW)
+            if constexpr (WW && !OTF)
                 rq = __builtin_amdgcn_make_buffer_rsrc((void *)(wq + il0 * nm), (short)0,
                                                        (int)((int64_t)N * nm * sizeof(T)), 0x00020000);
-            if constexpr (CC)
+            if constexpr (CC && !OTF)
                 rc = __builtin_amdgcn_make_buffer_rsrc((void *)(wc + il0 * nm), (short)0,
                                                        (int)((int64_t)N * nm * sizeof(T)), 0x00020000);
             // FP32c: the N terms of one l-row in FP32, row sums in FP64
@@ -345,9 +354,15 @@ __device__ __forceinline__ void pairs_w_body(const Geo &g, const typename V2<T>:
                 const uint32_t vo = ok1 ? (uint32_t)((mrow + mi) * (int)sizeof(T)) : OOB;
                 const int so = (int)((int64_t)t * nm * sizeof(T));
                 const T2 p = cmulT(gl, gm);
+                // weights formed here instead of read (FP64 only)
+                double owc = 0.0, owq = 0.0;
+                if constexpr (OTF)
+                    if (ok1) pair_weights(rad, g, l0, l1, t - h, m0, m1, mi - h, owc, owq);
                 if constexpr (WW) {
                     T a;
-                    if constexpr (sizeof(T) == 8)
+                    if constexpr (OTF)
+                        a = owq;
+                    else if constexpr (sizeof(T) == 8)
                         a = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rq, vo, so, 0));
                     else
                         a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rq, vo, so, 0));
@@ -367,7 +382,9 @@ __device__ __forceinline__ void pairs_w_body(const Geo &g, const typename V2<T>:
                 if constexpr (CC) {
                     const uint32_t vc = (isA ? dcA : dcB) ? vo : OOB;
                     T a;
-                    if constexpr (sizeof(T) == 8)
+                    if constexpr (OTF)
+                        a = (isA ? dcA : dcB) ? owc : 0.0;
+                    else if constexpr (sizeof(T) == 8)
                         a = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, vc, so, 0));
                     else
                         a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, vc, so, 0));
@@ -398,8 +415,9 @@ __device__ __forceinline__ void pairs_w_body(const Geo &g, const typename V2<T>:
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void pairs_w_kernel(Geo g, const Inst *D, IOs io, const T *wc, const T *wq) {
+template <typename T, bool OTF>
+__global__ __launch_bounds__(256) void pairs_w_kernel(Geo g, const Inst *D, IOs io, const T *wc, const T *wq,
+                                                      Radial rad) {
     extern __shared__ unsigned char pairs_lds[];
     const Inst &I = D[io.inst[blockIdx.z]];
     const int want_c = (I.terms & 1) != 0, want_w = (I.terms & 2) != 0;
@@ -443,11 +461,11 @@ __global__ __launch_bounds__(256) void pairs_w_kernel(Geo g, const Inst *D, IOs 
     T2 *gp = (T2 *)pairs_lds;
     const bool wave_c = __builtin_amdgcn_ballot_w64(dcA || dcB) != 0;
     if (want_w && wave_c)
-        pairs_w_body<T, true, true>(g, G, wc, wq, gp, s0, s1, k, valid, dcA, dcB, l0lo, l0hi, l1lo, l1hi, aw, ac);
+        pairs_w_body<T, true, true, OTF>(g, G, wc, wq, rad, gp, s0, s1, k, valid, dcA, dcB, l0lo, l0hi, l1lo, l1hi, aw, ac);
     else if (want_w)
-        pairs_w_body<T, true, false>(g, G, wc, wq, gp, s0, s1, k, valid, dcA, dcB, l0lo, l0hi, l1lo, l1hi, aw, ac);
+        pairs_w_body<T, true, false, OTF>(g, G, wc, wq, rad, gp, s0, s1, k, valid, dcA, dcB, l0lo, l0hi, l1lo, l1hi, aw, ac);
     else
-        pairs_w_body<T, false, true>(g, G, wc, wq, gp, s0, s1, k, valid, dcA, dcB, l0lo, l0hi, l1lo, l1hi, aw, ac);
+        pairs_w_body<T, false, true, OTF>(g, G, wc, wq, rad, gp, s0, s1, k, valid, dcA, dcB, l0lo, l0hi, l1lo, l1hi, aw, ac);
     if (!valid) return;
     const int s2[2] = {k - N, k};
     if (want_w)
@@ -488,31 +506,38 @@ void launch_pairs_reduce(const Geo &g, const Inst *D, const IOs &io, hipStream_t
 }
 
 void launch_pairs(const Geo &g, int prec, const Inst *D, const IOs &io, const void *wc, const void *wq, int w_any,
-                  hipStream_t s) {
+                  const Radial *otf, hipStream_t s) {
     const int N = g.N;
     const size_t lds = (size_t)N * N * (prec == 0 ? sizeof(double2) : sizeof(float2));  // one m_0 plane of G
+    const Radial rad = otf ? *otf : Radial{};
     if (w_any) {
         // outputs over E_g, x folded: N lanes per output row
         const int rows = 256 / N;
         dim3 grid((unsigned)((2 * N + rows - 1) / rows), (unsigned)((g.d == 3 ? 2 * N : 1) * pair_split(g)),
                   (unsigned)io.n);
-        if (prec == 0)
-            hipLaunchKernelGGL(pairs_w_kernel<double>, grid, dim3(256), lds, s, g, D, io, (const double *)wc,
-                               (const double *)wq);
+        if (prec == 0 && otf)
+            hipLaunchKernelGGL((pairs_w_kernel<double, true>), grid, dim3(256), lds, s, g, D, io, (const double *)wc,
+                               (const double *)wq, rad);
+        else if (prec == 0)
+            hipLaunchKernelGGL((pairs_w_kernel<double, false>), grid, dim3(256), lds, s, g, D, io, (const double *)wc,
+                               (const double *)wq, rad);
         else
-            hipLaunchKernelGGL(pairs_w_kernel<float>, grid, dim3(256), lds, s, g, D, io, (const float *)wc,
-                               (const float *)wq);
+            hipLaunchKernelGGL((pairs_w_kernel<float, false>), grid, dim3(256), lds, s, g, D, io, (const float *)wc,
+                               (const float *)wq, rad);
         return;
     }
     const int ext = N;
     const int rows = 256 / ext;
     dim3 grid((unsigned)((ext + rows - 1) / rows), (unsigned)((g.d == 3 ? ext : 1) * pair_split(g)), (unsigned)io.n);
-    if (prec == 0)
-        hipLaunchKernelGGL(pairs_kernel<double>, grid, dim3(256), lds, s, g, D, io, (const double *)wc,
-                           (const double *)wq, ext);
+    if (prec == 0 && otf)
+        hipLaunchKernelGGL((pairs_kernel<double, true>), grid, dim3(256), lds, s, g, D, io, (const double *)wc,
+                           (const double *)wq, rad, ext);
+    else if (prec == 0)
+        hipLaunchKernelGGL((pairs_kernel<double, false>), grid, dim3(256), lds, s, g, D, io, (const double *)wc,
+                           (const double *)wq, rad, ext);
     else
-        hipLaunchKernelGGL(pairs_kernel<float>, grid, dim3(256), lds, s, g, D, io, (const float *)wc,
-                           (const float *)wq, ext);
+        hipLaunchKernelGGL((pairs_kernel<float, false>), grid, dim3(256), lds, s, g, D, io, (const float *)wc,
+                           (const float *)wq, rad, ext);
 }
 
 // ---------------------------------------------------------------------------

@@ -84,6 +84,22 @@ def test_footprint_3d48_fp32_tables_fit_one_gpu():
     assert tab32 + plan32 < 250e9 < 288e9 < tab64
 
 
+def test_weights_on_the_fly_flag():
+    # FP64 only; the 3-D N = 48 FP64 set without weight tables fits one GPU
+    if not os.path.exists(bnq.LIBPATH):
+        pytest.skip("libbnq.so not built")
+    with pytest.raises(bnq.BnqError) as e:
+        bnq.footprint(bnq.Params(d=2, N=8, L=4.0, flags=2))
+    assert e.value.status == bnq.BNQ_EINVAL
+    with pytest.raises(bnq.BnqError) as e:
+        bnq.footprint(bnq.Params(d=2, N=8, L=4.0, precision=bnq.FP32C, flags=bnq.FLAG_WEIGHTS_OTF))
+    assert e.value.status == bnq.BNQ_ENOTSUP
+    _, full = bnq.footprint(bnq.Params(d=3, N=48, L=8.0))
+    _, rows = bnq.footprint(bnq.Params(d=3, N=48, L=8.0, flags=bnq.FLAG_WEIGHTS_OTF))
+    assert full - rows == 2 * 48 ** 6 * 8
+    assert rows < 180e9
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(bnq, "LIBPATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(bnq, "_lib", None)

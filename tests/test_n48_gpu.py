@@ -1,9 +1,11 @@
 """3-D N = 48 on one GPU.
 
-Only the FP32c kernel-mode tables fit (182 GB; the FP64 ones take 364 GB of
+The FP32c kernel-mode tables fit (182 GB; the FP64 ones would take 364 GB of
 the 288 GB of HBM), so an FP32c plan builds its FP32 tables directly (each
-value formed in FP64, stored rounded to nearest) and an FP64 plan is refused
-with ENOMEM before anything is allocated.  The oracle cannot evaluate a dense
+value formed in FP64, stored rounded to nearest).  An FP64 plan keeps the
+168 GB of FP64 trilinear rows and forms its pair weights on the fly
+(tests/test_n48_fp64_gpu.py); beside the FP32 set it is refused with ENOMEM
+before anything is allocated.  The oracle cannot evaluate a dense
 N = 48 operator in seconds; the operator is checked on a sparse spectrum,
 whose exact Galerkin sums the oracle forms over the support, and the tables
 on random index pairs against the oracle's own quadrature.
@@ -83,7 +85,16 @@ def test_fp32c_collide_sparse_spectrum_matches_oracle(plan48):
     assert abs(Qh[h, h, h]) <= TOL32 * np.abs(ref).max()
 
 
-def test_fp64_plan_refused_for_lack_of_memory(plan48):
+def test_fp64_plan_beside_the_fp32_tables_is_refused(plan48):
+    # the FP64 trilinear rows (168 GB) do not fit beside the FP32 set (182 GB)
     with pytest.raises(bnq.BnqError) as e:
         bnq.Plan(bnq.Params(d=3, N=N, eps=1, L=8.0))
     assert e.value.status == bnq.BNQ_ENOMEM
+
+
+def test_3d64_plan_refused_for_lack_of_memory():
+    # 3-D N = 64: 45760 trilinear rows of 2.4e6 values, over 400 GB even in FP32
+    for prec in (bnq.FP64, bnq.FP32C):
+        with pytest.raises(bnq.BnqError) as e:
+            bnq.Plan(bnq.Params(d=3, N=64, eps=1, L=8.0, precision=prec))
+        assert e.value.status == bnq.BNQ_ENOMEM

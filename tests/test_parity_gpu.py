@@ -297,6 +297,20 @@ def test_full_size_3d32_sparse_spectrum():
     assert _rel(Q, Qref) <= TOL
 
 
+@pytest.mark.parametrize("d,N,eps", [(2, 8, 1), (2, 16, -1), (2, 30, 0), (3, 6, 1), (3, 10, -1)])
+def test_weights_on_the_fly_equal_the_tables(d, N, eps):
+    # the pair sums forming their weights (BNQ_FLAG_WEIGHTS_OTF) run the code
+    # that built the tables: the same Qhat, bit for bit, and the oracle's
+    rng = np.random.default_rng(d * 100 + N)
+    f = 0.2 + 0.1 * rng.random((N,) * d)
+    L = 5.0
+    _, Qh_t = _gpu_collide(bnq.Params(d=d, N=N, eps=eps, L=L), f)
+    _, Qh_o = _gpu_collide(bnq.Params(d=d, N=N, eps=eps, L=L, flags=bnq.FLAG_WEIGHTS_OTF), f)
+    assert np.array_equal(Qh_t, Qh_o)
+    _, Qho, g, _ = _oracle_collide(d, N, f, eps, L)
+    _check(Qh_o, Qho, g)
+
+
 def test_invalid_calls_raise():
     plan = bnq.Plan(bnq.Params(d=2, N=8, eps=1, L=4.0))
     ft = torch.zeros(8, 8, dtype=torch.float64, device="cuda:0")
