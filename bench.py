@@ -186,17 +186,21 @@ def main():
     value = terms_step / (elapsed / args.steps)
 
     if eps != 0:
+        # per evaluation: one launch at N <= 32; larger sums are cut into
+        # several launches that together cover the evaluation's terms once
         t1_ms, t1_n = kt["trilinear"]
-        t1_avg_s = (t1_ms / t1_n) * 1e-3 if t1_n else float("nan")
+        evals = 4 * args.steps
+        t1_avg_s = (t1_ms / evals) * 1e-3 if t1_n else float("nan")
         flops_launch = counts["trilinear"] * FLOPS_PER_T1_TERM
         achieved = flops_launch / t1_avg_s / 1e12
         tr = measured_traffic() if (prec == bnq.FP64 and eps == -1) else None
         peak = PEAK_FP32_VALU if prec == bnq.FP32C else PEAK_FP64_VALU
+        # avg_ms is the trilinear time of one evaluation: one launch at N <= 32
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak / 1e12,
                     "unit": "TFLOP/s", "frac": round(achieved * 1e12 / peak, 4),
                     "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None,
                     "kernel": "trilinear_kernel", "avg_ms": round(t1_avg_s * 1e3, 3), "launches": t1_n,
-                    "flops_per_launch": flops_launch}
+                    "launches_per_eval": t1_n // max(1, evals), "flops_per_eval": flops_launch}
         if tr:
             roofline["traffic_detail"] = {k: tr[k] for k in ("fetch_bytes", "write_bytes", "fetch_scale",
                                                              "write_scale")}

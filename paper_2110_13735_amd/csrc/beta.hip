@@ -136,6 +136,16 @@ void launch_beta_rows(const Geo &g, const Radial &rad, const int *canon, int nca
     hipLaunchKernelGGL(beta_rows_kernel<float>, grid, dim3(256), 0, s, g, rad, canon, K);
 }
 
+// beta(a, a) for |a|^2 = q, q = 0 .. qmax
+__global__ void beta_diag_kernel(Radial rad, int qmax, double *out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q <= qmax) out[q] = beta_series(rad, q, q, (double)q);
+}
+
+void launch_beta_diag(const Radial &rad, int qmax, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(beta_diag_kernel, dim3((unsigned)((qmax + 256) / 256)), dim3(256), 0, s, rad, qmax, out);
+}
+
 __device__ static inline void mode_of(const Geo &g, int64_t i, int &k0, int &k1, int &k2) {
     k2 = (int)(i % g.N) - g.h;
     k1 = (int)((i / g.N) % g.N) - g.h;

@@ -147,7 +147,7 @@ struct TableSet {
     int device = 0;
     Geo g;
     int qmax = 0, M = 0;
-    double *J = nullptr, *coef = nullptr, *lrA = nullptr, *lrB = nullptr;
+    double *J = nullptr, *coef = nullptr, *lrA = nullptr, *lrB = nullptr, *bdiag = nullptr;
     int *mcut = nullptr;
     std::vector<int> canon;      // 3 per row
     std::vector<int> canon_row;  // [N][N][N] -> row or -1
@@ -164,6 +164,7 @@ struct TableSet {
         r.coef = coef;
         r.lrA = lrA;
         r.lrB = lrB;
+        r.bdiag = bdiag;
         r.M = M;
         r.d = d;
         return r;
@@ -198,7 +199,7 @@ void canon_list(int d, int N, std::vector<int> &canon, std::vector<int> &row) {
 size_t table_bytes_radial(int d, int N) {
     const int qmax = d * N * N;
     const int M = mcut_of(qmax) + 1;
-    return sizeof(double) * ((size_t)(qmax + 1) * M) + sizeof(int) * (qmax + 1);
+    return sizeof(double) * ((size_t)(qmax + 1) * (M + 1)) + sizeof(int) * (qmax + 1);
 }
 
 size_t table_values(int d, int N) {
@@ -216,6 +217,7 @@ void free_tables(TableSet *t) {
     hipFree(t->coef);
     hipFree(t->lrA);
     hipFree(t->lrB);
+    hipFree(t->bdiag);
     hipFree(t->mcut);
     hipFree(t->canon_d);
     hipFree(t->K);
@@ -292,6 +294,15 @@ bnq_status build_tables(TableSet *t, hipStream_t s) {
         return st;
     }
     launch_radial(d, kR, t->qmax, t->M, kNq, glx_d, glw_d, scratch, t->J, s);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(s));
+    if ((st = dalloc(&t->bdiag, (size_t)t->qmax + 1, "kernel-mode diagonal"))) {
+        hipFree(scratch);
+        hipFree(glx_d);
+        hipFree(glw_d);
+        return st;
+    }
+    launch_beta_diag(t->radial(), t->qmax, t->bdiag, s);
     LAUNCHCHK();
     HIPCHK(hipStreamSynchronize(s));
     hipFree(scratch);

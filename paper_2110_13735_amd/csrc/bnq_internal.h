@@ -93,6 +93,7 @@ struct Radial {
     const double *coef;  // [M] series coefficients (include C_phi)
     const double *lrA;   // [2M] Legendre recurrence constants (2n+1)/(n+1)
     const double *lrB;   // [2M] n/(n+1)
+    const double *bdiag; // [qmax+1] beta(a, a) for |a|^2 = q (the series at x = 1)
     int M;
     int d;
 };
@@ -130,10 +131,11 @@ struct Radial {
     const int qm = m0 * m0 + m1 * m1 + m2 * m2;
     const int qs = s0 * s0 + s1 * s1 + s2 * s2;
     const double blm = beta_series(rad, ql, qm, (double)abs(l0 * m0 + l1 * m1 + l2 * m2));
-    const double bmm = beta_series(rad, qm, qm, (double)qm);
-    const int dsl = abs(s0 * l0 + s1 * l1 + s2 * l2);
-    const double bsl = beta_series(rad, qs, ql, (double)dsl);
-    const double bls = beta_series(rad, ql, qs, (double)dsl);
+    const double bmm = rad.bdiag[qm];
+    // beta(l+m, l) = beta(l, l+m): the series is symmetric in its arguments,
+    // bit for bit (products of the two radial factors commute)
+    const double bsl = beta_series(rad, qs, ql, (double)abs(s0 * l0 + s1 * l1 + s2 * l2));
+    const double bls = bsl;
     const int hi = g.h - 1, lo = -g.h;
     const bool inI = s1 >= lo && s1 <= hi && s2 >= lo && s2 <= hi && (g.d == 2 || (s0 >= lo && s0 <= hi));
     wc = inI ? blm - bmm : 0.0;
@@ -254,6 +256,7 @@ void launch_weights(const Geo &g, const Radial &rad, double *wc, double *wq, hip
 void launch_weights(const Geo &g, const Radial &rad, float *wc, float *wq, hipStream_t s);
 void launch_gather(const double *base, const int64_t *idx, int64_t n, double *out, hipStream_t s);
 void launch_gather(const float *base, const int64_t *idx, int64_t n, double *out, hipStream_t s);
+void launch_beta_diag(const Radial &rad, int qmax, double *out, hipStream_t s);
 void launch_pair_weights_at(const Geo &g, const Radial &rad, const int64_t *idx, int64_t n, int which, double *out,
                             hipStream_t s);
 
