@@ -116,6 +116,11 @@ def main():
                          "FP32c (--N 32 or 48) with the error against FP64 every 10 steps; relax: the c2 "
                          "trajectory with entropy and distance to its Fermi-Dirac limit every 10 steps; batch: mixed "
                          "instances stepped together; serve: Poisson arrivals")
+    ap.add_argument("--separated", action="store_true",
+                    help="c1 only: the trilinear term by the separated-kernel transform route (rank-P kernel "
+                         "modes on the doubled grid) instead of the direct sum")
+    ap.add_argument("--angles", type=int, default=101,
+                    help="c1 --separated: angle count P (101 is the library's default at N=32)")
     ap.add_argument("--instances", type=int, default=60, help="batch workload: number of instances")
     ap.add_argument("--cells", choices=("mixed", "small"), default="mixed", help="batch workload: cell set")
     ap.add_argument("--rate", type=float, default=10.0, help="serve workload: mean arrivals per second")
@@ -299,7 +304,8 @@ def run_c1(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     f0, L = inp.two_gaussians_2d(N=32, R_v=4.0)
-    p = bnq.Params(d=2, N=32, eps=1, L=L)
+    sep = args.separated
+    p = bnq.Params(d=2, N=32, eps=1, L=L, flags=bnq.FLAG_T1_SEPARATED if sep else 0, angles=args.angles if sep else 0)
     plan = bnq.Plan(p)
     terms_step = 4.0 * bnq.terms_per_eval(p, plan.counts())
     f = torch.tensor(f0, device=dev)
@@ -307,19 +313,43 @@ def run_c1(args):
         g = f.clone()
         plan.step(g, args.dt, bnq.RK4)
     torch.cuda.synchronize()
+    plan.set_timing(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         plan.step(f, args.dt, bnq.RK4)
         mom = plan.moments(f, check=False)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    kt = plan.timing()
+    plan.set_timing(False)
+    t1_ms, t1_n = kt["trilinear"]
+    evals = 4 * args.steps
+    if sep:
+        # per (angle, shift): first-axis transforms of A and B (14 flops per
+        # term, M^2 N terms), second axis (16 flops per term, N^2 M terms) and
+        # the product (20 flops per output mode)
+        Nn, M, P = 32, 64, args.angles
+        flops_eval = float(P * M * M * (14 * M * M * Nn + 16 * Nn * Nn * M + 20 * Nn * Nn))
+        kernel = "sep_t1_kernel (+ sep_gt, sep_reduce)"
+    else:
+        flops_eval = plan.counts()["trilinear"] * FLOPS_PER_T1_TERM
+        kernel = "trilinear_kernel"
+    avg_s = t1_ms / evals * 1e-3
+    achieved = flops_eval / avg_s / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+                "frac": round(achieved * 1e12 / PEAK_FP64_VALU, 4), "traffic": None, "kernel": kernel,
+                "avg_ms": round(avg_s * 1e3, 3), "launches": t1_n, "flops_per_eval": flops_eval}
     out = {
         "metric": METRIC, "value": terms_step * args.steps / elapsed, "unit": "pair-terms/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"2-D bosons eps=+1, N=32^2, FP64, Maxwell molecules, hbar=1, two-Gaussian f0 cut at "
-                               f"R=4, L={L:.4f}, RK4 dt={args.dt}", "d": 2, "N": 32, "eps": 1, "dt": args.dt,
-                   "terms_per_eval": terms_step / 4},
+                               f"R=4, L={L:.4f}, RK4 dt={args.dt}"
+                               + (f", trilinear term by the separated route with P={args.angles} angles" if sep else ""),
+                   "d": 2, "N": 32, "eps": 1, "dt": args.dt, "terms_per_eval": terms_step / 4,
+                   "trilinear_route": "separated" if sep else "direct"},
+        "roofline": roofline,
+        "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kt.items()},
         "moments_last": {k: mom[k] for k in ("rho", "e", "H", "fmax")},
     }
     plan.close()

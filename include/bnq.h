@@ -103,6 +103,10 @@ typedef struct {
                            at different rates; the summation order, hence the last
                            bits, may change from run to run) */
     int32_t flags;      /* BNQ_FLAG_* bits, default 0 */
+    int32_t angles;     /* BNQ_FLAG_T1_SEPARATED only: the angle count P of the
+                           rank-P kernel modes (eq. alphap), 1..4096; 0 (default)
+                           = enough angles to reproduce the converged kernel
+                           modes to rounding */
 } bnq_params;
 
 /* FP64 only: the pair sums form their weights w_c, w_q from the kernel-mode
@@ -113,6 +117,20 @@ typedef struct {
  * the weights would take 196 GB more); the pair sums then cost about 1000
  * flops per weight instead of 16 bytes of HBM traffic. */
 #define BNQ_FLAG_WEIGHTS_OTF 1
+
+/* d = 2, FP64, N <= 32: the trilinear term Q_{1,q} is evaluated by the
+ * transform route of the appendix 'Fast evaluation of the collision kernel'
+ * with the rank-P kernel modes of section 'Fast computation of the collision
+ * modes' (eqs. betadD, alphap): beta(a,b) = (pi/P) sum_p alpha_p(a)
+ * alpha'_p(b) over the angles theta_p = p pi / P.  The spectrum is extended
+ * by zeros to the doubled grid (2N)^2, on which the route gives the linear
+ * Galerkin sum; with the default angle count it equals the direct trilinear
+ * sum to rounding.  It costs about 6 N^3 P (2N)^2 complex multiply-adds per
+ * evaluation (1.3e12 flops at N = 32, against 4.8e9 for the direct sum).
+ * The other terms keep the converged kernel-mode tables.  Plans with this
+ * flag are refused by bnq_batch_create (ENOTSUP).  Other d, precisions or
+ * N: ENOTSUP. */
+#define BNQ_FLAG_T1_SEPARATED 2
 
 #define BNQ_SCHED_STATIC 0
 #define BNQ_SCHED_DYNAMIC 1

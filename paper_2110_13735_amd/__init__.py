@@ -21,6 +21,7 @@ BNQ_OK, BNQ_EINVAL, BNQ_ENOMEM, BNQ_EHIP, BNQ_ENOTSUP, BNQ_ENONFINITE, BNQ_EBOUN
 T_CLASSICAL, T_QMULT, T_QTRI, T_ALL = 1, 2, 4, 7
 FP64, FP32C = 0, 1
 FLAG_WEIGHTS_OTF = 1
+FLAG_T1_SEPARATED = 2
 SCHED_STATIC, SCHED_DYNAMIC = 0, 1
 CORR_NONE, CORR_MASS, CORR_MOMENTS = 0, 1, 2
 RK4, EULER, SSPRK2 = 0, 1, 2
@@ -40,7 +41,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("N", ctypes.c_int32), ("eps", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("terms", ctypes.c_int32), ("correction", ctypes.c_int32),
                 ("hbar", ctypes.c_double), ("C_phi", ctypes.c_double), ("c", ctypes.c_double),
-                ("L", ctypes.c_double), ("schedule", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("L", ctypes.c_double), ("schedule", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("angles", ctypes.c_int32)]
 
 
 @dataclass
@@ -57,10 +59,11 @@ class Params:
     precision: int = FP64
     schedule: int = 0  # SCHED_STATIC
     flags: int = 0  # FLAG_*
+    angles: int = 0  # FLAG_T1_SEPARATED: angle count P (0 = enough for FP64)
 
     def _c(self) -> _Params:
         return _Params(self.d, self.N, self.eps, self.precision, self.terms, self.correction,
-                       self.hbar, self.C_phi, self.c, self.L, self.schedule, self.flags)
+                       self.hbar, self.C_phi, self.c, self.L, self.schedule, self.flags, self.angles)
 
 
 EQ_MAXWELL, EQ_QUANTUM, EQ_CONDENSATE, EQ_SATURATED, EQ_UNKNOWN = 0, 1, 2, 3, 4

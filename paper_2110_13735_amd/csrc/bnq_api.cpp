@@ -474,6 +474,11 @@ struct bnq_plan_s {
     double *ginv = nullptr;  // inverse Gram matrix for BNQ_CORR_MOMENTS
     double *dmat = nullptr;  // N x N spectral differentiation matrix (rescaled scheme)
     bool otf = false;        // FP64 pair weights formed on the fly (no weight tables)
+    // BNQ_FLAG_T1_SEPARATED: angle count, alpha rows, their cosine transforms
+    // over the doubled grid, the spectrum there and the per-block partials
+    int sepP = 0;
+    double *sep_al = nullptr, *sep_alp = nullptr;
+    double2 *sep_gc = nullptr, *sep_gt = nullptr, *sep_part = nullptr;
     int nslots = 0;
     T1Item *items = nullptr;
     T1B *bdesc = nullptr;
@@ -552,10 +557,27 @@ bnq_status validate(const bnq_params *p) {
         return fail(BNQ_EINVAL, "bad correction %d", p->correction);
     if (p->schedule != BNQ_SCHED_STATIC && p->schedule != BNQ_SCHED_DYNAMIC)
         return fail(BNQ_EINVAL, "bad schedule %d", p->schedule);
-    if (p->flags & ~BNQ_FLAG_WEIGHTS_OTF) return fail(BNQ_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->flags & ~(BNQ_FLAG_WEIGHTS_OTF | BNQ_FLAG_T1_SEPARATED))
+        return fail(BNQ_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->angles < 0) return fail(BNQ_EINVAL, "angles must be >= 0 (got %d)", p->angles);
+    if (p->angles > 0 && !(p->flags & BNQ_FLAG_T1_SEPARATED))
+        return fail(BNQ_EINVAL, "angles is read only with BNQ_FLAG_T1_SEPARATED");
+    if ((p->flags & BNQ_FLAG_T1_SEPARATED) && (p->d != 2 || p->precision != BNQ_FP64 || !sep_supported(p->N)))
+        return fail(BNQ_ENOTSUP, "the separated-kernel trilinear route is d = 2, FP64, N <= 32");
+    if (p->angles > 4096) return fail(BNQ_EINVAL, "angles must be <= 4096 (got %d)", p->angles);
     if ((p->flags & BNQ_FLAG_WEIGHTS_OTF) && p->precision != BNQ_FP64)
         return fail(BNQ_ENOTSUP, "weights on the fly are an FP64 mode");
     return BNQ_OK;
+}
+
+// workspace of the separated-kernel trilinear route (0 without the flag)
+size_t sep_bytes(const bnq_params *p) {
+    if (!(p->flags & BNQ_FLAG_T1_SEPARATED)) return 0;
+    const size_t N = p->N, M = 2 * N, na = (2 * N - 1) * (2 * N - 1);
+    const int Pn = p->angles > 0 ? p->angles : sep_auto_angles(p->N, kR);
+    int nc, jc, nbj;
+    sep_shape(p->N, Pn, &nc, &jc, &nbj);
+    return sizeof(double) * 2 * Pn * na + sizeof(double2) * (Pn * M * M + M * M + (size_t)Pn * nbj * N * N);
 }
 
 size_t plan_workspace_bytes(const bnq_params *p, int nslots_est) {
@@ -565,7 +587,7 @@ size_t plan_workspace_bytes(const bnq_params *p, int nslots_est) {
     const size_t f32 = p->precision == BNQ_FP32C ? sizeof(float2) * ((size_t)g.nm + nrot * g.next) : 0;
     return c * (6 * (size_t)g.nm + g.neg + nrot * g.next + (size_t)nslots_est * g.nm +
                 (size_t)pair_split(g) * ((size_t)g.neg + g.nm) + (size_t)outer_split(g) * g.nm) +
-           r * 5 * (size_t)g.nm + f32;
+           r * 5 * (size_t)g.nm + f32 + sep_bytes(p);
 }
 
 // Inverse of the Gram matrix of c = (1, v_1..v_d, |v|^2) over the velocity
@@ -844,6 +866,11 @@ void destroy_plan(bnq_plan_s *P) {
     hipFree(P->bdesc);
     hipFree(P->inst_d);
     hipFree(P->qctr);
+    hipFree(P->sep_al);
+    hipFree(P->sep_alp);
+    hipFree(P->sep_gc);
+    hipFree(P->sep_gt);
+    hipFree(P->sep_part);
     for (auto &e : P->evs) {
         hipEventDestroy(e.a);
         hipEventDestroy(e.b);
@@ -871,6 +898,9 @@ struct Exec {
     const Inst *D = nullptr;
     int prec = 0;               // 0 FP64, 1 FP32c
     bool otf = false;           // FP64: pair weights formed on the fly
+    int sepP = 0;               // > 0: trilinear term by the separated-kernel route
+    const double2 *sep_gc = nullptr;
+    double2 *sep_gt = nullptr, *sep_part = nullptr;
     int nq = 0;                 // dynamic schedule: queues (0 = static)
     int *qctr = nullptr;
     std::vector<Inst> Dh;       // host copies of D
@@ -892,6 +922,10 @@ Exec exec_of(bnq_plan_s *P) {
     E.D = P->inst_d;
     E.prec = P->p.precision == BNQ_FP32C ? 1 : 0;
     E.otf = P->otf;
+    E.sepP = P->sepP;
+    E.sep_gc = P->sep_gc;
+    E.sep_gt = P->sep_gt;
+    E.sep_part = P->sep_part;
     E.nq = P->nq;
     E.qctr = P->qctr;
     E.Dh.assign(1, P->ih);
@@ -953,7 +987,16 @@ bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s
             LAUNCHCHK();
         }
     }
-    if (any & BNQ_T_QTRI) {
+    if ((any & BNQ_T_QTRI) && E.sepP) {
+        Span sp(E.timer, 3, s);
+        for (const IOs &io : ios)
+            for (int z = 0; z < io.n; ++z) {
+                const Inst &I = E.Dh[io.inst[z]];
+                if (!(I.terms & BNQ_T_QTRI)) continue;
+                launch_sep_t1(g.N, E.sepP, I.Ghat, E.sep_gc, E.sep_gt, E.sep_part, I.T1, s);
+                LAUNCHCHK();
+            }
+    } else if (any & BNQ_T_QTRI) {
         {
             Span sp(E.timer, 4, s);
             for (const IOs &io : ios) {
@@ -1081,6 +1124,7 @@ void bnq_params_default(bnq_params *p) {
     p->L = 8.0;
     p->schedule = BNQ_SCHED_STATIC;
     p->flags = 0;
+    p->angles = 0;
 }
 
 bnq_status bnq_plan_footprint(const bnq_params *p, size_t *plan_bytes, size_t *table_bytes_out) {
@@ -1168,6 +1212,31 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
          (st = dalloc(&P->Gr32, P->grp.size() * (size_t)g.next, "FP32 rotated spectra")))) {
         destroy_plan(P);
         return st;
+    }
+    if (p->flags & BNQ_FLAG_T1_SEPARATED) {
+        const int N = p->N, M = 2 * N, na = (2 * N - 1) * (2 * N - 1);
+        const int Pn = p->angles > 0 ? p->angles : sep_auto_angles(N, kR);
+        int nc, jc, nbj;
+        sep_shape(N, Pn, &nc, &jc, &nbj);
+        P->sepP = Pn;
+        hipError_t e = sep_prepare();
+        if (e != hipSuccess) {
+            destroy_plan(P);
+            return fail(BNQ_EHIP, "separated route: %s", hipGetErrorString(e));
+        }
+        if ((st = dalloc(&P->sep_al, (size_t)Pn * na, "alpha rows")) ||
+            (st = dalloc(&P->sep_alp, (size_t)Pn * na, "alpha' rows")) ||
+            (st = dalloc(&P->sep_gc, (size_t)Pn * M * M, "alpha transforms")) ||
+            (st = dalloc(&P->sep_gt, (size_t)M * M, "spectrum on the doubled grid")) ||
+            (st = dalloc(&P->sep_part, (size_t)Pn * nbj * N * N, "separated-route partials"))) {
+            destroy_plan(P);
+            return st;
+        }
+        launch_sep_tables(N, Pn, kR, p->C_phi, P->sep_al, P->sep_alp, P->sep_gc, s);
+        if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess) {
+            destroy_plan(P);
+            return fail(BNQ_EHIP, "separated route tables: %s", hipGetErrorString(e));
+        }
     }
     {
         int dev = 0;
@@ -1729,6 +1798,7 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
     HIPCHK(hipGetDevice(&dev));
     for (int i = 0; i < n; ++i) {
         if (!plans[i] || !f[i]) return fail(BNQ_EINVAL, "plan or state %d is NULL", i);
+        if (plans[i]->sepP) return fail(BNQ_ENOTSUP, "plan %d uses the separated-kernel trilinear route", i);
         if (plans[i]->tabs->device != dev) return fail(BNQ_EINVAL, "plan %d lives on another device", i);
         for (int j = 0; j < i; ++j) {
             if (plans[j] == plans[i]) return fail(BNQ_EINVAL, "plan %d appears twice", i);

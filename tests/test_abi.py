@@ -89,7 +89,7 @@ def test_weights_on_the_fly_flag():
     if not os.path.exists(bnq.LIBPATH):
         pytest.skip("libbnq.so not built")
     with pytest.raises(bnq.BnqError) as e:
-        bnq.footprint(bnq.Params(d=2, N=8, L=4.0, flags=2))
+        bnq.footprint(bnq.Params(d=2, N=8, L=4.0, flags=4))
     assert e.value.status == bnq.BNQ_EINVAL
     with pytest.raises(bnq.BnqError) as e:
         bnq.footprint(bnq.Params(d=2, N=8, L=4.0, precision=bnq.FP32C, flags=bnq.FLAG_WEIGHTS_OTF))
@@ -105,3 +105,22 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(bnq, "_lib", None)
     with pytest.raises(RuntimeError):
         bnq.lib()
+
+
+def test_separated_route_flag():
+    # d = 2, FP64, N <= 32 only; its workspace is counted in the plan bytes
+    if not os.path.exists(bnq.LIBPATH):
+        pytest.skip("libbnq.so not built")
+    for kw in (dict(d=3, N=8), dict(d=2, N=34), dict(d=2, N=8, precision=bnq.FP32C)):
+        with pytest.raises(bnq.BnqError) as e:
+            bnq.footprint(bnq.Params(L=4.0, flags=bnq.FLAG_T1_SEPARATED, **kw))
+        assert e.value.status == bnq.BNQ_ENOTSUP
+    for bad in (dict(angles=5), dict(angles=-1, flags=bnq.FLAG_T1_SEPARATED),
+                dict(angles=5000, flags=bnq.FLAG_T1_SEPARATED)):
+        with pytest.raises(bnq.BnqError) as e:
+            bnq.footprint(bnq.Params(d=2, N=8, L=4.0, **bad))
+        assert e.value.status == bnq.BNQ_EINVAL
+    base, _ = bnq.footprint(bnq.Params(d=2, N=32, L=4.0))
+    sep, _ = bnq.footprint(bnq.Params(d=2, N=32, L=4.0, flags=bnq.FLAG_T1_SEPARATED, angles=100))
+    # alpha rows, their transforms, the doubled-grid spectrum and >= 2048 partial arrays
+    assert sep - base >= 8 * 2 * 100 * 63 ** 2 + 16 * (100 * 64 ** 2 + 64 ** 2 + 2048 * 32 ** 2)

@@ -1,0 +1,120 @@
+"""The trilinear term by the separated-kernel transform route on the GPU
+(BNQ_FLAG_T1_SEPARATED; section 'Fast computation of the collision modes',
+eqs. betadD and alphap; appendix 'Fast evaluation of the collision kernel').
+
+With the default angle count the rank-P kernel modes equal the converged
+ones to rounding, so the route is held to the direct oracle at the FP64
+bar; with a small explicit angle count it is held to the oracle's direct sum
+on the oracle's own rank-P table (oracle/separated.py), which checks the
+library's alpha rows against the paper's formulas."""
+import numpy as np
+import pytest
+
+import bnq_inputs as inp
+import oracle
+from oracle import separated as sp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+bnq = pytest.importorskip("paper_2110_13735_amd")
+
+DEV = "cuda:0"
+TOL = 1e-12
+
+
+def _datum(N, seed):
+    rng = np.random.default_rng(seed)
+    f0, L = inp.two_gaussians_2d(N=N, R_v=4.0)
+    return f0 * (1.0 + 0.2 * rng.standard_normal(f0.shape)), L
+
+
+def _t1_gpu(N, f, L, angles=0, flags=None):
+    p = bnq.Params(d=2, N=N, eps=1, L=L, terms=bnq.T_QTRI,
+                   flags=bnq.FLAG_T1_SEPARATED if flags is None else flags, angles=angles)
+    plan = bnq.Plan(p)
+    ft = torch.tensor(f, device=DEV)
+    Q = torch.empty_like(ft)
+    Qh = torch.empty(f.shape, dtype=torch.complex128, device=DEV)
+    plan.collide(ft, Q, Qh)
+    torch.cuda.synchronize()
+    out = Qh.cpu().numpy()  # eps = 1, hbar = 1: Qhat = T1
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("N", [8, 10, 30, 32])
+def test_default_angles_match_the_direct_oracle(N):
+    print(f"separated route, d=2 N={N}", flush=True)
+    f, L = _datum(N, seed=N)
+    G = oracle.dft(f)
+    ref = oracle.galerkin_sums(2, N, G, oracle.beta_table(2, N), want=("t1",))["t1"]
+    got = _t1_gpu(N, f, L)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"  rel err {err:.2e}", flush=True)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("N,angles", [(8, 3), (10, 5), (12, 1)])
+def test_explicit_angles_match_the_rank_p_oracle(N, angles):
+    # a rough datum (every mode populated) and too few angles for the rule
+    # to converge: the rank-P operator differs from the converged one
+    print(f"separated route, d=2 N={N} P={angles}", flush=True)
+    rng = np.random.default_rng(3 * N)
+    f, L = 0.5 + 0.3 * rng.random((N, N)), 3.0
+    G = oracle.dft(f)
+    ref = oracle.galerkin_sums(2, N, G, sp.beta_separated_table(2, N, angles), want=("t1",))["t1"]
+    got = _t1_gpu(N, f, L, angles=angles)
+    assert np.linalg.norm(got - ref) <= TOL * np.linalg.norm(ref)
+    # a coarse rule is a different operator: the converged one is visibly off
+    conv = oracle.galerkin_sums(2, N, G, oracle.beta_table(2, N), want=("t1",))["t1"]
+    assert np.linalg.norm(conv - ref) > 1e-6 * np.linalg.norm(ref)
+
+
+def test_full_operator_with_the_separated_route():
+    N = 16
+    f, L = _datum(N, seed=11)
+    Qo, Qho = oracle.Oracle(2, N).collide(f, -1, L, hbar=0.8)
+    plan = bnq.Plan(bnq.Params(d=2, N=N, eps=-1, L=L, hbar=0.8, flags=bnq.FLAG_T1_SEPARATED))
+    ft = torch.tensor(f, device=DEV)
+    Q = torch.empty_like(ft)
+    plan.collide(ft, Q)
+    # one RK4 step against the direct plan's
+    g1 = ft.clone()
+    plan.step(g1, 0.01)
+    torch.cuda.synchronize()
+    plan.close()
+    assert np.linalg.norm(Q.cpu().numpy() - Qo) <= TOL * np.linalg.norm(Qo)
+    direct = bnq.Plan(bnq.Params(d=2, N=N, eps=-1, L=L, hbar=0.8))
+    g2 = ft.clone()
+    direct.step(g2, 0.01)
+    torch.cuda.synchronize()
+    direct.close()
+    assert torch.max(torch.abs(g1 - g2)).item() <= 1e-13 * torch.max(torch.abs(g2)).item()
+
+
+def test_constant_datum():
+    # f constant: G = f delta_0 and T1 = beta(0,0) G_0^3 at n = 0 only
+    N = 8
+    f = np.full((N, N), 0.3)
+    got = _t1_gpu(N, f, 3.0)
+    b00 = oracle.beta_pairs(2, [[0, 0]], [[0, 0]])[0]
+    ref = np.zeros_like(got)
+    ref[N // 2, N // 2] = b00 * 0.3 ** 3
+    assert np.max(np.abs(got - ref)) <= 1e-13 * abs(ref[N // 2, N // 2])
+
+
+def test_unsupported_configurations_are_refused():
+    for kw in (dict(d=3, N=8), dict(d=2, N=34), dict(d=2, N=8, precision=bnq.FP32C)):
+        with pytest.raises(bnq.BnqError) as ex:
+            bnq.Plan(bnq.Params(eps=1, L=3.0, flags=bnq.FLAG_T1_SEPARATED, **kw))
+        assert ex.value.status == bnq.BNQ_ENOTSUP
+    with pytest.raises(bnq.BnqError) as ex:
+        bnq.Plan(bnq.Params(d=2, N=8, eps=1, L=3.0, angles=5))
+    assert ex.value.status == bnq.BNQ_EINVAL
+    plan = bnq.Plan(bnq.Params(d=2, N=8, eps=1, L=3.0, flags=bnq.FLAG_T1_SEPARATED))
+    f = torch.zeros((8, 8), dtype=torch.float64, device=DEV)
+    with pytest.raises(bnq.BnqError) as ex:
+        bnq.Batch([plan], [f])
+    assert ex.value.status == bnq.BNQ_ENOTSUP
+    plan.close()
