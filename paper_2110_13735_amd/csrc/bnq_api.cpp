@@ -1021,7 +1021,7 @@ bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s
         {
             Span sp(E.timer, 4, s);
             for (const IOs &io : ios) {
-                launch_reduce_partials(g, E.D, io, s);
+                launch_reduce_partials(g, E.D, io, max_slots, s);
                 LAUNCHCHK();
             }
         }

@@ -299,7 +299,7 @@ int t1_pairs_blocks_per_cu();
 int t1_rows_blocks_per_cu();
 int trilinear_blocks_per_cu(int prec);  // resident 64-lane trilinear workgroups per CU (0 on error)
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
-void launch_reduce_partials(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
+void launch_reduce_partials(const Geo &g, const Inst *D, const IOs &io, int max_slots, hipStream_t s);
 void launch_combine(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 void launch_moments_fix(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 

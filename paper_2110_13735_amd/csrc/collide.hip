@@ -687,12 +687,46 @@ void launch_zero_part(const Geo &g, const Inst *D, const IOs &io, int max_slots,
     hipLaunchKernelGGL(zero_part_kernel, dim3(nb, 1, (unsigned)io.n), dim3(256), 0, s, g, D, io);
 }
 
-__global__ void reduce_partials_kernel(Geo g, const Inst *D, IOs io) {
+// Trilinear partial arrays -> T1, in two passes with a fixed order.  Pass 1:
+// a workgroup sums one chunk of consecutive slots for 64 outputs (4 slot
+// phases per output, combined in LDS in phase order) and leaves the sum in
+// the chunk's first slot; pass 2 adds the chunk sums in chunk order.  The
+// chunks spread the slots over enough workgroups to fill the device also
+// when N^d is small.
+constexpr int RP_OUT = 64, RP_PH = 4;
+
+__global__ void __launch_bounds__(RP_OUT * RP_PH) reduce_chunks_kernel(Geo g, const Inst *D, IOs io, int chunk) {
+    const Inst &I = D[io.inst[blockIdx.z]];
+    const int s0 = blockIdx.y * chunk;
+    if (!(I.terms & 4) || s0 >= I.nslots) return;  // uniform over the workgroup
+    const int lane = threadIdx.x % RP_OUT, ph = threadIdx.x / RP_OUT;
+    const int64_t i = (int64_t)blockIdx.x * RP_OUT + lane;
+    const int s1 = min(I.nslots, s0 + chunk);
+    double re = 0.0, im = 0.0;
+    if (i < g.nm)
+        for (int s = s0 + ph; s < s1; s += RP_PH) {
+            const double2 v = ld2(I.part, (int64_t)s * g.nm + i);
+            re += v.x;
+            im += v.y;
+        }
+    __shared__ double2 red[RP_PH][RP_OUT];
+    red[ph][lane] = make_double2(re, im);
+    __syncthreads();
+    if (ph == 0 && i < g.nm) {
+        for (int q = 1; q < RP_PH; ++q) {
+            re += red[q][lane].x;
+            im += red[q][lane].y;
+        }
+        st2(I.part, (int64_t)s0 * g.nm + i, make_double2(re, im));
+    }
+}
+
+__global__ void reduce_final_kernel(Geo g, const Inst *D, IOs io, int chunk) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const Inst &I = D[io.inst[blockIdx.z]];
     if (i >= g.nm || !(I.terms & 4)) return;
     double re = 0.0, im = 0.0;
-    for (int s = 0; s < I.nslots; ++s) {
+    for (int s = 0; s < I.nslots; s += chunk) {
         const double2 v = ld2(I.part, (int64_t)s * g.nm + i);
         re += v.x;
         im += v.y;
@@ -700,8 +734,16 @@ __global__ void reduce_partials_kernel(Geo g, const Inst *D, IOs io) {
     st2(I.T1, i, make_double2(re, im));
 }
 
-void launch_reduce_partials(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_partials_kernel, grid_nm(g, io), dim3(256), 0, s, g, D, io);
+void launch_reduce_partials(const Geo &g, const Inst *D, const IOs &io, int max_slots, hipStream_t s) {
+    if (max_slots < 1) return;
+    const int64_t bx = (g.nm + RP_OUT - 1) / RP_OUT;
+    const int64_t want = std::max<int64_t>(1, (1024 + bx - 1) / bx);  // chunks for >= 1024 workgroups
+    const int nch = (int)std::min<int64_t>(want, std::max(1, max_slots / (2 * RP_PH)));
+    const int chunk = (max_slots + nch - 1) / nch;
+    const int ny = (max_slots + chunk - 1) / chunk;
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)bx, (unsigned)ny, (unsigned)io.n), dim3(RP_OUT * RP_PH), 0,
+                       s, g, D, io, chunk);
+    hipLaunchKernelGGL(reduce_final_kernel, grid_nm(g, io), dim3(256), 0, s, g, D, io, chunk);
 }
 
 // Qhat = [Qc] - alpha ([T1] + [X]) with the selected terms; optionally the

@@ -171,21 +171,33 @@ __global__ __launch_bounds__(256) void moments_part_kernel(Geo g, const double *
     if (threadIdx.x < MOM_FIELDS) part[(int64_t)blockIdx.x * MOM_FIELDS + threadIdx.x] = red[0][threadIdx.x];
 }
 
-__global__ void moments_final_kernel(int nblk, const double *part, double *out) {
-    const int k = threadIdx.x;
-    if (k >= MOM_FIELDS) return;
-    double a = k == 6 ? -INFINITY : (k == 7 ? INFINITY : 0.0);
-    for (int b = 0; b < nblk; ++b) {
-        const double v = part[(int64_t)b * MOM_FIELDS + k];
-        a = k == 6 ? fmax(a, v) : (k == 7 ? fmin(a, v) : a + v);
+// Field k of the per-block partials: sums, except the maximum (k = 6) and
+// minimum (k = 7) of f; a fixed tree over 256 threads per field.
+__device__ __forceinline__ double mom_op(int k, double a, double b) {
+    return k == 6 ? fmax(a, b) : (k == 7 ? fmin(a, b) : a + b);
+}
+
+__global__ void __launch_bounds__(256) moments_final_kernel(int nblk, const double *part, double *out) {
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    for (int k = 0; k < MOM_FIELDS; ++k) {
+        double a = k == 6 ? -INFINITY : (k == 7 ? INFINITY : 0.0);
+        for (int b = t; b < nblk; b += 256) a = mom_op(k, a, part[(int64_t)b * MOM_FIELDS + k]);
+        red[t] = a;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (t < w) red[t] = mom_op(k, red[t], red[t + w]);
+            __syncthreads();
+        }
+        if (t == 0) out[k] = red[0];
+        __syncthreads();
     }
-    out[k] = a;
 }
 
 void launch_moments(const Geo &g, const double *f, double L, double alpha, double *part, int nblk, double *out,
                     hipStream_t s) {
     hipLaunchKernelGGL(moments_part_kernel, dim3(nblk), dim3(256), 0, s, g, f, L, alpha, part);
-    hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(64), 0, s, nblk, part, out);
+    hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(256), 0, s, nblk, part, out);
 }
 
 // ---------------------------------------------------------------------------
