@@ -103,10 +103,11 @@ typedef struct {
                            at different rates; the summation order, hence the last
                            bits, may change from run to run) */
     int32_t flags;      /* BNQ_FLAG_* bits, default 0 */
-    int32_t angles;     /* BNQ_FLAG_T1_SEPARATED only: the angle count P of the
-                           rank-P kernel modes (eq. alphap), 1..4096; 0 (default)
-                           = enough angles to reproduce the converged kernel
-                           modes to rounding */
+    int32_t angles;     /* BNQ_FLAG_T1_SEPARATED only: d = 2, the angle count P of
+                           eq. alphap, 1..4096, 0 (default) = enough angles to
+                           reproduce the converged kernel modes to rounding;
+                           d = 3, the polar count M1 of eq. alphapprime (M2 =
+                           2 M1 azimuthal), 1..64, required */
 } bnq_params;
 
 /* FP64 only: the pair sums form their weights w_c, w_q from the kernel-mode
@@ -118,18 +119,24 @@ typedef struct {
  * flops per weight instead of 16 bytes of HBM traffic. */
 #define BNQ_FLAG_WEIGHTS_OTF 1
 
-/* d = 2, FP64, N <= 32: the trilinear term Q_{1,q} is evaluated by the
- * transform route of the appendix 'Fast evaluation of the collision kernel'
- * with the rank-P kernel modes of section 'Fast computation of the collision
- * modes' (eqs. betadD, alphap): beta(a,b) = (pi/P) sum_p alpha_p(a)
- * alpha'_p(b) over the angles theta_p = p pi / P.  The spectrum is extended
- * by zeros to the doubled grid (2N)^2, on which the route gives the linear
- * Galerkin sum; with the default angle count it equals the direct trilinear
- * sum to rounding.  It costs about 6 N^3 P (2N)^2 complex multiply-adds per
- * evaluation (1.3e12 flops at N = 32, against 4.8e9 for the direct sum).
- * The other terms keep the converged kernel-mode tables.  Plans with this
- * flag are refused by bnq_batch_create (ENOTSUP).  Other d, precisions or
- * N: ENOTSUP. */
+/* FP64, d = 2 with N <= 32 or d = 3 with N <= 8: the trilinear term Q_{1,q}
+ * is evaluated by the transform route of the appendix 'Fast evaluation of
+ * the collision kernel' with the rank-P kernel modes of section 'Fast
+ * computation of the collision modes' (eq. betadD): beta(a,b) = C sum_r
+ * alpha_r(a) alpha'_r(b) over P directions.
+ *   d = 2 (eq. alphap): P = angles, theta_p = p pi / P, C = pi / P.  With the
+ *     default angle count the rule reproduces the converged kernel modes to
+ *     rounding and the route equals the direct trilinear sum.
+ *   d = 3 (eq. alphapprime): M1 = angles polar and M2 = 2 angles azimuthal
+ *     directions, P = M1 M2, C = pi^2 / P; angles is required (1..64).  The
+ *     polar rule converges at second order, so this is the rank-P operator of
+ *     that rule, not the converged one.
+ * The spectrum is extended by zeros to the doubled grid (2N)^d, on which the
+ * route gives the linear Galerkin sum.  It costs about P (2N)^d transforms
+ * of size (2N)^d -> N^d per evaluation (1.2e12 flops at d = 2, N = 32,
+ * against 1.9e9 for the direct sum).  The other terms keep the converged
+ * kernel-mode tables.  Plans with this flag are refused by bnq_batch_create
+ * (ENOTSUP).  Other precisions or sizes: ENOTSUP. */
 #define BNQ_FLAG_T1_SEPARATED 2
 
 #define BNQ_SCHED_STATIC 0

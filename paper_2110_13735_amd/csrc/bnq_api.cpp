@@ -562,9 +562,12 @@ bnq_status validate(const bnq_params *p) {
     if (p->angles < 0) return fail(BNQ_EINVAL, "angles must be >= 0 (got %d)", p->angles);
     if (p->angles > 0 && !(p->flags & BNQ_FLAG_T1_SEPARATED))
         return fail(BNQ_EINVAL, "angles is read only with BNQ_FLAG_T1_SEPARATED");
-    if ((p->flags & BNQ_FLAG_T1_SEPARATED) && (p->d != 2 || p->precision != BNQ_FP64 || !sep_supported(p->N)))
-        return fail(BNQ_ENOTSUP, "the separated-kernel trilinear route is d = 2, FP64, N <= 32");
-    if (p->angles > 4096) return fail(BNQ_EINVAL, "angles must be <= 4096 (got %d)", p->angles);
+    if ((p->flags & BNQ_FLAG_T1_SEPARATED) && (p->precision != BNQ_FP64 || !sep_supported(p->d, p->N)))
+        return fail(BNQ_ENOTSUP, "the separated-kernel trilinear route is FP64, d = 2 with N <= 32 or d = 3 with N <= 8");
+    if (p->angles > (p->d == 2 ? 4096 : 64))
+        return fail(BNQ_EINVAL, "angles must be <= %d in %d-D (got %d)", p->d == 2 ? 4096 : 64, p->d, p->angles);
+    if ((p->flags & BNQ_FLAG_T1_SEPARATED) && p->d == 3 && p->angles == 0)
+        return fail(BNQ_EINVAL, "the 3-D separated route needs an explicit angle count");
     if ((p->flags & BNQ_FLAG_WEIGHTS_OTF) && p->precision != BNQ_FP64)
         return fail(BNQ_ENOTSUP, "weights on the fly are an FP64 mode");
     return BNQ_OK;
@@ -573,11 +576,13 @@ bnq_status validate(const bnq_params *p) {
 // workspace of the separated-kernel trilinear route (0 without the flag)
 size_t sep_bytes(const bnq_params *p) {
     if (!(p->flags & BNQ_FLAG_T1_SEPARATED)) return 0;
-    const size_t N = p->N, M = 2 * N, na = (2 * N - 1) * (2 * N - 1);
-    const int Pn = p->angles > 0 ? p->angles : sep_auto_angles(p->N, kR);
+    const size_t N = p->N, M = 2 * N, w = 2 * N - 1;
+    const size_t na = p->d == 2 ? w * w : w * w * w, Md = p->d == 2 ? M * M : M * M * M,
+                 Nd = p->d == 2 ? N * N : N * N * N;
+    const int Pn = sep_directions(p->d, p->angles > 0 ? p->angles : sep_auto_angles(p->N, kR));
     int nc, jc, nbj;
-    sep_shape(p->N, Pn, &nc, &jc, &nbj);
-    return sizeof(double) * 2 * Pn * na + sizeof(double2) * (Pn * M * M + M * M + (size_t)Pn * nbj * N * N);
+    sep_shape(p->d, p->N, Pn, &nc, &jc, &nbj);
+    return sizeof(double) * 2 * Pn * na + sizeof(double2) * (Pn * Md + Md + (size_t)Pn * nbj * Nd);
 }
 
 size_t plan_workspace_bytes(const bnq_params *p, int nslots_est) {
@@ -993,7 +998,7 @@ bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s
             for (int z = 0; z < io.n; ++z) {
                 const Inst &I = E.Dh[io.inst[z]];
                 if (!(I.terms & BNQ_T_QTRI)) continue;
-                launch_sep_t1(g.N, E.sepP, I.Ghat, E.sep_gc, E.sep_gt, E.sep_part, I.T1, s);
+                launch_sep_t1(g.d, g.N, E.sepP, I.Ghat, E.sep_gc, E.sep_gt, E.sep_part, I.T1, s);
                 LAUNCHCHK();
             }
     } else if (any & BNQ_T_QTRI) {
@@ -1214,10 +1219,13 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         return st;
     }
     if (p->flags & BNQ_FLAG_T1_SEPARATED) {
-        const int N = p->N, M = 2 * N, na = (2 * N - 1) * (2 * N - 1);
-        const int Pn = p->angles > 0 ? p->angles : sep_auto_angles(N, kR);
+        const int N = p->N, M = 2 * N, w = 2 * N - 1, d = p->d;
+        const size_t na = d == 2 ? (size_t)w * w : (size_t)w * w * w, Md = d == 2 ? (size_t)M * M : (size_t)M * M * M,
+                     Nd = d == 2 ? (size_t)N * N : (size_t)N * N * N;
+        const int angles = p->angles > 0 ? p->angles : sep_auto_angles(N, kR);
+        const int Pn = sep_directions(d, angles);
         int nc, jc, nbj;
-        sep_shape(N, Pn, &nc, &jc, &nbj);
+        sep_shape(d, N, Pn, &nc, &jc, &nbj);
         P->sepP = Pn;
         hipError_t e = sep_prepare();
         if (e != hipSuccess) {
@@ -1226,13 +1234,13 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         }
         if ((st = dalloc(&P->sep_al, (size_t)Pn * na, "alpha rows")) ||
             (st = dalloc(&P->sep_alp, (size_t)Pn * na, "alpha' rows")) ||
-            (st = dalloc(&P->sep_gc, (size_t)Pn * M * M, "alpha transforms")) ||
-            (st = dalloc(&P->sep_gt, (size_t)M * M, "spectrum on the doubled grid")) ||
-            (st = dalloc(&P->sep_part, (size_t)Pn * nbj * N * N, "separated-route partials"))) {
+            (st = dalloc(&P->sep_gc, (size_t)Pn * Md, "alpha transforms")) ||
+            (st = dalloc(&P->sep_gt, Md, "spectrum on the doubled grid")) ||
+            (st = dalloc(&P->sep_part, (size_t)Pn * nbj * Nd, "separated-route partials"))) {
             destroy_plan(P);
             return st;
         }
-        launch_sep_tables(N, Pn, kR, p->C_phi, P->sep_al, P->sep_alp, P->sep_gc, s);
+        launch_sep_tables(d, N, angles, kR, p->C_phi, P->sep_al, P->sep_alp, P->sep_gc, s);
         if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess) {
             destroy_plan(P);
             return fail(BNQ_EHIP, "separated route tables: %s", hipGetErrorString(e));

@@ -257,13 +257,15 @@ void launch_weights(const Geo &g, const Radial &rad, float *wc, float *wq, hipSt
 void launch_gather(const double *base, const int64_t *idx, int64_t n, double *out, hipStream_t s);
 void launch_gather(const float *base, const int64_t *idx, int64_t n, double *out, hipStream_t s);
 // trilinear term by the separated-kernel transform route, d = 2 (t1_separated.hip)
-bool sep_supported(int N);
+bool sep_supported(int d, int N);
 int sep_auto_angles(int N, double R);
-void sep_shape(int N, int P, int *nc, int *jc, int *nbj);
+int sep_directions(int d, int angles);  // P: the angle count in 2-D, M1 M2 = 2 angles^2 in 3-D
+void sep_shape(int d, int N, int P, int *nc, int *jc, int *nbj);
 hipError_t sep_prepare();
-void launch_sep_tables(int N, int P, double R, double Cphi, double *al, double *alp, double2 *gc, hipStream_t s);
-void launch_sep_t1(int N, int P, const double2 *Ghat, const double2 *gc, double2 *gt, double2 *part, double2 *T1,
-                   hipStream_t s);
+void launch_sep_tables(int d, int N, int angles, double R, double Cphi, double *al, double *alp, double2 *gc,
+                       hipStream_t s);
+void launch_sep_t1(int d, int N, int P, const double2 *Ghat, const double2 *gc, double2 *gt, double2 *part,
+                   double2 *T1, hipStream_t s);
 void launch_beta_diag(const Radial &rad, int qmax, double *out, hipStream_t s);
 void launch_pair_weights_at(const Geo &g, const Radial &rad, const int64_t *idx, int64_t n, int which, double *out,
                             hipStream_t s);

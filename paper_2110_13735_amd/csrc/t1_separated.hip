@@ -227,57 +227,309 @@ __global__ void sep_reduce_kernel(int nparts, int nm, double scale, const double
     T1[i] = make_double2(scale * re, scale * im);
 }
 
+// ---------------------------------------------------------------- d = 3
+// Directions e_r = (sin t_p cos f_q, sin t_p sin f_q, cos t_p), t_p = p pi / M1,
+// f_q = q pi / M2, r = q + M2 p (eq. alphapprime), C = pi^2 / (M1 M2):
+//   alpha_r(a)  = 4 C_phi sin t_p phi3(a . e_r),   phi3(s) = int_{-R}^{R} |r| e^{i r s} dr,
+//   alpha'_r(b) = psi(|b - (b . e_r) e_r|),        psi(s)  = int_0^pi phi3(s cos t) dt
+//                                                          = 2 pi R J_1(R s) / s.
+__device__ double sep_phi3(double R, double s) {
+    const double x = R * s;
+    if (fabs(x) < 0.05) {
+        // 2 R^2 sum_k (-1)^k x^{2k} / ((2k)! (2k + 2))
+        const double x2 = x * x;
+        return 2.0 * R * R * (0.5 - x2 / 8.0 + x2 * x2 / 144.0 - x2 * x2 * x2 / 5760.0);
+    }
+    const double h = sin(0.5 * x);
+    return 2.0 * R * R * (sin(x) / x - 2.0 * h * h / (x * x));
+}
+
+__device__ double sep_psi3(double R, double s) {
+    const double x = R * s;
+    if (fabs(x) < 1e-3) {
+        const double x2 = x * x;
+        return M_PI * R * R * (1.0 - x2 / 8.0 + x2 * x2 / 192.0);
+    }
+    return 2.0 * M_PI * R * R * j1(x) / x;
+}
+
+__global__ void sep_alpha3_kernel(int N, int M1, int M2, double R, double Cphi, double *al, double *alp) {
+    const int w = 2 * N - 1, na = w * w * w;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y, p = r / M2, q = r % M2;
+    if (i >= na) return;
+    const double a0 = (double)(i / (w * w) - (N - 1)), a1 = (double)((i / w) % w - (N - 1)),
+                 a2 = (double)(i % w - (N - 1));
+    double st, ct, sf, cf;
+    sincospi((double)p / M1, &st, &ct);
+    sincospi((double)q / M2, &sf, &cf);
+    const double e0 = st * cf, e1 = st * sf, e2 = ct;
+    const double pr = a0 * e0 + a1 * e1 + a2 * e2;
+    const double perp = sqrt(fmax(a0 * a0 + a1 * a1 + a2 * a2 - pr * pr, 0.0));
+    al[(int64_t)r * na + i] = 4.0 * Cphi * st * sep_phi3(R, pr);
+    alp[(int64_t)r * na + i] = sep_psi3(R, perp);
+}
+
+// gc[r][y] over y in [0, M)^3 row-major
+__global__ void sep_gc3_kernel(int N, int M, const double *al, const double *alp, double2 *gc) {
+    extern __shared__ double sh[];
+    const int w = 2 * N - 1, na = w * w * w;
+    double *sa = sh, *sb = sh + na, *cs = sh + 2 * na;
+    const int r = blockIdx.y;
+    for (int i = threadIdx.x; i < na; i += blockDim.x) {
+        sa[i] = al[(int64_t)r * na + i];
+        sb[i] = alp[(int64_t)r * na + i];
+    }
+    for (int t = threadIdx.x; t < M; t += blockDim.x) cs[t] = cospi(2.0 * t / M);
+    __syncthreads();
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= M * M * M) return;
+    const int y0 = y / (M * M), y1 = (y / M) % M, y2 = y % M;
+    double ga = 0.0, gb = 0.0;
+    for (int i0 = 0; i0 < w; ++i0)
+        for (int i1 = 0; i1 < w; ++i1) {
+            int t = pmod((i0 - (N - 1)) * y0 + (i1 - (N - 1)) * y1 - (N - 1) * y2, M);
+            const double *ra = sa + (i0 * w + i1) * w, *rb = sb + (i0 * w + i1) * w;
+            for (int i2 = 0; i2 < w; ++i2) {
+                const double c = cs[t];
+                ga += ra[i2] * c;
+                gb += rb[i2] * c;
+                t += y2;
+                if (t >= M) t -= M;
+            }
+        }
+    gc[(int64_t)r * M * M * M + y] = make_double2(ga, gb);
+}
+
+// Gt[x] = sum_{k in I_N} G_k e^{2 pi i k.x/M}, x in [0, M)^3 row-major
+__global__ void sep_gt3_kernel(int N, int M, const double2 *__restrict__ G, double2 *gt) {
+    extern __shared__ double2 tw[];
+    for (int t = threadIdx.x; t < M; t += blockDim.x) {
+        double sn, c;
+        sincospi(2.0 * t / M, &sn, &c);
+        tw[t] = make_double2(c, sn);
+    }
+    __syncthreads();
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= M * M * M) return;
+    const int x0 = x / (M * M), x1 = (x / M) % M, x2 = x % M, h = N / 2;
+    double re = 0.0, im = 0.0;
+    for (int k0 = 0; k0 < N; ++k0)
+        for (int k1 = 0; k1 < N; ++k1) {
+            int t = pmod((k0 - h) * x0 + (k1 - h) * x1 - h * x2, M);
+            for (int k2 = 0; k2 < N; ++k2) {
+                const double2 g = G[(k0 * N + k1) * N + k2], e = tw[t];
+                re += g.x * e.x - g.y * e.y;
+                im += g.x * e.y + g.y * e.x;
+                t += x2;
+                if (t >= M) t -= M;
+            }
+        }
+    gt[x] = make_double2(re, im);
+}
+
+// As sep_t1_kernel, with three passes: x0 -> n0 (in rounds of nc rows n0),
+// x1 -> n1, then x2 -> n2 and the product.
+constexpr int SEP3_T1MAX = 512;  // nc M^2
+constexpr int SEP3_T2MAX = 256;  // nc N M
+
+__global__ void __launch_bounds__(SEP_THREADS)
+sep_t1_3_kernel(int N, int M, int nc, int jc, const double2 *__restrict__ gc, const double2 *__restrict__ gt,
+                double2 *part) {
+    extern __shared__ double2 sm[];
+    const int MM = M * M, M3 = MM * M;
+    double2 *sG = sm, *sC = sm + M3, *sAA = sm + 2 * M3, *sAB = sAA + SEP3_T1MAX, *sBA = sAB + SEP3_T1MAX,
+            *sBB = sBA + SEP3_T2MAX, *sW = sBB + SEP3_T2MAX;
+    const int r = blockIdx.y, tid = threadIdx.x, h = N / 2;
+    for (int i = tid; i < M3; i += SEP_THREADS) {
+        sG[i] = gt[i];
+        sC[i] = gc[(int64_t)r * M3 + i];
+    }
+    for (int t = tid; t < M; t += SEP_THREADS) {
+        double sn, c;
+        sincospi(2.0 * t / M, &sn, &c);
+        sW[t] = make_double2(c, -sn);
+    }
+    __syncthreads();
+    const int rounds = (N + nc - 1) / nc;
+    double2 acc[SEP_ROUNDS];
+#pragma unroll
+    for (int k = 0; k < SEP_ROUNDS; ++k) acc[k] = make_double2(0.0, 0.0);
+    const int jlo = blockIdx.x * jc, jhi = min(M3, jlo + jc);
+    for (int j = jlo; j < jhi; ++j) {
+        const int j0 = j / MM, j1 = (j / M) % M, j2 = j % M;
+        const double2 gj = sG[j];
+#pragma unroll
+        for (int k = 0; k < SEP_ROUNDS; ++k) {
+            if (k < rounds) {
+                const int n0b = k * nc, ncr = min(nc, N - n0b);
+                // x0 -> n0: T1[n0l][x1][x2]
+                for (int o = tid; o < ncr * MM; o += SEP_THREADS) {
+                    const int x2 = o % M, x1 = (o / M) % M, n0l = o / MM;
+                    const int nm = pmod(n0b + n0l - h, M);
+                    const int v = pmod(x1 - j1, M) * M + pmod(x2 - j2, M);
+                    int u = pmod(-j0, M), t = 0;
+                    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+                    for (int x0 = 0; x0 < M; ++x0) {
+                        const double2 c = sC[u * MM + v], g = sG[x0 * MM + x1 * M + x2], e = sW[t];
+                        const double2 ge = cmul(g, e);
+                        ar += c.x * ge.x;
+                        ai += c.x * ge.y;
+                        br += c.y * ge.x;
+                        bi += c.y * ge.y;
+                        if (++u == M) u = 0;
+                        t += nm;
+                        if (t >= M) t -= M;
+                    }
+                    sAA[o] = make_double2(ar, ai);
+                    sAB[o] = make_double2(br, bi);
+                }
+                __syncthreads();
+                // x1 -> n1: T2[n0l][n1][x2]
+                if (tid < ncr * N * M) {
+                    const int x2 = tid % M, n1s = (tid / M) % N, n0l = tid / (M * N);
+                    const int nm = pmod(n1s - h, M);
+                    double2 A = make_double2(0.0, 0.0), B = make_double2(0.0, 0.0);
+                    int t = 0;
+                    for (int x1 = 0; x1 < M; ++x1) {
+                        const double2 e = sW[t];
+                        const double2 a = cmul(sAA[(n0l * M + x1) * M + x2], e),
+                                      b = cmul(sAB[(n0l * M + x1) * M + x2], e);
+                        A.x += a.x;
+                        A.y += a.y;
+                        B.x += b.x;
+                        B.y += b.y;
+                        t += nm;
+                        if (t >= M) t -= M;
+                    }
+                    sBA[tid] = A;
+                    sBB[tid] = B;
+                }
+                __syncthreads();
+                // x2 -> n2 and the product: one (n0, n1, n2) per thread
+                if (tid < ncr * N * N) {
+                    const int n2s = tid % N, n1s = (tid / N) % N, n0l = tid / (N * N);
+                    const int n2 = n2s - h, n1 = n1s - h, n0 = n0b + n0l - h;
+                    const int nm = pmod(n2, M);
+                    double2 A = make_double2(0.0, 0.0), B = make_double2(0.0, 0.0);
+                    int t = 0;
+                    for (int x2 = 0; x2 < M; ++x2) {
+                        const double2 e = sW[t];
+                        const double2 a = cmul(sBA[(n0l * N + n1s) * M + x2], e),
+                                      b = cmul(sBB[(n0l * N + n1s) * M + x2], e);
+                        A.x += a.x;
+                        A.y += a.y;
+                        B.x += b.x;
+                        B.y += b.y;
+                        t += nm;
+                        if (t >= M) t -= M;
+                    }
+                    const double2 wj = sW[pmod(n0 * j0 + n1 * j1 + n2 * j2, M)];
+                    const double2 q = cmul(cmul(gj, make_double2(wj.x, -wj.y)), cmul(A, B));
+                    acc[k].x += q.x;
+                    acc[k].y += q.y;
+                }
+                __syncthreads();
+            }
+        }
+    }
+    const int NN = N * N;
+    const int64_t base = ((int64_t)r * gridDim.x + blockIdx.x) * NN * N;
+#pragma unroll
+    for (int k = 0; k < SEP_ROUNDS; ++k) {
+        if (k < rounds) {
+            const int n0b = k * nc, ncr = min(nc, N - n0b);
+            if (tid < ncr * NN) part[base + (int64_t)n0b * NN + tid] = acc[k];
+        }
+    }
+}
+
 }  // namespace
 
-size_t sep_t1_lds_bytes(int M) { return sizeof(double2) * (2 * (size_t)M * M + 2 * SEP_TMAX + M); }
+size_t sep_t1_lds_bytes(int d, int M) {
+    return d == 2 ? sizeof(double2) * (2 * (size_t)M * M + 2 * SEP_TMAX + M)
+                  : sizeof(double2) * (2 * (size_t)M * M * M + 2 * SEP3_T1MAX + 2 * SEP3_T2MAX + M);
+}
 
-void sep_shape(int N, int P, int *nc, int *jc, int *nbj) {
-    const int M = 2 * N, MM = M * M;
-    *nc = std::min(N, SEP_THREADS / N);
-    const int want = std::max(1, (2048 + P - 1) / P);  // blocks per angle
-    *jc = (MM + want - 1) / want;
-    *nbj = (MM + *jc - 1) / *jc;
+int sep_directions(int d, int angles) { return d == 2 ? angles : 2 * angles * angles; }
+
+void sep_shape(int d, int N, int P, int *nc, int *jc, int *nbj) {
+    const int M = 2 * N, Md = d == 2 ? M * M : M * M * M;
+    *nc = d == 2 ? std::min(N, SEP_THREADS / N) : std::min(N, SEP3_T1MAX / (M * M));
+    const int want = std::max(1, (2048 + P - 1) / P);  // blocks per direction
+    *jc = (Md + want - 1) / want;
+    *nbj = (Md + *jc - 1) / *jc;
 }
 
 // Angles at which the half-period rectangle rule reproduces beta(a, b) to
 // rounding for every a, b in (-N, N)^2: the angular integrand has the
 // spectrum of e^{i x cos(.)} with x <= R (|a| + |b|) < 2 sqrt(2) R N, whose
 // Bessel coefficients are negligible past order x + 12 x^(1/3) + 24, and the
-// rule integrates every order below 2P exactly.
+// rule integrates every order below 2P exactly.  (The 3-D polar rule
+// converges at second order only: there the caller chooses the count.)
 int sep_auto_angles(int N, double R) {
     const double x = 2.0 * std::sqrt(2.0) * R * N;
     return (int)std::ceil(0.5 * x + 6.0 * std::cbrt(x)) + 12;
 }
 
-bool sep_supported(int N) {
-    if (N < 2 || N > 32 || (N & 1)) return false;
-    int nc = std::min(N, SEP_THREADS / N);
-    return 2 * N * nc <= SEP_TMAX && (N + nc - 1) / nc <= SEP_ROUNDS && sep_t1_lds_bytes(2 * N) <= 160 * 1024;
-}
-
-void launch_sep_tables(int N, int P, double R, double Cphi, double *al, double *alp, double2 *gc, hipStream_t s) {
-    const int w = 2 * N - 1, na = w * w, M = 2 * N;
-    hipLaunchKernelGGL(sep_alpha_kernel, dim3((na + 255) / 256, P), dim3(256), 0, s, N, P, R, Cphi, al, alp);
-    const size_t lds = sizeof(double) * (2 * (size_t)na + M);
-    hipLaunchKernelGGL(sep_gc_kernel, dim3((M * M + 255) / 256, P), dim3(256), lds, s, N, M, al, alp, gc);
-}
-
-void launch_sep_t1(int N, int P, const double2 *Ghat, const double2 *gc, double2 *gt, double2 *part, double2 *T1,
-                   hipStream_t s) {
+bool sep_supported(int d, int N) {
+    if (N < 2 || (N & 1)) return false;
     const int M = 2 * N;
     int nc, jc, nbj;
-    sep_shape(N, P, &nc, &jc, &nbj);
-    hipLaunchKernelGGL(sep_gt_kernel, dim3((M * M + 255) / 256), dim3(256), sizeof(double2) * M, s, N, M, Ghat, gt);
-    hipLaunchKernelGGL(sep_t1_kernel, dim3(nbj, P), dim3(SEP_THREADS), sep_t1_lds_bytes(M), s, N, M, nc, jc, gc, gt,
-                       part);
+    sep_shape(d, N, 1, &nc, &jc, &nbj);
+    if (nc < 1 || (N + nc - 1) / nc > SEP_ROUNDS || sep_t1_lds_bytes(d, M) > 160 * 1024) return false;
+    if (d == 2) return N <= 32 && M * nc <= SEP_TMAX && nc * N <= SEP_THREADS;
+    return d == 3 && N <= 8 && nc * M * M <= SEP3_T1MAX && nc * N * M <= SEP3_T2MAX && nc * N * M <= SEP_THREADS &&
+           nc * N * N <= SEP_THREADS;
+}
+
+void launch_sep_tables(int d, int N, int angles, double R, double Cphi, double *al, double *alp, double2 *gc,
+                       hipStream_t s) {
+    const int w = 2 * N - 1, M = 2 * N;
+    if (d == 2) {
+        const int na = w * w, P = angles;
+        hipLaunchKernelGGL(sep_alpha_kernel, dim3((na + 255) / 256, P), dim3(256), 0, s, N, P, R, Cphi, al, alp);
+        const size_t lds = sizeof(double) * (2 * (size_t)na + M);
+        hipLaunchKernelGGL(sep_gc_kernel, dim3((M * M + 255) / 256, P), dim3(256), lds, s, N, M, al, alp, gc);
+        return;
+    }
+    const int na = w * w * w, M1 = angles, M2 = 2 * angles, P = M1 * M2;
+    hipLaunchKernelGGL(sep_alpha3_kernel, dim3((na + 255) / 256, P), dim3(256), 0, s, N, M1, M2, R, Cphi, al, alp);
+    const size_t lds = sizeof(double) * (2 * (size_t)na + M);
+    hipLaunchKernelGGL(sep_gc3_kernel, dim3((M * M * M + 255) / 256, P), dim3(256), lds, s, N, M, al, alp, gc);
+}
+
+void launch_sep_t1(int d, int N, int P, const double2 *Ghat, const double2 *gc, double2 *gt, double2 *part,
+                   double2 *T1, hipStream_t s) {
+    const int M = 2 * N;
+    int nc, jc, nbj;
+    sep_shape(d, N, P, &nc, &jc, &nbj);
     const double M2 = (double)M * M;
-    const double scale = M_PI / P / (M2 * M2 * M2);
-    hipLaunchKernelGGL(sep_reduce_kernel, dim3((N * N + 255) / 256), dim3(256), 0, s, nbj * P, N * N, scale, part, T1);
+    if (d == 2) {
+        hipLaunchKernelGGL(sep_gt_kernel, dim3((M * M + 255) / 256), dim3(256), sizeof(double2) * M, s, N, M, Ghat,
+                           gt);
+        hipLaunchKernelGGL(sep_t1_kernel, dim3(nbj, P), dim3(SEP_THREADS), sep_t1_lds_bytes(2, M), s, N, M, nc, jc,
+                           gc, gt, part);
+        const double scale = M_PI / P / (M2 * M2 * M2);  // C M^-3d, C = pi / P
+        hipLaunchKernelGGL(sep_reduce_kernel, dim3((N * N + 255) / 256), dim3(256), 0, s, nbj * P, N * N, scale, part,
+                           T1);
+        return;
+    }
+    const int M3 = M * M * M, N3 = N * N * N;
+    hipLaunchKernelGGL(sep_gt3_kernel, dim3((M3 + 255) / 256), dim3(256), sizeof(double2) * M, s, N, M, Ghat, gt);
+    hipLaunchKernelGGL(sep_t1_3_kernel, dim3(nbj, P), dim3(SEP_THREADS), sep_t1_lds_bytes(3, M), s, N, M, nc, jc, gc,
+                       gt, part);
+    double scale = M_PI * M_PI / P;  // C M^-3d, C = pi^2 / (M1 M2) = pi^2 / P
+    for (int k = 0; k < 9; ++k) scale /= M;
+    hipLaunchKernelGGL(sep_reduce_kernel, dim3((N3 + 255) / 256), dim3(256), 0, s, nbj * P, N3, scale, part, T1);
 }
 
 hipError_t sep_prepare() {
-    return hipFuncSetAttribute((const void *)sep_t1_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)sep_t1_lds_bytes(64));
+    hipError_t e = hipFuncSetAttribute((const void *)sep_t1_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)sep_t1_lds_bytes(2, 64));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)sep_t1_3_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)sep_t1_lds_bytes(3, 16));
 }
 
 }  // namespace bnq

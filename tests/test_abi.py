@@ -108,13 +108,20 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
 
 
 def test_separated_route_flag():
-    # d = 2, FP64, N <= 32 only; its workspace is counted in the plan bytes
+    # FP64, d = 2 with N <= 32 or d = 3 with N <= 8; its workspace is counted in the plan bytes
     if not os.path.exists(bnq.LIBPATH):
         pytest.skip("libbnq.so not built")
-    for kw in (dict(d=3, N=8), dict(d=2, N=34), dict(d=2, N=8, precision=bnq.FP32C)):
+    for kw in (dict(d=3, N=10, angles=2), dict(d=2, N=34), dict(d=2, N=8, precision=bnq.FP32C)):
         with pytest.raises(bnq.BnqError) as e:
             bnq.footprint(bnq.Params(L=4.0, flags=bnq.FLAG_T1_SEPARATED, **kw))
         assert e.value.status == bnq.BNQ_ENOTSUP
+    with pytest.raises(bnq.BnqError) as e:  # 3-D needs an explicit angle count, at most 64
+        bnq.footprint(bnq.Params(d=3, N=8, L=4.0, flags=bnq.FLAG_T1_SEPARATED))
+    assert e.value.status == bnq.BNQ_EINVAL
+    with pytest.raises(bnq.BnqError) as e:
+        bnq.footprint(bnq.Params(d=3, N=8, L=4.0, flags=bnq.FLAG_T1_SEPARATED, angles=65))
+    assert e.value.status == bnq.BNQ_EINVAL
+    bnq.footprint(bnq.Params(d=3, N=8, L=4.0, flags=bnq.FLAG_T1_SEPARATED, angles=64))
     for bad in (dict(angles=5), dict(angles=-1, flags=bnq.FLAG_T1_SEPARATED),
                 dict(angles=5000, flags=bnq.FLAG_T1_SEPARATED)):
         with pytest.raises(bnq.BnqError) as e:

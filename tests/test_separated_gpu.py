@@ -71,6 +71,43 @@ def test_explicit_angles_match_the_rank_p_oracle(N, angles):
     assert np.linalg.norm(conv - ref) > 1e-6 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("N,angles", [(4, 2), (6, 3), (8, 2)])
+def test_3d_matches_the_rank_p_oracle(N, angles):
+    # eq. alphapprime with M1 = angles polar and M2 = 2 angles azimuthal
+    # directions: held to the oracle's direct sum on its own rank-P table
+    print(f"separated route, d=3 N={N} M1={angles}", flush=True)
+    rng = np.random.default_rng(5 * N)
+    f, L = 0.5 + 0.3 * rng.random((N, N, N)), 3.0
+    G = oracle.dft(f)
+    table = sp.beta_separated_table(3, N, (angles, 2 * angles), Cphi=1.3)
+    ref = oracle.galerkin_sums(3, N, G, table, want=("t1",))["t1"]
+    p = bnq.Params(d=3, N=N, eps=1, L=L, C_phi=1.3, terms=bnq.T_QTRI, flags=bnq.FLAG_T1_SEPARATED, angles=angles)
+    plan = bnq.Plan(p)
+    Qh = torch.empty((N,) * 3, dtype=torch.complex128, device=DEV)
+    plan.collide(torch.tensor(f, device=DEV), torch.empty((N,) * 3, dtype=torch.float64, device=DEV), Qh)
+    torch.cuda.synchronize()
+    plan.close()
+    err = np.linalg.norm(Qh.cpu().numpy() - ref) / np.linalg.norm(ref)
+    print(f"  rel err {err:.2e}", flush=True)
+    assert err <= TOL
+
+
+def test_collision_constant_enters_once():
+    # beta is linear in C_phi, and only alpha carries it
+    N, Cphi = 10, 1.7
+    rng = np.random.default_rng(7)
+    f, L = 0.5 + 0.3 * rng.random((N, N)), 3.0
+    G = oracle.dft(f)
+    ref = oracle.galerkin_sums(2, N, G, oracle.beta_table(2, N, Cphi=Cphi), want=("t1",))["t1"]
+    p = bnq.Params(d=2, N=N, eps=1, L=L, C_phi=Cphi, terms=bnq.T_QTRI, flags=bnq.FLAG_T1_SEPARATED)
+    plan = bnq.Plan(p)
+    Qh = torch.empty((N, N), dtype=torch.complex128, device=DEV)
+    plan.collide(torch.tensor(f, device=DEV), torch.empty((N, N), dtype=torch.float64, device=DEV), Qh)
+    torch.cuda.synchronize()
+    plan.close()
+    assert np.linalg.norm(Qh.cpu().numpy() - ref) <= TOL * np.linalg.norm(ref)
+
+
 def test_full_operator_with_the_separated_route():
     N = 16
     f, L = _datum(N, seed=11)
@@ -105,10 +142,13 @@ def test_constant_datum():
 
 
 def test_unsupported_configurations_are_refused():
-    for kw in (dict(d=3, N=8), dict(d=2, N=34), dict(d=2, N=8, precision=bnq.FP32C)):
+    for kw in (dict(d=3, N=10, angles=2), dict(d=2, N=34), dict(d=2, N=8, precision=bnq.FP32C)):
         with pytest.raises(bnq.BnqError) as ex:
             bnq.Plan(bnq.Params(eps=1, L=3.0, flags=bnq.FLAG_T1_SEPARATED, **kw))
         assert ex.value.status == bnq.BNQ_ENOTSUP
+    with pytest.raises(bnq.BnqError) as ex:  # 3-D: no default angle count
+        bnq.Plan(bnq.Params(d=3, N=8, eps=1, L=3.0, flags=bnq.FLAG_T1_SEPARATED))
+    assert ex.value.status == bnq.BNQ_EINVAL
     with pytest.raises(bnq.BnqError) as ex:
         bnq.Plan(bnq.Params(d=2, N=8, eps=1, L=3.0, angles=5))
     assert ex.value.status == bnq.BNQ_EINVAL
