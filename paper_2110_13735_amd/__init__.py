@@ -59,7 +59,7 @@ class Params:
     precision: int = FP64
     schedule: int = 0  # SCHED_STATIC
     flags: int = 0  # FLAG_*
-    angles: int = 0  # FLAG_T1_SEPARATED: angle count P (0 = enough for FP64)
+    angles: int = 0  # FLAG_T1_SEPARATED: 2-D angle count P (0 = enough for FP64); 3-D polar count M1 (required)
 
     def _c(self) -> _Params:
         return _Params(self.d, self.N, self.eps, self.precision, self.terms, self.correction,

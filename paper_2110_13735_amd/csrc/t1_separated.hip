@@ -1,6 +1,8 @@
-// Trilinear term by the separated-kernel transform route, d = 2 (section
-// 'Fast computation of the collision modes', eqs. betadD and alphap; appendix
-// 'Fast evaluation of the collision kernel').
+// Trilinear term by the separated-kernel transform route (section 'Fast
+// computation of the collision modes', eqs. betadD, alphap and alphapprime;
+// appendix 'Fast evaluation of the collision kernel').  Written out below for
+// d = 2; the d = 3 kernels further down follow the same steps over (2N)^3
+// with the directions of eq. alphapprime.
 //
 // With the kernel modes written as the rank-P sum
 //   beta(a, b) = C sum_p alpha_p(a) alpha'_p(b),   C = pi / P,  theta_p = p pi / P,
@@ -17,7 +19,7 @@
 //
 // Work: every (p, j) needs two M x M -> N x N transforms, done as DFTs by
 // matrix along each axis: 6 N^3 complex multiply-adds, P (2N)^2 times.  At
-// N = 32 that is about 1.3e12 flops per evaluation against 4.8e9 for the
+// N = 32 that is about 1.2e12 flops per evaluation against 1.9e9 for the
 // direct trilinear sum: the route is kept for what it computes, not for speed.
 #include "bnq_internal.h"
 
@@ -121,7 +123,8 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 // nc <= 256 / N rows so that each thread owns at most one (n0, n1) per
 // round (SEP_ROUNDS rounds at most); its sums over the block's shifts stay
 // in registers and are written once to the block's partial array.
-constexpr int SEP_THREADS = 256;
+constexpr int SEP_THREADS = 512;  // two waves per SIMD over the one workgroup an LDS-full CU holds
+constexpr int SEP_OUT = 256;      // bound on the outputs of one round (nc N in 2-D)
 constexpr int SEP_ROUNDS = 4;
 constexpr int SEP_TMAX = 512;  // M * nc
 
@@ -455,7 +458,7 @@ int sep_directions(int d, int angles) { return d == 2 ? angles : 2 * angles * an
 
 void sep_shape(int d, int N, int P, int *nc, int *jc, int *nbj) {
     const int M = 2 * N, Md = d == 2 ? M * M : M * M * M;
-    *nc = d == 2 ? std::min(N, SEP_THREADS / N) : std::min(N, SEP3_T1MAX / (M * M));
+    *nc = d == 2 ? std::min(N, SEP_OUT / N) : std::min(N, SEP3_T1MAX / (M * M));
     const int want = std::max(1, (2048 + P - 1) / P);  // blocks per direction
     *jc = (Md + want - 1) / want;
     *nbj = (Md + *jc - 1) / *jc;
@@ -478,7 +481,7 @@ bool sep_supported(int d, int N) {
     int nc, jc, nbj;
     sep_shape(d, N, 1, &nc, &jc, &nbj);
     if (nc < 1 || (N + nc - 1) / nc > SEP_ROUNDS || sep_t1_lds_bytes(d, M) > 160 * 1024) return false;
-    if (d == 2) return N <= 32 && M * nc <= SEP_TMAX && nc * N <= SEP_THREADS;
+    if (d == 2) return N <= 32 && M * nc <= SEP_TMAX && nc * N <= SEP_OUT;
     return d == 3 && N <= 8 && nc * M * M <= SEP3_T1MAX && nc * N * M <= SEP3_T2MAX && nc * N * M <= SEP_THREADS &&
            nc * N * N <= SEP_THREADS;
 }
