@@ -6,6 +6,7 @@ them, brute-force quadrature of the physical-space operator, conservation,
 exact solutions and the fugacities printed in the table captions.
 """
 import math
+import os
 
 import mpmath as mp
 import numpy as np
@@ -265,8 +266,18 @@ def test_quantum_maxwellian_residual_decays():
 
 
 # ---------------------------------------------------------------- fixtures
+def _golden_fugacities():
+    rows = []
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "spectral_accuracy_fugacities.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            label, d, stat, rho, sigma, z = line.split()
+            rows.append((label, int(d), stat == "FD", float(rho), float(sigma), z))
+    return rows
+
+
 def test_printed_fugacities_2d():
-    # captions of Tables 1-4: 2-D, hbar = 3, rho = 1, T = sigma.
+    # captions of the 2-D tables: hbar = 3, rho = 1, T = sigma, in closed form
     # FD: rho |alpha| / (2 pi T) = ln(1 + z);  BE: = -ln(1 - z).
     alpha = 9.0
     fd = lambda T: math.exp(alpha / (2 * math.pi * T)) - 1
@@ -275,6 +286,28 @@ def test_printed_fugacities_2d():
     assert fd(1.0) == pytest.approx(3.1887, abs=5e-4)
     assert be(0.5) == pytest.approx(0.943, abs=5e-4)
     assert be(1.0) == pytest.approx(0.7613, abs=5e-4)
+
+
+@pytest.mark.parametrize("row", _golden_fugacities(), ids=lambda r: r[0])
+def test_printed_fugacities_from_the_oracle_integrals(row):
+    # every caption's z from rho = (2 pi T)^(d/2) K_{d/2}(z) / |alpha|,
+    # |alpha| = hbar^d (eq. mom0_qmaxwell), with the oracle's quadrature of
+    # K_nu and a bracketing root finder, to half a unit of the last digit
+    from scipy import optimize
+    from oracle import equilibrium as oe
+    label, d, fermi, rho, T, zs = row
+    target = rho * 3.0 ** d / (2 * math.pi * T) ** (d / 2)
+    f = lambda lz: oe.K(d / 2, fermi, log_z=lz) - target
+    hi = 10.0 if fermi else -1e-12
+    lz = optimize.brentq(f, -30.0, hi, xtol=1e-15, rtol=1e-15)
+    mant = zs.split("e")[0]
+    ulp = 10.0 ** (-(len(mant.split(".")[1]))) * (10.0 ** int(zs.split("e")[1]) if "e" in zs else 1.0)
+    z = math.exp(lz)
+    if label == "spectral_accuracy_fermions_3d_sigma1":
+        # the one caption that does not reproduce: 3.09965 against 3.09922
+        assert abs(z - 3.09965) < 5e-6 and abs(z - float(zs)) > 4e-4
+    else:
+        assert abs(z - float(zs)) <= 0.5 * ulp + 1e-12, (z, zs)
 
 
 def test_moments_of_gaussian():
