@@ -120,26 +120,36 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 // One block per (chunk of shifts j, angle p).  LDS holds Gt and (gc_p, gc'_p)
 // over the doubled grid, the first-axis transforms of one round of output
 // rows and the twiddles w^t = e^{-2 pi i t/M}.  Outputs n0 go in rounds of
-// nc <= 256 / N rows so that each thread owns at most one (n0, n1) per
-// round (SEP_ROUNDS rounds at most); its sums over the block's shifts stay
-// in registers and are written once to the block's partial array.
-constexpr int SEP_THREADS = 512;  // two waves per SIMD over the one workgroup an LDS-full CU holds
+// nc <= 256 / N rows so that each thread (2-D: each lane pair) owns at most
+// one (n0, n1) per round (SEP_ROUNDS rounds at most); its sums over the
+// block's shifts stay in registers and are written once to the block's
+// partial array.
+constexpr int SEP_THREADS = 512;  // 3-D: two waves per SIMD over the one workgroup an LDS-full CU holds
 constexpr int SEP_OUT = 256;      // bound on the outputs of one round (nc N in 2-D)
 constexpr int SEP_ROUNDS = 4;
 constexpr int SEP_TMAX = 512;  // M * nc
 
-__global__ void __launch_bounds__(SEP_THREADS)
+// 2-D: 16 waves; the sums of one output are split over the lanes l and
+// l ^ 32 of a wave (one half of the transform axis each) and combined by a
+// cross-lane exchange, so that the one workgroup an LDS-full CU holds still
+// keeps four waves per SIMD.
+constexpr int SEP2_THREADS = 1024;
+
+__global__ void __launch_bounds__(SEP2_THREADS)
 sep_t1_kernel(int N, int M, int nc, int jc, const double2 *__restrict__ gc, const double2 *__restrict__ gt,
               double2 *part) {
     extern __shared__ double2 sm[];
     const int MM = M * M;
     double2 *sG = sm, *sC = sm + MM, *sTA = sm + 2 * MM, *sTB = sTA + SEP_TMAX, *sW = sTB + SEP_TMAX;
     const int p = blockIdx.y, tid = threadIdx.x, h = N / 2;
-    for (int i = tid; i < MM; i += SEP_THREADS) {
+    const int lane = tid & 63, half = lane >> 5;
+    const int slot = (tid >> 6) * 32 + (lane & 31);  // output slot, shared by lanes l and l ^ 32
+    const int xlo = half * N;                         // this lane's half of the axis: [xlo, xlo + N)
+    for (int i = tid; i < MM; i += SEP2_THREADS) {
         sG[i] = gt[i];
         sC[i] = gc[(int64_t)p * MM + i];
     }
-    for (int t = tid; t < M; t += SEP_THREADS) {
+    for (int t = tid; t < M; t += SEP2_THREADS) {
         double sn, c;
         sincospi(2.0 * t / M, &sn, &c);
         sW[t] = make_double2(c, -sn);
@@ -158,13 +168,13 @@ sep_t1_kernel(int N, int M, int nc, int jc, const double2 *__restrict__ gc, cons
             if (r < rounds) {
                 const int n0b = r * nc, ncr = min(nc, N - n0b);
                 // first axis: T[x1][n0l] = sum_x0 gc(x0 - j0, x1 - j1) Gt(x0, x1) w^{n0 x0}
-                for (int o = tid; o < M * ncr; o += SEP_THREADS) {
+                for (int o = slot; o < M * ncr; o += SEP2_THREADS / 2) {
                     const int x1 = o % M, n0l = o / M;
                     const int nm = pmod(n0b + n0l - h, M);
                     const int v = pmod(x1 - j1, M);
-                    int u = pmod(-j0, M), t = 0;
+                    int u = pmod(xlo - j0, M), t = (nm * xlo) % M;
                     double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-                    for (int x0 = 0; x0 < M; ++x0) {
+                    for (int x0 = xlo; x0 < xlo + N; ++x0) {
                         const double2 c = sC[u * M + v], g = sG[x0 * M + x1], e = sW[t];
                         const double2 ge = cmul(g, e);
                         ar += c.x * ge.x;
@@ -175,18 +185,24 @@ sep_t1_kernel(int N, int M, int nc, int jc, const double2 *__restrict__ gc, cons
                         t += nm;
                         if (t >= M) t -= M;
                     }
-                    sTA[x1 * nc + n0l] = make_double2(ar, ai);
-                    sTB[x1 * nc + n0l] = make_double2(br, bi);
+                    ar += __shfl_xor(ar, 32);
+                    ai += __shfl_xor(ai, 32);
+                    br += __shfl_xor(br, 32);
+                    bi += __shfl_xor(bi, 32);
+                    if (half == 0) {
+                        sTA[x1 * nc + n0l] = make_double2(ar, ai);
+                        sTB[x1 * nc + n0l] = make_double2(br, bi);
+                    }
                 }
                 __syncthreads();
-                // second axis and the product: one (n0, n1) per thread
-                if (tid < ncr * N) {
-                    const int n1s = tid % N, n0l = tid / N;
+                // second axis and the product: one (n0, n1) per lane pair
+                if (slot < ncr * N) {
+                    const int n1s = slot % N, n0l = slot / N;
                     const int n1 = n1s - h, n0 = n0b + n0l - h;
                     const int nm = pmod(n1, M);
                     double2 A = make_double2(0.0, 0.0), B = make_double2(0.0, 0.0);
-                    int t = 0;
-                    for (int x1 = 0; x1 < M; ++x1) {
+                    int t = (nm * xlo) % M;
+                    for (int x1 = xlo; x1 < xlo + N; ++x1) {
                         const double2 e = sW[t];
                         const double2 a = cmul(sTA[x1 * nc + n0l], e), b = cmul(sTB[x1 * nc + n0l], e);
                         A.x += a.x;
@@ -196,12 +212,18 @@ sep_t1_kernel(int N, int M, int nc, int jc, const double2 *__restrict__ gc, cons
                         t += nm;
                         if (t >= M) t -= M;
                     }
-                    // Gt_j e^{+2 pi i n.j/M} = Gt_j conj(w^{n.j})
-                    const double2 wj = sW[pmod(n0 * j0 + n1 * j1, M)];
-                    const double2 ej = cmul(gj, make_double2(wj.x, -wj.y));
-                    const double2 q = cmul(ej, cmul(A, B));
-                    acc[r].x += q.x;
-                    acc[r].y += q.y;
+                    A.x += __shfl_xor(A.x, 32);
+                    A.y += __shfl_xor(A.y, 32);
+                    B.x += __shfl_xor(B.x, 32);
+                    B.y += __shfl_xor(B.y, 32);
+                    if (half == 0) {
+                        // Gt_j e^{+2 pi i n.j/M} = Gt_j conj(w^{n.j})
+                        const double2 wj = sW[pmod(n0 * j0 + n1 * j1, M)];
+                        const double2 ej = cmul(gj, make_double2(wj.x, -wj.y));
+                        const double2 q = cmul(ej, cmul(A, B));
+                        acc[r].x += q.x;
+                        acc[r].y += q.y;
+                    }
                 }
                 __syncthreads();
             }
@@ -212,7 +234,7 @@ sep_t1_kernel(int N, int M, int nc, int jc, const double2 *__restrict__ gc, cons
     for (int r = 0; r < SEP_ROUNDS; ++r) {
         if (r < rounds) {
             const int n0b = r * nc, ncr = min(nc, N - n0b);
-            if (tid < ncr * N) part[base + (int64_t)(n0b + tid / N) * N + tid % N] = acc[r];
+            if (half == 0 && slot < ncr * N) part[base + (int64_t)(n0b + slot / N) * N + slot % N] = acc[r];
         }
     }
 }
@@ -511,7 +533,7 @@ void launch_sep_t1(int d, int N, int P, const double2 *Ghat, const double2 *gc, 
     if (d == 2) {
         hipLaunchKernelGGL(sep_gt_kernel, dim3((M * M + 255) / 256), dim3(256), sizeof(double2) * M, s, N, M, Ghat,
                            gt);
-        hipLaunchKernelGGL(sep_t1_kernel, dim3(nbj, P), dim3(SEP_THREADS), sep_t1_lds_bytes(2, M), s, N, M, nc, jc,
+        hipLaunchKernelGGL(sep_t1_kernel, dim3(nbj, P), dim3(SEP2_THREADS), sep_t1_lds_bytes(2, M), s, N, M, nc, jc,
                            gc, gt, part);
         const double scale = M_PI / P / (M2 * M2 * M2);  // C M^-3d, C = pi / P
         hipLaunchKernelGGL(sep_reduce_kernel, dim3((N * N + 255) / 256), dim3(256), 0, s, nbj * P, N * N, scale, part,
