@@ -398,7 +398,7 @@ static inline cplx cget(const double *G, int64_t i) {
 #define BT(a0, a1, a2, b0, b1, b2) (btab[xidx(g, a0, a1, a2) * g->xsize + xidx(g, b0, b1, b2)])
 
 /* Classical sum for one output mode n (gain_only: the Q1c term alone,
- * sum beta(l,m) G_l G_m, the scale against which cancellation is judged). */
+ * sum beta(l,m) G_l G_m, the scale against which cancellation is measured). */
 static cplx classical_mode(const geom_t *g, const double *G, const double *btab, const int *n, int gain_only) {
     cplx acc = {0.0, 0.0};
     for (int l0 = g->lo[0]; l0 <= g->hi[0]; ++l0)
