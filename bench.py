@@ -99,8 +99,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=32)
     ap.add_argument("--dt", type=float, default=None,
-                    help="time step (default 0.01; c3 and relax: 0.001, since those trajectories leave RK4's "
-                         "stability region at dt = 0.01)")
+                    help="time step (default 0.001 for the 3-D workloads c2, c3 and relax, whose data leave RK4's "
+                         "stability region at dt = 0.01; 0.01 for c1, batch and serve)")
     ap.add_argument("--precision", choices=("fp64", "fp32c"), default="fp64")
     ap.add_argument("--eps", type=int, choices=(-1, 0, 1), default=-1,
                     help="statistics: -1 fermions (default, the trilinear-bound workload), +1 bosons, "
@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--instances", type=int, default=60, help="batch workload: number of instances")
     ap.add_argument("--cells", choices=("mixed", "small"), default="mixed", help="batch workload: cell set")
     ap.add_argument("--rate", type=float, default=10.0, help="serve workload: mean arrivals per second")
+    ap.add_argument("--no-sub", action="store_true",
+                    help="c2: skip the short FP32c, classical (eps = 0) and serving sub-runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one 1 GiB device copy (read 1 GiB, write 1 GiB) so that a "
                          "counter run can calibrate FETCH_SIZE / WRITE_SIZE")
@@ -142,7 +144,7 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     if args.dt is None:
-        args.dt = 0.001 if args.workload in ("c3", "relax") else 0.01
+        args.dt = 0.001 if args.workload in ("c2", "c3", "relax") else 0.01
     if args.workload == "batch":
         return run_batch(args)
     if args.workload == "serve":
@@ -171,8 +173,10 @@ def main():
     stream = torch.cuda.current_stream()
 
     def one_step():
+        # raises (and the bench exits non-zero) when a step's health flags or
+        # the moments report a non-finite state or a fermion value >= 1
         plan.step(f, args.dt, bnq.RK4)
-        return plan.moments(f, check=False)
+        return plan.moments(f, check=True)
 
     for _ in range(args.warmup):
         one_step()
@@ -244,7 +248,9 @@ def main():
         "dtype": "f32c" if prec == bnq.FP32C else "f64",
         "data": "synthetic",
         "config": {"workload": f"3-D {STATS[eps]} eps={eps}, N={N}^3, {args.precision.upper()}, hard spheres, hbar=1, L=8, "
-                               f"three-Gaussian f0 (seed 0), RK4 dt={args.dt}, moments every step",
+                               f"three-Gaussian f0 (seed 0), RK4 dt={args.dt}, moments every step (dt=0.001: the "
+                               f"datum's loss rate ~1e3 puts dt=0.01 outside RK4's stability region; the work per "
+                               f"step does not depend on dt)",
                    "d": 3, "N": N, "eps": eps, "precision": args.precision, "schedule": args.schedule,
                    "scheme": "rk4", "dt": args.dt,
                    "terms_per_eval": terms_eval, "evals_per_step": 4,
@@ -253,10 +259,120 @@ def main():
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kt.items()},
         "moments_last": {k: mom[k] for k in ("rho", "e", "H", "fmax")},
     }
+    if eps == -1 and not args.no_sub:
+        # short runs of the other figures the metric names, same datum and dt
+        out["sub"] = {"fp32c": sub_fp32c(args, plan, f0, terms_eval),
+                      "eps0": sub_eps0(args, f0),
+                      "latency": sub_latency()}
+    plan.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_N)
-    plan.close()
     print(json.dumps(out))
+
+
+def sub_fp32c(args, plan64, f0, terms_eval, steps=3):
+    """The c2 step in FP32c (FP32 spectra, tables and short sums, FP64 long
+    sums, FP64 state) with the mass correction: terms/s, the trilinear
+    kernel's fraction of the FP32 peak, the error of Qhat against the FP64
+    plan on the initial state, and the mass drift over the steps."""
+    import torch
+    import paper_2110_13735_amd as bnq
+
+    dev = torch.device("cuda:0")
+    p = bnq.Params(d=3, N=args.N, eps=-1, L=8.0, precision=bnq.FP32C, correction=bnq.CORR_MASS,
+                   schedule=bnq.SCHED_DYNAMIC if args.schedule == "dynamic" else bnq.SCHED_STATIC)
+    plan = bnq.Plan(p)
+    f = torch.tensor(f0, device=dev)
+    Q = torch.empty_like(f)
+    Qh32 = torch.empty(f.shape, dtype=torch.complex128, device=dev)
+    Qh64 = torch.empty_like(Qh32)
+    plan.collide(f, Q, Qh32)
+    plan64.collide(f, Q, Qh64)
+    torch.cuda.synchronize()
+    qerr = (torch.linalg.norm(Qh32 - Qh64) / torch.linalg.norm(Qh64)).item()
+    rho0 = plan.moments(f)["rho"]
+    g = f.clone()
+    plan.step(g, args.dt, bnq.RK4)  # warm-up on a copy
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    drift = 0.0
+    elapsed = 0.0
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step(f, args.dt, bnq.RK4)
+        m = plan.moments(f, check=True)
+        elapsed += time.perf_counter() - t0
+        drift = max(drift, abs(m["rho"] - rho0) / rho0)
+    kt = plan.timing()
+    plan.set_timing(False)
+    plan.close()
+    t1_ms, t1_n = kt["trilinear"]
+    t1_avg_s = t1_ms / (4 * steps) * 1e-3
+    tf = plan64.counts()["trilinear"] * FLOPS_PER_T1_TERM / t1_avg_s / 1e12
+    return {"value": 4.0 * terms_eval * steps / elapsed, "unit": "pair-terms/s", "steps": steps,
+            "ms_per_step": 1e3 * elapsed / steps, "correction": "mass",
+            "trilinear_avg_ms": round(t1_avg_s * 1e3, 3), "trilinear_tflops": round(tf, 3),
+            "trilinear_frac_of_fp32_peak": round(tf * 1e12 / PEAK_FP32_VALU, 4),
+            "qhat_rel_err_vs_fp64": qerr, "mass_drift_max": drift}
+
+
+def sub_eps0(args, f0, steps=10):
+    """The classical operator (eps = 0) on the same datum, FP64 and FP32c:
+    only the pair sums over the classical weight table, an HBM-bound stream;
+    roofline of pairs_kernel from its algorithmic bytes (one weight per
+    classical pair)."""
+    import torch
+    import paper_2110_13735_amd as bnq
+
+    dev = torch.device("cuda:0")
+    res = {}
+    for name, prec in (("fp64", bnq.FP64), ("fp32c", bnq.FP32C)):
+        p = bnq.Params(d=3, N=args.N, eps=0, L=8.0, precision=prec)
+        plan = bnq.Plan(p)
+        terms = bnq.terms_per_eval(p, plan.counts())
+        f = torch.tensor(f0, device=dev)
+        for _ in range(2):
+            plan.step(f, args.dt, bnq.RK4)
+        torch.cuda.synchronize()
+        plan.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.step(f, args.dt, bnq.RK4)
+        plan.moments(f, check=True)
+        elapsed = time.perf_counter() - t0
+        kt = plan.timing()
+        plan.set_timing(False)
+        pr_ms, pr_n = kt["pairs"]
+        pr_s = pr_ms / pr_n * 1e-3
+        nbytes = plan.counts()["classical"] * (4 if prec == bnq.FP32C else 8)
+        gbs = nbytes / pr_s / 1e9
+        res[name] = {"value": 4.0 * terms * steps / elapsed, "unit": "pair-terms/s", "steps": steps,
+                     "ms_per_step": 1e3 * elapsed / steps,
+                     "roofline": {"bound": "hbm", "kernel": "pairs_kernel", "avg_ms": round(pr_s * 1e3, 4),
+                                  "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                  "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": nbytes}}
+        plan.close()
+    return res
+
+
+def sub_latency(n=40, rate=20.0):
+    """A short serving run: Poisson arrivals of 3-D requests, N in {8, 12, 16}
+    (weights 4:3:2), eps +-1, t_end ~ U[0.05, 0.2] at dt = 0.01: p50/p99
+    latency from arrival to completion."""
+    from paper_2110_13735_amd import serve
+    import bnq_inputs as inp
+
+    reqs = serve.poisson_requests(n, rate=rate, seed=0, cells=[((3, 8), 4), ((3, 12), 3), ((3, 16), 2)],
+                                  t_end=(0.05, 0.2))
+    srv = serve.Server(lambda r: inp.mixed_instance(r.d, r.N, r.eps, r.seed), budget_bytes=int(64e9), dt=0.01)
+    try:
+        st = srv.run(reqs)
+    finally:
+        srv.close()
+    return {"requests": n, "rate_per_s": rate, "p50_latency_s": st["p50_latency_s"],
+            "p99_latency_s": st["p99_latency_s"], "served_terms_per_s": st["terms_per_s"],
+            "completed": st.get("completed"), "failed": st.get("failed")}
 
 
 def measured_peaks(torch, dev):

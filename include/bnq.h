@@ -148,7 +148,12 @@ void bnq_params_default(bnq_params *p);
 
 /* Build a plan: validates *p, attaches the kernel-mode tables shared by
  * every plan with the same (d, N, C_phi), and allocates the plan's workspace
- * on the current device.  The tables of the plan's precision are built on
+ * on the current device.  The tables are the kernel modes beta(k,l) of the
+ * Lemma of section 'Fast spectral approximation of the BNE operator' (the
+ * integral over B(0,R)^2 of Btilde delta(z.y) e^{i(z.k + y.l)}), on the
+ * arguments the sums of bnq_collide read: the pair weights
+ * beta(l,m) - beta(m,m) and beta(l,m) - beta(l+m,l) - beta(l,l+m) for l, m in
+ * I_N, and beta(a,b) for the trilinear term, a, b in {-(N-1) .. N-1}^d.  The tables of the plan's precision are built on
  * first use: every value is computed in FP64 on the device and stored in
  * FP64 (BNQ_FP64) or rounded to FP32 (BNQ_FP32C), so an FP32c plan never
  * needs the FP64 tables (at 3-D N = 48 they take 364 GB, the FP32 ones
@@ -172,14 +177,44 @@ bnq_status bnq_plan_footprint(const bnq_params *p, size_t *plan_bytes, size_t *t
 /* Q = c (L/pi)^(d+gamma) Re IDFT(Qhat) for the grid distribution f (the right
  * hand side of the semi-discrete equation).  If Qhat is non-NULL the
  * Galerkin modes Qhat_n (before the prefactor) are also written.  f and Q
- * must not alias.  Errors: EINVAL (null f or Q), EHIP. */
+ * must not alias.  Defined by: G_k, step 2(a) of section 'Numerical scheme for
+ * the velocity rescaled BNE' (normalisation N^-d); Qhat_n, the Fourier modes
+ * of the six Carleman terms in the Lemma of section 'Fast spectral
+ * approximation of the BNE operator', assembled with the signs of section
+ * 'The Carleman representation' (Q = Q+c - Q-c - alpha (Q1q + Q2q - Q3q -
+ * Q4q)); the prefactor, the classical method of section 'Application to the
+ * space homogeneous BNE' (lambda = 0, omega = 1, mu = (L/pi)^d).
+ * Errors: EINVAL (null f or Q), EHIP. */
 bnq_status bnq_collide(bnq_plan_t plan, const double *f, double *Q, void *Qhat, bnq_stream_t stream);
 
 /* Advance f (in place) by one step of size dt of d f/dt = c (L/pi)^(d+gamma) Q(f)
- * with scheme BNQ_RK4 (classical fourth order), BNQ_SSPRK2 (Shu–Osher second
- * order) or BNQ_EULER, state and stage arithmetic in FP64.  Errors: EINVAL,
- * EHIP. */
+ * (the semi-discrete equation of the classical method, section 'Application
+ * to the space homogeneous BNE'; the forward Euler scheme of section
+ * 'Numerical scheme for the velocity rescaled BNE' with lambda = 0, its
+ * second-order Runge-Kutta remark, and the strong-stability-preserving RK2
+ * of the relaxation experiments of section 'Trends to equilibrium') with
+ * scheme BNQ_RK4 (classical fourth order), BNQ_SSPRK2 (Shu–Osher second
+ * order) or BNQ_EULER, state and stage arithmetic in FP64.
+ * Health: the kernel that writes the new state records, in the plan's health
+ * flags (host-visible memory, no host synchronisation), whether it wrote a
+ * non-finite value (BNQ_HEALTH_NONFINITE) or, for fermions (eps = -1), a
+ * value f >= 1/|alpha| (BNQ_HEALTH_BOUND).  bnq_step reads the flags before
+ * enqueuing: once a step that set them has completed on the device, every
+ * later bnq_step returns ENONFINITE (or EBOUND) and enqueues nothing, so f
+ * keeps the state that step wrote.  bnq_health() reads (optionally waiting
+ * for the stream) and clears them.
+ * Errors: EINVAL, EHIP, ENONFINITE, EBOUND. */
 bnq_status bnq_step(bnq_plan_t plan, double *f, double dt, int32_t scheme, bnq_stream_t stream);
+
+#define BNQ_HEALTH_NONFINITE 1
+#define BNQ_HEALTH_BOUND 2
+/* Health flags of the plan's steps (bnq_step, and bnq_batch_step for a plan
+ * in a batch): *flags_host (optional) <- BNQ_HEALTH_* bits recorded by the
+ * steps that have completed; wait != 0 first synchronises `stream`, so that
+ * every step enqueued on it is included; clear != 0 resets the flags
+ * afterwards.  Returns ENONFINITE or EBOUND when the flags are set (before
+ * clearing), else OK.  Errors: EINVAL, EHIP. */
+bnq_status bnq_health(bnq_plan_t plan, int32_t wait, int32_t clear, int32_t *flags_host, bnq_stream_t stream);
 
 /* Discrete moments (section 'Numerical results' diagnostics, classical method), written to the
  * host array out_host[BNQ_MOMENTS_LEN] in this order:
@@ -193,6 +228,7 @@ bnq_status bnq_step(bnq_plan_t plan, double *f, double dt, int32_t scheme, bnq_s
  * Inf, EBOUND if eps = -1 and max f >= 1/|alpha| (moments still written). */
 #define BNQ_MOMENTS_LEN 10
 bnq_status bnq_moments(bnq_plan_t plan, const double *f, double *out_host, bnq_stream_t stream);
+
 
 /* ---- limit states (section 'Convergence towards a steady state') --------
  * The state a solution relaxes to, for given mass rho, mean velocity u and
@@ -360,7 +396,11 @@ bnq_status bnq_plan_autotune(bnq_plan_t plan, const double *f, int32_t reps, dou
  * bnq_batch_collide(): Q[i] <- operator of f[i] (as bnq_collide), Qhat[i]
  *   optional (Qhat may be NULL, or hold NULL entries).
  * bnq_batch_step(): advances every f[i] in place by dt[i] (host array of n)
- *   with scheme (as bnq_step).  use_graph != 0 captures the whole step into a
+ *   with scheme (as bnq_step).  Each member's health flags are recorded as
+ *   by bnq_step (read them with bnq_health on the member's plan); if a
+ *   member's flags are set by a completed step, the call returns ENONFINITE
+ *   or EBOUND (the message names the member) and enqueues nothing: the
+ *   caller removes that member (a new batch) and steps the others on.  use_graph != 0 captures the whole step into a
  *   HIP graph on the first call and replays it while (scheme, dt, stream)
  *   are unchanged (a change recaptures); it needs a non-default stream.
  * bnq_batch_destroy(): waits for the batch's work and frees its arrays (not

@@ -26,6 +26,7 @@ SCHED_STATIC, SCHED_DYNAMIC = 0, 1
 CORR_NONE, CORR_MASS, CORR_MOMENTS = 0, 1, 2
 RK4, EULER, SSPRK2 = 0, 1, 2
 MOMENTS_LEN = 10
+HEALTH_NONFINITE, HEALTH_BOUND = 1, 2
 NKERNELS = 8
 KERNEL_FAMILIES = ("dft", "pairs", "outer", "trilinear", "reduce", "combine", "step", "moments")
 MOMENT_NAMES = ("rho", "u0", "u1", "u2", "Ec", "e", "H", "fmax", "fmin", "n_excluded")
@@ -131,6 +132,7 @@ def lib():
         L.bnq_collide.argtypes = [vp, vp, vp, vp, vp]
         L.bnq_step.argtypes = [vp, vp, f64, i32, vp]
         L.bnq_moments.argtypes = [vp, vp, vp, vp]
+        L.bnq_health.argtypes = [vp, i32, i32, vp, vp]
         L.bnq_table_lookup.argtypes = [vp, i32, i64, vp, vp, vp]
         L.bnq_plan_counts.argtypes = [vp, vp]
         L.bnq_plan_set_timing.argtypes = [vp, i32]
@@ -149,7 +151,7 @@ def lib():
         L.bnq_rescaled_init.argtypes = [vp, vp, f64, vp, RS, vp]
         L.bnq_step_rescaled.argtypes = [vp, vp, RS, f64, vp]
         for fn in ("bnq_plan", "bnq_plan_destroy", "bnq_plan_footprint", "bnq_collide", "bnq_step",
-                   "bnq_moments", "bnq_table_lookup", "bnq_plan_counts", "bnq_plan_set_timing",
+                   "bnq_moments", "bnq_health", "bnq_table_lookup", "bnq_plan_counts", "bnq_plan_set_timing",
                    "bnq_plan_timing", "bnq_plan_autotune", "bnq_batch_create", "bnq_batch_destroy", "bnq_batch_collide",
                    "bnq_batch_step", "bnq_equilibrium_solve", "bnq_fd_be_log", "bnq_equilibrium_fill",
                    "bnq_equilibrium_distance", "bnq_rescaled_init", "bnq_step_rescaled"):
@@ -232,6 +234,14 @@ class Plan:
         res = dict(zip(MOMENT_NAMES, out.tolist()))
         res["status"] = st
         return res
+
+    def health(self, wait: bool = True, clear: bool = False, stream=None) -> int:
+        """BNQ_HEALTH_* bits recorded by completed steps (bnq_health); never
+        raises for set flags."""
+        fl = ctypes.c_int32(0)
+        _check(lib().bnq_health(self._h, 1 if wait else 0, 1 if clear else 0, ctypes.byref(fl), _stream(stream)),
+               allow=(BNQ_ENONFINITE, BNQ_EBOUND))
+        return fl.value
 
     def equilibrium_fill(self, eq: Equilibrium, out, stream=None):
         _check(lib().bnq_equilibrium_fill(self._h, ctypes.byref(eq), _ptr(out), _stream(stream)))

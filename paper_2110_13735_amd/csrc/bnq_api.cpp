@@ -471,6 +471,7 @@ struct bnq_plan_s {
     int nbdesc = 0;
     double *kbuf[4] = {nullptr, nullptr, nullptr, nullptr}, *ybuf = nullptr;
     double *mom_part = nullptr, *mom_out = nullptr;
+    int *health = nullptr;  // two flag words in pinned, device-coherent host memory
     double *ginv = nullptr;  // inverse Gram matrix for BNQ_CORR_MOMENTS
     double *dmat = nullptr;  // N x N spectral differentiation matrix (rescaled scheme)
     bool otf = false;        // FP64 pair weights formed on the fly (no weight tables)
@@ -864,6 +865,7 @@ void destroy_plan(bnq_plan_s *P) {
     hipFree(P->ybuf);
     hipFree(P->mom_part);
     hipFree(P->mom_out);
+    if (P->health) hipHostFree(P->health);
     hipFree(P->ginv);
     hipFree(P->dmat);
     hipFree(P->t1cut);
@@ -1110,6 +1112,20 @@ bnq_status run_step(const Exec &E, double *const *f, const double *dt, int schem
     return BNQ_OK;
 }
 
+// Status recorded in the plan's health flags by steps that have completed on
+// the device (read without synchronisation): ENONFINITE before EBOUND.
+bnq_status health_status(const bnq_plan_s *P, int member) {
+    const volatile int *h = P->health;
+    if (h[0])
+        return member >= 0 ? fail(BNQ_ENONFINITE, "a step of instance %d wrote a non-finite value", member)
+                           : fail(BNQ_ENONFINITE, "a step wrote a non-finite value");
+    if (h[1])
+        return member >= 0
+                   ? fail(BNQ_EBOUND, "a step of instance %d wrote a value at or above 1/alpha (fermion bound)", member)
+                   : fail(BNQ_EBOUND, "a step wrote a value at or above 1/alpha (fermion bound)");
+    return BNQ_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1202,8 +1218,8 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         (st = dalloc(&P->xpart, (size_t)outer_split(g) * nm, "outer sum slices")) ||
         (st = dalloc(&P->T1, nm, "trilinear modes")) || (st = dalloc(&P->X, nm, "outer modes")) ||
         (st = dalloc(&P->Qh, nm, "modes")) || (st = dalloc(&P->ybuf, nm, "stage")) ||
-        (st = dalloc(&P->mom_part, (size_t)MOM_BLOCKS * MOM_FIELDS, "moment partials")) ||
-        (st = dalloc(&P->mom_out, (size_t)MOM_FIELDS, "moments"))) {
+        (st = dalloc(&P->mom_part, moments_scratch_doubles(MOM_BLOCKS), "moment partials")) ||
+        (st = dalloc(&P->mom_out, (size_t)MOM_OUT, "moments"))) {
         destroy_plan(P);
         return st;
     }
@@ -1212,6 +1228,15 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
             destroy_plan(P);
             return st;
         }
+    {
+        const hipError_t e = hipHostMalloc((void **)&P->health, 2 * sizeof(int), hipHostMallocCoherent);
+        if (e != hipSuccess) {
+            P->health = nullptr;
+            destroy_plan(P);
+            return fail(BNQ_ENOMEM, "health flags: %s", hipGetErrorString(e));
+        }
+        P->health[0] = P->health[1] = 0;
+    }
     if (p->precision == BNQ_FP32C &&
         ((st = dalloc(&P->G32, nm, "FP32 spectrum")) ||
          (st = dalloc(&P->Gr32, P->grp.size() * (size_t)g.next, "FP32 rotated spectra")))) {
@@ -1283,6 +1308,8 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         I.corr_mom = p->correction == BNQ_CORR_MOMENTS;
         I.hstep = 2.0 * p->L / p->N;
         I.ginv = nullptr;
+        I.health = P->health;
+        I.fbound = P->alpha > 0 ? 1.0 / P->alpha : INFINITY;
         if (I.corr_mom) {
             std::vector<double> gi;
             if ((st = gram_inverse(p->d, p->N, I.hstep, gi)) || (st = upload(&P->ginv, gi, "moment Gram matrix"))) {
@@ -1332,6 +1359,8 @@ bnq_status bnq_step(bnq_plan_t P, double *f, double dt, int32_t scheme, bnq_stre
     if (!P) return fail(BNQ_EINVAL, "plan is NULL");
     if (!f) return fail(BNQ_EINVAL, "f is NULL");
     if (!std::isfinite(dt)) return fail(BNQ_EINVAL, "dt must be finite");
+    bnq_status st;
+    if ((st = health_status(P, -1))) return st;
     hipStream_t s = (hipStream_t)stream;
     P->last = s;
     const Exec E = exec_of(P);
@@ -1348,30 +1377,24 @@ bnq_status bnq_moments(bnq_plan_t P, const double *f, double *out_host, bnq_stre
         launch_moments(P->g, f, P->p.L, P->alpha, P->mom_part, MOM_BLOCKS, P->mom_out, s);
         LAUNCHCHK();
     }
-    double r[MOM_FIELDS];
+    double r[MOM_OUT];
     HIPCHK(hipMemcpyAsync(r, P->mom_out, sizeof r, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    const double dv = std::pow(2.0 * P->p.L / P->p.N, P->p.d);
-    const double rho = dv * r[0];
-    double u[3] = {0, 0, 0};
-    // moments are reported with axis order (x0, x1, x2) of the storage
-    const int first = P->p.d == 3 ? 0 : 1;
-    for (int i = 0; i < 3; ++i) u[i] = rho != 0 ? dv * r[1 + i] / rho : 0.0;
-    const double Ec = dv * r[4];
-    const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    out_host[0] = rho;
-    for (int i = 0; i < 3; ++i) out_host[1 + i] = 0.0;
-    for (int i = first; i < 3; ++i) out_host[1 + i - first] = u[i];
-    out_host[4] = Ec;
-    out_host[5] = rho != 0 ? (Ec - rho * u2) / (2.0 * rho) : 0.0;
-    out_host[6] = dv * r[5];
-    out_host[7] = r[6];
-    out_host[8] = r[7];
-    out_host[9] = r[8] + r[9];
-    if (r[9] > 0) return fail(BNQ_ENONFINITE, "f holds %.0f non-finite values", r[9]);
-    if (P->p.eps == -1 && r[6] * std::fabs(P->alpha) >= 1.0)
-        return fail(BNQ_EBOUND, "fermion bound violated: max f = %.17g >= 1/|alpha|", r[6]);
+    for (int k = 0; k < BNQ_MOMENTS_LEN; ++k) out_host[k] = r[k];
+    if (r[10] > 0) return fail(BNQ_ENONFINITE, "f holds %.0f non-finite values", r[10]);
+    if (P->p.eps == -1 && r[7] * std::fabs(P->alpha) >= 1.0)
+        return fail(BNQ_EBOUND, "fermion bound violated: max f = %.17g >= 1/|alpha|", r[7]);
     return BNQ_OK;
+}
+
+bnq_status bnq_health(bnq_plan_t P, int32_t wait, int32_t clear, int32_t *flags_host, bnq_stream_t stream) {
+    if (!P) return fail(BNQ_EINVAL, "plan is NULL");
+    if (wait) HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    const int fl = (P->health[0] ? BNQ_HEALTH_NONFINITE : 0) | (P->health[1] ? BNQ_HEALTH_BOUND : 0);
+    if (flags_host) *flags_host = fl;
+    const bnq_status st = health_status(P, -1);
+    if (clear) P->health[0] = P->health[1] = 0;
+    return st;
 }
 
 bnq_status bnq_equilibrium_solve(int32_t d, int32_t eps, double hbar, double rho, const double *u, double e,
@@ -1479,7 +1502,7 @@ bnq_status xi_sums(bnq_plan_s *P, const double *x, hipStream_t s, double r[5]) {
     launch_moments(P->g, x, M_PI, 0.0, P->mom_part, MOM_BLOCKS, P->mom_out, s);
     LAUNCHCHK();
     double buf[MOM_FIELDS];
-    HIPCHK(hipMemcpyAsync(buf, P->mom_out, sizeof buf, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(buf, P->mom_part + moments_sums_offset(MOM_BLOCKS), sizeof buf, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (buf[9] > 0) return fail(BNQ_ENONFINITE, "%.0f non-finite values", buf[9]);
     for (int k = 0; k < 5; ++k) r[k] = buf[k];
@@ -1936,6 +1959,10 @@ bnq_status bnq_batch_step(bnq_batch_t B, const double *dt, int32_t scheme, int32
     const int n = (int)B->f.size();
     for (int i = 0; i < n; ++i)
         if (!std::isfinite(dt[i])) return fail(BNQ_EINVAL, "dt[%d] must be finite", i);
+    for (int i = 0; i < n; ++i) {
+        bnq_status st = health_status(B->plans[i], i);
+        if (st) return st;
+    }
     hipStream_t s = (hipStream_t)stream;
     for (auto *P : B->plans) P->last = s;
     if (!use_graph) return batch_step_enqueue(B, dt, scheme, s);

@@ -229,6 +229,11 @@ struct Inst {
     int corr_mom;  // 1: project Q onto zero mass, momentum and energy
     double hstep;  // velocity step 2 L / N
     const double *ginv;  // inverse Gram matrix of {1, v, |v|^2} over the grid, (d+2)^2
+    // health of the state written by the last stage of a step: two flag
+    // words in host-visible memory ([0] a non-finite value, [1] a value at or
+    // above fbound), set by the device, read and cleared by the host
+    int *health;
+    double fbound;  // 1/alpha for Fermi-Dirac statistics (alpha > 0), else +inf
 };
 
 // Buffers a kernel can be pointed at.
@@ -310,10 +315,19 @@ void launch_moments_fix(const Geo &g, const Inst *D, const IOs &io, hipStream_t 
 void launch_stage(const Geo &g, const Inst *D, const IOs &io, double a, int ks, int to_out, hipStream_t s);
 void launch_rk4_final(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 void launch_ssprk2_final(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
-void launch_moments(const Geo &g, const double *f, double L, double alpha, double *part, int nblk,
-                    double *out, hipStream_t s);
+// Moments of grid values f on [-L, L)^d: two passes over nblk workgroups with
+// fixed reduction trees; res receives MOM_OUT values: rho, u[3], E_c, e, H,
+// max f, min f, excluded + non-finite nodes, non-finite nodes (the order of
+// bnq_moments, plus the non-finite count).  scratch holds
+// moments_scratch_doubles(nblk) doubles; the raw first-pass totals (sum f,
+// sum v f per storage axis, sum |v|^2 f, ...) end at moments_sums_offset.
 constexpr int MOM_BLOCKS = 256;
 constexpr int MOM_FIELDS = 12;
+constexpr int MOM_OUT = 11;
+constexpr size_t moments_sums_offset(int nblk) { return (size_t)nblk * (MOM_FIELDS + 1); }
+constexpr size_t moments_scratch_doubles(int nblk) { return moments_sums_offset(nblk) + MOM_FIELDS; }
+void launch_moments(const Geo &g, const double *f, double L, double alpha, double *scratch, int nblk, double *res,
+                    hipStream_t s);
 
 // A limit state on the grid (kinds as BNQ_EQ_*): M(v) with r2 = |v - u|^2
 //   kind 0: c0 exp(-r2 / 2T)                       (c0 = rho (2 pi T)^(-d/2))

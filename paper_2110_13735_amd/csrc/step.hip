@@ -4,7 +4,7 @@
 // stage combinations are plain FP64 vector updates.  Moments and entropy
 // follow the diagnostics list of section 'Numerical results' (classical method, omega = 1):
 //   rho = dv sum f, u = dv sum v f / rho, E_c = dv sum |v|^2 f,
-//   e = (E_c - rho |u|^2) / (2 rho),
+//   e = dv sum |v - u|^2 f / (2 rho)   (a second pass, after u is known),
 //   H = dv sum [f ln f + (1 - alpha f)/alpha ln(1 - alpha f)]   (alpha != 0)
 //     = dv sum f ln f                                          (alpha  = 0)
 // over nodes with f > 0 and 1 - alpha f > 0.  Reductions use a fixed
@@ -18,14 +18,36 @@ namespace bnq {
 
 static dim3 grid_nm(const Geo &g, const IOs &io) { return dim3((unsigned)((g.nm + 255) / 256), 1, (unsigned)io.n); }
 
-// y = in + a dt k[ks], into Inst::ybuf (to_out = 0) or io.out (to_out = 1)
+// Health of a state value written by the last stage of a step: a wave that
+// wrote a non-finite value, or a Fermi-Dirac value at or above 1/alpha,
+// records it in the instance's two host-visible flag words (plain stores of
+// 1 by one lane per wave; no host synchronisation).  Every lane of the wave
+// must reach this call.
+__device__ __forceinline__ void record_health(const Inst &I, bool valid, double v) {
+    const bool nf = valid && !isfinite(v);
+    const bool bd = valid && v >= I.fbound;  // false for NaN
+    const unsigned long long mnf = __ballot(nf), mbd = __ballot(bd);
+    if ((threadIdx.x & 63) == 0 && I.health) {
+        volatile int *h = I.health;
+        if (mnf) h[0] = 1;
+        if (mbd) h[1] = 1;
+    }
+}
+
+// y = in + a dt k[ks], into Inst::ybuf (to_out = 0) or io.out (to_out = 1,
+// the last stage of an Euler step: its values are health-checked)
 __global__ void stage_kernel(Geo g, const Inst *D, IOs io, double a, int ks, int to_out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.nm) return;
+    const bool valid = i < g.nm;
     const int z = blockIdx.z;
     const Inst &I = D[io.inst[z]];
-    const gptr<double> y = glob(to_out ? io.out[z] : I.ybuf);
-    y[i] = fma(a * io.dt[z], glob((const double *)I.k[ks])[i], glob(io.in[z])[i]);
+    double v = 0.0;
+    if (valid) {
+        const gptr<double> y = glob(to_out ? io.out[z] : I.ybuf);
+        v = fma(a * io.dt[z], glob((const double *)I.k[ks])[i], glob(io.in[z])[i]);
+        y[i] = v;
+    }
+    if (to_out) record_health(I, valid, v);
 }
 
 void launch_stage(const Geo &g, const Inst *D, const IOs &io, double a, int ks, int to_out, hipStream_t s) {
@@ -35,13 +57,18 @@ void launch_stage(const Geo &g, const Inst *D, const IOs &io, double a, int ks, 
 // f <- f + dt/6 (k1 + 2 k2 + 2 k3 + k4), f = io.out
 __global__ void rk4_final_kernel(Geo g, const Inst *D, IOs io) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.nm) return;
+    const bool valid = i < g.nm;
     const int z = blockIdx.z;
     const Inst &I = D[io.inst[z]];
-    const gptr<double> f = glob(io.out[z]);
-    const double k0 = glob((const double *)I.k[0])[i], k1 = glob((const double *)I.k[1])[i];
-    const double k2 = glob((const double *)I.k[2])[i], k3 = glob((const double *)I.k[3])[i];
-    f[i] = f[i] + (io.dt[z] / 6.0) * (k0 + 2.0 * k1 + 2.0 * k2 + k3);
+    double v = 0.0;
+    if (valid) {
+        const gptr<double> f = glob(io.out[z]);
+        const double k0 = glob((const double *)I.k[0])[i], k1 = glob((const double *)I.k[1])[i];
+        const double k2 = glob((const double *)I.k[2])[i], k3 = glob((const double *)I.k[3])[i];
+        v = f[i] + (io.dt[z] / 6.0) * (k0 + 2.0 * k1 + 2.0 * k2 + k3);
+        f[i] = v;
+    }
+    record_health(I, valid, v);
 }
 
 void launch_rk4_final(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
@@ -51,11 +78,16 @@ void launch_rk4_final(const Geo &g, const Inst *D, const IOs &io, hipStream_t s)
 // Shu–Osher SSP-RK2: y = f + dt k1;  f <- (f + y + dt k(y)) / 2, f = io.out
 __global__ void ssprk2_final_kernel(Geo g, const Inst *D, IOs io) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.nm) return;
+    const bool valid = i < g.nm;
     const int z = blockIdx.z;
     const Inst &I = D[io.inst[z]];
-    const gptr<double> f = glob(io.out[z]);
-    f[i] = 0.5 * (f[i] + fma(io.dt[z], glob((const double *)I.k[1])[i], glob((const double *)I.ybuf)[i]));
+    double v = 0.0;
+    if (valid) {
+        const gptr<double> f = glob(io.out[z]);
+        v = 0.5 * (f[i] + fma(io.dt[z], glob((const double *)I.k[1])[i], glob((const double *)I.ybuf)[i]));
+        f[i] = v;
+    }
+    record_health(I, valid, v);
 }
 
 void launch_ssprk2_final(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
@@ -194,10 +226,79 @@ __global__ void __launch_bounds__(256) moments_final_kernel(int nblk, const doub
     }
 }
 
-void launch_moments(const Geo &g, const double *f, double L, double alpha, double *part, int nblk, double *out,
+// Second pass: sum |v - u|^2 f over the finite nodes, with u = (sum v f) /
+// (sum f) from the first pass's totals (the internal energy without the
+// cancellation of E_c - rho |u|^2 when the drift is large).
+__global__ __launch_bounds__(256) void moments_center_kernel(Geo g, const double *f, double L, const double *sums,
+                                                             double *part2) {
+    __shared__ double red[256];
+    const double s0 = sums[0];
+    const double u0 = s0 != 0.0 ? sums[1] / s0 : 0.0, u1 = s0 != 0.0 ? sums[2] / s0 : 0.0,
+                 u2 = s0 != 0.0 ? sums[3] / s0 : 0.0;
+    const double hstep = 2.0 * L / g.N;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.nm;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = f[i];
+        if (!isfinite(v)) continue;
+        const double w2 = (double)((int)(i % g.N) - g.h) * hstep - u2;
+        const double w1 = (double)((int)((i / g.N) % g.N) - g.h) * hstep - u1;
+        const double w0 = g.d == 3 ? (double)((int)(i / ((int64_t)g.N * g.N)) - g.h) * hstep - u0 : 0.0;
+        acc += (w0 * w0 + w1 * w1 + w2 * w2) * v;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part2[blockIdx.x] = red[0];
+}
+
+// Totals of the second pass (fixed tree) and the reported moments:
+//   res = rho, u (axis order of the used axes, zero-padded to 3), E_c, e, H,
+//         max f, min f, excluded + non-finite nodes, non-finite nodes.
+__global__ void __launch_bounds__(256) moments_finish_kernel(Geo g, double L, int nblk, const double *part2,
+                                                             const double *sums, double *res) {
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    double a = 0.0;
+    for (int b = t; b < nblk; b += 256) a += part2[b];
+    red[t] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t != 0) return;
+    const double h = 2.0 * L / g.N;
+    const double dv = g.d == 3 ? h * h * h : h * h;
+    const double rho = dv * sums[0];
+    const int first = g.d == 3 ? 0 : 1;
+    double u[3] = {0.0, 0.0, 0.0};
+    for (int i = first; i < 3; ++i) u[i - first] = rho != 0.0 ? dv * sums[1 + i] / rho : 0.0;
+    res[0] = rho;
+    res[1] = u[0];
+    res[2] = u[1];
+    res[3] = u[2];
+    res[4] = dv * sums[4];
+    res[5] = rho != 0.0 ? dv * red[0] / (2.0 * rho) : 0.0;
+    res[6] = dv * sums[5];
+    res[7] = sums[6];
+    res[8] = sums[7];
+    res[9] = sums[8] + sums[9];
+    res[10] = sums[9];
+}
+
+// scratch: nblk x MOM_FIELDS first-pass partials, nblk second-pass partials,
+// MOM_FIELDS totals (moments_scratch_doubles(nblk) doubles)
+void launch_moments(const Geo &g, const double *f, double L, double alpha, double *scratch, int nblk, double *res,
                     hipStream_t s) {
+    double *part = scratch, *part2 = scratch + (size_t)nblk * MOM_FIELDS, *sums = part2 + nblk;
     hipLaunchKernelGGL(moments_part_kernel, dim3(nblk), dim3(256), 0, s, g, f, L, alpha, part);
-    hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(256), 0, s, nblk, part, out);
+    hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(256), 0, s, nblk, part, sums);
+    hipLaunchKernelGGL(moments_center_kernel, dim3(nblk), dim3(256), 0, s, g, f, L, sums, part2);
+    hipLaunchKernelGGL(moments_finish_kernel, dim3(1), dim3(256), 0, s, g, L, nblk, part2, sums, res);
 }
 
 // ---------------------------------------------------------------------------

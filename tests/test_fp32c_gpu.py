@@ -1,12 +1,13 @@
 """FP32c precision pattern: spectra, tables and short partial sums in FP32,
-long sums in FP64.  Parity with the FP64 oracle to 1e-5 (norm-wise, relative
-to max(|ref|, |classical gain|) as for FP64), at small sizes over several
+long sums in FP64.  Parity with the FP64 oracle to 1e-5 (the criteria of
+tests/parity.py, as for FP64), at small sizes over several
 tiles and ragged windows and at the full 3-D N = 32 shape."""
 import numpy as np
 import pytest
 
 import bnq_inputs as inp
 import oracle
+from tests.parity import check
 
 pytestmark = pytest.mark.gpu
 
@@ -39,10 +40,8 @@ def test_fp32c_collide_matches_oracle(d, N, eps):
     Q, Qh = _gpu(bnq.Params(d=d, N=N, eps=eps, L=L, precision=bnq.FP32C), f)
     o = oracle.Oracle(d, N)
     Qo, Qho, m = o.collide(f, eps, L, full=True)
-    gain = np.linalg.norm(m["gain"])
-    qgain = np.linalg.norm(oracle.prefactor(d, L) * oracle.idft_real(m["gain"]))
-    assert _rel(Qh, Qho, gain) <= TOL32
-    assert _rel(Q, Qo, qgain) <= TOL32
+    check(Qh, Qho, m["gain"], tol=TOL32)
+    check(Q, Qo, oracle.prefactor(d, L) * oracle.idft_real(m["gain"]), tol=TOL32)
 
 
 def test_fp32c_is_not_fp64():
@@ -62,8 +61,8 @@ def test_fp32c_full_size_3d32_sparse_spectrum():
     Qc, T1, Xq = oracle.sparse_modes(d, N, sm, co, eps)
     alpha = oracle.alpha_of(eps, d)
     ref = oracle.sparse_dense(d, N, Qc) - alpha * (oracle.sparse_dense(d, N, T1) + oracle.sparse_dense(d, N, Xq))
-    assert _rel(Qh, ref) <= TOL32
-    assert _rel(Q, oracle.prefactor(d, L) * oracle.idft_real(ref)) <= TOL32
+    check(Qh, ref, tol=TOL32)
+    check(Q, oracle.prefactor(d, L) * oracle.idft_real(ref), tol=TOL32)
 
 
 def test_fp32c_and_fp64_instances_in_one_batch():

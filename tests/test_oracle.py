@@ -344,3 +344,99 @@ def test_moment_projection_properties(d, N):
     coef, *_ = np.linalg.lstsq(basis.T, D, rcond=None)
     assert np.linalg.norm(basis.T @ coef - D) <= 1e-12 * np.linalg.norm(Q)
     assert np.allclose(oracle.project_moments(P, d, N, L), P, rtol=0, atol=1e-13 * np.max(np.abs(Q)))
+
+
+def _polylog_series(nu, z, fermi, terms=2000):
+    # complete Fermi-Dirac / Bose-Einstein integral for 0 < z < 1 by its power
+    # series: sum_k (-1)^(k+1) z^k / k^nu (FD) or sum_k z^k / k^nu (BE)
+    k = np.arange(1, terms + 1, dtype=np.float64)
+    sgn = (-1.0) ** (k + 1) if fermi else 1.0
+    return float(np.sum(sgn * z ** k / k ** nu))
+
+
+def _quantum_maxwellian_entropy(d, alpha, z, T):
+    # The quantum Maxwellian f = (1/|alpha|) / (z^-1 e^{|v|^2/2T} + sgn alpha)
+    # (section 'Convergence towards a steady state', eq. def_Mq_2d and its 3-D
+    # form).  Writing y = z^-1 e^{|v|^2/2T} and s = sgn alpha, the entropy
+    # density f ln f + (1 - alpha f)/alpha ln(1 - alpha f) is
+    #   -f ln|alpha| - f ln y - (1/alpha) ln(1 + s/y),
+    # and integrating the series of each term over R^d gives
+    #   rho   = (2 pi T)^(d/2) K_{d/2}(z) / |alpha|,
+    #   rho e = (d/2) T (2 pi T)^(d/2) K_{d/2+1}(z) / |alpha|,
+    #   H     = rho (ln z - ln|alpha|) - (rho e / T)(1 + 2/d),
+    # with K_nu the Fermi-Dirac (alpha > 0) or Bose-Einstein (alpha < 0)
+    # integral (mom02_qmaxwell).
+    fermi = alpha > 0
+    rho = (2 * math.pi * T) ** (d / 2) * _polylog_series(d / 2, z, fermi) / abs(alpha)
+    rhoe = (d / 2) * T * (2 * math.pi * T) ** (d / 2) * _polylog_series(d / 2 + 1, z, fermi) / abs(alpha)
+    H = rho * (math.log(z) - math.log(abs(alpha))) - rhoe / T * (1 + 2 / d)
+    return rho, rhoe / rho, H
+
+
+def _qmaxwellian_grid(d, N, L, alpha, z, T):
+    v = inp.velocity_grid(d, N, L)
+    r2 = np.sum(v * v, axis=-1)
+    return (1 / abs(alpha)) / (np.exp(r2 / (2 * T)) / z + (1.0 if alpha > 0 else -1.0))
+
+
+# fine grids: the discrete sums of these analytic, fast-decaying integrands
+# equal the integrals to rounding (the nearest complex singularity of the
+# Bose-Einstein case, |v| = sqrt(2 T |ln z|), bounds the grid step)
+QM_CASES = [(2, 128, 8.0, -1, 1.0, 0.5, 0.5), (2, 128, 8.0, 1, 1.0, 0.5, 0.5), (2, 128, 8.0, -1, 1.5, 0.7, 0.4),
+            (2, 128, 8.0, 1, 1.3, 0.3, 0.6), (3, 64, 6.0, -1, 1.0, 0.5, 0.5), (3, 64, 6.0, 1, 1.2, 0.3, 0.5)]
+
+
+@pytest.mark.parametrize("d,N,L,eps,hbar,z,T", QM_CASES)
+def test_quantum_entropy_of_quantum_maxwellian_closed_form(d, N, L, eps, hbar, z, T):
+    alpha = oracle.alpha_of(eps, d, hbar)
+    f = _qmaxwellian_grid(d, N, L, alpha, z, T)
+    m = oracle.moments(f, L, eps, hbar)
+    rho, e, H = _quantum_maxwellian_entropy(d, alpha, z, T)
+    assert m["n_excluded"] == 0
+    assert m["rho"] == pytest.approx(rho, rel=1e-12)
+    assert m["e"] == pytest.approx(e, rel=1e-12)
+    assert m["H"] == pytest.approx(H, rel=1e-11, abs=1e-12)
+
+
+def test_quantum_entropy_pin_rejects_planted_mistakes():
+    # the closed form above tells the oracle's entropy from a flipped sign of
+    # its second term and from a missing 1/alpha there (|alpha| != 1)
+    d, N, L, eps, hbar, z, T = 2, 128, 8.0, 1, 1.3, 0.3, 0.6
+    alpha = oracle.alpha_of(eps, d, hbar)
+    f = _qmaxwellian_grid(d, N, L, alpha, z, T)
+    _, _, H = _quantum_maxwellian_entropy(d, alpha, z, T)
+    dv = (2 * L / N) ** d
+    om = 1 - alpha * f
+    flipped = dv * np.sum(f * np.log(f) - om / alpha * np.log(om))
+    no_inv = dv * np.sum(f * np.log(f) + om * np.log(om))
+    assert abs(flipped - H) > 1e-3 * abs(H)
+    assert abs(no_inv - H) > 1e-3 * abs(H)
+
+
+def test_rk4_step_is_fourth_order():
+    # Oracle.rk4_step against a fine-step reference of the same scheme over a
+    # fixed horizon: the error falls 16-fold per halving of dt (a second-order
+    # scheme, planted below, falls 4-fold and fails the same bound)
+    d, N, L, eps, T = 2, 8, 5.0, 1, 0.5
+    o = oracle.Oracle(d, N)
+    f0 = inp.gaussian_mixture(d, N, L, seed=3, kmin=2)
+
+    def run(n, step):
+        f = f0.copy()
+        for _ in range(n):
+            f = step(f, T / n)
+        return f
+
+    rk4 = lambda f, dt: o.rk4_step(f, dt, eps, L)
+
+    def midpoint(f, dt):
+        k1 = o.rhs(f, eps, L)
+        return f + dt * o.rhs(f + 0.5 * dt * k1, eps, L)
+
+    ref = run(128, rk4)
+    e = [np.abs(run(n, rk4) - ref).max() for n in (4, 8, 16)]
+    assert e[2] > 1e-11  # above rounding
+    for a, b in zip(e, e[1:]):
+        assert 13.0 < a / b < 19.0, e
+    e2 = [np.abs(run(n, midpoint) - ref).max() for n in (4, 8)]
+    assert not (13.0 < e2[0] / e2[1] < 19.0)

@@ -1,10 +1,11 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-FP64 bar: norm-wise error <= 1e-12 on Qhat (Galerkin modes), on Q (grid
-values) and after a time step, relative to max(|ref|, |classical gain|):
-near an equilibrium Qhat is a small difference of gain and loss terms of
-size |gain|, and no summation order resolves it better than ~1e-16 of that
-scale.  Kernel-mode tables <= 1e-12 absolute (beta(0,0) = 50.9 in 2-D and
+FP64 bar (see _check): 1e-12 on Qhat (Galerkin modes), on Q (grid values)
+and after a time step, norm-wise and element-wise relative to the larger of
+the result and the classical gain term, and purely relative wherever the gain
+is at most ten times the result: near an equilibrium Qhat is a small
+difference of gain and loss terms of size |gain|, and no summation order
+resolves it better than ~1e-16 of that scale.  Kernel-mode tables <= 1e-12 absolute (beta(0,0) = 50.9 in 2-D and
 324.1 in 3-D).
 """
 import math
@@ -14,6 +15,7 @@ import pytest
 
 import bnq_inputs as inp
 import oracle
+from tests.parity import check
 
 pytestmark = pytest.mark.gpu
 
@@ -35,17 +37,16 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-def _check(got, ref, scale=0.0, tol=TOL):
-    err = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), scale, 1e-300)
-    assert err <= tol, f"error {err:.3e} > {tol:.1e} (|ref| {np.linalg.norm(ref):.3e}, scale {scale:.3e})"
+_check = check
 
 
 def _oracle_collide(d, N, f, eps, L, **kw):
+    """Oracle Q, Qhat, and the classical gain term as modes and as grid values
+    (after the same prefactor and inverse transform as Q)."""
     o = _oracle(d, N)
     Q, Qh, m = o.collide(f, eps, L, full=True, **kw)
-    gain = np.linalg.norm(m["gain"])
-    qgain = np.linalg.norm(oracle.prefactor(d, L, kw.get("c", 1.0)) * oracle.idft_real(m["gain"]))
-    return Q, Qh, gain, qgain
+    qgain = oracle.prefactor(d, L, kw.get("c", 1.0)) * oracle.idft_real(m["gain"])
+    return Q, Qh, m["gain"], qgain
 
 
 def _gpu_collide(p, f):
@@ -149,9 +150,8 @@ def test_scalings_hbar_cphi_c():
     p = bnq.Params(d=d, N=N, eps=-1, L=L, hbar=0.7, C_phi=1.7, c=2.5)
     Q, Qh = _gpu_collide(p, f)
     Qo, Qho, m = oracle.Oracle(d, N, Cphi=1.7).collide(f, -1, L, hbar=0.7, c=2.5, full=True)
-    g = np.linalg.norm(m["gain"])
-    _check(Qh, Qho, g)
-    _check(Q, Qo, np.linalg.norm(oracle.prefactor(d, L, 2.5) * oracle.idft_real(m["gain"])))
+    _check(Qh, Qho, m["gain"])
+    _check(Q, Qo, oracle.prefactor(d, L, 2.5) * oracle.idft_real(m["gain"]))
 
 
 def test_c1_boson_2d32_collide_and_rk4_step():
@@ -295,9 +295,9 @@ def test_full_size_3d32_sparse_spectrum(schedule, precision):
     alpha = oracle.alpha_of(eps, d)
     ref = oracle.sparse_dense(d, N, Qc) - alpha * (oracle.sparse_dense(d, N, T1) + oracle.sparse_dense(d, N, Xq))
     tol = TOL if precision == 0 else 1e-5
-    assert _rel(Qh, ref) <= tol
+    _check(Qh, ref, tol=tol)
     Qref = oracle.prefactor(d, L) * oracle.idft_real(ref)
-    assert _rel(Q, Qref) <= tol
+    _check(Q, Qref, tol=tol)
 
 
 @pytest.mark.parametrize("d,N,eps", [(2, 8, 1), (2, 16, -1), (2, 30, 0), (3, 6, 1), (3, 10, -1)])
