@@ -229,6 +229,21 @@ bnq_status bnq_health(bnq_plan_t plan, int32_t wait, int32_t clear, int32_t *fla
 #define BNQ_MOMENTS_LEN 10
 bnq_status bnq_moments(bnq_plan_t plan, const double *f, double *out_host, bnq_stream_t stream);
 
+/* bnq_moments without any allocation and without a plan, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops
+ * that must not call the allocator).  The grid is given by p's d, N, L and
+ * the entropy's alpha by p's eps and hbar (other fields are validated as by
+ * bnq_plan and otherwise ignored).  f is a DEVICE array of N^d FP64 values;
+ * out is a DEVICE array of BNQ_MOMENTS_LEN + 1 doubles, written
+ * asynchronously on `stream` with the values of bnq_moments in the same
+ * order, followed by the number of non-finite values of f (no status is
+ * returned for them: nothing is synchronised).  The partial sums live in a
+ * static device array of 32 KiB per device (enough for every valid N), kept
+ * until the process ends and shared by every call on that device: calls
+ * that overlap on one device (other streams, other host threads) race.
+ * Errors: EINVAL (params, null pointers, a grid whose partials would not fit
+ * the array), EHIP. */
+bnq_status bnq_moments_noalloc(const bnq_params *p, const double *f, double *out, bnq_stream_t stream);
 
 /* ---- limit states (section 'Convergence towards a steady state') --------
  * The state a solution relaxes to, for given mass rho, mean velocity u and

@@ -133,6 +133,7 @@ def lib():
         L.bnq_step.argtypes = [vp, vp, f64, i32, vp]
         L.bnq_moments.argtypes = [vp, vp, vp, vp]
         L.bnq_health.argtypes = [vp, i32, i32, vp, vp]
+        L.bnq_moments_noalloc.argtypes = [P, vp, vp, vp]
         L.bnq_table_lookup.argtypes = [vp, i32, i64, vp, vp, vp]
         L.bnq_plan_counts.argtypes = [vp, vp]
         L.bnq_plan_set_timing.argtypes = [vp, i32]
@@ -151,7 +152,7 @@ def lib():
         L.bnq_rescaled_init.argtypes = [vp, vp, f64, vp, RS, vp]
         L.bnq_step_rescaled.argtypes = [vp, vp, RS, f64, vp]
         for fn in ("bnq_plan", "bnq_plan_destroy", "bnq_plan_footprint", "bnq_collide", "bnq_step",
-                   "bnq_moments", "bnq_health", "bnq_table_lookup", "bnq_plan_counts", "bnq_plan_set_timing",
+                   "bnq_moments", "bnq_health", "bnq_moments_noalloc", "bnq_table_lookup", "bnq_plan_counts", "bnq_plan_set_timing",
                    "bnq_plan_timing", "bnq_plan_autotune", "bnq_batch_create", "bnq_batch_destroy", "bnq_batch_collide",
                    "bnq_batch_step", "bnq_equilibrium_solve", "bnq_fd_be_log", "bnq_equilibrium_fill",
                    "bnq_equilibrium_distance", "bnq_rescaled_init", "bnq_step_rescaled"):
@@ -339,6 +340,14 @@ class Batch:
         n = len(self.plans)
         dts = np.broadcast_to(np.asarray(dt, dtype=np.float64), (n,)).copy()
         _check(lib().bnq_batch_step(self._h, dts.ctypes.data, int(scheme), 1 if graph else 0, _stream(stream)))
+
+
+def moments_noalloc(p: Params, f, out, stream=None):
+    """bnq_moments_noalloc: moments of device array f into the device array
+    out (MOMENTS_LEN + 1 FP64 values, the last the non-finite count),
+    asynchronously, with no allocation."""
+    cp = p._c()
+    _check(lib().bnq_moments_noalloc(ctypes.byref(cp), _ptr(f), _ptr(out), _stream(stream)))
 
 
 def terms_per_eval(p: Params, counts: dict) -> float:

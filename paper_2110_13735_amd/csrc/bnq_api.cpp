@@ -1397,6 +1397,24 @@ bnq_status bnq_health(bnq_plan_t P, int32_t wait, int32_t clear, int32_t *flags_
     return st;
 }
 
+bnq_status bnq_moments_noalloc(const bnq_params *p, const double *f, double *out, bnq_stream_t stream) {
+    bnq_status st = validate(p);
+    if (st) return st;
+    if (!f || !out) return fail(BNQ_EINVAL, "f and out must be device pointers");
+    const Geo g = make_geo(p->d, p->N);
+    const int nblk = MOM_BLOCKS;  // as bnq_moments: the same reduction order, the same bits
+    if (moments_scratch_doubles(nblk) > NOALLOC_SCRATCH_DOUBLES)
+        return fail(BNQ_EINVAL, "N^d = %lld needs %zu doubles of scratch, more than the %zu available", (long long)g.nm,
+                    moments_scratch_doubles(nblk), NOALLOC_SCRATCH_DOUBLES);
+    double *scr = nullptr;
+    const hipError_t e = noalloc_scratch(&scr);
+    if (e != hipSuccess) return fail(BNQ_EHIP, "static scratch address: %s", hipGetErrorString(e));
+    const double alpha = -(double)p->eps * std::pow(p->hbar, p->d);
+    launch_moments(g, f, p->L, alpha, scr, nblk, out, (hipStream_t)stream);
+    LAUNCHCHK();
+    return BNQ_OK;
+}
+
 bnq_status bnq_equilibrium_solve(int32_t d, int32_t eps, double hbar, double rho, const double *u, double e,
                                  bnq_equilibrium *out) {
     if (!out) return fail(BNQ_EINVAL, "out is NULL");

@@ -328,6 +328,11 @@ constexpr size_t moments_sums_offset(int nblk) { return (size_t)nblk * (MOM_FIEL
 constexpr size_t moments_scratch_doubles(int nblk) { return moments_sums_offset(nblk) + MOM_FIELDS; }
 void launch_moments(const Geo &g, const double *f, double L, double alpha, double *scratch, int nblk, double *res,
                     hipStream_t s);
+// Allocation-free entry point: a static device array of this many doubles
+// per device (step.hip), and its address on the current device.
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = 4096;
+static_assert(moments_scratch_doubles(MOM_BLOCKS) <= NOALLOC_SCRATCH_DOUBLES, "moment partials fit the static scratch");
+hipError_t noalloc_scratch(double **out);
 
 // A limit state on the grid (kinds as BNQ_EQ_*): M(v) with r2 = |v - u|^2
 //   kind 0: c0 exp(-r2 / 2T)                       (c0 = rho (2 pi T)^(-d/2))

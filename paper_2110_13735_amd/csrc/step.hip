@@ -11,6 +11,8 @@
 // assignment of nodes to blocks and a fixed tree, so results are
 // bit-reproducible.
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "bnq_internal.h"
 
@@ -299,6 +301,31 @@ void launch_moments(const Geo &g, const double *f, double L, double alpha, doubl
     hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(256), 0, s, nblk, part, sums);
     hipLaunchKernelGGL(moments_center_kernel, dim3(nblk), dim3(256), 0, s, g, f, L, sums, part2);
     hipLaunchKernelGGL(moments_finish_kernel, dim3(1), dim3(256), 0, s, g, L, nblk, part2, sums, res);
+}
+
+// Device memory of the allocation-free moments entry point: a file-scope
+// array, one copy per device, shared by every such call on that device.
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+// Address of this device's copy of `scratch` (the array's name is a host-side
+// stand-in and must never be passed to a kernel).  Looked up once per device
+// with that device current, then cached.
+hipError_t noalloc_scratch(double **out) {
+    static std::mutex mu;
+    static std::vector<double *> addr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+    if (!addr[dev]) {
+        double *p = nullptr;
+        e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
