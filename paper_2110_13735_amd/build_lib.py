@@ -21,7 +21,7 @@ FLAGS = [
     "-Wall", "-Wno-unused-result", "-Wno-unused-value",
     "-I", os.path.join(ROOT, "include"),
 ]
-SOURCES = ["beta.hip", "collide.hip", "t1_pairs.hip", "t1_rows.hip", "t1_separated.hip", "step.hip", "equilibrium.cpp",
+SOURCES = ["beta.hip", "collide.hip", "t1_pairs.hip", "t1_mfma.hip", "t1_separated.hip", "step.hip", "equilibrium.cpp",
            "bnq_api.cpp"]
 
 

@@ -103,18 +103,26 @@ void launch_radial(int d, double R, int qmax, int M, int nq, const double *glx, 
     hipLaunchKernelGGL(radial_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, qmax, M, nq, S, J);
 }
 
-// K[kc][a] = beta(a, b_c[kc]) for a in A, stored as [a0][a2 (padded)][a1];
-// the x padding holds zeros.  Every value is formed in FP64; an FP32 table
-// holds it rounded to nearest.
+// K[kc][a] = beta(a, b_c[kc]) for a in A, stored as [a0][a2 (padded)][a1]
+// (FP64: idx_K, read by the vector-unit kernel) or [a0][a1][a2 (padded)]
+// (FP32: idx_Kx, read by the matrix-core kernel); the x padding holds zeros.
+// Every value is formed in FP64; an FP32 table holds it rounded to nearest.
 template <typename T>
 __global__ void beta_rows_kernel(Geo g, Radial rad, const int *canon, T *K) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int kc = blockIdx.y;
     if (i >= g.nak) return;
     const int A = 2 * g.N - 1;
-    const int a1 = (int)(i % A) - (g.N - 1);
-    const int a2 = (int)((i / A) % g.kax) - (g.N - 1) - KPADLO;
-    const int a0 = g.d == 3 ? (int)(i / ((int64_t)A * g.kax)) - (g.N - 1) : 0;
+    int a0, a1, a2;
+    if constexpr (sizeof(T) == 8) {
+        a1 = (int)(i % A) - (g.N - 1);
+        a2 = (int)((i / A) % g.kax) - (g.N - 1) - KPADLO;
+        a0 = g.d == 3 ? (int)(i / ((int64_t)A * g.kax)) - (g.N - 1) : 0;
+    } else {
+        a2 = (int)(i % g.kax) - (g.N - 1) - KPADLO;
+        a1 = (int)((i / g.kax) % A) - (g.N - 1);
+        a0 = g.d == 3 ? (int)(i / ((int64_t)A * g.kax)) - (g.N - 1) : 0;
+    }
     double v = 0.0;
     if (a2 >= -(g.N - 1) && a2 <= g.N - 1) {
         const int b0 = canon[3 * kc], b1 = canon[3 * kc + 1], b2 = canon[3 * kc + 2];

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <array>
 #include <map>
 #include <mutex>
 #include <queue>
@@ -482,8 +483,9 @@ struct bnq_plan_s {
     double2 *sep_gc = nullptr, *sep_gt = nullptr, *sep_part = nullptr;
     int nslots = 0;
     T1Item *items = nullptr;
-    T1B *bdesc = nullptr;
-    std::vector<T1Item> items_h;  // per-slot item lists (host copy), slot offsets
+    T1B *bdesc = nullptr;         // FP64: one descriptor per b
+    T1G *gdesc = nullptr;         // FP32c: one descriptor per group of b (matrix-core kernel)
+    std::vector<T1Item> items_h;  // per-list item lists (host copy), list offsets
     std::vector<int> off_h;       // (dynamic schedule: queue offsets)
     int nq = 0;                   // dynamic schedule: queues (0 = static)
     int *qctr = nullptr;
@@ -648,6 +650,10 @@ double t1_terms(int d, int N) {
 
 int t1_chunks(double terms) { return std::max(1, (int)std::ceil(terms / 2e13)); }
 
+// Static item lists of a trilinear launch over nslots partial arrays: one
+// per 64-lane workgroup (FP64), one per 4-wave matrix-core workgroup (FP32c).
+int t1_lists(int prec, int nslots) { return prec ? nslots / T1M_WAVES : nslots; }
+
 // Item ranges of the launches: off holds the nl + 1 boundaries of the nl
 // slot lists (or queues); launch r covers [cut[r nl + i], cut[(r + 1) nl + i])
 // of list i, so the launches together walk every list once, in order.
@@ -660,7 +666,10 @@ std::vector<int> t1_cuts(const std::vector<int> &off, int nchunk) {
     return cut;
 }
 
+bnq_status build_t1_work_mfma(bnq_plan_s *P);
+
 bnq_status build_t1_work(bnq_plan_s *P) {
+    if (P->p.precision == BNQ_FP32C) return build_t1_work_mfma(P);
     const Geo &g = P->g;
     const TableSet *t = P->tabs;
     const int d = g.d, N = g.N, h = g.h;
@@ -745,7 +754,7 @@ bnq_status build_t1_work(bnq_plan_s *P) {
     int dev = 0, cus = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int per_cu = trilinear_blocks_per_cu(P->p.precision == BNQ_FP32C ? 1 : 0);
+    const int per_cu = trilinear_blocks_per_cu(P->p.precision == BNQ_FP32C ? 1 : 0, N);
     if (cus <= 0 || per_cu <= 0) return fail(BNQ_EHIP, "trilinear occupancy query failed");
     const int nx = P->tune.xcd ? std::max(1, cus / kCusPerXcd) : 1;
     int ns_want = std::min(kMaxSlots, std::max(1, cus * per_cu / std::max(1, P->tune.slot_div)));
@@ -821,10 +830,171 @@ bnq_status build_t1_work(bnq_plan_s *P) {
     return dalloc(&P->part, (size_t)ns * g.nm, "trilinear partial sums");
 }
 
+// FP32c: groups of b for the matrix-core kernel and their items (a group and
+// a block of T1M_BLOCK outputs of its window).  The groups, ordered by
+// canonical row, are cut into one contiguous run of equal cost per XCD and
+// dealt to that XCD's workgroups in snake order (static schedule), or made
+// the XCD's queue (dynamic schedule), as for the FP64 kernel.
+bnq_status build_t1_work_mfma(bnq_plan_s *P) {
+    const Geo &g = P->g;
+    const TableSet *t = P->tabs;
+    const int d = g.d, N = g.N, h = g.h;
+    std::vector<T1G> gd;
+    std::vector<std::array<int, 3>> glo, ghi;  // member window edges (lower edge lo_j of the rotated I_N)
+    std::map<std::pair<int, int>, int> gidx;   // (row, lo_x) -> group
+    const int b0lo = d == 3 ? -N + 1 : 0, b0hi = d == 3 ? N - 2 : 0;
+    for (int b0 = b0lo; b0 <= b0hi; ++b0)
+        for (int b1 = -N + 1; b1 <= N - 2; ++b1)
+            for (int b2 = -N + 1; b2 <= N - 2; ++b2) {
+                const int b[3] = {b0, b1, b2};
+                int bc[3], perm[3], sgn[3];
+                canonicalize(d, b, bc, perm, sgn);
+                const int rot = rot_index(P->grp, perm, sgn);
+                const int kc = t->canon_row[((size_t)bc[0] * N + bc[1]) * N + bc[2]];
+                if (rot < 0 || kc < 0) return fail(BNQ_EINVAL, "internal: canonical form of b not found");
+                int lo[3];
+                for (int i = 0; i < 3; ++i) lo[perm[i]] = (d == 2 && i == 0) ? 0 : -h + (sgn[i] < 0 ? 1 : 0);
+                bool empty = false;
+                for (int j = 0; j < 3; ++j) {
+                    if (d == 2 && j == 0) continue;
+                    const int L0 = lo[j], H0 = lo[j] + N - 1, c = bc[j];
+                    if (L0 + c > H0 || std::max(L0, c - H0) > std::min(H0, c - L0)) empty = true;
+                }
+                if (empty) continue;
+                const auto key = std::make_pair(kc, d == 3 ? lo[2] : 0);
+                auto it = gidx.find(key);
+                int gi;
+                if (it == gidx.end()) {
+                    gi = (int)gd.size();
+                    gidx[key] = gi;
+                    T1G G{};
+                    G.kc = kc;
+                    for (int j = 0; j < 3; ++j) G.bc[j] = bc[j];
+                    gd.push_back(G);
+                    glo.push_back({INT32_MAX, INT32_MAX, INT32_MAX});
+                    ghi.push_back({INT32_MIN, INT32_MIN, INT32_MIN});
+                } else {
+                    gi = it->second;
+                }
+                T1G &G = gd[gi];
+                if (G.nrot >= 24) return fail(BNQ_EINVAL, "internal: more than 24 rotations in a trilinear group");
+                G.rot[G.nrot++] = rot;
+                for (int j = 0; j < 3; ++j) {
+                    glo[gi][j] = std::min(glo[gi][j], lo[j]);
+                    ghi[gi][j] = std::max(ghi[gi][j], lo[j]);
+                }
+            }
+    struct It {
+        T1Item it;
+        double cost;
+    };
+    std::vector<It> items;
+    for (size_t gi = 0; gi < gd.size(); ++gi) {
+        T1G &G = gd[gi];
+        for (int j = 0; j < 3; ++j) {
+            if (d == 2 && j == 0) {
+                G.wn0[j] = G.wp0[j] = 0;
+                G.wnl[j] = G.wpl[j] = 1;
+                continue;
+            }
+            const int c = G.bc[j], la = glo[gi][j], lb = ghi[gi][j];
+            // outputs: lo + c .. lo + N - 1; inner: max(lo, c - lo - N + 1) .. min(lo + N - 1, c - lo)
+            G.wn0[j] = la + c;
+            G.wnl[j] = lb + N - 1 - (la + c) + 1;
+            const int p0 = std::min(std::max(la, c - la - N + 1), std::max(lb, c - lb - N + 1));
+            const int p1 = std::max(std::min(la + N - 1, c - la), std::min(lb + N - 1, c - lb));
+            G.wp0[j] = p0;
+            G.wpl[j] = p1 - p0 + 1;
+        }
+        const int W = G.wnl[0] * G.wnl[1] * G.wnl[2];
+        const double rows = (double)G.wpl[0] * G.wpl[1];
+        const int KS = (G.wpl[2] + 3) / 4, NT = (2 * G.nrot + 15) / 16;
+        // the kernel stages rows of more than 64 inner values for at most 8 rotations
+        if (4 * KS > 64 && G.nrot > 8) return fail(BNQ_ENOTSUP, "trilinear rows of %d values in 3-D", G.wpl[2]);
+        const double cost = rows * (KS * NT * 2 * 32 + 150) + NT * 8 * 1000;
+        for (int mb = 0; mb * T1M_BLOCK < W; ++mb) {
+            // kernel-mode values the item stages per row: its output x-lines
+            // times every n'_x - p'_x
+            const int lnx = G.wnl[2], m0 = mb * T1M_BLOCK;
+            const int nlines = (std::min(m0 + T1M_BLOCK, W) - 1) / lnx - m0 / lnx + 1;
+            if (nlines * (lnx + 4 * KS - 1) > T1M_KLINE)
+                return fail(BNQ_ENOTSUP, "trilinear item stages %d kernel-mode values per row (at most %d)",
+                            nlines * (lnx + 4 * KS - 1), T1M_KLINE);
+            It x;
+            x.it.b = (int)gi;
+            x.it.t0 = mb;
+            x.it.nt = 0;
+            x.it.inst = 0;
+            x.cost = cost;
+            items.push_back(x);
+        }
+    }
+    int dev = 0, cus = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int per_cu = trilinear_blocks_per_cu(1, N);
+    if (cus <= 0 || per_cu <= 0) return fail(BNQ_EHIP, "trilinear occupancy query failed");
+    const int nx = P->tune.xcd ? std::max(1, cus / kCusPerXcd) : 1;
+    int nwg = std::min(kMaxSlots / T1M_WAVES, std::max(1, cus * per_cu / std::max(1, P->tune.slot_div)));
+    nwg = std::max(nx, nwg - nwg % nx);
+    double total = 0;
+    for (const It &x : items) total += x.cost;
+    std::vector<int> off(1, 0);
+    std::vector<T1Item> flat;
+    flat.reserve(items.size());
+    if (P->p.schedule == BNQ_SCHED_DYNAMIC) {
+        size_t i = 0;
+        double acc = 0;
+        for (int x = 0; x < nx; ++x) {
+            const double cut = total * (x + 1) / nx;
+            for (; i < items.size() && (x == nx - 1 || acc + 0.5 * items[i].cost <= cut); ++i) {
+                acc += items[i].cost;
+                flat.push_back(items[i].it);
+            }
+            off.push_back((int)flat.size());
+        }
+        P->nq = nx;
+    } else {
+        std::vector<std::vector<T1Item>> per(nwg);
+        const int wpx = nwg / nx;  // workgroups per XCD
+        size_t i = 0;
+        double acc = 0;
+        for (int x = 0; x < nx; ++x) {
+            const double cut = total * (x + 1) / nx;
+            size_t k = 0;
+            for (; i < items.size() && (x == nx - 1 || acc + 0.5 * items[i].cost <= cut); ++i, ++k) {
+                acc += items[i].cost;
+                const size_t round = k / wpx, j = k % wpx;
+                const size_t sj = (round & 1) ? wpx - 1 - j : j;
+                per[x + nx * sj].push_back(items[i].it);
+            }
+        }
+        off.assign(nwg + 1, 0);
+        for (int w = 0; w < nwg; ++w) {
+            off[w] = (int)flat.size();
+            flat.insert(flat.end(), per[w].begin(), per[w].end());
+        }
+        off[nwg] = (int)flat.size();
+    }
+    P->nslots = nwg * T1M_WAVES;
+    P->nbdesc = (int)gd.size();
+    P->items_h = flat;
+    P->off_h = off;
+    P->nchunk = t1_chunks(t1_terms(d, N));
+    bnq_status st;
+    if ((st = upload(&P->gdesc, gd, "trilinear groups")) ||
+        (!flat.empty() && (st = upload(&P->items, flat, "trilinear items"))) ||
+        (st = upload(&P->t1cut, t1_cuts(off, P->nchunk), P->nq ? "trilinear queues" : "trilinear lists")) ||
+        (P->nq && (st = dalloc(&P->qctr, (size_t)((P->nq + 1) & ~1), "trilinear queue tickets"))))
+        return st;
+    return dalloc(&P->part, (size_t)P->nslots * g.nm, "trilinear partial sums");
+}
+
 // Rebuilds the trilinear work lists and partial arrays for P->tune.
 bnq_status rebuild_t1(bnq_plan_s *P, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
     hipFree(P->bdesc);
+    hipFree(P->gdesc);
     hipFree(P->items);
     hipFree(P->t1cut);
     hipFree(P->part);
@@ -832,6 +1002,7 @@ bnq_status rebuild_t1(bnq_plan_s *P, hipStream_t s) {
     P->qctr = nullptr;
     P->nq = 0;
     P->bdesc = nullptr;
+    P->gdesc = nullptr;
     P->items = nullptr;
     P->t1cut = nullptr;
     P->part = nullptr;
@@ -871,6 +1042,7 @@ void destroy_plan(bnq_plan_s *P) {
     hipFree(P->t1cut);
     hipFree(P->items);
     hipFree(P->bdesc);
+    hipFree(P->gdesc);
     hipFree(P->inst_d);
     hipFree(P->qctr);
     hipFree(P->sep_al);
@@ -902,6 +1074,7 @@ struct Exec {
     const int *t1cut = nullptr;    // their item ranges, (nchunk + 1) x (nq or nslots)
     const T1Item *items = nullptr;
     const T1B *bdesc = nullptr;
+    const T1G *gdesc = nullptr;
     const Inst *D = nullptr;
     int prec = 0;               // 0 FP64, 1 FP32c
     bool otf = false;           // FP64: pair weights formed on the fly
@@ -926,6 +1099,7 @@ Exec exec_of(bnq_plan_s *P) {
     E.t1cut = P->t1cut;
     E.items = P->items;
     E.bdesc = P->bdesc;
+    E.gdesc = P->gdesc;
     E.D = P->inst_d;
     E.prec = P->p.precision == BNQ_FP32C ? 1 : 0;
     E.otf = P->otf;
@@ -1013,7 +1187,7 @@ bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s
                 LAUNCHCHK();
             }
         }
-        const int nl = E.nq ? E.nq : E.nslots;
+        const int nl = E.nq ? E.nq : t1_lists(E.prec, E.nslots);
         for (int r = 0; r < E.nchunk; ++r) {
             if (E.nq) {
                 launch_zero(E.qctr, (int64_t)((E.nq + 1) & ~1) * (int64_t)sizeof(int), s);  // whole 8-byte words
@@ -1021,7 +1195,8 @@ bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s
             }
             Span sp(E.timer, 3, s);
             launch_trilinear(g, E.prec, E.nslots, E.t1cut + (size_t)r * nl, E.t1cut + (size_t)(r + 1) * nl, E.items,
-                             E.bdesc, E.prec ? (const void *)E.t->K32 : (const void *)E.t->K, E.D, E.rots, E.nq,
+                             E.prec ? (const void *)E.gdesc : (const void *)E.bdesc,
+                             E.prec ? (const void *)E.t->K32 : (const void *)E.t->K, E.D, E.rots, E.nq,
                              E.qctr, s);
             LAUNCHCHK();
         }
@@ -1647,7 +1822,8 @@ bnq_status bnq_table_lookup(bnq_plan_t P, int32_t table, int64_t n, const int32_
             int ap[3];
             for (int c = 0; c < 3; ++c) ap[perm[c]] = sgn[c] * x[c];
             const int kc = t->canon_row[((size_t)bc[0] * N + bc[1]) * N + bc[2]];
-            idx[i] = (int64_t)kc * g.nak + idx_K(g, ap[0], ap[1], ap[2]);
+            // the FP64 rows are y-fastest, the FP32 ones x-fastest
+            idx[i] = (int64_t)kc * g.nak + (t->K ? idx_K(g, ap[0], ap[1], ap[2]) : idx_Kx(g, ap[0], ap[1], ap[2]));
         } else if (table == 1 || table == 2) {
             for (int c = (d == 3 ? 0 : 1); c < 3; ++c)
                 if (x[c] < -h || x[c] >= h || y[c] < -h || y[c] >= h)
@@ -1903,12 +2079,13 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
                 off.push_back((int)items.size());
             }
         } else {
-            off.assign(ns + 1, 0);
-            for (int sl = 0; sl < ns; ++sl) {
+            const int prec = G.E.prec, nl = t1_lists(prec, ns);
+            off.assign(nl + 1, 0);
+            for (int sl = 0; sl < nl; ++sl) {
                 off[sl] = (int)items.size();
                 for (size_t j = 0; j < G.members.size(); ++j) {
                     const bnq_plan_s *P = plans[G.members[j]];
-                    if (!(P->ih.terms & BNQ_T_QTRI) || sl >= P->nslots) continue;
+                    if (!(P->ih.terms & BNQ_T_QTRI) || sl >= t1_lists(prec, P->nslots)) continue;
                     for (int k = P->off_h[sl]; k < P->off_h[sl + 1]; ++k) {
                         T1Item x = P->items_h[k];
                         x.inst = (int)j;
@@ -1916,7 +2093,7 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
                     }
                 }
             }
-            off[ns] = (int)items.size();
+            off[nl] = (int)items.size();
         }
         // launches per evaluation: by the trilinear terms of the whole group
         double terms = 0;

@@ -55,6 +55,13 @@ __host__ __device__ inline int64_t idx_K(const Geo &g, int a0, int a1, int a2) {
     const int A = 2 * g.N - 1;
     return ((int64_t)(g.d == 3 ? a0 + g.N - 1 : 0) * g.kax + (a2 + g.N - 1 + KPADLO)) * A + (a1 + g.N - 1);
 }
+// offset of a inside a stored trilinear row of the x-fastest layout (the FP32
+// rows, read by the matrix-core trilinear kernel): [a0][a1][a2 + pad], x
+// padded as in idx_K
+__host__ __device__ inline int64_t idx_Kx(const Geo &g, int a0, int a1, int a2) {
+    const int A = 2 * g.N - 1;
+    return ((int64_t)(g.d == 3 ? a0 + g.N - 1 : 0) * A + (a1 + g.N - 1)) * g.kax + (a2 + g.N - 1 + KPADLO);
+}
 __host__ __device__ inline int64_t idx_X(const Geo &g, int q0, int q1, int q2) {
     const int X = g.N + 1;
     return ((int64_t)(g.d == 3 ? q0 + g.h : 0) * X + (q1 + g.h)) * X + (q2 + g.h);
@@ -75,6 +82,19 @@ struct T1B {
     int wplo[3], wphi[3];  // inner window in the rotated frame
     int nxb;         // x-blocks of the output window
     int pad;         // outputs per x-block (6, 7 or 8; always 8 for FP32c)
+};
+
+// A group of the matrix-core trilinear sum: the b = R b_c (canonical row kc)
+// whose rotated frames share the lower edge of the x window (3-D), or all of
+// them (2-D); outputs n' and inner modes p' run over the union of the
+// members' windows (first value and length per rotated axis).
+struct T1G {
+    int kc;
+    int bc[3];
+    int wn0[3], wnl[3];
+    int wp0[3], wpl[3];
+    int nrot;
+    int rot[24];
 };
 
 struct T1Item {
@@ -293,18 +313,22 @@ void launch_zero_part(const Geo &g, const Inst *D, const IOs &io, int max_slots,
 // nq = 0: static per-slot lists; nq > 0: dynamic tickets over nq queues
 // Trilinear sum over the item ranges [lo[i], hi[i]) of the nslots slots
 // (static) or nq queues (dynamic).
+// desc: T1B array (FP64) or T1G array (FP32c); nslots partial arrays
 void launch_trilinear(const Geo &g, int prec, int nslots, const int *lo, const int *hi, const T1Item *items,
-                      const T1B *bdesc, const void *K, const Inst *D, const Rot *rots, int nq, int *qctr,
+                      const void *desc, const void *K, const Inst *D, const Rot *rots, int nq, int *qctr,
                       hipStream_t s);
 void launch_t1_pairs(const Geo &g, int nslots, const int *lo, const int *hi, const T1Item *items,
                      const T1B *bdesc, const double *K, const Inst *D, const Rot *rots, int nq, int *qctr,
                      hipStream_t s);
-void launch_t1_rows(const Geo &g, int nslots, const int *lo, const int *hi, const T1Item *items,
-                    const T1B *bdesc, const float *K, const Inst *D, const Rot *rots, int nq, int *qctr,
-                    hipStream_t s);
+// FP32c: matrix-core kernel, nwg workgroups of 4 waves, partial array 4 wg + wave
+void launch_t1_mfma(const Geo &g, int nwg, const int *lo, const int *hi, const T1Item *items, const T1G *gdesc,
+                    const float *K, const Inst *D, const Rot *rots, int nq, int *qctr, hipStream_t s);
 int t1_pairs_blocks_per_cu();
-int t1_rows_blocks_per_cu();
-int trilinear_blocks_per_cu(int prec);  // resident 64-lane trilinear workgroups per CU (0 on error)
+int t1_mfma_blocks_per_cu(int N);
+constexpr int T1M_WAVES = 8;     // waves (partial arrays) per matrix-core workgroup
+constexpr int T1M_BLOCK = 128;   // outputs of a matrix-core item
+constexpr int T1M_KLINE = 1280;  // kernel-mode values a matrix-core item stages per inner row (LDS floats)
+int trilinear_blocks_per_cu(int prec, int N);  // resident trilinear workgroups per CU (0 on error)
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_reduce_partials(const Geo &g, const Inst *D, const IOs &io, int max_slots, hipStream_t s);
 void launch_combine(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
