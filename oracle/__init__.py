@@ -71,6 +71,12 @@ def lib():
         L.or_beta3_inv.restype = f64
         L.or_beta2_vec.argtypes = [f64, f64, f64, f64, f64, f64, i32]
         L.or_beta2_vec.restype = f64
+        L.or_beta3_series_pairs.argtypes = [i64, vp, vp, vp, vp, i32, vp, f64]
+        L.or_beta3_series_pairs.restype = None
+        L.or_series_modes.argtypes = [i32, vp, vp, i32, vp, f64, i32, i64, vp, vp, vp, vp, vp, vp]
+        L.or_series_modes.restype = None
+        L.or_w_series.argtypes = [i32, vp, vp, i32, vp, f64, vp]
+        L.or_w_series.restype = None
         _lib = L
     return _lib
 
@@ -259,6 +265,74 @@ class Oracle:
         k3 = self.rhs(f + 0.5 * dt * k2, eps, L, hbar, c)
         k4 = self.rhs(f + dt * k3, eps, L, hbar, c)
         return f + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+
+
+# --------------------------------------------------------------------------
+# 3-D kernel modes by their Funk–Hecke series (bnq_oracle.c, beta3_series):
+# for full-size checks, where a quadrature per kernel mode is too slow
+class RadialSeries:
+    """Radial integrals J_n(s) = int_0^R r j_n(r s) dr at s = sqrt(q), q = 0 ..
+    qmax, even n only (J[q, m] = J_{2m}), by Gauss-Legendre over spherical
+    Bessel values (scipy), and the number of even orders kept per q: the
+    series is cut where J_n(s) has fallen below rounding, n > R s +
+    12 (R s)^(1/3) + 24 (doubling the cut changes nothing, tests)."""
+
+    def __init__(self, qmax: int, R: float = R_DEFAULT, nodes: int = 200, extra: float = 1.0):
+        from scipy.special import spherical_jn
+        x, w = np.polynomial.legendre.leggauss(nodes)
+        r = 0.5 * R * (x + 1.0)
+        wr = 0.5 * R * w * r
+        kap = np.sqrt(np.arange(qmax + 1, dtype=np.float64))
+        ncut = np.ceil(extra * (R * kap + 12.0 * np.cbrt(R * kap) + 24.0)).astype(np.int64)
+        self.mcut = np.ascontiguousarray(ncut // 2 + 1, dtype=np.int32)
+        self.nm = int(self.mcut.max())
+        orders = 2 * np.arange(self.nm)
+        J = np.zeros((qmax + 1, self.nm))
+        for q in range(qmax + 1):
+            m = int(self.mcut[q])
+            J[q, :m] = spherical_jn(orders[:m, None], r[None, :] * kap[q]) @ wr
+        self.J = np.ascontiguousarray(J)
+        self.qmax, self.R = qmax, R
+
+
+def beta3_series_pairs(a, b, rs: RadialSeries, Cphi: float = 1.0) -> np.ndarray:
+    """beta(a_i, b_i) for 3-D integer vectors (n x 3) by the series."""
+    A = np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(-1, 3))
+    B = np.ascontiguousarray(np.asarray(b, dtype=np.int32).reshape(-1, 3))
+    if max(np.max(np.sum(A.astype(np.int64) ** 2, axis=1)), np.max(np.sum(B.astype(np.int64) ** 2, axis=1))) > rs.qmax:
+        raise ValueError("vector beyond the radial table")
+    out = np.zeros(A.shape[0])
+    lib().or_beta3_series_pairs(A.shape[0], A.ctypes.data, B.ctypes.data, out.ctypes.data, rs.J.ctypes.data, rs.nm,
+                                rs.mcut.ctypes.data, Cphi)
+    return out
+
+
+def series_modes(f: np.ndarray, eps: int, select, hbar: float = 1.0, Cphi: float = 1.0, rs: RadialSeries = None):
+    """3-D Galerkin modes at the output modes `select` (linear indices in I_N)
+    with series kernel modes: dict of complex arrays over I_N (zero where not
+    selected) 'Qc', 'gain', 'T1', 'Xq' and 'Qhat' = Qc - alpha (T1 + Xq), the
+    quantum parts only when eps != 0.  W is summed over all of E first."""
+    N = f.shape[0]
+    if f.ndim != 3:
+        raise ValueError("3-D data only")
+    if rs is None:
+        rs = RadialSeries(3 * N * N)
+    G = np.ascontiguousarray(dft(f), dtype=np.complex128)
+    sel = np.ascontiguousarray(select, dtype=np.int64)
+    out = {k: np.zeros(G.size, dtype=np.complex128) for k in ("Qc", "gain", "T1", "Xq")}
+    W = np.zeros((2 * N) ** 3, dtype=np.complex128)
+    want = 1
+    if eps != 0:
+        lib().or_w_series(N, G.ctypes.data, rs.J.ctypes.data, rs.nm, rs.mcut.ctypes.data, Cphi, W.ctypes.data)
+        want |= 2 | 4
+    lib().or_series_modes(N, G.ctypes.data, rs.J.ctypes.data, rs.nm, rs.mcut.ctypes.data, Cphi, want, sel.size,
+                          sel.ctypes.data, W.ctypes.data, out["Qc"].ctypes.data, out["gain"].ctypes.data,
+                          out["T1"].ctypes.data, out["Xq"].ctypes.data)
+    res = {k: v.reshape(G.shape) for k, v in out.items()}
+    alpha = alpha_of(eps, 3, hbar)
+    res["Qhat"] = res["Qc"] - alpha * (res["T1"] + res["Xq"])
+    res["Ghat"] = G
+    return res
 
 
 # --------------------------------------------------------------------------

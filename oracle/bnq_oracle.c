@@ -536,3 +536,163 @@ int or_num_threads(void) {
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------- */
+/* 3-D kernel modes by their Funk–Hecke series, for full-size checks where a
+ * quadrature per value is too slow.  Expanding both plane waves of the
+ * Lemma's integral in spherical harmonics, the delta(z.y) constraint gives
+ * int_{S^2} delta(e.e') P_n(e'.l) de' = 2 pi P_n(0) P_n(e.l), and with
+ * Btilde = 4 C_phi (hard spheres)
+ *   beta(k,l) = 32 pi^2 C_phi sum_{n even} (2n+1) P_n(0) P_n(cos g)
+ *               J_n(|k|) J_n(|l|),   J_n(s) = int_0^R r j_n(r s) dr,
+ * g the angle between k and l (odd n drop out: P_n(0) = 0).  The radial
+ * integrals come from the caller (oracle.radial_series: Gauss–Legendre over
+ * spherical Bessel values), J[q * nm + m] = J_{2m}(sqrt q), and mcut[q] the
+ * number of even orders kept for |k|^2 = q; the series is cut at the smaller
+ * of the two counts.  Pinned against the quadrature above. */
+static double beta3_series(const double *J, int nm, const int *mcut, double Cphi, int64_t qa, int64_t qb,
+                           int64_t ab) {
+    const int mc = mcut[qa] < mcut[qb] ? mcut[qa] : mcut[qb];
+    double x = 1.0;
+    if (qa > 0 && qb > 0) {
+        x = (double)(ab < 0 ? -ab : ab) / sqrt((double)qa * (double)qb);
+        if (x > 1.0) x = 1.0;
+    }
+    const double *Ja = J + qa * nm, *Jb = J + qb * nm;
+    /* P_{2m}(0) = (-1)^m (2m-1)!! / (2m)!!, and (pe, po) = (P_{2m}(x),
+     * P_{2m+1}(x)) by the three-term recurrence (n+1) P_{n+1} = (2n+1) x P_n - n P_{n-1} */
+    double p0 = 1.0, pe = 1.0, po = x, sum = Ja[0] * Jb[0];
+    for (int m = 1; m < mc; ++m) {
+        p0 *= -(2.0 * m - 1.0) / (2.0 * m);
+        const double pe1 = ((4.0 * m - 1.0) * x * po - (2.0 * m - 1.0) * pe) / (2.0 * m);
+        const double po1 = ((4.0 * m + 1.0) * x * pe1 - 2.0 * m * po) / (2.0 * m + 1.0);
+        pe = pe1;
+        po = po1;
+        sum += (4.0 * m + 1.0) * p0 * pe * Ja[m] * Jb[m];
+    }
+    return 32.0 * OR_PI * OR_PI * Cphi * sum;
+}
+
+/* Exported: beta for n pairs of integer 3-vectors by the series. */
+void or_beta3_series_pairs(int64_t n, const int32_t *a, const int32_t *b, double *out, const double *J, int nm,
+                           const int *mcut, double Cphi) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t *x = a + 3 * i, *y = b + 3 * i;
+        const int64_t qa = (int64_t)x[0] * x[0] + (int64_t)x[1] * x[1] + (int64_t)x[2] * x[2];
+        const int64_t qb = (int64_t)y[0] * y[0] + (int64_t)y[1] * y[1] + (int64_t)y[2] * y[2];
+        const int64_t ab = (int64_t)x[0] * y[0] + (int64_t)x[1] * y[1] + (int64_t)x[2] * y[2];
+        out[i] = beta3_series(J, nm, mcut, Cphi, qa, qb, ab);
+    }
+}
+
+static inline int64_t dot3(int a0, int a1, int a2, int b0, int b1, int b2) {
+    return (int64_t)a0 * b0 + (int64_t)a1 * b1 + (int64_t)a2 * b2;
+}
+#define BS(a0, a1, a2, b0, b1, b2) \
+    beta3_series(J, nm, mcut, Cphi, dot3(a0, a1, a2, a0, a1, a2), dot3(b0, b1, b2, b0, b1, b2), dot3(a0, a1, a2, b0, b1, b2))
+
+/* Exported: 3-D Galerkin sums at selected output modes (linear indices in
+ * I_N, `sel`), with kernel modes from the series, written at the same
+ * positions of the output arrays (complex, over I_N):
+ *   want & 1: Qc_n = sum_{l+m=n} [beta(l,m) - beta(m,m)] G_l G_m and the gain
+ *             term Qg_n = sum_{l+m=n} beta(l,m) G_l G_m;
+ *   want & 4: T1_n = sum_{k+l+m=n} beta(k+m, l+m) G_k G_l G_m;
+ *   want & 2: X_n = sum_k G_k W_{n-k} from the pair sum W over X (or_w_series).
+ * Every index in I_N, as in the Lemma; the direct sums, no reordering. */
+void or_series_modes(int N, const double *G, const double *J, int nm, const int *mcut, double Cphi, int want,
+                     int64_t nsel, const int64_t *sel, const double *W, double *Qc, double *Qg, double *T1,
+                     double *Xo) {
+    geom_t gg;
+    geom_init(&gg, 3, N);
+    const geom_t *g = &gg;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nsel; ++q) {
+        const int64_t i = sel[q];
+        int n[3];
+        mode_of(g, i, n);
+        if (want & 1) {
+            cplx c = {0.0, 0.0}, c2 = {0.0, 0.0};
+            for (int l0 = g->lo[0]; l0 <= g->hi[0]; ++l0)
+                for (int l1 = g->lo[1]; l1 <= g->hi[1]; ++l1)
+                    for (int l2 = g->lo[2]; l2 <= g->hi[2]; ++l2) {
+                        const int m0 = n[0] - l0, m1 = n[1] - l1, m2 = n[2] - l2;
+                        if (!in_grid(g, m0, m1, m2)) continue;
+                        const double blm = BS(l0, l1, l2, m0, m1, m2), bmm = BS(m0, m1, m2, m0, m1, m2);
+                        const cplx p = cmul(cget(G, gidx(g, l0, l1, l2)), cget(G, gidx(g, m0, m1, m2)));
+                        c.re += (blm - bmm) * p.re;
+                        c.im += (blm - bmm) * p.im;
+                        c2.re += blm * p.re;
+                        c2.im += blm * p.im;
+                    }
+            Qc[2 * i] = c.re;
+            Qc[2 * i + 1] = c.im;
+            Qg[2 * i] = c2.re;
+            Qg[2 * i + 1] = c2.im;
+        }
+        if (want & 4) {
+            cplx acc = {0.0, 0.0};
+            for (int k0 = g->lo[0]; k0 <= g->hi[0]; ++k0)
+                for (int k1 = g->lo[1]; k1 <= g->hi[1]; ++k1)
+                    for (int k2 = g->lo[2]; k2 <= g->hi[2]; ++k2) {
+                        const cplx gk = cget(G, gidx(g, k0, k1, k2));
+                        for (int l0 = g->lo[0]; l0 <= g->hi[0]; ++l0)
+                            for (int l1 = g->lo[1]; l1 <= g->hi[1]; ++l1)
+                                for (int l2 = g->lo[2]; l2 <= g->hi[2]; ++l2) {
+                                    const int m0 = n[0] - k0 - l0, m1 = n[1] - k1 - l1, m2 = n[2] - k2 - l2;
+                                    if (!in_grid(g, m0, m1, m2)) continue;
+                                    const double w = BS(k0 + m0, k1 + m1, k2 + m2, l0 + m0, l1 + m1, l2 + m2);
+                                    const cplx p = cmul(cmul(gk, cget(G, gidx(g, l0, l1, l2))),
+                                                        cget(G, gidx(g, m0, m1, m2)));
+                                    acc.re += w * p.re;
+                                    acc.im += w * p.im;
+                                }
+                    }
+            T1[2 * i] = acc.re;
+            T1[2 * i + 1] = acc.im;
+        }
+        if (want & 2) {
+            cplx acc = {0.0, 0.0};
+            for (int k0 = g->lo[0]; k0 <= g->hi[0]; ++k0)
+                for (int k1 = g->lo[1]; k1 <= g->hi[1]; ++k1)
+                    for (int k2 = g->lo[2]; k2 <= g->hi[2]; ++k2) {
+                        const cplx p = cmul(cget(G, gidx(g, k0, k1, k2)),
+                                            cget(W, xidx(g, n[0] - k0, n[1] - k1, n[2] - k2)));
+                        acc.re += p.re;
+                        acc.im += p.im;
+                    }
+            Xo[2 * i] = acc.re;
+            Xo[2 * i + 1] = acc.im;
+        }
+    }
+}
+
+/* Exported: the pair sum W_s = sum_{l+m=s} [beta(l,m) - beta(l+m,l) -
+ * beta(l,l+m)] G_l G_m over s in X = {-N .. N-1}^3 (3-D, series kernel modes),
+ * complex, X order. */
+void or_w_series(int N, const double *G, const double *J, int nm, const int *mcut, double Cphi, double *W) {
+    geom_t gg;
+    geom_init(&gg, 3, N);
+    const geom_t *g = &gg;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t s = 0; s < g->xsize; ++s) {
+        const int s2 = (int)(s % g->xn[2]) + g->xlo[2];
+        const int s1 = (int)((s / g->xn[2]) % g->xn[1]) + g->xlo[1];
+        const int s0 = (int)(s / ((int64_t)g->xn[1] * g->xn[2])) + g->xlo[0];
+        cplx acc = {0.0, 0.0};
+        for (int l0 = g->lo[0]; l0 <= g->hi[0]; ++l0)
+            for (int l1 = g->lo[1]; l1 <= g->hi[1]; ++l1)
+                for (int l2 = g->lo[2]; l2 <= g->hi[2]; ++l2) {
+                    const int m0 = s0 - l0, m1 = s1 - l1, m2 = s2 - l2;
+                    if (!in_grid(g, m0, m1, m2)) continue;
+                    const double w = BS(l0, l1, l2, m0, m1, m2) - BS(s0, s1, s2, l0, l1, l2) -
+                                     BS(l0, l1, l2, s0, s1, s2);
+                    const cplx p = cmul(cget(G, gidx(g, l0, l1, l2)), cget(G, gidx(g, m0, m1, m2)));
+                    acc.re += w * p.re;
+                    acc.im += w * p.im;
+                }
+        W[2 * s] = acc.re;
+        W[2 * s + 1] = acc.im;
+    }
+}
+#undef BS

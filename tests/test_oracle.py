@@ -440,3 +440,51 @@ def test_rk4_step_is_fourth_order():
         assert 13.0 < a / b < 19.0, e
     e2 = [np.abs(run(n, midpoint) - ref).max() for n in (4, 8)]
     assert not (13.0 < e2[0] / e2[1] < 19.0)
+
+
+# ---------------------------------------------------------------- series kernel modes (3-D)
+def test_beta3_series_matches_quadrature():
+    # the Funk-Hecke series of the Lemma's integral against the polar
+    # quadrature of the same integral, random pairs and the axes
+    rs = oracle.RadialSeries(3 * 12 * 12)
+    rng = np.random.default_rng(1)
+    a = rng.integers(-11, 12, (300, 3))
+    b = rng.integers(-11, 12, (300, 3))
+    a[:3] = 0
+    b[2:5] = 0
+    b00 = 8 * math.pi ** 2 * oracle.R_DEFAULT ** 4
+    got = oracle.beta3_series_pairs(a, b, rs)
+    ref = oracle.beta_pairs(3, a, b)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * b00
+
+
+def test_beta3_series_closed_forms_and_cut():
+    # beta(0,0) = 8 pi^2 R^4, beta(k,0) = 16 pi^2 R^2 (1 - cos R|k|) / |k|^2
+    # (hard spheres, C_phi = 1); doubling the series cut and the radial nodes
+    # changes nothing at rounding level
+    R = oracle.R_DEFAULT
+    rs = oracle.RadialSeries(3 * 20 * 20)
+    k = np.array([[0, 0, 0], [1, 0, 0], [3, 4, 0], [7, 7, 7], [19, 2, 5]])
+    z = np.zeros_like(k)
+    got = oracle.beta3_series_pairs(k, z, rs)
+    kk = np.sqrt(np.sum(k ** 2, axis=1).astype(float))
+    ref = np.where(kk == 0, 8 * math.pi ** 2 * R ** 4,
+                   16 * math.pi ** 2 * R ** 2 * (1 - np.cos(R * kk)) / np.where(kk == 0, 1, kk) ** 2)
+    assert np.allclose(got, ref, rtol=0, atol=1e-13 * ref[0])
+    rng = np.random.default_rng(7)
+    a = rng.integers(-19, 20, (200, 3))
+    b = rng.integers(-19, 20, (200, 3))
+    fine = oracle.RadialSeries(3 * 20 * 20, nodes=400, extra=2.0)
+    assert np.max(np.abs(oracle.beta3_series_pairs(a, b, fine) - oracle.beta3_series_pairs(a, b, rs))) <= 1e-14 * ref[0]
+
+
+@pytest.mark.parametrize("eps", [-1, 1])
+def test_series_modes_equal_the_dense_sums(eps):
+    # the sampled-mode sums with series kernel modes equal the table-based
+    # direct sums (Qc, gain, T1, X) at every mode of a small dense datum
+    N, L = 6, 5.0
+    f = inp.gaussian_mixture(3, N, L, seed=4, fmax=0.9)
+    m = oracle.Oracle(3, N).modes(f, eps)
+    s = oracle.series_modes(f, eps, np.arange(N ** 3))
+    for k in ("Qc", "gain", "T1", "Xq", "Qhat"):
+        assert np.max(np.abs(s[k] - m[k])) <= 1e-13 * np.max(np.abs(m[k])), k
