@@ -101,7 +101,8 @@ def main():
     ap.add_argument("--dt", type=float, default=None,
                     help="time step (default 0.001 for the 3-D workloads c2, c3 and relax, whose data leave RK4's "
                          "stability region at dt = 0.01; 0.01 for c1, batch and serve)")
-    ap.add_argument("--precision", choices=("fp64", "fp32c"), default="fp64")
+    ap.add_argument("--precision", choices=("fp64", "fp32c"), default=None,
+                    help="arithmetic of the pair sums (default fp32c for c5, fp64 otherwise)")
     ap.add_argument("--eps", type=int, choices=(-1, 0, 1), default=-1,
                     help="statistics: -1 fermions (default, the trilinear-bound workload), +1 bosons, "
                          "0 classical (only the weight streaming of the pair sums: HBM-bound)")
@@ -110,12 +111,14 @@ def main():
                          "between runs) or static (the library default, bitwise reproducible)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-N", type=int, default=10)
-    ap.add_argument("--workload", choices=("c1", "c2", "c3", "relax", "batch", "serve"), default="c2",
+    ap.add_argument("--workload", choices=("c1", "c2", "c3", "relax", "batch", "serve", "c5"), default="c2",
                     help="c2: the 3-D N=32 fermion RK4 step (default); c1: the 2-D N=32 boson RK4 step; "
                          "c3: 3-D bosons near condensation in "
                          "FP32c (--N 32 or 48) with the error against FP64 every 10 steps; relax: the c2 "
                          "trajectory with entropy and distance to its Fermi-Dirac limit every 10 steps; batch: mixed "
-                         "instances stepped together; serve: Poisson arrivals")
+                         "instances stepped together; serve: Poisson arrivals (small cells); c5: the serving "
+                         "shape N in {16, 24, 32, 48} at 200 req/s in a bounded window, with the sustainable "
+                         "rate and a rate sweep on a reduced mix")
     ap.add_argument("--separated", action="store_true",
                     help="c1 only: the trilinear term by the separated-kernel transform route (rank-P kernel "
                          "modes on the doubled grid) instead of the direct sum")
@@ -123,7 +126,14 @@ def main():
                     help="c1 --separated: angle count P (101 is the library's default at N=32)")
     ap.add_argument("--instances", type=int, default=60, help="batch workload: number of instances")
     ap.add_argument("--cells", choices=("mixed", "small"), default="mixed", help="batch workload: cell set")
-    ap.add_argument("--rate", type=float, default=10.0, help="serve workload: mean arrivals per second")
+    ap.add_argument("--rate", type=float, default=None,
+                    help="serve / c5 workloads: mean arrivals per second (default 10 for serve, 200 for c5)")
+    ap.add_argument("--window", type=float, default=150.0, help="c5: wall-clock window of the full-mix run (s)")
+    ap.add_argument("--max-service", type=float, default=60.0,
+                    help="c5: refuse requests whose estimated service time exceeds this (s)")
+    ap.add_argument("--max-active", type=int, default=32, help="c5: most requests served at once")
+    ap.add_argument("--sweep", default="0.25,0.5,0.75,1,1.5",
+                    help="c5: offered rates (req/s) of the reduced-mix sweep; empty to skip")
     ap.add_argument("--no-sub", action="store_true",
                     help="c2: skip the short FP32c, classical (eps = 0) and serving sub-runs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -145,10 +155,16 @@ def main():
         __graft_entry__.build()
     if args.dt is None:
         args.dt = 0.001 if args.workload in ("c2", "c3", "relax") else 0.01
+    if args.rate is None:
+        args.rate = 200.0 if args.workload == "c5" else 10.0
+    if args.precision is None:
+        args.precision = "fp32c" if args.workload == "c5" else "fp64"
     if args.workload == "batch":
         return run_batch(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "c5":
+        return run_c5(args)
     if args.workload == "c3":
         return run_c3(args)
     if args.workload == "relax":
@@ -767,6 +783,133 @@ def run_serve(args):
                    "rate_per_s": args.rate},
         "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
         "serve": st,
+    }
+    print(json.dumps(out))
+
+
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_c5(args):
+    """The serving shape: Poisson arrivals at 200 req/s of 3-D solves, N in
+    {16, 24, 32, 48} (weights 4:3:2:1), eps in {-1, +1}, t_end ~ U[0.5, 5] at
+    dt = 0.01, mixed Gaussian data, FP32c.
+
+    1. Calibration: device seconds per RK4 step of one lone request at
+       N = 16, 24, 32 (measured); N = 48 from N = 32 by the growth of the
+       trilinear term count, (48/32)^9.
+    2. The first 256 arrivals served for a bounded wall-clock window, with
+       requests whose estimated service time exceeds --max-service refused:
+       offered against achieved load (device seconds per second), completions
+       and p50/p99 latency of what completed, and the rate the full mix could
+       sustain (1 / mean service time).
+    3. A rate sweep on a reduced mix (N in {16, 24}, weights 4:1, t_end ~
+       U[0.05, 0.2]): latency and achieved load per offered rate, arrivals
+       over about 40 s each, at most 60 s per rate."""
+    import collections
+
+    import numpy as np
+    import torch
+
+    from paper_2110_13735_amd import serve
+    import bnq_inputs as inp
+    import paper_2110_13735_amd as bnq
+
+    prec = bnq.FP32C if args.precision == "fp32c" else bnq.FP64
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    make = lambda r: inp.mixed_instance(r.d, r.N, r.eps, r.seed)  # noqa: E731
+    cost = {}
+    for N in (16, 24, 32):
+        f0, L = inp.mixed_instance(3, N, -1, 99)
+        with bnq.Plan(bnq.Params(d=3, N=N, eps=-1, L=L, precision=prec)) as pl:
+            f = torch.tensor(f0, device=dev)
+            pl.step(f, args.dt)
+            torch.cuda.synchronize()
+            k = 4 if N < 32 else 1
+            t0 = time.perf_counter()
+            for _ in range(k):
+                pl.step(f, args.dt)
+            torch.cuda.synchronize()
+            cost[N] = (time.perf_counter() - t0) / k
+        _progress(f"calibration: 3-D N={N}: {cost[N]:.4g} s per RK4 step")
+    cost[48] = cost[32] * 1.5 ** 9
+    step_cost = lambda r: cost[r.N]  # noqa: E731
+
+    def nsteps(r):
+        return max(1, int(math.ceil(r.t_end / args.dt - 1e-9)))
+
+    def hook_every(reqs, period):
+        last = [0.0]
+
+        def hook(srv, now):
+            if now - last[0] >= period:
+                last[0] = now
+                _progress(f"t={now:.0f}s done={sum(r.status == 'done' for r in reqs)} "
+                          f"active={sum(r.status == 'active' for r in reqs)}")
+        return hook
+
+    def serve_run(reqs, max_wall, max_service):
+        srv = serve.Server(make, budget_bytes=int(200e9), dt=args.dt, precision=prec, max_service_s=max_service,
+                           step_cost=step_cost, max_active=args.max_active)
+        try:
+            st = srv.run(reqs, max_wall=max_wall, on_tick=hook_every(reqs, 15.0))
+        finally:
+            srv.close()
+        span = max(r.arrival for r in reqs)
+        offered = sum(nsteps(r) * cost[r.N] for r in reqs) / max(span, 1e-9)
+        st["offered_device_s_per_s"] = offered
+        st["achieved_device_s_per_s"] = st["busy_s"] / st["elapsed_s"]
+        st["arrival_span_s"] = span
+        return st
+
+    # 2. the full mix
+    cells = [((3, 16), 4), ((3, 24), 3), ((3, 32), 2), ((3, 48), 1)]
+    reqs = serve.poisson_requests(256, rate=args.rate, seed=0, cells=cells, t_end=(0.5, 5.0))
+    mean_service = sum(nsteps(r) * cost[r.N] for r in reqs) / len(reqs)
+    _progress(f"full mix: 256 arrivals at {args.rate} req/s, mean service {mean_service:.1f} s, "
+              f"window {args.window} s")
+    full = serve_run(reqs, args.window, args.max_service)
+    per_cell = {}
+    for N in (16, 24, 32, 48):
+        rs = [r for r in reqs if r.N == N]
+        per_cell[f"3d{N}"] = {"arrivals": len(rs), "completed": sum(r.status == "done" for r in rs),
+                              "refused": sum(r.status == "refused" for r in rs),
+                              "failed": sum(r.status == "failed" for r in rs),
+                              "failed_eps": dict(collections.Counter(r.eps for r in rs if r.status == "failed")),
+                              "failed_steps_mean": float(np.mean([r.steps for r in rs if r.status == "failed"]))
+                              if any(r.status == "failed" for r in rs) else None,
+                              "est_service_s_mean": float(np.mean([nsteps(r) * cost[N] for r in rs])) if rs else 0}
+    full["per_cell"] = per_cell
+    # 3. the reduced-mix sweep
+    reduced = [((3, 16), 4), ((3, 24), 1)]
+    sweep = []
+    for rate in [float(x) for x in args.sweep.split(",") if x.strip()]:
+        n = max(8, int(round(rate * 40)))
+        rs = serve.poisson_requests(n, rate=rate, seed=1, cells=reduced, t_end=(0.05, 0.2))
+        _progress(f"sweep: {n} arrivals at {rate} req/s")
+        st = serve_run(rs, 60.0, None)
+        sweep.append({"rate_per_s": rate, "requests": n, "completed": st["completed"],
+                      "unfinished": st["unfinished"], "p50_latency_s": st["p50_latency_s"],
+                      "p99_latency_s": st["p99_latency_s"], "offered_device_s_per_s": st["offered_device_s_per_s"],
+                      "achieved_device_s_per_s": st["achieved_device_s_per_s"], "terms_per_s": st["terms_per_s"]})
+    red = serve.poisson_requests(1000, rate=1.0, seed=1, cells=reduced, t_end=(0.05, 0.2))
+    out = {
+        "metric": "served collision pair-terms/s; p50/p99 solve latency (serving shape)",
+        "value": full["terms_per_s"], "unit": "pair-terms/s", "n_gpus": 1, "steps": full["ticks"], "warmup": 0,
+        "ms_per_step": 1e3 * full["busy_s"] / max(1, full["ticks"]), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32c" if prec == bnq.FP32C else "f64", "data": "synthetic",
+        "config": {"workload": f"first 256 Poisson arrivals at {args.rate} req/s, 3-D N in (16, 24, 32, 48) "
+                               f"weights 4:3:2:1, eps +-1, t_end U[0.5, 5], RK4 dt={args.dt}, mixed Gaussian data; "
+                               f"{args.window} s window, at most {args.max_active} served at once, refusal above "
+                               f"{args.max_service} s estimated service",
+                   "rate_per_s": args.rate},
+        "p50_latency_s": full["p50_latency_s"], "p99_latency_s": full["p99_latency_s"],
+        "calibration_s_per_step": {f"3d{k}": v for k, v in cost.items()},
+        "full_mix_mean_service_s": mean_service, "full_mix_sustainable_rate_per_s": 1.0 / mean_service,
+        "reduced_mix_sustainable_rate_per_s": 1.0 / (sum(nsteps(r) * cost[r.N] for r in red) / len(red)),
+        "serve": full, "sweep": sweep,
     }
     print(json.dumps(out))
 

@@ -164,3 +164,29 @@ def test_pair_sums_at_the_largest_n_batched_and_solo():
     assert abs(qh[N // 2, N // 2]) <= 1e-12 * np.abs(qh).max()
     pa.close()
     pb.close()
+
+
+def test_graph_replayed_batch_matches_oracle():
+    """Each member of a graph-replayed batch, after two RK4 steps, against the
+    oracle's own RK4 trajectory (no solo run in between)."""
+    import oracle
+
+    plans, fs = _instances(seed0=40)
+    f0 = [f.cpu().numpy() for f in fs]
+    dt = 0.01
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with bnq.Batch(plans, fs) as B:
+        for _ in range(2):
+            B.step(dt, bnq.RK4, graph=True, stream=s)
+        s.synchronize()
+    for i, ((d, N, eps, cphi, hbar), f) in enumerate(zip(MIX, f0)):
+        L = 6.0 if d == 2 else 5.0
+        o = oracle.Oracle(d, N, Cphi=cphi)
+        for _ in range(2):
+            f = o.rk4_step(f, dt, eps, L, hbar=hbar)
+        got = fs[i].cpu().numpy()
+        err = np.linalg.norm(got - f) / np.linalg.norm(f)
+        assert err <= 1e-12, f"instance {i} {MIX[i]}: relative error {err:.2e}"
+    for pl in plans:
+        pl.close()
