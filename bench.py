@@ -33,6 +33,8 @@ STATS = {-1: "fermions", 0: "classical", 1: "bosons"}
 METRIC = "collision pair-terms/s at N=32^3 (FP32c vs FP64); p50/p99 solve latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trilinear_3d32_fp64_hbm_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_13735_amd", "csrc", "t1_pairs.hip")
+PAIRS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairs_3d32_fp64_hbm_traffic.json")
+PAIRS_SOURCE = os.path.join(ROOT, "paper_2110_13735_amd", "csrc", "collide.hip")
 PEAK_FP64_VALU = 78.6e12  # MI355X dense FP64 vector, FLOP/s
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E, GB/s
 PEAK_FP32_VALU = 157.3e12  # MI355X dense FP32 vector, FLOP/s (published; counts packed FP32)
@@ -88,6 +90,17 @@ def measured_traffic():
     with open(TRAFFIC_FILE) as fh:
         rec = json.load(fh)
     if rec.get("kernel_code_sha256") != code_hash(KERNEL_SOURCE):
+        return None
+    return rec
+
+
+def measured_pairs_traffic(kernel):
+    """The same for a pair-sum kernel (3-D N=32 FP64), keyed by kernel name."""
+    if not os.path.exists(PAIRS_TRAFFIC_FILE):
+        return None
+    with open(PAIRS_TRAFFIC_FILE) as fh:
+        rec = json.load(fh).get(kernel)
+    if rec is None or rec.get("kernel_code_sha256") != code_hash(PAIRS_SOURCE):
         return None
     return rec
 
@@ -238,8 +251,10 @@ def main():
         pr_avg_s = (pr_ms / pr_n) * 1e-3 if pr_n else float("nan")
         bytes_launch = counts["classical"] * (4 if prec == bnq.FP32C else 8)
         achieved = bytes_launch / pr_avg_s / 1e9
+        tr = measured_pairs_traffic("pairs_kernel<double, false>") if (prec == bnq.FP64 and N == 32) else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "kernel": "pairs_kernel",
+                    "frac": round(achieved / PEAK_HBM_GBS, 4),
+                    "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None, "kernel": "pairs_kernel",
                     "avg_ms": round(pr_avg_s * 1e3, 4), "launches": pr_n, "bytes_per_launch": bytes_launch}
         roofline["measured_peaks"] = measured_peaks(torch, dev)
         roofline["frac_of_measured_copy"] = round(achieved / roofline["measured_peaks"]["hbm_copy_GB_s"], 4)
@@ -363,11 +378,13 @@ def sub_eps0(args, f0, steps=10):
         pr_s = pr_ms / pr_n * 1e-3
         nbytes = plan.counts()["classical"] * (4 if prec == bnq.FP32C else 8)
         gbs = nbytes / pr_s / 1e9
+        tr = measured_pairs_traffic("pairs_kernel<double, false>") if (prec == bnq.FP64 and args.N == 32) else None
         res[name] = {"value": 4.0 * terms * steps / elapsed, "unit": "pair-terms/s", "steps": steps,
                      "ms_per_step": 1e3 * elapsed / steps,
                      "roofline": {"bound": "hbm", "kernel": "pairs_kernel", "avg_ms": round(pr_s * 1e3, 4),
                                   "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                  "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": nbytes}}
+                                  "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": nbytes,
+                                  "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None}}
         plan.close()
     return res
 

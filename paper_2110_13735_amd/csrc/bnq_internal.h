@@ -217,6 +217,18 @@ __device__ __forceinline__ double2 cmulT(double2 a, double2 b) { return cmul(a, 
 __device__ __forceinline__ float2 cmulT(float2 a, float2 b) { return cmulf(a, b); }
 __device__ __forceinline__ double2 ldT2(const double2 *p, int64_t i) { return ld2(p, i); }
 __device__ __forceinline__ float2 ldT2(const float2 *p, int64_t i) { return ld2f(p, i); }
+// A load through the constant address space: with a wave-uniform address it
+// becomes a scalar load (the value lands in scalar registers and costs no
+// vector memory instruction).  Only for data no kernel writes while the
+// reading kernel runs.
+__device__ __forceinline__ double2 ld_uniform(const double2 *p, int64_t i) {
+    const __attribute__((address_space(4))) double *q = (const __attribute__((address_space(4))) double *)p;
+    return make_double2(q[2 * i], q[2 * i + 1]);
+}
+__device__ __forceinline__ float2 ld_uniform(const float2 *p, int64_t i) {
+    const __attribute__((address_space(4))) float *q = (const __attribute__((address_space(4))) float *)p;
+    return make_float2(q[2 * i], q[2 * i + 1]);
+}
 
 
 // ---- instances --------------------------------------------------------------

@@ -194,7 +194,7 @@ __device__ __forceinline__ void pairs_body(const Geo &g, const typename V2<T>::t
             for (int j = 0; j < N; ++j) {
                 const int m2 = s2 - (j - h);
                 const bool ok = ok1 && m2 >= -h && m2 < h;
-                const T2 gl = Gl[j];
+                const T2 gl = ld_uniform(Gl, j);  // uniform over the wave
                 const T2 gm = gp[grow + (ok ? m2 + h : 0)];
                 const uint32_t vo = ok ? (uint32_t)((mrow + m2 + h) * (int)sizeof(T)) : OOB;
                 const int so = (int)((int64_t)j * nm * sizeof(T));
@@ -349,7 +349,7 @@ __device__ __forceinline__ void pairs_w_body(const Geo &g, const typename V2<T>:
             for (int t = 0; t < N; ++t) {
                 const bool isA = t <= k;
                 const int mi = isA ? k - t : k - t + N;
-                const T2 gl = Gl[t];
+                const T2 gl = ld_uniform(Gl, t);  // uniform over the wave
                 const T2 gm = gp[grow + mi];
                 const uint32_t vo = ok1 ? (uint32_t)((mrow + mi) * (int)sizeof(T)) : OOB;
                 const int so = (int)((int64_t)t * nm * sizeof(T));
