@@ -138,7 +138,13 @@ def main():
     ap.add_argument("--angles", type=int, default=101,
                     help="c1 --separated: angle count P (101 is the library's default at N=32)")
     ap.add_argument("--instances", type=int, default=60, help="batch workload: number of instances")
-    ap.add_argument("--cells", choices=("mixed", "small"), default="mixed", help="batch workload: cell set")
+    ap.add_argument("--cells", choices=("mixed", "small", "c4"), default="mixed",
+                    help="batch workload: cell set (c4: all 18 cells d in {2, 3}, N in {16, 24, 32}, eps in {-1, 0, 1})")
+    ap.add_argument("--tuning", default=None,
+                    help="batch workload: JSON file of tuned trilinear work distributions (read; with --autotune, "
+                         "written)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batch workload: autotune the first quantum instance of each cell before batching")
     ap.add_argument("--rate", type=float, default=None,
                     help="serve / c5 workloads: mean arrivals per second (default 10 for serve, 200 for c5)")
     ap.add_argument("--window", type=float, default=150.0, help="c5: wall-clock window of the full-mix run (s)")
@@ -692,7 +698,8 @@ def run_c3(args):
 
 
 BATCH_CELLS = {"mixed": [(2, 16), (2, 24), (2, 32), (3, 16), (3, 24)],
-               "small": [(2, 8), (2, 16), (2, 24), (3, 8), (3, 12)]}
+               "small": [(2, 8), (2, 16), (2, 24), (3, 8), (3, 12)],
+               "c4": [(2, 16), (2, 24), (2, 32), (3, 16), (3, 24), (3, 32)]}
 
 
 def run_batch(args):
@@ -710,39 +717,61 @@ def run_batch(args):
     torch.cuda.set_device(dev)
     cell_set = BATCH_CELLS[args.cells]
     cells = [(d, N, e) for (d, N) in cell_set for e in (-1, 0, 1)]
+    prec = bnq.FP32C if args.precision == "fp32c" else bnq.FP64
+    if args.tuning and os.path.exists(args.tuning) and not args.autotune:
+        _progress(f"tuning records loaded: {bnq.load_tuning(args.tuning)}")
     plans, f_b, f_s, terms = [], [], [], 0.0
+    tuned, tune_ms = set(), {}
     for i in range(args.instances):
         d, N, eps = cells[i % len(cells)]
         f0, L = inp.mixed_instance(d, N, eps, seed=i)
-        p = bnq.Params(d=d, N=N, eps=eps, L=L, precision=bnq.FP32C if args.precision == "fp32c" else bnq.FP64)
+        p = bnq.Params(d=d, N=N, eps=eps, L=L, precision=prec)
         pl = bnq.Plan(p)
+        if args.autotune and eps != 0 and (d, N, prec) not in tuned:
+            # the first quantum instance of a cell picks the work distribution;
+            # plans created afterwards start with the recorded choice
+            ch, ms = pl.autotune(torch.tensor(f0, device=dev), reps=2)
+            tuned.add((d, N, prec))
+            tune_ms[(d, N, prec)] = ms
+            _progress(f"autotune ({d}, {N}): choice {ch}, ms {np.round(ms, 3).tolist()}")
         plans.append(pl)
         terms += 4.0 * bnq.terms_per_eval(p, pl.counts())
         f_b.append(torch.tensor(f0, device=dev))
         f_s.append(torch.tensor(f0, device=dev))
+    if args.autotune and args.tuning:
+        _progress(f"tuning records saved: {bnq.save_tuning(args.tuning, sorted(tuned), tune_ms)}")
     dt = args.dt
     stream = torch.cuda.Stream()
     batch = bnq.Batch(plans, f_b)
     torch.cuda.synchronize()
+    _progress(f"{len(plans)} plans, {len(cells)} cells, {terms:.3e} terms per step")
 
     def solo_step():
         for pl, f in zip(plans, f_s):
             pl.step(f, dt)
 
-    for _ in range(args.warmup):
+    for w in range(args.warmup):
         batch.step(dt, bnq.RK4, graph=True, stream=stream)
         stream.synchronize()  # the plans' workspaces serve both runs: never overlap them
         solo_step()
         torch.cuda.synchronize()
+        _progress(f"warmup step {w + 1} done")
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         batch.step(dt, bnq.RK4, graph=True, stream=stream)
+        if args.steps > 1:
+            stream.synchronize()
+            _progress(f"batched step {k + 1}: {time.perf_counter() - t0:.1f} s")
     stream.synchronize()
     t_batch = (time.perf_counter() - t0) / args.steps
+    _progress(f"batched: {t_batch:.3f} s per step")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         solo_step()
+        if args.steps > 1:
+            torch.cuda.synchronize()
+            _progress(f"solo step {k + 1}: {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     t_solo = (time.perf_counter() - t0) / args.steps
     same = all(torch.equal(a, b) for a, b in zip(f_b, f_s))
@@ -764,7 +793,8 @@ def run_batch(args):
         "data": "synthetic",
         "config": {"workload": f"{args.instances} instances over cells (d, N) in {cell_set} x eps in (-1, 0, 1), "
                                f"Gaussian-mixture data (seed = instance), RK4 dt={dt}, one HIP-graph replay per step",
-                   "instances": args.instances, "terms_per_step": terms},
+                   "instances": args.instances, "terms_per_step": terms,
+                   "tuning": {f"{d}d{N}": bnq.tune_get(d, N, prec) for (d, N) in cell_set}},
         "solo": {"value": terms / t_solo, "ms_per_step": 1e3 * t_solo, "speedup": t_solo / t_batch},
         "bitwise_equal_to_solo": bool(same),
     }

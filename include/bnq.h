@@ -395,6 +395,17 @@ bnq_status bnq_plan_timing(bnq_plan_t plan, double *ms_host, int64_t *launches_h
 bnq_status bnq_plan_autotune(bnq_plan_t plan, const double *f, int32_t reps, double *ms_host, int32_t *choice_host,
                              bnq_stream_t stream);
 
+/* The process's record of tuned trilinear work distributions, per device and
+ * (d, N, precision): the index (0 .. 3, the candidates of bnq_plan_autotune)
+ * that plans created afterwards on the current device start with.
+ * bnq_tune_get(): *choice = the recorded index, or -1 if none.
+ * bnq_tune_set(): records choice for the current device (-1 removes the
+ *   record), e.g. from a table persisted by an earlier process; plans that
+ *   exist keep theirs.  Errors: EINVAL (choice outside -1 .. 3, d not 2 or 3,
+ *   unknown precision). */
+bnq_status bnq_tune_get(int32_t d, int32_t N, int32_t precision, int32_t *choice);
+bnq_status bnq_tune_set(int32_t d, int32_t N, int32_t precision, int32_t choice);
+
 /* ---- Batches ------------------------------------------------------------
  * Many independent instances of the same problem (the homogeneous equation
  * of section 'Convergence towards a steady state', each with its own plan and

@@ -16,6 +16,11 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libbnq.so")
+# Trilinear work distributions measured by bnq_plan_autotune on an MI355X for
+# the batch cells (d in {2, 3}, N in {16, 24, 32}, FP64 and FP32c); not loaded
+# by default (a tuned choice may change the last bits of a result): pass it to
+# load_tuning.
+TUNING_MI355X = os.path.join(HERE, "tuning_mi355x.json")
 
 BNQ_OK, BNQ_EINVAL, BNQ_ENOMEM, BNQ_EHIP, BNQ_ENOTSUP, BNQ_ENONFINITE, BNQ_EBOUND = 0, -1, -2, -3, -4, -5, -6
 T_CLASSICAL, T_QMULT, T_QTRI, T_ALL = 1, 2, 4, 7
@@ -139,6 +144,8 @@ def lib():
         L.bnq_plan_set_timing.argtypes = [vp, i32]
         L.bnq_plan_timing.argtypes = [vp, vp, vp]
         L.bnq_plan_autotune.argtypes = [vp, vp, i32, vp, vp, vp]
+        L.bnq_tune_get.argtypes = [i32, i32, i32, ctypes.POINTER(i32)]
+        L.bnq_tune_set.argtypes = [i32, i32, i32, i32]
         L.bnq_batch_create.argtypes = [i32, vp, vp, ctypes.POINTER(vp)]
         L.bnq_batch_destroy.argtypes = [vp]
         L.bnq_batch_collide.argtypes = [vp, vp, vp, vp]
@@ -153,7 +160,7 @@ def lib():
         L.bnq_step_rescaled.argtypes = [vp, vp, RS, f64, vp]
         for fn in ("bnq_plan", "bnq_plan_destroy", "bnq_plan_footprint", "bnq_collide", "bnq_step",
                    "bnq_moments", "bnq_health", "bnq_moments_noalloc", "bnq_table_lookup", "bnq_plan_counts", "bnq_plan_set_timing",
-                   "bnq_plan_timing", "bnq_plan_autotune", "bnq_batch_create", "bnq_batch_destroy", "bnq_batch_collide",
+                   "bnq_plan_timing", "bnq_plan_autotune", "bnq_tune_get", "bnq_tune_set", "bnq_batch_create", "bnq_batch_destroy", "bnq_batch_collide",
                    "bnq_batch_step", "bnq_equilibrium_solve", "bnq_fd_be_log", "bnq_equilibrium_fill",
                    "bnq_equilibrium_distance", "bnq_rescaled_init", "bnq_step_rescaled"):
             getattr(L, fn).restype = ctypes.c_int
@@ -296,6 +303,60 @@ class Plan:
         n = np.zeros(NKERNELS, dtype=np.int64)
         _check(lib().bnq_plan_timing(self._h, ms.ctypes.data, n.ctypes.data))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_FAMILIES)}
+
+
+def tune_get(d: int, N: int, precision: int):
+    """bnq_tune_get: the recorded trilinear work distribution (0 .. 3) for
+    (d, N, precision) on the current device, or None."""
+    ch = ctypes.c_int32(-1)
+    _check(lib().bnq_tune_get(int(d), int(N), int(precision), ctypes.byref(ch)))
+    return None if ch.value < 0 else ch.value
+
+
+def tune_set(d: int, N: int, precision: int, choice):
+    """bnq_tune_set: record a choice (None removes the record)."""
+    _check(lib().bnq_tune_set(int(d), int(N), int(precision), -1 if choice is None else int(choice)))
+
+
+def save_tuning(path: str, cells, ms=None, device: str = ""):
+    """Write the recorded choices of `cells` [(d, N, precision)] to a JSON file,
+    merged into what the file already holds (the entries of other cells
+    stay); ms: optional {cell: candidate times in ms} kept beside them."""
+    import json
+    data = {"format": "bnq-tuning-1", "device": device, "entries": []}
+    if os.path.exists(path):
+        with open(path) as fh:
+            data = json.load(fh)
+    ent = {(e["d"], e["N"], e["precision"]): e for e in data.get("entries", [])}
+    for d, N, prec in cells:
+        ch = tune_get(d, N, prec)
+        if ch is None:
+            continue
+        e = {"d": int(d), "N": int(N), "precision": int(prec), "choice": int(ch)}
+        if ms and (d, N, prec) in ms:
+            e["ms"] = [float(x) for x in ms[(d, N, prec)]]
+        ent[(d, N, prec)] = e
+    data["entries"] = [ent[k] for k in sorted(ent)]
+    if device:
+        data["device"] = device
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1)
+    os.replace(tmp, path)
+    return len(data["entries"])
+
+
+def load_tuning(path: str) -> int:
+    """Record every choice of a file written by save_tuning for the current
+    device (plans created afterwards start with them); returns the count."""
+    import json
+    with open(path) as fh:
+        data = json.load(fh)
+    if data.get("format") != "bnq-tuning-1":
+        raise ValueError(f"{path}: not a bnq tuning file")
+    for e in data["entries"]:
+        tune_set(e["d"], e["N"], e["precision"], e["choice"])
+    return len(data["entries"])
 
 
 class Batch:

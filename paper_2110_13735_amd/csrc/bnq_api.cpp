@@ -454,7 +454,9 @@ struct T1Tune {
 const T1Tune kTuneCandidates[] = {{1, 1}, {2, 1}, {1, 0}, {2, 0}};
 constexpr int kNumTune = 4;
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, T1Tune> g_tune;  // (device, d, N) -> choice of bnq_plan_autotune
+// (device, d, N, precision) -> index in kTuneCandidates chosen by
+// bnq_plan_autotune or set by bnq_tune_set
+std::map<std::tuple<int, int, int, int>, int> g_tune;
 }  // namespace
 
 struct bnq_plan_s {
@@ -593,6 +595,7 @@ size_t plan_workspace_bytes(const bnq_params *p, int nslots_est) {
     const size_t c = sizeof(double2), r = sizeof(double);
     const size_t nrot = p->d == 3 ? 48 : 8;
     const size_t f32 = p->precision == BNQ_FP32C ? sizeof(float2) * ((size_t)g.nm + nrot * g.next) : 0;
+    if (p->eps == 0 || !(p->terms & BNQ_T_QTRI)) nslots_est = 0;  // no trilinear partial arrays
     return c * (6 * (size_t)g.nm + g.neg + nrot * g.next + (size_t)nslots_est * g.nm +
                 (size_t)pair_split(g) * ((size_t)g.neg + g.nm) + (size_t)outer_split(g) * g.nm) +
            r * 5 * (size_t)g.nm + f32 + sep_bytes(p);
@@ -1450,10 +1453,11 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         int dev = 0;
         HIPCHK(hipGetDevice(&dev));
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune.find(std::make_tuple(dev, p->d, p->N));
-        if (it != g_tune.end()) P->tune = it->second;
+        auto it = g_tune.find(std::make_tuple(dev, p->d, p->N, (int)p->precision));
+        if (it != g_tune.end()) P->tune = kTuneCandidates[it->second];
     }
-    if ((st = build_t1_work(P))) {
+    // work lists and per-slot partial arrays only for plans with the trilinear term
+    if (p->eps != 0 && (p->terms & BNQ_T_QTRI) && (st = build_t1_work(P))) {
         destroy_plan(P);
         return st;
     }
@@ -1910,11 +1914,36 @@ bnq_status bnq_plan_autotune(bnq_plan_t P, const double *f, int32_t reps, double
         int dev = 0;
         HIPCHK(hipGetDevice(&dev));
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[std::make_tuple(dev, P->p.d, P->p.N)] = P->tune;
+        g_tune[std::make_tuple(dev, P->p.d, P->p.N, (int)P->p.precision)] = best;
     }
     if (ms_host)
         for (int c = 0; c < kNumTune; ++c) ms_host[c] = ms[c];
     if (choice_host) *choice_host = best;
+    return BNQ_OK;
+}
+
+bnq_status bnq_tune_get(int32_t d, int32_t N, int32_t precision, int32_t *choice) {
+    if (!choice) return fail(BNQ_EINVAL, "choice is NULL");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(dev, (int)d, (int)N, (int)precision));
+    *choice = it == g_tune.end() ? -1 : it->second;
+    return BNQ_OK;
+}
+
+bnq_status bnq_tune_set(int32_t d, int32_t N, int32_t precision, int32_t choice) {
+    if (choice < -1 || choice >= kNumTune) return fail(BNQ_EINVAL, "choice %d outside -1 .. %d", choice, kNumTune - 1);
+    if (d != 2 && d != 3) return fail(BNQ_EINVAL, "d must be 2 or 3");
+    if (precision != BNQ_FP64 && precision != BNQ_FP32C) return fail(BNQ_EINVAL, "unknown precision %d", precision);
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto key = std::make_tuple(dev, (int)d, (int)N, (int)precision);
+    if (choice < 0)
+        g_tune.erase(key);
+    else
+        g_tune[key] = choice;
     return BNQ_OK;
 }
 
@@ -2051,7 +2080,14 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
         }
     }
     for (auto &G : B->groups) {
+        // the group's trilinear descriptors and schedule come from a member
+        // that has the trilinear term (plans without it build no work lists)
         bnq_plan_s *P0 = plans[G.members[0]];
+        for (int m : G.members)
+            if (plans[m]->ih.terms & BNQ_T_QTRI) {
+                P0 = plans[m];
+                break;
+            }
         G.E = exec_of(P0);
         G.E.timer = nullptr;
         G.E.Dh.clear();
