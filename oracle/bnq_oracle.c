@@ -612,7 +612,7 @@ void or_series_modes(int N, const double *G, const double *J, int nm, const int 
         int n[3];
         mode_of(g, i, n);
         if (want & 1) {
-            cplx c = {0.0, 0.0}, c2 = {0.0, 0.0};
+            long double cr = 0.0L, ci = 0.0L, c2r = 0.0L, c2i = 0.0L;
             for (int l0 = g->lo[0]; l0 <= g->hi[0]; ++l0)
                 for (int l1 = g->lo[1]; l1 <= g->hi[1]; ++l1)
                     for (int l2 = g->lo[2]; l2 <= g->hi[2]; ++l2) {
@@ -620,18 +620,18 @@ void or_series_modes(int N, const double *G, const double *J, int nm, const int 
                         if (!in_grid(g, m0, m1, m2)) continue;
                         const double blm = BS(l0, l1, l2, m0, m1, m2), bmm = BS(m0, m1, m2, m0, m1, m2);
                         const cplx p = cmul(cget(G, gidx(g, l0, l1, l2)), cget(G, gidx(g, m0, m1, m2)));
-                        c.re += (blm - bmm) * p.re;
-                        c.im += (blm - bmm) * p.im;
-                        c2.re += blm * p.re;
-                        c2.im += blm * p.im;
+                        cr += (blm - bmm) * p.re;
+                        ci += (blm - bmm) * p.im;
+                        c2r += blm * p.re;
+                        c2i += blm * p.im;
                     }
-            Qc[2 * i] = c.re;
-            Qc[2 * i + 1] = c.im;
-            Qg[2 * i] = c2.re;
-            Qg[2 * i + 1] = c2.im;
+            Qc[2 * i] = (double)cr;
+            Qc[2 * i + 1] = (double)ci;
+            Qg[2 * i] = (double)c2r;
+            Qg[2 * i + 1] = (double)c2i;
         }
         if (want & 4) {
-            cplx acc = {0.0, 0.0};
+            long double ar = 0.0L, ai = 0.0L;
             for (int k0 = g->lo[0]; k0 <= g->hi[0]; ++k0)
                 for (int k1 = g->lo[1]; k1 <= g->hi[1]; ++k1)
                     for (int k2 = g->lo[2]; k2 <= g->hi[2]; ++k2) {
@@ -644,25 +644,25 @@ void or_series_modes(int N, const double *G, const double *J, int nm, const int 
                                     const double w = BS(k0 + m0, k1 + m1, k2 + m2, l0 + m0, l1 + m1, l2 + m2);
                                     const cplx p = cmul(cmul(gk, cget(G, gidx(g, l0, l1, l2))),
                                                         cget(G, gidx(g, m0, m1, m2)));
-                                    acc.re += w * p.re;
-                                    acc.im += w * p.im;
+                                    ar += w * p.re;
+                                    ai += w * p.im;
                                 }
                     }
-            T1[2 * i] = acc.re;
-            T1[2 * i + 1] = acc.im;
+            T1[2 * i] = (double)ar;
+            T1[2 * i + 1] = (double)ai;
         }
         if (want & 2) {
-            cplx acc = {0.0, 0.0};
+            long double ar = 0.0L, ai = 0.0L;
             for (int k0 = g->lo[0]; k0 <= g->hi[0]; ++k0)
                 for (int k1 = g->lo[1]; k1 <= g->hi[1]; ++k1)
                     for (int k2 = g->lo[2]; k2 <= g->hi[2]; ++k2) {
                         const cplx p = cmul(cget(G, gidx(g, k0, k1, k2)),
                                             cget(W, xidx(g, n[0] - k0, n[1] - k1, n[2] - k2)));
-                        acc.re += p.re;
-                        acc.im += p.im;
+                        ar += p.re;
+                        ai += p.im;
                     }
-            Xo[2 * i] = acc.re;
-            Xo[2 * i + 1] = acc.im;
+            Xo[2 * i] = (double)ar;
+            Xo[2 * i + 1] = (double)ai;
         }
     }
 }
@@ -679,7 +679,7 @@ void or_w_series(int N, const double *G, const double *J, int nm, const int *mcu
         const int s2 = (int)(s % g->xn[2]) + g->xlo[2];
         const int s1 = (int)((s / g->xn[2]) % g->xn[1]) + g->xlo[1];
         const int s0 = (int)(s / ((int64_t)g->xn[1] * g->xn[2])) + g->xlo[0];
-        cplx acc = {0.0, 0.0};
+        long double ar = 0.0L, ai = 0.0L;
         for (int l0 = g->lo[0]; l0 <= g->hi[0]; ++l0)
             for (int l1 = g->lo[1]; l1 <= g->hi[1]; ++l1)
                 for (int l2 = g->lo[2]; l2 <= g->hi[2]; ++l2) {
@@ -688,11 +688,11 @@ void or_w_series(int N, const double *G, const double *J, int nm, const int *mcu
                     const double w = BS(l0, l1, l2, m0, m1, m2) - BS(s0, s1, s2, l0, l1, l2) -
                                      BS(l0, l1, l2, s0, s1, s2);
                     const cplx p = cmul(cget(G, gidx(g, l0, l1, l2)), cget(G, gidx(g, m0, m1, m2)));
-                    acc.re += w * p.re;
-                    acc.im += w * p.im;
+                    ar += w * p.re;
+                    ai += w * p.im;
                 }
-        W[2 * s] = acc.re;
-        W[2 * s + 1] = acc.im;
+        W[2 * s] = (double)ar;
+        W[2 * s + 1] = (double)ai;
     }
 }
 #undef BS

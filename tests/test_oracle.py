@@ -488,3 +488,19 @@ def test_series_modes_equal_the_dense_sums(eps):
     s = oracle.series_modes(f, eps, np.arange(N ** 3))
     for k in ("Qc", "gain", "T1", "Xq", "Qhat"):
         assert np.max(np.abs(s[k] - m[k])) <= 1e-13 * np.max(np.abs(m[k])), k
+
+
+@pytest.mark.parametrize("name", ["dense_3d16_all_modes.npz", "c2_3d32_sampled_modes.npz"])
+def test_stored_dense_goldens_conserve_mass(name):
+    # the collision operator conserves mass (eq. conservationQ with psi = 1),
+    # and so does its Galerkin form: Qhat_0 = Qc_0 - alpha (T1_0 + X_0) = 0,
+    # where T1_0 and X_0 are each about a quarter of the gain term; the stored
+    # oracle values must keep that cancellation far below the 1e-12 bar
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    z = np.load(path, allow_pickle=False)
+    modes = [tuple(int(v) for v in m) for m in z["modes"]]
+    i0 = modes.index((0, 0, 0))
+    alpha = oracle.alpha_of(int(z["eps"]), 3)
+    q0 = z["Qc"][i0] - alpha * (z["T1"][i0] + z["Xq"][i0])
+    assert abs(z["T1"][i0]) > 0.1 * abs(z["gain"][i0])
+    assert abs(q0) <= 1e-14 * abs(z["gain"][i0])
