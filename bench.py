@@ -155,6 +155,9 @@ def main():
                     help="c5: offered rates (req/s) of the reduced-mix sweep; empty to skip")
     ap.add_argument("--no-sub", action="store_true",
                     help="c2: skip the short FP32c, classical (eps = 0) and serving sub-runs")
+    ap.add_argument("--metrics", default=None,
+                    help="append JSON lines to this file: every timed step's moments (c2), every request and a "
+                         "summary (serve, c5)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one 1 GiB device copy (read 1 GiB, write 1 GiB) so that a "
                          "counter run can calibrate FETCH_SIZE / WRITE_SIZE")
@@ -220,8 +223,15 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mom = None
-    for _ in range(args.steps):
+    log = None
+    if args.metrics:
+        from paper_2110_13735_amd.metrics import MetricsLog
+        log = MetricsLog(args.metrics)
+    for k in range(args.steps):
         mom = one_step()
+        if log is not None:  # moments() has synchronised: the step is complete
+            log.write("step", step=args.warmup + k + 1, t=(args.warmup + k + 1) * args.dt,
+                      wall_since_start_s=time.perf_counter() - t0, **mom)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kt = plan.timing()
@@ -816,8 +826,12 @@ def run_serve(args):
     prec = bnq.FP32C if args.precision == "fp32c" else bnq.FP64
     srv = serve.Server(lambda r: inp.mixed_instance(r.d, r.N, r.eps, r.seed), budget_bytes=int(64e9), dt=args.dt,
                        precision=prec)
+    log = None
+    if args.metrics:
+        from paper_2110_13735_amd.metrics import MetricsLog
+        log = MetricsLog(args.metrics)
     try:
-        st = srv.run(reqs)
+        st = srv.run(reqs, metrics=log)
     finally:
         srv.close()
     out = {
@@ -883,6 +897,11 @@ def run_c5(args):
         _progress(f"calibration: 3-D N={N}: {cost[N]:.4g} s per RK4 step")
     cost[48] = cost[32] * 1.5 ** 9
     step_cost = lambda r: cost[r.N]  # noqa: E731
+    log = None
+    if args.metrics:
+        from paper_2110_13735_amd.metrics import MetricsLog
+        log = MetricsLog(args.metrics)
+        log.write("calibration", s_per_step={f"3d{k}": v for k, v in cost.items()})
 
     def nsteps(r):
         return max(1, int(math.ceil(r.t_end / args.dt - 1e-9)))
@@ -901,7 +920,7 @@ def run_c5(args):
         srv = serve.Server(make, budget_bytes=int(200e9), dt=args.dt, precision=prec, max_service_s=max_service,
                            step_cost=step_cost, max_active=args.max_active)
         try:
-            st = srv.run(reqs, max_wall=max_wall, on_tick=hook_every(reqs, 15.0))
+            st = srv.run(reqs, max_wall=max_wall, on_tick=hook_every(reqs, 15.0), metrics=log)
         finally:
             srv.close()
         span = max(r.arrival for r in reqs)

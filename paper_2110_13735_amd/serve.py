@@ -319,7 +319,10 @@ class Server:
         inst["bytes"] = own
         return inst, need
 
-    def run(self, requests, max_wall: float | None = None, on_tick=None) -> dict:
+    def run(self, requests, max_wall: float | None = None, on_tick=None, metrics=None) -> dict:
+        """Serve `requests` until all have left (or max_wall seconds); on_tick(server,
+        now) is called at every tick boundary; metrics: a MetricsLog that gets
+        one line per request that leaves and a summary line."""
         ex = self.ex
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         lanes = {}  # (d, N) -> _Lane
@@ -463,14 +466,24 @@ class Server:
         done = [r for r in requests if r.status == "done" and r.done is not None]
         lat = np.array([r.latency for r in done]) if done else np.array([np.nan])
         count = collections.Counter(r.status for r in requests)
-        return {"completed": len(done), "failed": count.get("failed", 0), "cancelled": count.get("cancelled", 0),
-                "refused": count.get("refused", 0), "unfinished": count.get("active", 0) + count.get("pending", 0),
-                "requests": len(requests), "elapsed_s": elapsed, "ticks": ticks, "rebuilds": rebuilds,
-                "terms": terms_done, "terms_per_s": terms_done / elapsed if elapsed > 0 else 0.0,
-                "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
-                "mean_queue_s": float(np.mean([r.admitted - r.arrival for r in done])) if done else float("nan"),
-                "busy_s": busy, "device_s_per_step_member": {f"{k[0]}d{k[1]}": v for k, v in self.member_s.items()},
-                "fail_reasons": dict(collections.Counter(r.reason for r in requests if r.status == "failed"))}
+        if metrics is not None:
+            for r in requests:
+                metrics.write("request", rid=r.rid, d=r.d, N=r.N, eps=r.eps, t_end=r.t_end, status=r.status,
+                              reason=r.reason, arrival_s=r.arrival, admitted_s=r.admitted, done_s=r.done,
+                              latency_s=r.latency if r.done is not None else None,
+                              queue_s=(r.admitted - r.arrival) if r.admitted is not None else None,
+                              steps=r.steps, terms=r.terms)
+        stats = {"completed": len(done), "failed": count.get("failed", 0), "cancelled": count.get("cancelled", 0),
+                 "refused": count.get("refused", 0), "unfinished": count.get("active", 0) + count.get("pending", 0),
+                 "requests": len(requests), "elapsed_s": elapsed, "ticks": ticks, "rebuilds": rebuilds,
+                 "terms": terms_done, "terms_per_s": terms_done / elapsed if elapsed > 0 else 0.0,
+                 "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+                 "mean_queue_s": float(np.mean([r.admitted - r.arrival for r in done])) if done else float("nan"),
+                 "busy_s": busy, "device_s_per_step_member": {f"{k[0]}d{k[1]}": v for k, v in self.member_s.items()},
+                 "fail_reasons": dict(collections.Counter(r.reason for r in requests if r.status == "failed"))}
+        if metrics is not None:
+            metrics.write("serve_summary", **stats)
+        return stats
 
     def close(self):
         self.ex.close()
