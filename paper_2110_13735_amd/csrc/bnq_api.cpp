@@ -920,9 +920,10 @@ bnq_status build_t1_work_mfma(bnq_plan_s *P) {
             // times every n'_x - p'_x
             const int lnx = G.wnl[2], m0 = mb * T1M_BLOCK;
             const int nlines = (std::min(m0 + T1M_BLOCK, W) - 1) / lnx - m0 / lnx + 1;
-            if (nlines * (lnx + 4 * KS - 1) > T1M_KLINE)
+            const int lw4 = (lnx + 4 * KS - 1 + 3) & ~3;  // line stride in LDS
+            if (nlines * lw4 > T1M_KLINE)
                 return fail(BNQ_ENOTSUP, "trilinear item stages %d kernel-mode values per row (at most %d)",
-                            nlines * (lnx + 4 * KS - 1), T1M_KLINE);
+                            nlines * lw4, T1M_KLINE);
             It x;
             x.it.b = (int)gi;
             x.it.t0 = mb;

@@ -339,7 +339,7 @@ int t1_pairs_blocks_per_cu();
 int t1_mfma_blocks_per_cu(int N);
 constexpr int T1M_WAVES = 8;     // waves (partial arrays) per matrix-core workgroup
 constexpr int T1M_BLOCK = 128;   // outputs of a matrix-core item
-constexpr int T1M_KLINE = 1280;  // kernel-mode values a matrix-core item stages per inner row (LDS floats)
+constexpr int T1M_KLINE = 1536;  // kernel-mode values a matrix-core item stages per inner row (LDS floats)
 int trilinear_blocks_per_cu(int prec, int N);  // resident trilinear workgroups per CU (0 on error)
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_reduce_partials(const Geo &g, const Inst *D, const IOs &io, int max_slots, hipStream_t s);

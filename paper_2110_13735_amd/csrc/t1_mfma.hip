@@ -128,29 +128,33 @@ __device__ __forceinline__ void pstage_store(const PStage<NP> &S, const PVals<NP
 }
 
 // Kernel-mode staging.  The block's outputs cover nl x-lines; line l holds
-// K(a) for a = (nz - pz, ny - py, ax0 + x), x < lw, at float l * lw + x,
-// with lw = (window x length) + 4 KS - 1 and ax0 = wn0_x - wp0_x - 4 KS + 1:
-// every n'_x - p'_x of the line and of the row (a_y, a_z clamped into the
-// row: a clamped value only meets a zero pair product or an output that is
-// not written).  Element e = tid + 256 q of the nl * lw values.
-constexpr int KSL = (T1M_KLINE + NTH - 1) / NTH;
+// K(a) for a = (nz - pz, ny - py, ax0 + x), x < lw, at float l * lw4 + x
+// (lw4: lw rounded up to a multiple of 4), with lw = (window x length) +
+// 4 KS - 1 and ax0 = wn0_x - wp0_x - 4 KS + 1: every n'_x - p'_x of the line
+// and of the row (a_y, a_z clamped into the row: a clamped value only meets a
+// zero pair product or an output that is not written).  A thread stages 4
+// consecutive values of a line with one 16-byte load and one 16-byte LDS
+// store (the padding values past lw are never read); T1M_KLINE <= 4 NTH, so
+// one slot per thread, and the waves past the block's lines issue nothing.
+constexpr int KSL = (T1M_KLINE / 4 + NTH - 1) / NTH;
+static_assert(T1M_KLINE % 4 == 0 && KSL == 1, "one 16-byte kernel-mode slot per thread");
 struct KStage {
-    int ny[KSL], nz[KSL];  // the element's output line
-    int ax[KSL];           // its a_x, -1000: not staged
+    int ny[KSL], nz[KSL];  // the slot's output line
+    int ax[KSL];           // a_x of its first value, -1000: not staged
 };
 struct KVals {
-    float v[KSL];
+    f4v v[KSL];
 };
 
-__device__ __forceinline__ void kstage_setup(const T1G &G, int l0, int nl, int lw, int ax0, int tid, KStage &S) {
+__device__ __forceinline__ void kstage_setup(const T1G &G, int l0, int nl, int lw4, int ax0, int tid, KStage &S) {
 #pragma unroll
     for (int q = 0; q < KSL; ++q) {
-        const int e = tid + NTH * q;
-        const int l = e / lw, x = e - l * lw;
+        const int e = 4 * (tid + NTH * q);
+        const int l = e / lw4, x = e - l * lw4;
         const int L = l0 + l;
         S.ny[q] = G.wn0[1] + L % G.wnl[1];
         S.nz[q] = G.wn0[0] + L / G.wnl[1];
-        S.ax[q] = e < nl * lw ? ax0 + x : -1000;
+        S.ax[q] = e < nl * lw4 ? ax0 + x : -1000;
     }
 }
 
@@ -162,14 +166,14 @@ __device__ __forceinline__ void kstage_load(const Geo &g, __amdgpu_buffer_rsrc_t
         const int a0 = g.d == 3 ? min(max(S.nz[q] - pz, -N1), N1) : 0;
         const int a1 = min(max(S.ny[q] - py, -N1), N1);
         const int off = S.ax[q] > -1000 ? 4 * (int)idx_Kx(g, a0, a1, S.ax[q]) : OOB;
-        V.v[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(kr, off, 0, 0));
+        V.v[q] = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(kr, off, 0, 0));
     }
 }
 
 __device__ __forceinline__ void kstage_store(const KStage &S, const KVals &V, int tid, float *kl) {
 #pragma unroll
     for (int q = 0; q < KSL; ++q)
-        if (S.ax[q] > -1000) kl[tid + NTH * q] = V.v[q];
+        if (S.ax[q] > -1000) reinterpret_cast<f4v *>(kl)[tid + NTH * q] = V.v[q];
 }
 
 // The rows and the epilogue of one item with NT column tiles.  KSM: k-steps
@@ -197,7 +201,7 @@ __device__ __forceinline__ void t1m_item(const Geo &g, const T1G &G, const Inst 
     const int m0 = t0 * MBLK;
     const int l0 = m0 / lnx;
     const int nlines = (min(m0 + MBLK, W) - 1) / lnx - l0 + 1;
-    const int lw = lnx + 4 * KS - 1;
+    const int lw4 = (lnx + 4 * KS - 1 + 3) & ~3;
     const int ax0 = rfl(G.wn0[2]) - px0 - 4 * KS + 1;
     const int mbase = m0 + wave * (MTL * 16);
     // this lane's A values: K line of its output, at x - u + 4 KS - 1
@@ -205,7 +209,7 @@ __device__ __forceinline__ void t1m_item(const Geo &g, const T1G &G, const Inst 
 #pragma unroll
     for (int tm = 0; tm < MTL; ++tm) {
         const int m = min(mbase + tm * 16 + li, W - 1);
-        abase[tm] = (m / lnx - l0) * lw + m % lnx + 4 * KS - 1 - lk;
+        abase[tm] = (m / lnx - l0) * lw4 + m % lnx + 4 * KS - 1 - lk;
     }
     const int kc = __builtin_amdgcn_readfirstlane(G.kc);
     const __amdgpu_buffer_rsrc_t kr = __builtin_amdgcn_make_buffer_rsrc(
@@ -231,7 +235,7 @@ __device__ __forceinline__ void t1m_item(const Geo &g, const T1G &G, const Inst 
     PVals<NP> pv;
     KVals kv;
     pstage_setup(g, G, KS, NT, tid, ps);
-    kstage_setup(G, l0, nlines, lw, ax0, tid, ks);
+    kstage_setup(G, l0, nlines, lw4, ax0, tid, ks);
     __syncthreads();  // the previous item's epilogue is done with the buffers
     pstage_load(gr, hp_of(wp00, wp01), hq_of(wp00, wp01), ps, pv);
     kstage_load(g, kr, wp00, wp01, ks, kv);
@@ -350,7 +354,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
                                                       const Rot *rots, int nq, int *qctr) {
     constexpr int RB = KSM * NTM * 64 + T1M_KLINE;
     static_assert(2 * RB >= 2 * MW * EPW, "epilogue fits the row buffers");
-    __shared__ float buf[2 * RB];
+    __shared__ __align__(16) float buf[2 * RB];
     __shared__ int tick;
     const int tid = threadIdx.x;
     const int wg = blockIdx.x;
