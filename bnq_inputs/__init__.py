@@ -222,3 +222,26 @@ def quantum_maxwellian(d: int, N: int, L: float, z: float, T: float, alpha: floa
     if truncate:
         return _truncate(f, v, L)
     return np.ascontiguousarray(f)
+
+
+def relaxation_datum(kind: str, d: int, N: int, L: float, rho: float = 1.0, e: float = 1.0, sigma: float = 1.0):
+    """Initial data of 'Relaxation towards equilibrium' (mean velocity 0):
+      'ball'      the indicator datum, rho / |B(0, A)| on the ball of radius
+                  A = 2 sqrt(e) (2-D, eq. fermions_2d_init_indicator) or
+                  A = sqrt(10 e / 3) (3-D, eq. fermions_3d_init_cmax), so that
+                  its internal energy (half the second moment per particle) is e;
+      'maxwellian' rho / (2 pi sigma)^(d/2) exp(-|v|^2 / (2 sigma)) (eqs.
+                  fermions_2d_init_cmax, fermions_3d_init_ball).
+    The paper gives rho = sigma = 1 for the Maxwellian and leaves rho, e of the
+    ball unstated; rho = e = 1 here."""
+    v = velocity_grid(d, N, L)
+    r2 = np.sum(v * v, axis=-1)
+    if kind == "ball":
+        A = 2.0 * math.sqrt(e) if d == 2 else math.sqrt(10.0 * e / 3.0)
+        vol = math.pi * A * A if d == 2 else 4.0 * math.pi * A ** 3 / 3.0
+        f = np.where(r2 <= A * A, rho / vol, 0.0)
+    elif kind == "maxwellian":
+        f = rho / (2.0 * math.pi * sigma) ** (d / 2.0) * np.exp(-r2 / (2.0 * sigma))
+    else:
+        raise ValueError(f"unknown relaxation datum {kind!r}")
+    return np.ascontiguousarray(f, dtype=np.float64)

@@ -139,6 +139,14 @@ typedef struct {
  * (ENOTSUP).  Other precisions or sizes: ENOTSUP. */
 #define BNQ_FLAG_T1_SEPARATED 2
 
+/* The step health flags (bnq_step, bnq_batch_step, bnq_health) do not record
+ * Fermi-Dirac values at or above 1/|alpha|; non-finite values are still
+ * recorded.  For experiments whose data start above that bound, as some of
+ * the runs of section 'Relaxation towards equilibrium' do (a Maxwellian
+ * datum with hbar close to the saturation threshold), and whose maximum is
+ * then followed with bnq_moments. */
+#define BNQ_FLAG_NO_FERMI_BOUND 4
+
 #define BNQ_SCHED_STATIC 0
 #define BNQ_SCHED_DYNAMIC 1
 

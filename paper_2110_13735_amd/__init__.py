@@ -27,6 +27,7 @@ T_CLASSICAL, T_QMULT, T_QTRI, T_ALL = 1, 2, 4, 7
 FP64, FP32C = 0, 1
 FLAG_WEIGHTS_OTF = 1
 FLAG_T1_SEPARATED = 2
+FLAG_NO_FERMI_BOUND = 4
 SCHED_STATIC, SCHED_DYNAMIC = 0, 1
 CORR_NONE, CORR_MASS, CORR_MOMENTS = 0, 1, 2
 RK4, EULER, SSPRK2 = 0, 1, 2

@@ -562,7 +562,7 @@ bnq_status validate(const bnq_params *p) {
         return fail(BNQ_EINVAL, "bad correction %d", p->correction);
     if (p->schedule != BNQ_SCHED_STATIC && p->schedule != BNQ_SCHED_DYNAMIC)
         return fail(BNQ_EINVAL, "bad schedule %d", p->schedule);
-    if (p->flags & ~(BNQ_FLAG_WEIGHTS_OTF | BNQ_FLAG_T1_SEPARATED))
+    if (p->flags & ~(BNQ_FLAG_WEIGHTS_OTF | BNQ_FLAG_T1_SEPARATED | BNQ_FLAG_NO_FERMI_BOUND))
         return fail(BNQ_EINVAL, "unknown flags 0x%x", p->flags);
     if (p->angles < 0) return fail(BNQ_EINVAL, "angles must be >= 0 (got %d)", p->angles);
     if (p->angles > 0 && !(p->flags & BNQ_FLAG_T1_SEPARATED))
@@ -1489,7 +1489,7 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         I.hstep = 2.0 * p->L / p->N;
         I.ginv = nullptr;
         I.health = P->health;
-        I.fbound = P->alpha > 0 ? 1.0 / P->alpha : INFINITY;
+        I.fbound = (P->alpha > 0 && !(p->flags & BNQ_FLAG_NO_FERMI_BOUND)) ? 1.0 / P->alpha : INFINITY;
         if (I.corr_mom) {
             std::vector<double> gi;
             if ((st = gram_inverse(p->d, p->N, I.hstep, gi)) || (st = upload(&P->ginv, gi, "moment Gram matrix"))) {

@@ -89,7 +89,7 @@ def test_weights_on_the_fly_flag():
     if not os.path.exists(bnq.LIBPATH):
         pytest.skip("libbnq.so not built")
     with pytest.raises(bnq.BnqError) as e:
-        bnq.footprint(bnq.Params(d=2, N=8, L=4.0, flags=4))
+        bnq.footprint(bnq.Params(d=2, N=8, L=4.0, flags=8))  # no such flag
     assert e.value.status == bnq.BNQ_EINVAL
     with pytest.raises(bnq.BnqError) as e:
         bnq.footprint(bnq.Params(d=2, N=8, L=4.0, precision=bnq.FP32C, flags=bnq.FLAG_WEIGHTS_OTF))
