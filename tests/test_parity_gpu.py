@@ -402,3 +402,34 @@ def test_quantum_maxwellian_residual_decays_beyond_oracle_sizes(species):
     assert res[2] < res[1] / 5
     assert res[2] < 1e-5
     assert min(wrong) > 1e4 * res[2]
+
+
+@pytest.mark.parametrize("eps,precision", [(-1, 0), (1, 0), (0, 0), (-1, 1)])
+def test_largest_2d_grid_sparse_spectrum(eps, precision):
+    # the largest grid the library takes (N = 64) in 2-D, every kernel at that
+    # shape, on a sparse spectrum whose exact sums the oracle evaluates
+    d, N, L = 2, 64, 8.0
+    f, sm, co = inp.sparse_spectrum(d, N, seed=11, nmodes=10, amp=0.2)
+    Q, Qh = _gpu_collide(bnq.Params(d=d, N=N, eps=eps, L=L, precision=precision), f)
+    Qc, T1, Xq = oracle.sparse_modes(d, N, sm, co, eps)
+    alpha = oracle.alpha_of(eps, d)
+    ref = oracle.sparse_dense(d, N, Qc) - alpha * (oracle.sparse_dense(d, N, T1) + oracle.sparse_dense(d, N, Xq))
+    tol = TOL if precision == 0 else 1e-5
+    _check(Qh, ref, tol=tol)
+    _check(Q, oracle.prefactor(d, L) * oracle.idft_real(ref), tol=tol)
+
+
+@pytest.mark.parametrize("d,N", [(2, 16), (3, 8)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_zero_datum_gives_zero(d, N, precision):
+    # the degenerate datum f = 0: every term vanishes exactly, for every
+    # statistics and precision, and a step leaves it at zero
+    for eps in (-1, 0, 1):
+        f = np.zeros((N,) * d)
+        Q, Qh = _gpu_collide(bnq.Params(d=d, N=N, eps=eps, L=5.0, precision=precision), f)
+        assert not np.any(Q) and not np.any(Qh), (eps, precision)
+        with bnq.Plan(bnq.Params(d=d, N=N, eps=eps, L=5.0, precision=precision)) as pl:
+            ft = torch.zeros((N,) * d, dtype=torch.float64, device="cuda:0")
+            pl.step(ft, 0.01)
+            torch.cuda.synchronize()
+            assert not torch.any(ft)
