@@ -72,19 +72,23 @@ __device__ __forceinline__ void decode(const T1G &G, int m, int &n0, int &n1, in
 // tile t) is 64 floats: column 16 t + j at inner offset 4 s + k in float
 // k * 16 + j; rotation r fills columns 2 r (re) and 2 r + 1 (im), so a
 // fragment is 32 complex values, (k, r mod 8) at float2 k * 8 + r mod 8.
-// Thread tid stages, in slot q, fragment f = 8 q + tid / 32 (fragments
-// numbered s * NT + t) at float2 tid mod 32: the 64 lanes of a wave write 512
-// consecutive bytes.  Elements past the row or past the group's rotations
-// are zeros, so every entry of the row's fragments is written.
+// Thread tid stages, in slot q, the pair e = tid + NTH q: fragment f = e / 16
+// (fragments numbered s * NT + t), entries (2 k2, r8) and (2 k2 + 1, r8) with
+// k2 = (e / 8) mod 2 and r8 = e mod 8, i.e. inner offsets u and u + 1
+// (u = 4 s + 2 k2) of rotation r = 8 t + r8.  Each spectrum factor of the
+// pair comes with one 16-byte load of two consecutive values.  Entries past
+// the row or past the group's rotations are zeros, so every entry of the
+// row's fragments is written.
 template <int NP>
 struct PStage {
     int rbase[NP];  // float2 offset of the slot's rotated spectrum, -1: zero
-    int u[NP];      // inner offset p'_x - wp0_x
-    int sidx[NP];   // float2 index in the fragment buffer, -1: not staged
+    int u[NP];      // inner offset p'_x - wp0_x of the pair's first entry
+    int sidx[NP];   // float2 index of the first entry in the fragment buffer, -1: not staged
+    int lim[NP];    // entries of the pair inside the row: 0, 1 or 2
 };
 template <int NP>
 struct PVals {
-    float2 x[NP], y[NP];  // the two spectrum values, multiplied when stored
+    f4v x[NP], y[NP];  // the spectrum values, multiplied when stored
 };
 
 // byte offset past every buffer: a load there returns zero
@@ -94,19 +98,26 @@ template <int NP>
 __device__ __forceinline__ void pstage_setup(const Geo &g, const T1G &G, int KS, int NT, int tid, PStage<NP> &S) {
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-        const int f = (NTH / 32) * q + (tid >> 5), e = tid & 31;
+        const int e = tid + NTH * q;
+        const int f = e >> 4, k2 = (e >> 3) & 1, r8 = e & 7;
         const int s = NT == 1 ? f : (NT == 2 ? f >> 1 : (f * 21846) >> 16);  // f / NT for f < 3 * 64
         const int t = f - s * NT;
-        const int k = e >> 3, r = 8 * t + (e & 7), u = 4 * s + k;
-        S.sidx[q] = s < KS ? f * 32 + e : -1;
+        const int r = 8 * t + r8, u = 4 * s + 2 * k2;
+        S.sidx[q] = s < KS ? f * 32 + 16 * k2 + r8 : -1;
         S.u[q] = u;
-        S.rbase[q] = (s < KS && r < G.nrot && u < G.wpl[2]) ? (int)(G.rot[r] * g.next) : -1;
+        const int lim = (s < KS && r < G.nrot) ? min(max(G.wpl[2] - u, 0), 2) : 0;
+        S.lim[q] = lim;
+        S.rbase[q] = lim > 0 ? (int)(G.rot[r] * g.next) : -1;
     }
 }
 
 // hp, hq: float2 offsets of p' = (pz, py, wp0_x) and of b_c - p' in a
-// rotated spectrum; slot (u, r) reads G_r(p' + u e_x) and G_r(b_c - p' - u e_x)
-// (zeros for a slot with no pair product).  Nothing waits for the loads here.
+// rotated spectrum; the pair (u, u + 1) of slot q reads G_r(p' + u e_x),
+// G_r(p' + (u + 1) e_x) (in range: p' + u lies in I_N, so p' + (u + 1) e_x
+// lies in the stored {-N/2..N/2}) and G_r(b_c - p' - u e_x) with its
+// neighbour: G_r(b_c - p' - (u + 1) e_x) when both entries are in the row
+// (that mode is then in I_N), else G_r(b_c - p' - (u - 1) e_x), which is in
+// the stored range as well.  Nothing waits for the loads here.
 template <int NP>
 __device__ __forceinline__ void pstage_load(__amdgpu_buffer_rsrc_t gr, int hp, int hq, const PStage<NP> &S,
                                             PVals<NP> &V) {
@@ -114,9 +125,9 @@ __device__ __forceinline__ void pstage_load(__amdgpu_buffer_rsrc_t gr, int hp, i
     for (int q = 0; q < NP; ++q) {
         const int b = S.rbase[q];
         const int ox = b >= 0 ? 8 * (b + hp + S.u[q]) : OOB;
-        const int oy = b >= 0 ? 8 * (b + hq - S.u[q]) : OOB;
-        V.x[q] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(gr, ox, 0, 0));
-        V.y[q] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(gr, oy, 0, 0));
+        const int oy = b >= 0 ? 8 * (b + hq - S.u[q] - (S.lim[q] == 2 ? 1 : 0)) : OOB;
+        V.x[q] = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(gr, ox, 0, 0));
+        V.y[q] = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(gr, oy, 0, 0));
     }
 }
 
@@ -124,7 +135,17 @@ template <int NP>
 __device__ __forceinline__ void pstage_store(const PStage<NP> &S, const PVals<NP> &V, float *bs) {
 #pragma unroll
     for (int q = 0; q < NP; ++q)
-        if (S.sidx[q] >= 0) reinterpret_cast<float2 *>(bs)[S.sidx[q]] = cmulf(V.x[q], V.y[q]);
+        if (S.sidx[q] >= 0) {
+            const f4v x = V.x[q], y = V.y[q];
+            const bool two = S.lim[q] == 2;
+            // y holds (y_{u+1}, y_u) when both entries are in the row, else (y_u, y_{u-1})
+            const float2 yu = two ? make_float2(y[2], y[3]) : make_float2(y[0], y[1]);
+            const float2 p0 = S.lim[q] > 0 ? cmulf(make_float2(x[0], x[1]), yu) : make_float2(0.0f, 0.0f);
+            const float2 p1 = two ? cmulf(make_float2(x[2], x[3]), make_float2(y[0], y[1])) : make_float2(0.0f, 0.0f);
+            float2 *b2 = reinterpret_cast<float2 *>(bs);
+            b2[S.sidx[q]] = p0;
+            b2[S.sidx[q] + 8] = p1;
+        }
 }
 
 // Kernel-mode staging.  The block's outputs cover nl x-lines; line l holds
@@ -184,7 +205,7 @@ __device__ __forceinline__ void t1m_item(const Geo &g, const T1G &G, const Inst 
                                          int t0, int wg, float *buf) {
     constexpr int BF = KSM * NTM * 64;       // B fragment floats of a row
     constexpr int RB = BF + T1M_KLINE;       // row buffer floats
-    constexpr int NP = (KSM * NT + NTH / 32 - 1) / (NTH / 32);  // fragment slots per thread
+    constexpr int NP = (KSM * NT * 16 + NTH - 1) / NTH;  // entry pairs per thread (16 per fragment)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
     // the descriptor fields the rows use, uniform and in scalar registers
