@@ -610,7 +610,7 @@ def run_c3(args):
     torch.cuda.set_device(dev)
     N, L, eps = args.N, 3.0, 1
     sched = bnq.SCHED_DYNAMIC if args.schedule == "dynamic" else bnq.SCHED_STATIC
-    p32 = bnq.Params(d=3, N=N, eps=eps, L=L, precision=bnq.FP32C, schedule=sched)
+    p32 = bnq.Params(d=3, N=N, eps=eps, L=L, precision=bnq.FP32C, schedule=sched, correction=bnq.CORR_MASS)
     f0 = inp.boson_condensing_3d(N=N, L=L)
     t_plan = time.perf_counter()
     plan = bnq.Plan(p32)
@@ -735,7 +735,8 @@ def run_batch(args):
     for i in range(args.instances):
         d, N, eps = cells[i % len(cells)]
         f0, L = inp.mixed_instance(d, N, eps, seed=i)
-        p = bnq.Params(d=d, N=N, eps=eps, L=L, precision=prec)
+        p = bnq.Params(d=d, N=N, eps=eps, L=L, precision=prec,
+                       correction=bnq.CORR_MASS if prec == bnq.FP32C else bnq.CORR_NONE)
         pl = bnq.Plan(p)
         if args.autotune and eps != 0 and (d, N, prec) not in tuned:
             # the first quantum instance of a cell picks the work distribution;

@@ -41,8 +41,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import (BNQ_EBOUND, BNQ_ENONFINITE, HEALTH_BOUND, HEALTH_NONFINITE, RK4, Batch, BnqError, Params, Plan,
-               footprint, terms_per_eval)
+from . import (BNQ_EBOUND, BNQ_ENONFINITE, CORR_MASS, CORR_NONE, FP32C, HEALTH_BOUND, HEALTH_NONFINITE, RK4, Batch,
+               BnqError, Params, Plan, footprint, terms_per_eval)
 
 
 @dataclass
@@ -113,7 +113,9 @@ class GpuExecutor:
 
     # sizes -------------------------------------------------------------
     def params(self, req, L):
-        return Params(d=req.d, N=req.N, eps=req.eps, L=L, precision=self.precision)
+        # FP32c solves keep their mass to rounding with the mass correction
+        return Params(d=req.d, N=req.N, eps=req.eps, L=L, precision=self.precision,
+                      correction=CORR_MASS if self.precision == FP32C else CORR_NONE)
 
     def footprint(self, req):
         """(bytes of the request's own workspace and state, bytes of its cell's
