@@ -34,7 +34,9 @@ METRIC = "collision pair-terms/s at N=32^3 (FP32c vs FP64); p50/p99 solve latenc
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trilinear_3d32_fp64_hbm_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_13735_amd", "csrc", "t1_pairs.hip")
 PAIRS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairs_3d32_fp64_hbm_traffic.json")
-PAIRS_SOURCE = os.path.join(ROOT, "paper_2110_13735_amd", "csrc", "collide.hip")
+# the pair-sum kernels and the header that fixes their l-chunking (pair_split)
+PAIRS_SOURCE = (os.path.join(ROOT, "paper_2110_13735_amd", "csrc", "collide.hip"),
+                os.path.join(ROOT, "paper_2110_13735_amd", "csrc", "bnq_internal.h"))
 PEAK_FP64_VALU = 78.6e12  # MI355X dense FP64 vector, FLOP/s
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E, GB/s
 PEAK_FP32_VALU = 157.3e12  # MI355X dense FP32 vector, FLOP/s (published; counts packed FP32)
@@ -68,13 +70,15 @@ def cpu_baseline(sample_N: int = 10, nthreads=None):
                       f"at 3-D N={sample_N}: {terms:.3e} terms in {dt:.2f} s"}
 
 
-def code_hash(path):
-    """SHA-256 of a C/HIP source with comments and blank space removed, so that
-    only a change of the code itself counts."""
+def code_hash(*paths):
+    """SHA-256 of C/HIP sources (concatenated) with comments and blank space
+    removed, so that only a change of the code itself counts."""
     import hashlib
     import re
-    with open(path) as fh:
-        src = fh.read()
+    src = ""
+    for path in paths:
+        with open(path) as fh:
+            src += fh.read() + "\n"
     src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
     src = re.sub(r"//[^\n]*", " ", src)
     src = " ".join(src.split())
@@ -100,7 +104,7 @@ def measured_pairs_traffic(kernel):
         return None
     with open(PAIRS_TRAFFIC_FILE) as fh:
         rec = json.load(fh).get(kernel)
-    if rec is None or rec.get("kernel_code_sha256") != code_hash(PAIRS_SOURCE):
+    if rec is None or rec.get("kernel_code_sha256") != code_hash(*PAIRS_SOURCE):
         return None
     return rec
 
@@ -731,7 +735,7 @@ def run_batch(args):
     if args.tuning and os.path.exists(args.tuning) and not args.autotune:
         _progress(f"tuning records loaded: {bnq.load_tuning(args.tuning)}")
     plans, f_b, f_s, terms = [], [], [], 0.0
-    tuned, tune_ms = set(), {}
+    tuned, tune_ms, tuned_pairs = set(), {}, {}
     for i in range(args.instances):
         d, N, eps = cells[i % len(cells)]
         f0, L = inp.mixed_instance(d, N, eps, seed=i)
@@ -745,12 +749,19 @@ def run_batch(args):
             tuned.add((d, N, prec))
             tune_ms[(d, N, prec)] = ms
             _progress(f"autotune ({d}, {N}): choice {ch}, ms {np.round(ms, 3).tolist()}")
+        if args.autotune and (d, N, prec, int(eps == 0)) not in tuned_pairs:
+            # likewise the pair-sum l-chunking, once per cell and eps == 0 or not
+            sp, ms = pl.autotune_pairs(torch.tensor(f0, device=dev), reps=3)
+            tuned_pairs[(d, N, prec, int(eps == 0))] = (eps, ms)
+            _progress(f"pair autotune ({d}, {N}, eps={eps}): split {sp}, ms {np.round(ms, 3).tolist()}")
         plans.append(pl)
         terms += 4.0 * bnq.terms_per_eval(p, pl.counts())
         f_b.append(torch.tensor(f0, device=dev))
         f_s.append(torch.tensor(f0, device=dev))
     if args.autotune and args.tuning:
-        _progress(f"tuning records saved: {bnq.save_tuning(args.tuning, sorted(tuned), tune_ms)}")
+        pc = {(d, N, pr, e): ms for (d, N, pr, _), (e, ms) in tuned_pairs.items()}
+        _progress(f"tuning records saved: "
+                  f"{bnq.save_tuning(args.tuning, sorted(tuned), tune_ms, pair_cells=sorted(pc), pair_ms=pc)}")
     dt = args.dt
     stream = torch.cuda.Stream()
     batch = bnq.Batch(plans, f_b)
@@ -805,7 +816,9 @@ def run_batch(args):
         "config": {"workload": f"{args.instances} instances over cells (d, N) in {cell_set} x eps in (-1, 0, 1), "
                                f"Gaussian-mixture data (seed = instance), RK4 dt={dt}, one HIP-graph replay per step",
                    "instances": args.instances, "terms_per_step": terms,
-                   "tuning": {f"{d}d{N}": bnq.tune_get(d, N, prec) for (d, N) in cell_set}},
+                   "tuning": {f"{d}d{N}": bnq.tune_get(d, N, prec) for (d, N) in cell_set},
+                   "pair_split": {f"{d}d{N}" + ("eps0" if e == 0 else ""): bnq.tune_pairs_get(d, N, prec, e)
+                                  for (d, N, e) in cells}},
         "solo": {"value": terms / t_solo, "ms_per_step": 1e3 * t_solo, "speedup": t_solo / t_batch},
         "bitwise_equal_to_solo": bool(same),
     }

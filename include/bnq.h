@@ -173,7 +173,8 @@ void bnq_params_default(bnq_params *p);
 bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out);
 
 /* Release the plan (waits for its stream work); drops its reference to the
- * shared tables (freed with the last reference).  NULL is accepted. */
+ * shared tables (freed with the last reference).  NULL is accepted.
+ * Errors: EINVAL while a batch holds the plan (destroy the batch first). */
 bnq_status bnq_plan_destroy(bnq_plan_t plan);
 
 /* Device bytes the plan would need: *plan_bytes for its own workspace,
@@ -399,7 +400,7 @@ bnq_status bnq_plan_timing(bnq_plan_t plan, double *ms_host, int64_t *launches_h
  * Synchronises the stream.  Results stay within the parity tolerance of the
  * default distribution but may differ from it in the last bits (a different
  * summation order).  No-op for plans without the trilinear term.
- * Errors: EINVAL, ENOMEM, EHIP. */
+ * Errors: EINVAL (also while a batch holds the plan), ENOMEM, EHIP. */
 bnq_status bnq_plan_autotune(bnq_plan_t plan, const double *f, int32_t reps, double *ms_host, int32_t *choice_host,
                              bnq_stream_t stream);
 
@@ -414,6 +415,30 @@ bnq_status bnq_plan_autotune(bnq_plan_t plan, const double *f, int32_t reps, dou
 bnq_status bnq_tune_get(int32_t d, int32_t N, int32_t precision, int32_t *choice);
 bnq_status bnq_tune_set(int32_t d, int32_t N, int32_t precision, int32_t choice);
 
+/* The l-chunking of the pair sums (section 'Fast spectral approximation of
+ * the BNE operator', the classical and W sums over pairs (l, m)): the l box
+ * of every output is cut into `split` slices, one workgroup and partial array
+ * each, added in slice order.  A plan starts with the split recorded for
+ * (device, d, N, precision, eps == 0), else 32 slices for eps = 0 in 3-D and
+ * 16 otherwise (at most N).  The split changes the summation order, hence the
+ * last bits of a result, within the parity tolerance.
+ * bnq_plan_autotune_pairs(): times the pair sums (classical, and W when the
+ *   plan has them) with 8, 16 and 32 slices (those <= min(N, 32)) on f
+ *   (device, the plan's layout; one evaluation first forms the spectrum),
+ *   reps timed runs each; keeps the fastest for this plan and records it for
+ *   plans created afterwards.  ms_host (optional, 3 doubles): mean time of
+ *   each candidate (0 where not run); split_host (optional): the split kept.
+ *   Synchronises the stream.  Errors: EINVAL (also while a batch holds the
+ *   plan), ENOMEM, EHIP.
+ * bnq_tune_pairs_get(): *split = the recorded split for (d, N, precision,
+ *   eps == 0) on the current device, or 0 if none.
+ * bnq_tune_pairs_set(): records split (1 .. min(N, 32); 0 removes the record).
+ *   Errors: EINVAL. */
+bnq_status bnq_plan_autotune_pairs(bnq_plan_t plan, const double *f, int32_t reps, double *ms_host,
+                                   int32_t *split_host, bnq_stream_t stream);
+bnq_status bnq_tune_pairs_get(int32_t d, int32_t N, int32_t precision, int32_t eps, int32_t *split);
+bnq_status bnq_tune_pairs_set(int32_t d, int32_t N, int32_t precision, int32_t eps, int32_t split);
+
 /* ---- Batches ------------------------------------------------------------
  * Many independent instances of the same problem (the homogeneous equation
  * of section 'Convergence towards a steady state', each with its own plan and
@@ -424,8 +449,9 @@ bnq_status bnq_tune_set(int32_t d, int32_t N, int32_t precision, int32_t choice)
  *
  * bnq_batch_create(): plans[i] (distinct, same device) and its state f[i]
  *   (device, FP64, the plan's layout; distinct).  The batch keeps these
- *   pointers: plans and states must outlive it, and a plan must not be used
- *   on its own while a batch call that includes it is in flight.
+ *   pointers: plans and states must outlive it (bnq_plan_destroy refuses a
+ *   plan a batch holds), a plan must not be used on its own while a batch
+ *   call that includes it is in flight, and a held plan cannot be autotuned.
  *   Errors: EINVAL (NULL / duplicate / other device), ENOMEM.
  * bnq_batch_collide(): Q[i] <- operator of f[i] (as bnq_collide), Qhat[i]
  *   optional (Qhat may be NULL, or hold NULL entries).

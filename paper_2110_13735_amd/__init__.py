@@ -147,6 +147,9 @@ def lib():
         L.bnq_plan_autotune.argtypes = [vp, vp, i32, vp, vp, vp]
         L.bnq_tune_get.argtypes = [i32, i32, i32, ctypes.POINTER(i32)]
         L.bnq_tune_set.argtypes = [i32, i32, i32, i32]
+        L.bnq_plan_autotune_pairs.argtypes = [vp, vp, i32, vp, vp, vp]
+        L.bnq_tune_pairs_get.argtypes = [i32, i32, i32, i32, ctypes.POINTER(i32)]
+        L.bnq_tune_pairs_set.argtypes = [i32, i32, i32, i32, i32]
         L.bnq_batch_create.argtypes = [i32, vp, vp, ctypes.POINTER(vp)]
         L.bnq_batch_destroy.argtypes = [vp]
         L.bnq_batch_collide.argtypes = [vp, vp, vp, vp]
@@ -161,7 +164,8 @@ def lib():
         L.bnq_step_rescaled.argtypes = [vp, vp, RS, f64, vp]
         for fn in ("bnq_plan", "bnq_plan_destroy", "bnq_plan_footprint", "bnq_collide", "bnq_step",
                    "bnq_moments", "bnq_health", "bnq_moments_noalloc", "bnq_table_lookup", "bnq_plan_counts", "bnq_plan_set_timing",
-                   "bnq_plan_timing", "bnq_plan_autotune", "bnq_tune_get", "bnq_tune_set", "bnq_batch_create", "bnq_batch_destroy", "bnq_batch_collide",
+                   "bnq_plan_timing", "bnq_plan_autotune", "bnq_tune_get", "bnq_tune_set", "bnq_plan_autotune_pairs",
+                   "bnq_tune_pairs_get", "bnq_tune_pairs_set", "bnq_batch_create", "bnq_batch_destroy", "bnq_batch_collide",
                    "bnq_batch_step", "bnq_equilibrium_solve", "bnq_fd_be_log", "bnq_equilibrium_fill",
                    "bnq_equilibrium_distance", "bnq_rescaled_init", "bnq_step_rescaled"):
             getattr(L, fn).restype = ctypes.c_int
@@ -296,6 +300,15 @@ class Plan:
                                        _stream(stream)))
         return ch.value, ms
 
+    def autotune_pairs(self, f, reps: int = 3, stream=None):
+        """Pick the fastest l-chunking of the pair sums (8, 16 or 32 slices) on
+        input f; returns (slices kept, mean ms of each candidate, 0 = not run)."""
+        ms = np.zeros(3)
+        sp = ctypes.c_int32(0)
+        _check(lib().bnq_plan_autotune_pairs(self._h, _ptr(f), int(reps), ms.ctypes.data, ctypes.byref(sp),
+                                             _stream(stream)))
+        return sp.value, ms
+
     def set_timing(self, enable: bool):
         _check(lib().bnq_plan_set_timing(self._h, 1 if enable else 0))
 
@@ -319,16 +332,35 @@ def tune_set(d: int, N: int, precision: int, choice):
     _check(lib().bnq_tune_set(int(d), int(N), int(precision), -1 if choice is None else int(choice)))
 
 
-def save_tuning(path: str, cells, ms=None, device: str = ""):
-    """Write the recorded choices of `cells` [(d, N, precision)] to a JSON file,
-    merged into what the file already holds (the entries of other cells
-    stay); ms: optional {cell: candidate times in ms} kept beside them."""
+def tune_pairs_get(d: int, N: int, precision: int, eps: int):
+    """bnq_tune_pairs_get: the recorded pair-sum slices for (d, N, precision,
+    eps == 0) on the current device, or None."""
+    sp = ctypes.c_int32(0)
+    _check(lib().bnq_tune_pairs_get(int(d), int(N), int(precision), int(eps), ctypes.byref(sp)))
+    return sp.value or None
+
+
+def tune_pairs_set(d: int, N: int, precision: int, eps: int, split):
+    """bnq_tune_pairs_set: record a pair-sum split (None removes the record)."""
+    _check(lib().bnq_tune_pairs_set(int(d), int(N), int(precision), int(eps), 0 if split is None else int(split)))
+
+
+def save_tuning(path: str, cells, ms=None, device: str = "", pair_cells=(), pair_ms=None):
+    """Write the recorded choices to a JSON file, merged into what the file
+    already holds (the entries of other cells stay):
+      cells [(d, N, precision)]: the trilinear work distribution ('choice');
+      pair_cells [(d, N, precision, eps)]: the pair-sum split ('pair_split',
+      keyed by eps == 0 as 'eps0');
+    ms / pair_ms: optional {cell: candidate times in ms} kept beside them."""
     import json
     data = {"format": "bnq-tuning-1", "device": device, "entries": []}
     if os.path.exists(path):
         with open(path) as fh:
             data = json.load(fh)
-    ent = {(e["d"], e["N"], e["precision"]): e for e in data.get("entries", [])}
+
+    def key(e):
+        return (e["d"], e["N"], e["precision"], "pairs" if "pair_split" in e else "trilinear", e.get("eps0", -1))
+    ent = {key(e): e for e in data.get("entries", [])}
     for d, N, prec in cells:
         ch = tune_get(d, N, prec)
         if ch is None:
@@ -336,7 +368,15 @@ def save_tuning(path: str, cells, ms=None, device: str = ""):
         e = {"d": int(d), "N": int(N), "precision": int(prec), "choice": int(ch)}
         if ms and (d, N, prec) in ms:
             e["ms"] = [float(x) for x in ms[(d, N, prec)]]
-        ent[(d, N, prec)] = e
+        ent[key(e)] = e
+    for d, N, prec, eps in pair_cells:
+        sp = tune_pairs_get(d, N, prec, eps)
+        if sp is None:
+            continue
+        e = {"d": int(d), "N": int(N), "precision": int(prec), "eps0": int(eps == 0), "pair_split": int(sp)}
+        if pair_ms and (d, N, prec, eps) in pair_ms:
+            e["ms"] = [float(x) for x in pair_ms[(d, N, prec, eps)]]
+        ent[key(e)] = e
     data["entries"] = [ent[k] for k in sorted(ent)]
     if device:
         data["device"] = device
@@ -356,7 +396,10 @@ def load_tuning(path: str) -> int:
     if data.get("format") != "bnq-tuning-1":
         raise ValueError(f"{path}: not a bnq tuning file")
     for e in data["entries"]:
-        tune_set(e["d"], e["N"], e["precision"], e["choice"])
+        if "pair_split" in e:
+            tune_pairs_set(e["d"], e["N"], e["precision"], 0 if e["eps0"] else 1, e["pair_split"])
+        else:
+            tune_set(e["d"], e["N"], e["precision"], e["choice"])
     return len(data["entries"])
 
 

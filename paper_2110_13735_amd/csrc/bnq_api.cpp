@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <array>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <queue>
@@ -72,6 +73,7 @@ Geo make_geo(int d, int N) {
     g.nak = (int64_t)g.ea0 * g.kax * (2 * N - 1);
     g.ex0 = d == 3 ? N + 1 : 1;
     g.next = (int64_t)g.ex0 * (N + 1) * (N + 1);
+    g.psplit = pair_split_default(d, N, 1);
     return g;
 }
 
@@ -457,6 +459,11 @@ std::mutex g_tune_mu;
 // (device, d, N, precision) -> index in kTuneCandidates chosen by
 // bnq_plan_autotune or set by bnq_tune_set
 std::map<std::tuple<int, int, int, int>, int> g_tune;
+// (device, d, N, precision, eps == 0) -> pair-sum slices chosen by
+// bnq_plan_autotune_pairs or set by bnq_tune_pairs_set
+std::map<std::tuple<int, int, int, int, int>, int> g_tune_pairs;
+const int kPairSplitCandidates[] = {8, 16, 32};
+constexpr int kNumPairSplit = 3;
 }  // namespace
 
 struct bnq_plan_s {
@@ -496,6 +503,7 @@ struct bnq_plan_s {
     T1Tune tune;                  // trilinear work distribution
     Inst ih{};                    // workspace pointers and scalars (host copy)
     Inst *inst_d = nullptr;       // device copy, one entry
+    std::atomic<int> nbatch{0};   // batches holding this plan (they copy its workspace pointers)
     double counts[4] = {0, 0, 0, 0};
     // timing
     bool timing = false;
@@ -597,7 +605,7 @@ size_t plan_workspace_bytes(const bnq_params *p, int nslots_est) {
     const size_t f32 = p->precision == BNQ_FP32C ? sizeof(float2) * ((size_t)g.nm + nrot * g.next) : 0;
     if (p->eps == 0 || !(p->terms & BNQ_T_QTRI)) nslots_est = 0;  // no trilinear partial arrays
     return c * (6 * (size_t)g.nm + g.neg + nrot * g.next + (size_t)nslots_est * g.nm +
-                (size_t)pair_split(g) * ((size_t)g.neg + g.nm) + (size_t)outer_split(g) * g.nm) +
+                (size_t)pair_split_max(g.N) * ((size_t)g.neg + g.nm) + (size_t)outer_split(g) * g.nm) +
            r * 5 * (size_t)g.nm + f32 + sep_bytes(p);
 }
 
@@ -1360,6 +1368,14 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
     bnq_plan_s *P = new bnq_plan_s;
     P->p = *p;
     P->g = make_geo(p->d, p->N);
+    P->g.psplit = pair_split_default(p->d, p->N, p->eps);
+    {
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_pairs.find(std::make_tuple(dev, p->d, p->N, (int)p->precision, p->eps == 0 ? 1 : 0));
+        if (it != g_tune_pairs.end()) P->g.psplit = it->second;
+    }
     const Geo &g = P->g;
     P->alpha = -(double)p->eps * std::pow(p->hbar, p->d);
     P->pref = p->c * std::pow(p->L / M_PI, p->d + (p->d == 3 ? 1 : 0));
@@ -1393,7 +1409,7 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         (st = dalloc(&P->Ghat, nm, "spectrum")) || (st = dalloc(&P->tmp, nm, "dft scratch")) ||
         (st = dalloc(&P->tmp2, nm, "dft scratch")) || (st = dalloc(&P->Gr, P->grp.size() * (size_t)g.next, "rotated spectra")) ||
         (st = dalloc(&P->W, (size_t)g.neg, "pair sum W")) || (st = dalloc(&P->Qc, nm, "classical modes")) ||
-        (st = dalloc(&P->ppart, (size_t)pair_split(g) * ((size_t)g.neg + nm), "pair sum slices")) ||
+        (st = dalloc(&P->ppart, (size_t)pair_split_max(g.N) * ((size_t)g.neg + nm), "pair sum slices")) ||
         (st = dalloc(&P->xpart, (size_t)outer_split(g) * nm, "outer sum slices")) ||
         (st = dalloc(&P->T1, nm, "trilinear modes")) || (st = dalloc(&P->X, nm, "outer modes")) ||
         (st = dalloc(&P->Qh, nm, "modes")) || (st = dalloc(&P->ybuf, nm, "stage")) ||
@@ -1516,6 +1532,7 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
 
 bnq_status bnq_plan_destroy(bnq_plan_t plan) {
     if (!plan) return BNQ_OK;
+    if (plan->nbatch > 0) return fail(BNQ_EINVAL, "plan is held by %d batch(es): destroy them first", (int)plan->nbatch);
     hipStreamSynchronize(plan->last);
     destroy_plan(plan);
     return BNQ_OK;
@@ -1875,6 +1892,7 @@ bnq_status bnq_plan_autotune(bnq_plan_t P, const double *f, int32_t reps, double
                              bnq_stream_t stream) {
     if (!P || !f) return fail(BNQ_EINVAL, "plan and f must be non-NULL");
     if (reps < 1) return fail(BNQ_EINVAL, "reps must be >= 1");
+    if (P->nbatch > 0) return fail(BNQ_EINVAL, "plan is held by a batch, whose copy of its work would go stale");
     hipStream_t s = (hipStream_t)stream;
     P->last = s;
     double ms[kNumTune];
@@ -1920,6 +1938,120 @@ bnq_status bnq_plan_autotune(bnq_plan_t P, const double *f, int32_t reps, double
     if (ms_host)
         for (int c = 0; c < kNumTune; ++c) ms_host[c] = ms[c];
     if (choice_host) *choice_host = best;
+    return BNQ_OK;
+}
+
+bnq_status bnq_plan_autotune_pairs(bnq_plan_t P, const double *f, int32_t reps, double *ms_host,
+                                   int32_t *split_host, bnq_stream_t stream) {
+    if (!P || !f) return fail(BNQ_EINVAL, "plan and f must be non-NULL");
+    if (reps < 1) return fail(BNQ_EINVAL, "reps must be >= 1");
+    if (P->nbatch > 0) return fail(BNQ_EINVAL, "plan is held by a batch, whose copy of its work would go stale");
+    hipStream_t s = (hipStream_t)stream;
+    P->last = s;
+    const int any = P->ih.terms;
+    double ms[kNumPairSplit];
+    for (int c = 0; c < kNumPairSplit; ++c) ms[c] = 0.0;
+    if (!(any & (BNQ_T_CLASSICAL | BNQ_T_QMULT))) {  // no pair sums to time
+        if (ms_host)
+            for (int c = 0; c < kNumPairSplit; ++c) ms_host[c] = 0.0;
+        if (split_host) *split_host = P->g.psplit;
+        return BNQ_OK;
+    }
+    // candidates capped at the largest split the workspace holds; a cap that
+    // repeats the previous candidate is not run again
+    const int smax = pair_split_max(P->g.N);
+    int best = -1, best_k = P->g.psplit;
+    double *Q = nullptr;
+    bnq_status st;
+    if ((st = dalloc(&Q, (size_t)P->g.nm, "autotune output"))) return st;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        hipFree(Q);
+        if (a) hipEventDestroy(a);
+        return fail(BNQ_EHIP, "event creation failed");
+    }
+    const bool timing = P->timing;
+    P->timing = false;
+    // one evaluation forms the spectrum the pair sums read
+    st = bnq_collide(P, f, Q, nullptr, stream);
+    for (int c = 0, prev = 0; c < kNumPairSplit && !st; ++c) {
+        const int k = std::min(kPairSplitCandidates[c], smax);
+        if (k == prev) continue;
+        prev = k;
+        Exec E = exec_of(P);
+        E.timer = nullptr;
+        E.g.psplit = k;
+        const Radial rad = E.t->radial();
+        const std::vector<IOs> ios = make_ios(1, nullptr, [](IOs &, int, int) {});
+        auto run = [&]() {
+            for (const IOs &io : ios) {
+                launch_pairs(E.g, E.prec, E.D, io, E.prec ? (const void *)E.t->wc32 : (const void *)E.t->wc,
+                             E.prec ? (const void *)E.t->wq32 : (const void *)E.t->wq, (any & BNQ_T_QMULT) != 0,
+                             E.otf ? &rad : nullptr, s);
+                launch_pairs_reduce(E.g, E.D, io, s);
+            }
+        };
+        run();  // warm-up
+        hipEventRecord(a, s);
+        for (int r = 0; r < reps; ++r) run();
+        hipEventRecord(b, s);
+        const hipError_t e1 = hipGetLastError(), e2 = hipEventSynchronize(b);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            st = fail(BNQ_EHIP, "pair-sum autotune failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+            break;
+        }
+        float t = 0;
+        hipEventElapsedTime(&t, a, b);
+        ms[c] = t / reps;
+        if (best < 0 || ms[c] < ms[best]) {
+            best = c;
+            best_k = k;
+        }
+    }
+    P->timing = timing;
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    hipFree(Q);
+    if (st) return st;
+    // the pair sums rewrite W and Qc from the spectrum; the split kept is the
+    // one every later evaluation of this plan uses
+    P->g.psplit = best_k;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_pairs[std::make_tuple(dev, P->p.d, P->p.N, (int)P->p.precision, P->p.eps == 0 ? 1 : 0)] = best_k;
+    }
+    if (ms_host)
+        for (int c = 0; c < kNumPairSplit; ++c) ms_host[c] = ms[c];
+    if (split_host) *split_host = best_k;
+    return BNQ_OK;
+}
+
+bnq_status bnq_tune_pairs_get(int32_t d, int32_t N, int32_t precision, int32_t eps, int32_t *split) {
+    if (!split) return fail(BNQ_EINVAL, "split is NULL");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_pairs.find(std::make_tuple(dev, (int)d, (int)N, (int)precision, eps == 0 ? 1 : 0));
+    *split = it == g_tune_pairs.end() ? 0 : it->second;
+    return BNQ_OK;
+}
+
+bnq_status bnq_tune_pairs_set(int32_t d, int32_t N, int32_t precision, int32_t eps, int32_t split) {
+    if (d != 2 && d != 3) return fail(BNQ_EINVAL, "d must be 2 or 3");
+    if (N < 2 || N > 64 || (N & 1)) return fail(BNQ_EINVAL, "N must be even in [2, 64]");
+    if (precision != BNQ_FP64 && precision != BNQ_FP32C) return fail(BNQ_EINVAL, "unknown precision %d", precision);
+    if (split < 0 || split > pair_split_max(N))
+        return fail(BNQ_EINVAL, "split %d outside 0 .. %d", split, pair_split_max(N));
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto key = std::make_tuple(dev, (int)d, (int)N, (int)precision, eps == 0 ? 1 : 0);
+    if (split == 0)
+        g_tune_pairs.erase(key);
+    else
+        g_tune_pairs[key] = split;
     return BNQ_OK;
 }
 
@@ -2065,12 +2197,12 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
     B->f.assign(f, f + n);
     // A dynamic group lets any of its waves take any member's items, so its
     // members must have the same number of partial arrays.
-    std::map<std::tuple<const TableSet *, int, int, int>, int> gidx;
+    std::map<std::tuple<const TableSet *, int, int, int, int>, int> gidx;
     for (int i = 0; i < n; ++i) {
         const bnq_plan_s *Pi = plans[i];
         const int dyn_slots = (Pi->nq && (Pi->ih.terms & BNQ_T_QTRI)) ? Pi->nslots : 0;
         const auto key = std::make_tuple((const TableSet *)Pi->tabs, (int)Pi->p.precision + 2 * (int)Pi->otf,
-                                         (int)Pi->p.schedule, dyn_slots);
+                                         (int)Pi->p.schedule, dyn_slots, Pi->g.psplit);
         auto it = gidx.find(key);
         if (it == gidx.end()) {
             gidx[key] = (int)B->groups.size();
@@ -2152,6 +2284,7 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
         G.E.t1cut = G.t1cut;
         G.E.items = G.items;
     }
+    for (auto *P : B->plans) ++P->nbatch;
     *out = B;
     return BNQ_OK;
 }
@@ -2159,7 +2292,10 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
 bnq_status bnq_batch_destroy(bnq_batch_t B) {
     if (!B) return BNQ_OK;
     if (B->g_stream) hipStreamSynchronize(B->g_stream);
-    for (auto *P : B->plans) hipStreamSynchronize(P->last);
+    for (auto *P : B->plans) {
+        hipStreamSynchronize(P->last);
+        --P->nbatch;
+    }
     destroy_batch(B);
     return BNQ_OK;
 }

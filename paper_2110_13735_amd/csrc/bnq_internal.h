@@ -36,6 +36,7 @@ struct Geo {
     int64_t nak;  // stored row length ea0 * kax * (2N-1)
     int ex0;      // extent of axis 0 in Ext (1 or N+1)
     int64_t next; // |Ext|
+    int psplit;   // slices of the l box of the pair sums (1 .. pair_split_max), chosen per plan
 };
 
 __host__ __device__ inline int64_t idx_I(const Geo &g, int k0, int k1, int k2) {
@@ -238,10 +239,19 @@ __device__ __forceinline__ float2 ld_uniform(const float2 *p, int64_t i) {
 constexpr int BNQ_MAXB = 64;  // instances per launch
 
 // Workspace of one instance (device memory, fixed for the plan's lifetime).
-// The pair sums split the l box of every output into this many slices along
-// its outermost axis (l_0 in 3-D, l_1 in 2-D), one workgroup per slice, and
-// add the slices in a fixed order afterwards.
-__host__ __device__ inline int pair_split(const Geo &g) { return g.N < (g.d == 3 ? 8 : 16) ? g.N : (g.d == 3 ? 8 : 16); }
+// The pair sums split the l box of every output into psplit slices along l_0
+// (3-D) or l_1 (2-D), one workgroup and partial array each, added in slice
+// order: the l-chunking of these sums.  The workspace holds pair_split_max
+// slices, so a plan can take any count up to it.
+__host__ __device__ inline int pair_split(const Geo &g) { return g.psplit; }
+__host__ __device__ inline int pair_split_max(int N) { return N < 32 ? N : 32; }
+// default: 32 slices for the classical sums alone (eps = 0), 16 with W sums
+// (measured at 3-D N = 32: 0.94 / 0.97 / 1.03 ms at 32 / 16 / 8 slices for
+// eps = 0; 3.45 / 3.44 / 3.60 ms with W sums)
+__host__ __device__ inline int pair_split_default(int d, int N, int eps) {
+    const int k = (d == 3 && eps == 0) ? 32 : 16;
+    return N < k ? N : k;
+}
 
 // The outer sum likewise splits its k box into this many slices (k_0 in 3-D,
 // k_1 in 2-D).
