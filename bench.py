@@ -732,6 +732,7 @@ def run_batch(args):
     cell_set = BATCH_CELLS[args.cells]
     cells = [(d, N, e) for (d, N) in cell_set for e in (-1, 0, 1)]
     prec = bnq.FP32C if args.precision == "fp32c" else bnq.FP64
+    sched = bnq.SCHED_DYNAMIC if args.schedule == "dynamic" else bnq.SCHED_STATIC
     if args.tuning and os.path.exists(args.tuning) and not args.autotune:
         _progress(f"tuning records loaded: {bnq.load_tuning(args.tuning)}")
     plans, f_b, f_s, terms = [], [], [], 0.0
@@ -739,7 +740,7 @@ def run_batch(args):
     for i in range(args.instances):
         d, N, eps = cells[i % len(cells)]
         f0, L = inp.mixed_instance(d, N, eps, seed=i)
-        p = bnq.Params(d=d, N=N, eps=eps, L=L, precision=prec,
+        p = bnq.Params(d=d, N=N, eps=eps, L=L, precision=prec, schedule=sched,
                        correction=bnq.CORR_MASS if prec == bnq.FP32C else bnq.CORR_NONE)
         pl = bnq.Plan(p)
         if args.autotune and eps != 0 and (d, N, prec) not in tuned:
@@ -765,8 +766,10 @@ def run_batch(args):
     dt = args.dt
     stream = torch.cuda.Stream()
     batch = bnq.Batch(plans, f_b)
+    layout = batch.layout()
     torch.cuda.synchronize()
-    _progress(f"{len(plans)} plans, {len(cells)} cells, {terms:.3e} terms per step")
+    _progress(f"{len(plans)} plans, {len(cells)} cells, {terms:.3e} terms per step; "
+              f"{layout[0]} groups, {layout[1]} shared trilinear launch(es) per stage")
 
     def solo_step():
         for pl, f in zip(plans, f_s):
@@ -797,6 +800,7 @@ def run_batch(args):
     torch.cuda.synchronize()
     t_solo = (time.perf_counter() - t0) / args.steps
     same = all(torch.equal(a, b) for a, b in zip(f_b, f_s))
+    rel = max((torch.linalg.norm(a - b) / torch.linalg.norm(b)).item() for a, b in zip(f_b, f_s))
     batch.close()
     for pl in plans:
         pl.close()
@@ -815,12 +819,14 @@ def run_batch(args):
         "data": "synthetic",
         "config": {"workload": f"{args.instances} instances over cells (d, N) in {cell_set} x eps in (-1, 0, 1), "
                                f"Gaussian-mixture data (seed = instance), RK4 dt={dt}, one HIP-graph replay per step",
-                   "instances": args.instances, "terms_per_step": terms,
+                   "instances": args.instances, "terms_per_step": terms, "schedule": args.schedule,
+                   "groups": layout[0], "shared_trilinear_launches_per_stage": layout[1],
                    "tuning": {f"{d}d{N}": bnq.tune_get(d, N, prec) for (d, N) in cell_set},
                    "pair_split": {f"{d}d{N}" + ("eps0" if e == 0 else ""): bnq.tune_pairs_get(d, N, prec, e)
                                   for (d, N, e) in cells}},
         "solo": {"value": terms / t_solo, "ms_per_step": 1e3 * t_solo, "speedup": t_solo / t_batch},
         "bitwise_equal_to_solo": bool(same),
+        "max_rel_diff_vs_solo": rel,
     }
     print(json.dumps(out))
 

@@ -442,10 +442,15 @@ bnq_status bnq_tune_pairs_set(int32_t d, int32_t N, int32_t precision, int32_t e
 /* ---- Batches ------------------------------------------------------------
  * Many independent instances of the same problem (the homogeneous equation
  * of section 'Convergence towards a steady state', each with its own plan and
- * state) evaluated together.  Plans that share (d, N, C_phi) form a group:
- * each group runs one launch per kernel for all of its instances, and one
- * trilinear launch over the merged work of all of them; every instance's
- * result is bitwise identical to what its own plan computes alone.
+ * state) evaluated together.  Plans that share (d, N, C_phi), precision and
+ * pair-sum split form a group: each group runs one launch per kernel for all
+ * of its instances.  The trilinear sums of every instance of every group run
+ * as one shared launch per stage over the merged work lists (instances of
+ * different (d, N) included); instances of different precision, matrix-core
+ * variant or dynamic queue layout get a shared launch each.  Under the static
+ * schedule every instance's result is bitwise identical to what its own plan
+ * computes alone (an instance's list runs whole on one workgroup, its items in
+ * order, into its own partial arrays).
  *
  * bnq_batch_create(): plans[i] (distinct, same device) and its state f[i]
  *   (device, FP64, the plan's layout; distinct).  The batch keeps these
@@ -464,9 +469,12 @@ bnq_status bnq_tune_pairs_set(int32_t d, int32_t N, int32_t precision, int32_t e
  *   HIP graph on the first call and replays it while (scheme, dt, stream)
  *   are unchanged (a change recaptures); it needs a non-default stream.
  * bnq_batch_destroy(): waits for the batch's work and frees its arrays (not
- *   the plans or states). */
+ *   the plans or states).
+ * bnq_batch_layout(): *groups = number of groups, *trilinear_sets = number
+ *   of shared trilinear launches per stage (either pointer may be NULL). */
 bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f, bnq_batch_t *out);
 bnq_status bnq_batch_destroy(bnq_batch_t batch);
+bnq_status bnq_batch_layout(bnq_batch_t batch, int32_t *groups, int32_t *trilinear_sets);
 bnq_status bnq_batch_collide(bnq_batch_t batch, double *const *Q, void *const *Qhat, bnq_stream_t stream);
 bnq_status bnq_batch_step(bnq_batch_t batch, const double *dt, int32_t scheme, int32_t use_graph,
                           bnq_stream_t stream);

@@ -152,6 +152,7 @@ def lib():
         L.bnq_tune_pairs_set.argtypes = [i32, i32, i32, i32, i32]
         L.bnq_batch_create.argtypes = [i32, vp, vp, ctypes.POINTER(vp)]
         L.bnq_batch_destroy.argtypes = [vp]
+        L.bnq_batch_layout.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.bnq_batch_collide.argtypes = [vp, vp, vp, vp]
         L.bnq_batch_step.argtypes = [vp, vp, i32, i32, vp]
         EQ = ctypes.POINTER(Equilibrium)
@@ -165,7 +166,7 @@ def lib():
         for fn in ("bnq_plan", "bnq_plan_destroy", "bnq_plan_footprint", "bnq_collide", "bnq_step",
                    "bnq_moments", "bnq_health", "bnq_moments_noalloc", "bnq_table_lookup", "bnq_plan_counts", "bnq_plan_set_timing",
                    "bnq_plan_timing", "bnq_plan_autotune", "bnq_tune_get", "bnq_tune_set", "bnq_plan_autotune_pairs",
-                   "bnq_tune_pairs_get", "bnq_tune_pairs_set", "bnq_batch_create", "bnq_batch_destroy", "bnq_batch_collide",
+                   "bnq_tune_pairs_get", "bnq_tune_pairs_set", "bnq_batch_create", "bnq_batch_destroy", "bnq_batch_layout", "bnq_batch_collide",
                    "bnq_batch_step", "bnq_equilibrium_solve", "bnq_fd_be_log", "bnq_equilibrium_fill",
                    "bnq_equilibrium_distance", "bnq_rescaled_init", "bnq_step_rescaled"):
             getattr(L, fn).restype = ctypes.c_int
@@ -434,6 +435,12 @@ class Batch:
 
     def __exit__(self, *a):
         self.close()
+
+    def layout(self):
+        """(groups, shared trilinear launches per stage)."""
+        g, t = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().bnq_batch_layout(self._h, ctypes.byref(g), ctypes.byref(t)))
+        return g.value, t.value
 
     def collide(self, Q, Qhat=None, stream=None):
         n = len(self.plans)

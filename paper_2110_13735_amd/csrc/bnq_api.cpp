@@ -495,6 +495,7 @@ struct bnq_plan_s {
     T1B *bdesc = nullptr;         // FP64: one descriptor per b
     T1G *gdesc = nullptr;         // FP32c: one descriptor per group of b (matrix-core kernel)
     std::vector<T1Item> items_h;  // per-list item lists (host copy), list offsets
+    std::vector<float> icost_h;   // model cost of each item of items_h
     std::vector<int> off_h;       // (dynamic schedule: queue offsets)
     int nq = 0;                   // dynamic schedule: queues (0 = static)
     int *qctr = nullptr;
@@ -667,13 +668,26 @@ int t1_lists(int prec, int nslots) { return prec ? nslots / T1M_WAVES : nslots; 
 
 // Item ranges of the launches: off holds the nl + 1 boundaries of the nl
 // slot lists (or queues); launch r covers [cut[r nl + i], cut[(r + 1) nl + i])
-// of list i, so the launches together walk every list once, in order.
-std::vector<int> t1_cuts(const std::vector<int> &off, int nchunk) {
+// of list i, so the launches together walk every list once, in order.  The
+// cuts split each list by model cost (cost[k] of item k), so that every
+// launch gives each list the same share of its work also when a list holds
+// items of very different sizes (a batch's instances of different N).
+std::vector<int> t1_cuts(const std::vector<int> &off, const std::vector<float> &cost, int nchunk) {
     const size_t nl = off.size() - 1;
     std::vector<int> cut((nchunk + 1) * nl);
-    for (int r = 0; r <= nchunk; ++r)
-        for (size_t i = 0; i < nl; ++i)
-            cut[r * nl + i] = off[i] + (int)((int64_t)(off[i + 1] - off[i]) * r / nchunk);
+    for (size_t i = 0; i < nl; ++i) {
+        double total = 0;
+        for (int k = off[i]; k < off[i + 1]; ++k) total += cost[k];
+        int k = off[i];
+        double acc = 0;
+        cut[i] = off[i];
+        for (int r = 1; r < nchunk; ++r) {
+            const double target = total * r / nchunk;
+            while (k < off[i + 1] && acc + 0.5 * cost[k] <= target) acc += cost[k++];
+            cut[r * nl + i] = k;
+        }
+        cut[nchunk * nl + i] = off[i + 1];
+    }
     return cut;
 }
 
@@ -742,6 +756,7 @@ bnq_status build_t1_work(bnq_plan_s *P) {
                     x.it.t0 = t0;
                     x.it.nt = std::min(64, ntasks - t0);
                     x.it.inst = 0;
+                    x.it.slot = 0;
                     x.cost = cost;
                     items.push_back(x);
                 }
@@ -776,6 +791,7 @@ bnq_status build_t1_work(bnq_plan_s *P) {
         double total = 0, acc = 0;
         for (const It &x : items) total += x.cost;
         std::vector<T1Item> flat;
+        std::vector<float> fcost;
         flat.reserve(items.size());
         size_t i = 0;
         for (int x = 0; x < nx; ++x) {
@@ -783,6 +799,7 @@ bnq_status build_t1_work(bnq_plan_s *P) {
             for (; i < items.size() && (x == nx - 1 || acc + 0.5 * items[i].cost <= cut); ++i) {
                 acc += items[i].cost;
                 flat.push_back(items[i].it);
+                fcost.push_back((float)items[i].cost);
             }
             qoff.push_back((int)flat.size());
         }
@@ -790,20 +807,21 @@ bnq_status build_t1_work(bnq_plan_s *P) {
         P->nbdesc = (int)bd.size();
         P->nq = nx;
         P->items_h = flat;
+        P->icost_h = fcost;
         P->off_h = qoff;
         bnq_status st;
         P->nchunk = t1_chunks(t1_terms(d, N));
         if ((st = upload(&P->bdesc, bd, "trilinear b descriptors")) ||
             (!flat.empty() && (st = upload(&P->items, flat, "trilinear items"))) ||
-            (st = upload(&P->t1cut, t1_cuts(qoff, P->nchunk), "trilinear queues")) ||
+            (st = upload(&P->t1cut, t1_cuts(qoff, fcost, P->nchunk), "trilinear queues")) ||
             (st = dalloc(&P->qctr, (size_t)((nx + 1) & ~1), "trilinear queue tickets")))
             return st;
         return dalloc(&P->part, (size_t)ns_want * g.nm, "trilinear partial sums");
     }
     const int ns = (int)std::max<size_t>(1, std::min<size_t>(ns_want, items.size()));
-    std::vector<std::vector<T1Item>> per(ns);
+    std::vector<std::vector<It>> per(ns);
     if (ns < ns_want) {
-        for (size_t i = 0; i < items.size(); ++i) per[i].push_back(items[i].it);
+        for (size_t i = 0; i < items.size(); ++i) per[i].push_back(items[i]);
     } else {
         double total = 0;
         for (const It &x : items) total += x.cost;
@@ -817,26 +835,32 @@ bnq_status build_t1_work(bnq_plan_s *P) {
                 acc += items[i].cost;
                 const size_t round = k / spx, j = k % spx;
                 const size_t sj = (round & 1) ? spx - 1 - j : j;
-                per[x + nx * sj].push_back(items[i].it);
+                per[x + nx * sj].push_back(items[i]);
             }
         }
     }
     std::vector<int> off(ns + 1, 0);
     std::vector<T1Item> flat;
+    std::vector<float> fcost;
     flat.reserve(items.size());
     for (int s = 0; s < ns; ++s) {
         off[s] = (int)flat.size();
-        flat.insert(flat.end(), per[s].begin(), per[s].end());
+        for (const It &x : per[s]) {
+            flat.push_back(x.it);
+            flat.back().slot = s;
+            fcost.push_back((float)x.cost);
+        }
     }
     off[ns] = (int)flat.size();
     P->nslots = ns;
     P->nbdesc = (int)bd.size();
     P->items_h = flat;
+    P->icost_h = fcost;
     P->off_h = off;
     P->nchunk = t1_chunks(t1_terms(d, N));
     bnq_status st;
     if ((st = upload(&P->bdesc, bd, "trilinear b descriptors")) || (st = upload(&P->items, flat, "trilinear items")) ||
-        (st = upload(&P->t1cut, t1_cuts(off, P->nchunk), "trilinear slot ranges")))
+        (st = upload(&P->t1cut, t1_cuts(off, fcost, P->nchunk), "trilinear slot ranges")))
         return st;
     return dalloc(&P->part, (size_t)ns * g.nm, "trilinear partial sums");
 }
@@ -937,6 +961,7 @@ bnq_status build_t1_work_mfma(bnq_plan_s *P) {
             x.it.t0 = mb;
             x.it.nt = 0;
             x.it.inst = 0;
+            x.it.slot = 0;
             x.cost = cost;
             items.push_back(x);
         }
@@ -953,6 +978,7 @@ bnq_status build_t1_work_mfma(bnq_plan_s *P) {
     for (const It &x : items) total += x.cost;
     std::vector<int> off(1, 0);
     std::vector<T1Item> flat;
+    std::vector<float> fcost;
     flat.reserve(items.size());
     if (P->p.schedule == BNQ_SCHED_DYNAMIC) {
         size_t i = 0;
@@ -962,12 +988,13 @@ bnq_status build_t1_work_mfma(bnq_plan_s *P) {
             for (; i < items.size() && (x == nx - 1 || acc + 0.5 * items[i].cost <= cut); ++i) {
                 acc += items[i].cost;
                 flat.push_back(items[i].it);
+                fcost.push_back((float)items[i].cost);
             }
             off.push_back((int)flat.size());
         }
         P->nq = nx;
     } else {
-        std::vector<std::vector<T1Item>> per(nwg);
+        std::vector<std::vector<It>> per(nwg);
         const int wpx = nwg / nx;  // workgroups per XCD
         size_t i = 0;
         double acc = 0;
@@ -978,25 +1005,30 @@ bnq_status build_t1_work_mfma(bnq_plan_s *P) {
                 acc += items[i].cost;
                 const size_t round = k / wpx, j = k % wpx;
                 const size_t sj = (round & 1) ? wpx - 1 - j : j;
-                per[x + nx * sj].push_back(items[i].it);
+                per[x + nx * sj].push_back(items[i]);
             }
         }
         off.assign(nwg + 1, 0);
         for (int w = 0; w < nwg; ++w) {
             off[w] = (int)flat.size();
-            flat.insert(flat.end(), per[w].begin(), per[w].end());
+            for (const It &x : per[w]) {
+                flat.push_back(x.it);
+                flat.back().slot = w;
+                fcost.push_back((float)x.cost);
+            }
         }
         off[nwg] = (int)flat.size();
     }
     P->nslots = nwg * T1M_WAVES;
     P->nbdesc = (int)gd.size();
     P->items_h = flat;
+    P->icost_h = fcost;
     P->off_h = off;
     P->nchunk = t1_chunks(t1_terms(d, N));
     bnq_status st;
     if ((st = upload(&P->gdesc, gd, "trilinear groups")) ||
         (!flat.empty() && (st = upload(&P->items, flat, "trilinear items"))) ||
-        (st = upload(&P->t1cut, t1_cuts(off, P->nchunk), P->nq ? "trilinear queues" : "trilinear lists")) ||
+        (st = upload(&P->t1cut, t1_cuts(off, fcost, P->nchunk), P->nq ? "trilinear queues" : "trilinear lists")) ||
         (P->nq && (st = dalloc(&P->qctr, (size_t)((P->nq + 1) & ~1), "trilinear queue tickets"))))
         return st;
     return dalloc(&P->part, (size_t)P->nslots * g.nm, "trilinear partial sums");
@@ -1022,6 +1054,7 @@ bnq_status rebuild_t1(bnq_plan_s *P, hipStream_t s) {
     if (st) return st;
     P->ih.part = P->part;
     P->ih.nslots = P->nslots;
+    P->ih.t1d = P->p.precision == BNQ_FP32C ? (const void *)P->gdesc : (const void *)P->bdesc;
     HIPCHK(hipMemcpy(P->inst_d, &P->ih, sizeof(Inst), hipMemcpyHostToDevice));
     return BNQ_OK;
 }
@@ -1071,30 +1104,42 @@ void destroy_plan(bnq_plan_s *P) {
     delete P;
 }
 
+// One trilinear sum over the work of a set of instances: a plan alone, a
+// batch group, or every instance of a batch whose sums share one launch.  The
+// set's lists (static) or queues (dynamic) hold, per slot or queue, the
+// instances' own items one instance after the other, so that every
+// instance's partial sums are formed in exactly the order of its solo
+// evaluation (static schedule).  nchunk launches walk the ranges t1cut.
+struct TriSet {
+    int prec = 0;               // 0 FP64, 1 FP32c
+    int Nmax = 0;               // largest N of the set (selects the matrix-core variant)
+    int nslots = 0;             // partial arrays the launch writes per instance (at most)
+    int nq = 0;                 // dynamic schedule: queues (0 = static)
+    int nchunk = 1;
+    const int *t1cut = nullptr; // (nchunk + 1) x (nq or lists) item ranges
+    const T1Item *items = nullptr;
+    const Inst *D = nullptr;    // the instances the items index
+    int *qctr = nullptr;        // queue tickets (dynamic)
+};
+
 // A set of instances evaluated together: one plan alone, or the instances of
-// a batch that share geometry and tables.  Kernels index the device array D;
-// the trilinear work lists of all instances are merged (per slot, the
-// instances' own lists one after the other, so that every instance's partial
-// sums are formed in exactly the order of its solo evaluation).
+// a batch that share geometry and tables.  Kernels index the device array D.
+// The trilinear sum runs over tri, or, in a batch (tri_shared), in a launch
+// shared with the instances of other groups.
 struct Exec {
     Geo g;
     const TableSet *t = nullptr;
     const double2 *tw = nullptr;
     const Rot *rots = nullptr;
-    int nrot = 0, nslots = 0;
-    int nchunk = 1;                // trilinear launches
-    const int *t1cut = nullptr;    // their item ranges, (nchunk + 1) x (nq or nslots)
-    const T1Item *items = nullptr;
-    const T1B *bdesc = nullptr;
-    const T1G *gdesc = nullptr;
+    int nrot = 0;
+    TriSet tri;
+    bool tri_shared = false;
     const Inst *D = nullptr;
     int prec = 0;               // 0 FP64, 1 FP32c
     bool otf = false;           // FP64: pair weights formed on the fly
     int sepP = 0;               // > 0: trilinear term by the separated-kernel route
     const double2 *sep_gc = nullptr;
     double2 *sep_gt = nullptr, *sep_part = nullptr;
-    int nq = 0;                 // dynamic schedule: queues (0 = static)
-    int *qctr = nullptr;
     std::vector<Inst> Dh;       // host copies of D
     bnq_plan_s *timer = nullptr;  // plan whose timing spans record this run
 };
@@ -1106,21 +1151,22 @@ Exec exec_of(bnq_plan_s *P) {
     E.tw = P->tw;
     E.rots = P->rots_d;
     E.nrot = (int)P->grp.size();
-    E.nslots = P->nslots;
-    E.nchunk = P->nchunk;
-    E.t1cut = P->t1cut;
-    E.items = P->items;
-    E.bdesc = P->bdesc;
-    E.gdesc = P->gdesc;
     E.D = P->inst_d;
     E.prec = P->p.precision == BNQ_FP32C ? 1 : 0;
+    E.tri.prec = E.prec;
+    E.tri.Nmax = P->g.N;
+    E.tri.nslots = P->nslots;
+    E.tri.nq = P->nq;
+    E.tri.nchunk = P->nchunk;
+    E.tri.t1cut = P->t1cut;
+    E.tri.items = P->items;
+    E.tri.D = P->inst_d;
+    E.tri.qctr = P->qctr;
     E.otf = P->otf;
     E.sepP = P->sepP;
     E.sep_gc = P->sep_gc;
     E.sep_gt = P->sep_gt;
     E.sep_part = P->sep_part;
-    E.nq = P->nq;
-    E.qctr = P->qctr;
     E.Dh.assign(1, P->ih);
     E.timer = P;
     return E;
@@ -1144,13 +1190,25 @@ std::vector<IOs> make_ios(int n, const double *dt, F fill) {
     return v;
 }
 
-bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s) {
+int terms_of(const Exec &E) {
+    int any = 0;
+    for (const Inst &I : E.Dh) any |= I.terms;
+    return any;
+}
+
+int max_slots_of(const Exec &E) {
+    int m = 0;
+    for (const Inst &I : E.Dh)
+        if (I.terms & BNQ_T_QTRI) m = std::max(m, I.nslots);
+    return m;
+}
+
+// The phases of an evaluation before its trilinear sum: spectra, pair sums,
+// outer sum, and the rotated spectra and cleared partial arrays the
+// trilinear sum reads and writes (or the whole separated-kernel route).
+bnq_status collide_pre(const Exec &E, const std::vector<IOs> &ios, hipStream_t s) {
     const Geo &g = E.g;
-    int any = 0, max_slots = 0;
-    for (const Inst &I : E.Dh) {
-        any |= I.terms;
-        if (I.terms & BNQ_T_QTRI) max_slots = std::max(max_slots, I.nslots);
-    }
+    const int any = terms_of(E), max_slots = max_slots_of(E);
     {
         Span sp(E.timer, 0, s);
         for (const IOs &io : ios) {
@@ -1190,34 +1248,44 @@ bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s
                 LAUNCHCHK();
             }
     } else if (any & BNQ_T_QTRI) {
-        {
-            Span sp(E.timer, 4, s);
-            for (const IOs &io : ios) {
-                launch_rotate(g, E.prec, E.D, io, E.rots, E.nrot, s);
-                LAUNCHCHK();
-                launch_zero_part(g, E.D, io, max_slots, s);
-                LAUNCHCHK();
-            }
-        }
-        const int nl = E.nq ? E.nq : t1_lists(E.prec, E.nslots);
-        for (int r = 0; r < E.nchunk; ++r) {
-            if (E.nq) {
-                launch_zero(E.qctr, (int64_t)((E.nq + 1) & ~1) * (int64_t)sizeof(int), s);  // whole 8-byte words
-                LAUNCHCHK();
-            }
-            Span sp(E.timer, 3, s);
-            launch_trilinear(g, E.prec, E.nslots, E.t1cut + (size_t)r * nl, E.t1cut + (size_t)(r + 1) * nl, E.items,
-                             E.prec ? (const void *)E.gdesc : (const void *)E.bdesc,
-                             E.prec ? (const void *)E.t->K32 : (const void *)E.t->K, E.D, E.rots, E.nq,
-                             E.qctr, s);
+        Span sp(E.timer, 4, s);
+        for (const IOs &io : ios) {
+            launch_rotate(g, E.prec, E.D, io, E.rots, E.nrot, s);
+            LAUNCHCHK();
+            launch_zero_part(g, E.D, io, max_slots, s);
             LAUNCHCHK();
         }
-        {
-            Span sp(E.timer, 4, s);
-            for (const IOs &io : ios) {
-                launch_reduce_partials(g, E.D, io, max_slots, s);
-                LAUNCHCHK();
-            }
+    }
+    return BNQ_OK;
+}
+
+bool has_tri_launch(const Exec &E) { return (terms_of(E) & BNQ_T_QTRI) && !E.sepP; }
+
+bnq_status run_tri(const TriSet &T, bnq_plan_s *timer, hipStream_t s) {
+    const int nl = T.nq ? T.nq : t1_lists(T.prec, T.nslots);
+    for (int r = 0; r < T.nchunk; ++r) {
+        if (T.nq) {
+            launch_zero(T.qctr, (int64_t)((T.nq + 1) & ~1) * (int64_t)sizeof(int), s);  // whole 8-byte words
+            LAUNCHCHK();
+        }
+        Span sp(timer, 3, s);
+        launch_trilinear(T.prec, T.Nmax, T.nslots, T.t1cut + (size_t)r * nl, T.t1cut + (size_t)(r + 1) * nl, T.items,
+                         T.D, T.nq, T.qctr, s);
+        LAUNCHCHK();
+    }
+    return BNQ_OK;
+}
+
+// The phases after the trilinear sum: partial arrays reduced, combined, the
+// inverse transform, the moment projection.
+bnq_status collide_post(const Exec &E, const std::vector<IOs> &ios, hipStream_t s) {
+    const Geo &g = E.g;
+    if (has_tri_launch(E)) {
+        const int max_slots = max_slots_of(E);
+        Span sp(E.timer, 4, s);
+        for (const IOs &io : ios) {
+            launch_reduce_partials(g, E.D, io, max_slots, s);
+            LAUNCHCHK();
         }
     }
     {
@@ -1239,64 +1307,84 @@ bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s
     return BNQ_OK;
 }
 
-// One time step of every instance: f[i] advanced in place by dt[i].
-bnq_status run_step(const Exec &E, double *const *f, const double *dt, int scheme, hipStream_t s) {
-    const int n = (int)E.Dh.size();
+// One evaluation of every instance of the groups Es (instances and buffers
+// per group in ios[i]): all groups' phases before the trilinear sums, the
+// sums (each group's own launch, or the shared launches of sets), then all
+// groups' phases after them.
+bnq_status collide_groups(const std::vector<const Exec *> &Es, const std::vector<std::vector<IOs>> &ios,
+                          const std::vector<TriSet> &sets, hipStream_t s) {
+    bnq_status st;
+    for (size_t i = 0; i < Es.size(); ++i)
+        if ((st = collide_pre(*Es[i], ios[i], s))) return st;
+    for (const Exec *E : Es)
+        if (has_tri_launch(*E) && !E->tri_shared && (st = run_tri(E->tri, E->timer, s))) return st;
+    for (const TriSet &T : sets)
+        if ((st = run_tri(T, nullptr, s))) return st;
+    for (size_t i = 0; i < Es.size(); ++i)
+        if ((st = collide_post(*Es[i], ios[i], s))) return st;
+    return BNQ_OK;
+}
+
+bnq_status run_collide(const Exec &E, const std::vector<IOs> &ios, hipStream_t s) {
+    return collide_groups({&E}, {ios}, {}, s);
+}
+
+// One time step of every instance of the groups Es: f[i][j] (instance j of
+// group i) advanced in place by dt[i][j].  Every stage evaluates all groups
+// together (collide_groups), so a batch's trilinear sums share launches.
+bnq_status step_groups(const std::vector<const Exec *> &Es, const std::vector<double *const *> &f,
+                       const std::vector<const double *> &dt, const std::vector<TriSet> &sets, int scheme,
+                       hipStream_t s) {
     if (scheme != BNQ_EULER && scheme != BNQ_SSPRK2 && scheme != BNQ_RK4)
         return fail(BNQ_EINVAL, "unknown scheme %d", scheme);
+    const size_t ng = Es.size();
     auto coll = [&](int stage) {
-        return make_ios(n, dt, [&](IOs &io, int z, int i) {
-            io.in[z] = stage == 0 ? f[i] : E.Dh[i].ybuf;
-            io.out[z] = E.Dh[i].k[stage];
-        });
+        std::vector<std::vector<IOs>> io(ng);
+        for (size_t i = 0; i < ng; ++i)
+            io[i] = make_ios((int)Es[i]->Dh.size(), dt[i], [&](IOs &x, int z, int j) {
+                x.in[z] = stage == 0 ? f[i][j] : Es[i]->Dh[j].ybuf;
+                x.out[z] = Es[i]->Dh[j].k[stage];
+            });
+        return collide_groups(Es, io, sets, s);
     };
-    const std::vector<IOs> upd = make_ios(n, dt, [&](IOs &io, int z, int i) {
-        io.in[z] = f[i];
-        io.out[z] = f[i];
-    });
-    bnq_status st;
-    if ((st = run_collide(E, coll(0), s))) return st;
-    if (scheme == BNQ_EULER) {
-        Span sp(E.timer, 6, s);
-        for (const IOs &io : upd) {
-            launch_stage(E.g, E.D, io, 1.0, 0, 1, s);
-            LAUNCHCHK();
-        }
-        return BNQ_OK;
-    }
-    if (scheme == BNQ_SSPRK2) {
-        {
-            Span sp(E.timer, 6, s);
-            for (const IOs &io : upd) {
-                launch_stage(E.g, E.D, io, 1.0, 0, 0, s);
+    std::vector<std::vector<IOs>> upd(ng);
+    for (size_t i = 0; i < ng; ++i)
+        upd[i] = make_ios((int)Es[i]->Dh.size(), dt[i], [&](IOs &x, int z, int j) {
+            x.in[z] = f[i][j];
+            x.out[z] = f[i][j];
+        });
+    // kind 0: stage value (a, ks, to_out), 1: SSP-RK2 final, 2: RK4 final
+    auto update = [&](int kind, double a, int ks, int to_out) -> bnq_status {
+        for (size_t i = 0; i < ng; ++i) {
+            Span sp(Es[i]->timer, 6, s);
+            for (const IOs &io : upd[i]) {
+                if (kind == 0)
+                    launch_stage(Es[i]->g, Es[i]->D, io, a, ks, to_out, s);
+                else if (kind == 1)
+                    launch_ssprk2_final(Es[i]->g, Es[i]->D, io, s);
+                else
+                    launch_rk4_final(Es[i]->g, Es[i]->D, io, s);
                 LAUNCHCHK();
             }
         }
-        if ((st = run_collide(E, coll(1), s))) return st;
-        Span sp(E.timer, 6, s);
-        for (const IOs &io : upd) {
-            launch_ssprk2_final(E.g, E.D, io, s);
-            LAUNCHCHK();
-        }
         return BNQ_OK;
+    };
+    bnq_status st;
+    if ((st = coll(0))) return st;
+    if (scheme == BNQ_EULER) return update(0, 1.0, 0, 1);
+    if (scheme == BNQ_SSPRK2) {
+        if ((st = update(0, 1.0, 0, 0)) || (st = coll(1))) return st;
+        return update(1, 0.0, 0, 0);
     }
     const double a[3] = {0.5, 0.5, 1.0};
-    for (int stg = 1; stg < 4; ++stg) {
-        {
-            Span sp(E.timer, 6, s);
-            for (const IOs &io : upd) {
-                launch_stage(E.g, E.D, io, a[stg - 1], stg - 1, 0, s);
-                LAUNCHCHK();
-            }
-        }
-        if ((st = run_collide(E, coll(stg), s))) return st;
-    }
-    Span sp(E.timer, 6, s);
-    for (const IOs &io : upd) {
-        launch_rk4_final(E.g, E.D, io, s);
-        LAUNCHCHK();
-    }
-    return BNQ_OK;
+    for (int stg = 1; stg < 4; ++stg)
+        if ((st = update(0, a[stg - 1], stg - 1, 0)) || (st = coll(stg))) return st;
+    return update(2, 0.0, 0, 0);
+}
+
+// One time step of every instance of E: f[i] advanced in place by dt[i].
+bnq_status run_step(const Exec &E, double *const *f, const double *dt, int scheme, hipStream_t s) {
+    return step_groups({&E}, {f}, {dt}, {}, scheme, s);
 }
 
 // Status recorded in the plan's health flags by steps that have completed on
@@ -1506,6 +1594,10 @@ bnq_status bnq_plan(const bnq_params *p, bnq_stream_t stream, bnq_plan_t *out) {
         I.ginv = nullptr;
         I.health = P->health;
         I.fbound = (P->alpha > 0 && !(p->flags & BNQ_FLAG_NO_FERMI_BOUND)) ? 1.0 / P->alpha : INFINITY;
+        I.geo = P->g;
+        I.K = p->precision == BNQ_FP32C ? (const void *)P->tabs->K32 : (const void *)P->tabs->K;
+        I.t1d = p->precision == BNQ_FP32C ? (const void *)P->gdesc : (const void *)P->bdesc;
+        I.rots = P->rots_d;
         if (I.corr_mom) {
             std::vector<double> gi;
             if ((st = gram_inverse(p->d, p->N, I.hstep, gi)) || (st = upload(&P->ginv, gi, "moment Gram matrix"))) {
@@ -2016,6 +2108,8 @@ bnq_status bnq_plan_autotune_pairs(bnq_plan_t P, const double *f, int32_t reps, 
     // the pair sums rewrite W and Qc from the spectrum; the split kept is the
     // one every later evaluation of this plan uses
     P->g.psplit = best_k;
+    P->ih.geo = P->g;
+    HIPCHK(hipMemcpy(P->inst_d, &P->ih, sizeof(Inst), hipMemcpyHostToDevice));
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     {
@@ -2128,9 +2222,15 @@ const char *bnq_last_error(void) { return g_err.c_str(); }
 // ---------------------------------------------------------------------------
 // Batches (a fixed set of plans and state arrays evaluated together).
 struct bnq_batch_s {
+    // instances that share geometry and tables: one launch per kernel
     struct Group {
         Exec E;
         std::vector<int> members;  // positions in the batch
+        Inst *D = nullptr;
+    };
+    // one trilinear sum per stage over the instances of several groups
+    struct Shared {
+        TriSet T;
         Inst *D = nullptr;
         int *t1cut = nullptr;
         T1Item *items = nullptr;
@@ -2139,6 +2239,7 @@ struct bnq_batch_s {
     std::vector<bnq_plan_s *> plans;
     std::vector<double *> f;
     std::vector<Group> groups;
+    std::vector<Shared> shared;
     hipGraphExec_t gexec = nullptr;  // captured step, replayed while (scheme, dt, stream) match
     int g_scheme = -1;
     std::vector<double> g_dt;
@@ -2150,27 +2251,39 @@ namespace {
 void destroy_batch(bnq_batch_s *B) {
     if (!B) return;
     if (B->gexec) hipGraphExecDestroy(B->gexec);
-    for (auto &G : B->groups) {
-        hipFree(G.D);
-        hipFree(G.t1cut);
-        hipFree(G.items);
-        hipFree(G.qctr);
+    for (auto &G : B->groups) hipFree(G.D);
+    for (auto &S : B->shared) {
+        hipFree(S.D);
+        hipFree(S.t1cut);
+        hipFree(S.items);
+        hipFree(S.qctr);
     }
     delete B;
 }
 
+std::vector<TriSet> shared_sets(const bnq_batch_s *B) {
+    std::vector<TriSet> v;
+    for (const auto &S : B->shared) v.push_back(S.T);
+    return v;
+}
+
 bnq_status batch_step_enqueue(bnq_batch_s *B, const double *dt, int scheme, hipStream_t s) {
-    for (auto &G : B->groups) {
-        std::vector<double *> fs;
-        std::vector<double> dts;
+    std::vector<const Exec *> Es;
+    std::vector<std::vector<double *>> fs(B->groups.size());
+    std::vector<std::vector<double>> dts(B->groups.size());
+    std::vector<double *const *> fp;
+    std::vector<const double *> dp;
+    for (size_t i = 0; i < B->groups.size(); ++i) {
+        const auto &G = B->groups[i];
+        Es.push_back(&G.E);
         for (int m : G.members) {
-            fs.push_back(B->f[m]);
-            dts.push_back(dt[m]);
+            fs[i].push_back(B->f[m]);
+            dts[i].push_back(dt[m]);
         }
-        bnq_status st = run_step(G.E, fs.data(), dts.data(), scheme, s);
-        if (st) return st;
+        fp.push_back(fs[i].data());
+        dp.push_back(dts[i].data());
     }
-    return BNQ_OK;
+    return step_groups(Es, fp, dp, shared_sets(B), scheme, s);
 }
 
 }  // namespace
@@ -2195,14 +2308,13 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
     bnq_batch_s *B = new bnq_batch_s;
     B->plans.assign(plans, plans + n);
     B->f.assign(f, f + n);
-    // A dynamic group lets any of its waves take any member's items, so its
-    // members must have the same number of partial arrays.
-    std::map<std::tuple<const TableSet *, int, int, int, int>, int> gidx;
+    // Groups: instances that share geometry, tables, precision and the
+    // pair-sum split run each kernel as one launch.
+    std::map<std::tuple<const TableSet *, int, int>, int> gidx;
     for (int i = 0; i < n; ++i) {
         const bnq_plan_s *Pi = plans[i];
-        const int dyn_slots = (Pi->nq && (Pi->ih.terms & BNQ_T_QTRI)) ? Pi->nslots : 0;
         const auto key = std::make_tuple((const TableSet *)Pi->tabs, (int)Pi->p.precision + 2 * (int)Pi->otf,
-                                         (int)Pi->p.schedule, dyn_slots, Pi->g.psplit);
+                                         Pi->g.psplit);
         auto it = gidx.find(key);
         if (it == gidx.end()) {
             gidx[key] = (int)B->groups.size();
@@ -2213,8 +2325,8 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
         }
     }
     for (auto &G : B->groups) {
-        // the group's trilinear descriptors and schedule come from a member
-        // that has the trilinear term (plans without it build no work lists)
+        // rotations and transforms come from a member with the trilinear term
+        // if there is one (plans without it build no work lists)
         bnq_plan_s *P0 = plans[G.members[0]];
         for (int m : G.members)
             if (plans[m]->ih.terms & BNQ_T_QTRI) {
@@ -2223,69 +2335,137 @@ bnq_status bnq_batch_create(int32_t n, const bnq_plan_t *plans, double *const *f
             }
         G.E = exec_of(P0);
         G.E.timer = nullptr;
+        G.E.tri_shared = true;
         G.E.Dh.clear();
-        int ns = 0;
-        for (int m : G.members) {
-            G.E.Dh.push_back(plans[m]->ih);
-            ns = std::max(ns, plans[m]->nslots);
+        for (int m : G.members) G.E.Dh.push_back(plans[m]->ih);
+        bnq_status st;
+        if ((st = upload(&G.D, G.E.Dh, "batch instance descriptors"))) {
+            destroy_batch(B);
+            return st;
+        }
+        G.E.D = G.D;
+    }
+    // Shared trilinear sums: every instance with the term whose kernel
+    // variant and schedule agree (dynamic queues also need equal slot
+    // counts: any wave may take any instance's item) joins one launch per
+    // stage.  Members are ordered by decreasing trilinear work, so that in a
+    // queue the large instances' items come first and the small ones fill
+    // the tail.
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> sidx;
+    for (int i = 0; i < n; ++i) {
+        const bnq_plan_s *Pi = plans[i];
+        if (!(Pi->ih.terms & BNQ_T_QTRI)) continue;
+        const int prec = Pi->p.precision == BNQ_FP32C ? 1 : 0;
+        const auto key = std::make_tuple(prec, prec ? t1_mfma_class(Pi->g.N) : 0, Pi->nq, Pi->nq ? Pi->nslots : 0);
+        sidx[key].push_back(i);
+    }
+    for (auto &kv : sidx) {
+        std::vector<int> mem = kv.second;
+        std::stable_sort(mem.begin(), mem.end(), [&](int a, int b) {
+            return t1_terms(plans[a]->g.d, plans[a]->g.N) > t1_terms(plans[b]->g.d, plans[b]->g.N);
+        });
+        B->shared.emplace_back();
+        auto &S = B->shared.back();
+        const bnq_plan_s *Q0 = plans[mem[0]];
+        S.T.prec = Q0->p.precision == BNQ_FP32C ? 1 : 0;
+        S.T.nq = Q0->nq;
+        std::vector<Inst> Dh;
+        double terms = 0;
+        for (int m : mem) {
+            Dh.push_back(plans[m]->ih);
+            S.T.Nmax = std::max(S.T.Nmax, plans[m]->g.N);
+            S.T.nslots = std::max(S.T.nslots, plans[m]->nslots);
+            terms += t1_terms(plans[m]->g.d, plans[m]->g.N);
         }
         std::vector<int> off;
         std::vector<T1Item> items;
-        const int nq = P0->nq;
-        if (nq) {
+        std::vector<float> cost;
+        if (S.T.nq) {
             // dynamic: queue x holds every member's queue-x items, member by member
             off.assign(1, 0);
-            for (int x = 0; x < nq; ++x) {
-                for (size_t j = 0; j < G.members.size(); ++j) {
-                    const bnq_plan_s *P = plans[G.members[j]];
-                    if (!(P->ih.terms & BNQ_T_QTRI)) continue;
+            for (int x = 0; x < S.T.nq; ++x) {
+                for (size_t j = 0; j < mem.size(); ++j) {
+                    const bnq_plan_s *P = plans[mem[j]];
                     for (int k = P->off_h[x]; k < P->off_h[x + 1]; ++k) {
                         T1Item it = P->items_h[k];
                         it.inst = (int)j;
                         items.push_back(it);
+                        cost.push_back(P->icost_h[k]);
                     }
                 }
                 off.push_back((int)items.size());
             }
         } else {
-            const int prec = G.E.prec, nl = t1_lists(prec, ns);
+            // static: every member's list sl runs as list (sl + o_j) mod nl of
+            // the set (its items keep their own list in T1Item::slot, hence
+            // their partial arrays).  Members that fill every list take
+            // o_j = 0; the others, whose few items sit in their first lists,
+            // are placed one after another around the ring of lists, so that
+            // small instances do not all load the same workgroups.  In a set
+            // list the members' items are interleaved by their relative
+            // position in their own lists: instances of one cell have the same
+            // items, so the workgroups walk the kernel-mode rows once for all
+            // of them (each row is read for every instance while it is in L2)
+            // instead of once per instance; every instance's own items keep
+            // their order.
+            const int nl = t1_lists(S.T.prec, S.T.nslots);
+            struct Ent {
+                double r;  // relative position in the member's list
+                int j, k;  // member, index into its items_h
+            };
+            std::vector<std::vector<Ent>> per(nl);
+            int ring = 0;
+            for (size_t j = 0; j < mem.size(); ++j) {
+                const bnq_plan_s *P = plans[mem[j]];
+                const int nlj = t1_lists(S.T.prec, P->nslots);
+                int used = 0;
+                for (int sl = 0; sl < nlj; ++sl)
+                    if (P->off_h[sl + 1] > P->off_h[sl]) used = sl + 1;
+                const int o = used >= nl ? 0 : ring;
+                if (used < nl) ring = (ring + used) % nl;
+                for (int sl = 0; sl < nlj; ++sl) {
+                    const int L = (sl + o) % nl, k0 = P->off_h[sl], n_sl = P->off_h[sl + 1] - k0;
+                    for (int k = k0; k < k0 + n_sl; ++k) per[L].push_back({(k - k0 + 0.5) / n_sl, (int)j, k});
+                }
+            }
             off.assign(nl + 1, 0);
-            for (int sl = 0; sl < nl; ++sl) {
-                off[sl] = (int)items.size();
-                for (size_t j = 0; j < G.members.size(); ++j) {
-                    const bnq_plan_s *P = plans[G.members[j]];
-                    if (!(P->ih.terms & BNQ_T_QTRI) || sl >= t1_lists(prec, P->nslots)) continue;
-                    for (int k = P->off_h[sl]; k < P->off_h[sl + 1]; ++k) {
-                        T1Item x = P->items_h[k];
-                        x.inst = (int)j;
-                        items.push_back(x);
-                    }
+            for (int L = 0; L < nl; ++L) {
+                std::stable_sort(per[L].begin(), per[L].end(), [](const Ent &a, const Ent &b) { return a.r < b.r; });
+                off[L] = (int)items.size();
+                for (const Ent &e : per[L]) {
+                    const bnq_plan_s *P = plans[mem[e.j]];
+                    T1Item x = P->items_h[e.k];
+                    x.inst = e.j;
+                    items.push_back(x);
+                    cost.push_back(P->icost_h[e.k]);
                 }
             }
             off[nl] = (int)items.size();
         }
-        // launches per evaluation: by the trilinear terms of the whole group
-        double terms = 0;
-        for (int m : G.members)
-            if (plans[m]->ih.terms & BNQ_T_QTRI) terms += t1_terms(plans[m]->g.d, plans[m]->g.N);
-        G.E.nchunk = t1_chunks(terms);
+        // launches per evaluation: by the trilinear terms of the whole set
+        S.T.nchunk = t1_chunks(terms);
         bnq_status st;
-        if ((st = upload(&G.D, G.E.Dh, "batch instance descriptors")) ||
-            (st = upload(&G.t1cut, t1_cuts(off, G.E.nchunk), nq ? "batch queues" : "batch slot ranges")) ||
-            (nq && (st = dalloc(&G.qctr, (size_t)((nq + 1) & ~1), "batch queue tickets"))) ||
-            (!items.empty() && (st = upload(&G.items, items, "batch trilinear items")))) {
+        if ((st = upload(&S.D, Dh, "batch trilinear instances")) ||
+            (st = upload(&S.t1cut, t1_cuts(off, cost, S.T.nchunk), S.T.nq ? "batch queues" : "batch slot ranges")) ||
+            (S.T.nq && (st = dalloc(&S.qctr, (size_t)((S.T.nq + 1) & ~1), "batch queue tickets"))) ||
+            (!items.empty() && (st = upload(&S.items, items, "batch trilinear items")))) {
             destroy_batch(B);
             return st;
         }
-        G.E.nq = nq;
-        G.E.qctr = G.qctr;
-        G.E.D = G.D;
-        G.E.nslots = ns;
-        G.E.t1cut = G.t1cut;
-        G.E.items = G.items;
+        S.T.D = S.D;
+        S.T.t1cut = S.t1cut;
+        S.T.items = S.items;
+        S.T.qctr = S.qctr;
     }
     for (auto *P : B->plans) ++P->nbatch;
     *out = B;
+    return BNQ_OK;
+}
+
+bnq_status bnq_batch_layout(bnq_batch_t B, int32_t *groups, int32_t *trilinear_sets) {
+    if (!B) return fail(BNQ_EINVAL, "batch is NULL");
+    if (groups) *groups = (int32_t)B->groups.size();
+    if (trilinear_sets) *trilinear_sets = (int32_t)B->shared.size();
     return BNQ_OK;
 }
 
@@ -2309,17 +2489,18 @@ bnq_status bnq_batch_collide(bnq_batch_t B, double *const *Q, void *const *Qhat,
     }
     hipStream_t s = (hipStream_t)stream;
     for (auto *P : B->plans) P->last = s;
+    std::vector<const Exec *> Es;
+    std::vector<std::vector<IOs>> ios;
     for (auto &G : B->groups) {
-        const int m = (int)G.members.size();
-        bnq_status st = run_collide(G.E, make_ios(m, nullptr, [&](IOs &io, int z, int j) {
-                                        const int i = G.members[j];
-                                        io.in[z] = B->f[i];
-                                        io.out[z] = Q[i];
-                                        io.qhat[z] = Qhat ? (double2 *)Qhat[i] : nullptr;
-                                    }), s);
-        if (st) return st;
+        Es.push_back(&G.E);
+        ios.push_back(make_ios((int)G.members.size(), nullptr, [&](IOs &io, int z, int j) {
+            const int i = G.members[j];
+            io.in[z] = B->f[i];
+            io.out[z] = Q[i];
+            io.qhat[z] = Qhat ? (double2 *)Qhat[i] : nullptr;
+        }));
     }
-    return BNQ_OK;
+    return collide_groups(Es, ios, shared_sets(B), s);
 }
 
 bnq_status bnq_batch_step(bnq_batch_t B, const double *dt, int32_t scheme, int32_t use_graph, bnq_stream_t stream) {

@@ -103,6 +103,9 @@ struct T1Item {
     int t0;    // first task
     int nt;    // number of tasks (<= 64)
     int inst;  // instance (index into the launch's Inst array)
+    int slot;  // static schedule: the item's list in its instance's own plan,
+               // which names the partial arrays it adds into (the list may
+               // run on another workgroup in a batch); unused when dynamic
 };
 
 constexpr int T1_RB = 8;      // outputs per lane along x
@@ -230,6 +233,33 @@ __device__ __forceinline__ float2 ld_uniform(const float2 *p, int64_t i) {
     const __attribute__((address_space(4))) float *q = (const __attribute__((address_space(4))) float *)p;
     return make_float2(q[2 * i], q[2 * i + 1]);
 }
+// A geometry or a pointer held in device memory, read the same way.
+__device__ __forceinline__ Geo ld_uniform_geo(const Geo *p) {
+    typedef const __attribute__((address_space(4))) Geo CGeo;
+    const CGeo *q = (const CGeo *)p;
+    Geo g;
+    g.d = q->d;
+    g.N = q->N;
+    g.h = q->h;
+    g.e0 = q->e0;
+    g.lo0 = q->lo0;
+    g.nm = q->nm;
+    g.eg0 = q->eg0;
+    g.neg = q->neg;
+    g.ea0 = q->ea0;
+    g.na = q->na;
+    g.kax = q->kax;
+    g.nak = q->nak;
+    g.ex0 = q->ex0;
+    g.next = q->next;
+    g.psplit = q->psplit;
+    return g;
+}
+template <typename T>
+__device__ __forceinline__ T *ld_uniform_ptr(T *const *p) {
+    typedef T *const __attribute__((address_space(4))) CP;
+    return *(CP *)p;
+}
 
 
 // ---- instances --------------------------------------------------------------
@@ -276,6 +306,13 @@ struct Inst {
     // above fbound), set by the device, read and cleared by the host
     int *health;
     double fbound;  // 1/alpha for Fermi-Dirac statistics (alpha > 0), else +inf
+    // The instance's geometry, tables and trilinear work descriptors, read by
+    // the trilinear kernels per work item, so that one launch can serve
+    // instances of different (d, N).
+    Geo geo;
+    const void *K;      // kernel-mode rows: double (FP64) or float (FP32c)
+    const void *t1d;    // work descriptors: T1B (FP64) or T1G (FP32c)
+    const Rot *rots;    // the rotations the descriptors index
 };
 
 // Buffers a kernel can be pointed at.
@@ -331,20 +368,25 @@ void launch_pairs(const Geo &g, int prec, const Inst *D, const IOs &io, const vo
                   const Radial *otf, hipStream_t s);
 void launch_outer(const Geo &g, const Inst *D, const IOs &io, hipStream_t s);
 void launch_zero_part(const Geo &g, const Inst *D, const IOs &io, int max_slots, hipStream_t s);
-// prec 0: FP64 (K is double), 1: FP32c (K is float, spectra Inst::Gr32)
-// nq = 0: static per-slot lists; nq > 0: dynamic tickets over nq queues
 // Trilinear sum over the item ranges [lo[i], hi[i]) of the nslots slots
-// (static) or nq queues (dynamic).
-// desc: T1B array (FP64) or T1G array (FP32c); nslots partial arrays
-void launch_trilinear(const Geo &g, int prec, int nslots, const int *lo, const int *hi, const T1Item *items,
-                      const void *desc, const void *K, const Inst *D, const Rot *rots, int nq, int *qctr,
-                      hipStream_t s);
-void launch_t1_pairs(const Geo &g, int nslots, const int *lo, const int *hi, const T1Item *items,
-                     const T1B *bdesc, const double *K, const Inst *D, const Rot *rots, int nq, int *qctr,
-                     hipStream_t s);
-// FP32c: matrix-core kernel, nwg workgroups of 4 waves, partial array 4 wg + wave
-void launch_t1_mfma(const Geo &g, int nwg, const int *lo, const int *hi, const T1Item *items, const T1G *gdesc,
-                    const float *K, const Inst *D, const Rot *rots, int nq, int *qctr, hipStream_t s);
+// (static, nq = 0) or of the nq queues (dynamic tickets, nq > 0).  An item
+// names its instance in D, whose geometry, kernel-mode rows and descriptors
+// (Inst::geo, K, t1d, rots) it uses: the instances of one launch may differ
+// in (d, N).  prec 0: FP64 (double rows); 1: FP32c (float rows, spectra
+// Inst::Gr32, the matrix-core kernel for rows of at most N + 1 inner values:
+// every instance of the launch has N <= Nmax, and Nmax selects the kernel,
+// see t1_mfma_class).
+void launch_trilinear(int prec, int Nmax, int nslots, const int *lo, const int *hi, const T1Item *items,
+                      const Inst *D, int nq, int *qctr, hipStream_t s);
+void launch_t1_pairs(int nslots, const int *lo, const int *hi, const T1Item *items, const Inst *D, int nq,
+                     int *qctr, hipStream_t s);
+// FP32c: matrix-core kernel, nwg workgroups of T1M_WAVES waves, partial array
+// T1M_WAVES wg + wave
+void launch_t1_mfma(int Nmax, int nwg, const int *lo, const int *hi, const T1Item *items, const Inst *D, int nq,
+                    int *qctr, hipStream_t s);
+// the matrix-core kernel variant that serves N (instances of one launch must
+// share it: the variants differ in LDS, hence in resident workgroups)
+int t1_mfma_class(int N);
 int t1_pairs_blocks_per_cu();
 int t1_mfma_blocks_per_cu(int N);
 constexpr int T1M_WAVES = 8;     // waves (partial arrays) per matrix-core workgroup

@@ -650,14 +650,12 @@ void launch_outer(const Geo &g, const Inst *D, const IOs &io, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Trilinear sum: FP64 in t1_pairs.hip (vector units), FP32c in t1_mfma.hip
 // (matrix cores, 4 partial arrays per workgroup).
-void launch_trilinear(const Geo &g, int prec, int nslots, const int *lo, const int *hi, const T1Item *items,
-                      const void *desc, const void *K, const Inst *D, const Rot *rots, int nq, int *qctr,
-                      hipStream_t s) {
+void launch_trilinear(int prec, int Nmax, int nslots, const int *lo, const int *hi, const T1Item *items,
+                      const Inst *D, int nq, int *qctr, hipStream_t s) {
     if (prec == 0)
-        launch_t1_pairs(g, nslots, lo, hi, items, (const T1B *)desc, (const double *)K, D, rots, nq, qctr, s);
+        launch_t1_pairs(nslots, lo, hi, items, D, nq, qctr, s);
     else
-        launch_t1_mfma(g, nslots / T1M_WAVES, lo, hi, items, (const T1G *)desc, (const float *)K, D, rots, nq, qctr,
-                       s);
+        launch_t1_mfma(Nmax, nslots / T1M_WAVES, lo, hi, items, D, nq, qctr, s);
 }
 
 int trilinear_blocks_per_cu(int prec, int N) { return prec == 0 ? t1_pairs_blocks_per_cu() : t1_mfma_blocks_per_cu(N); }

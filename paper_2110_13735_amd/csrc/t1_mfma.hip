@@ -15,10 +15,12 @@
 // windows (a mode outside one rotation's own window meets a zero P_R, or an
 // output that is not written).  Then T1(R n') += G(R (n' - b_c)) Y_R(n').
 //
-// A workgroup of 4 waves takes an item (group, block of 128 outputs n' in the
-// flattened window, x fastest); each wave owns 2 tiles of 16 outputs and up
+// A workgroup of 8 waves takes an item (group, block of 128 outputs n' in the
+// flattened window, x fastest); each wave owns one tile of 16 outputs and up
 // to 3 tiles of 16 columns (8 rotations x re/im), and adds its results into
-// its own partial array.  Inner rows (p'_y, p'_z) are walked in order.  For
+// its own partial array.  The item names its instance, whose geometry, rows
+// and descriptors it uses, so one launch can serve instances of different
+// (d, N) (of one kernel variant).  Inner rows (p'_y, p'_z) are walked in order.  For
 // every row the workgroup stages in LDS, while the previous row runs on the
 // matrix cores,
 //   - the pair products of the row (one p'_x and rotation per thread, from
@@ -370,9 +372,8 @@ __device__ __forceinline__ void t1m_item(const Geo &g, const T1G &G, const Inst 
 }
 
 template <int KSM>
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4, 4))) void t1_mfma_kernel(Geo g, const int *lo, const int *hi, const T1Item *items,
-                                                      const T1G *gdesc, const float *K, const Inst *D,
-                                                      const Rot *rots, int nq, int *qctr) {
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4, 4))) void t1_mfma_kernel(const int *lo, const int *hi, const T1Item *items,
+                                                      const Inst *D, int nq, int *qctr) {
     constexpr int RB = KSM * NTM * 64 + T1M_KLINE;
     static_assert(2 * RB >= 2 * MW * EPW, "epilogue fits the row buffers");
     __shared__ __align__(16) float buf[2 * RB];
@@ -408,15 +409,23 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
         // every buffer load becomes a loop over lanes)
         it = __builtin_amdgcn_readfirstlane(it);
         const T1Item item = items[it];
-        const T1G &G = gdesc[item.b];
         const Inst &I = D[item.inst];
+        // the instance's geometry, rows and descriptors: scalar loads (no
+        // kernel writes the instance table during the launch)
+        const Geo g = ld_uniform_geo(&I.geo);
+        const float *K = (const float *)ld_uniform_ptr(&I.K);
+        const Rot *rots = ld_uniform_ptr(&I.rots);
+        const T1G &G = ((const T1G *)ld_uniform_ptr(&I.t1d))[item.b];
         const int NT = (2 * G.nrot + 15) >> 4;
+        // the workgroup whose partial arrays the item adds into: static, the
+        // item's own list; dynamic, this one
+        const int pw = nq ? wg : __builtin_amdgcn_readfirstlane(item.slot);
         if (NT == 3)
-            t1m_item<KSM, 3>(g, G, I, K, rots, item.t0, wg, buf);
+            t1m_item<KSM, 3>(g, G, I, K, rots, item.t0, pw, buf);
         else if (NT == 2)
-            t1m_item<KSM, 2>(g, G, I, K, rots, item.t0, wg, buf);
+            t1m_item<KSM, 2>(g, G, I, K, rots, item.t0, pw, buf);
         else
-            t1m_item<KSM, 1>(g, G, I, K, rots, item.t0, wg, buf);
+            t1m_item<KSM, 1>(g, G, I, K, rots, item.t0, pw, buf);
     }
 }
 
@@ -429,18 +438,20 @@ int blocks_per_cu() {
 }  // namespace
 
 // rows hold at most N + 1 inner values: k-steps of 4 per row
-void launch_t1_mfma(const Geo &g, int nwg, const int *lo, const int *hi, const T1Item *items, const T1G *gdesc,
-                    const float *K, const Inst *D, const Rot *rots, int nq, int *qctr, hipStream_t s) {
-    if (g.N <= 34)
-        hipLaunchKernelGGL(t1_mfma_kernel<9>, dim3(nwg), dim3(NTH), 0, s, g, lo, hi, items, gdesc, K, D, rots, nq, qctr);
-    else if (g.N <= 50)
-        hipLaunchKernelGGL(t1_mfma_kernel<13>, dim3(nwg), dim3(NTH), 0, s, g, lo, hi, items, gdesc, K, D, rots, nq,
-                           qctr);
-    else
-        hipLaunchKernelGGL(t1_mfma_kernel<17>, dim3(nwg), dim3(NTH), 0, s, g, lo, hi, items, gdesc, K, D, rots, nq,
-                           qctr);
+int t1_mfma_class(int N) { return N <= 34 ? 9 : (N <= 50 ? 13 : 17); }
+
+void launch_t1_mfma(int Nmax, int nwg, const int *lo, const int *hi, const T1Item *items, const Inst *D, int nq,
+                    int *qctr, hipStream_t s) {
+    switch (t1_mfma_class(Nmax)) {
+        case 9: hipLaunchKernelGGL(t1_mfma_kernel<9>, dim3(nwg), dim3(NTH), 0, s, lo, hi, items, D, nq, qctr); break;
+        case 13: hipLaunchKernelGGL(t1_mfma_kernel<13>, dim3(nwg), dim3(NTH), 0, s, lo, hi, items, D, nq, qctr); break;
+        default: hipLaunchKernelGGL(t1_mfma_kernel<17>, dim3(nwg), dim3(NTH), 0, s, lo, hi, items, D, nq, qctr); break;
+    }
 }
 
-int t1_mfma_blocks_per_cu(int N) { return N <= 34 ? blocks_per_cu<9>() : (N <= 50 ? blocks_per_cu<13>() : blocks_per_cu<17>()); }
+int t1_mfma_blocks_per_cu(int N) {
+    const int c = t1_mfma_class(N);
+    return c == 9 ? blocks_per_cu<9>() : (c == 13 ? blocks_per_cu<13>() : blocks_per_cu<17>());
+}
 
 }  // namespace bnq

@@ -420,14 +420,12 @@ __device__ __forceinline__ const typename V2<T>::type *rotated_of(const Inst &I)
 // instance.  A long evaluation is cut into several launches, each over its
 // own ranges, which continue the same partial sums.
 template <typename T>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void trilinear_kernel(Geo g, const int *lo, const int *hi, const T1Item *items,
-                                                       const T1B *bdesc, const T *K, const Inst *D,
-                                                       const Rot *rots, int nq, int *qctr) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void trilinear_kernel(const int *lo, const int *hi, const T1Item *items,
+                                                       const Inst *D, int nq, int *qctr) {
     using T2 = typename V2<T>::type;
     __shared__ T2 pl[2][64];  // pair products of rows A and B, one p_x per lane
     const int slot = blockIdx.x;
     const int lane = threadIdx.x;
-    const int A = 2 * g.N - 1;
     int it = nq ? -1 : lo[slot] - 1;
     const int it_end = nq ? 0 : hi[slot];
     int q = nq ? (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) % (unsigned)nq) : 0;
@@ -452,9 +450,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
             it = got;
         }
         const T1Item item = items[it];
-        const T1B B = bdesc[item.b];
         const Inst &I = D[item.inst];
-        double2 *mypart = I.part + (int64_t)slot * g.nm;
+        // the instance's geometry, rows and descriptors: scalar loads (no
+        // kernel writes the instance table during the launch)
+        const Geo g = ld_uniform_geo(&I.geo);
+        const T *K = (const T *)ld_uniform_ptr(&I.K);
+        const Rot *rots = ld_uniform_ptr(&I.rots);
+        const T1B B = ((const T1B *)ld_uniform_ptr(&I.t1d))[item.b];
+        const int A = 2 * g.N - 1;
+        // static: the item's own list names its partial array; dynamic: the
+        // wave's slot
+        double2 *mypart = I.part + (int64_t)(nq ? slot : item.slot) * g.nm;
         const bool active = lane < item.nt;
         const int t = item.t0 + (active ? lane : 0);
         const int wny = B.wnhi[1] - B.wnlo[1] + 1;
@@ -536,11 +542,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tr
 
 }  // namespace
 
-void launch_t1_pairs(const Geo &g, int nslots, const int *lo, const int *hi, const T1Item *items,
-                     const T1B *bdesc, const double *K, const Inst *D, const Rot *rots, int nq, int *qctr,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(trilinear_kernel<double>, dim3(nslots), dim3(64), 0, s, g, lo, hi, items, bdesc, K, D,
-                       rots, nq, qctr);
+void launch_t1_pairs(int nslots, const int *lo, const int *hi, const T1Item *items, const Inst *D, int nq,
+                     int *qctr, hipStream_t s) {
+    hipLaunchKernelGGL(trilinear_kernel<double>, dim3(nslots), dim3(64), 0, s, lo, hi, items, D, nq, qctr);
 }
 
 int t1_pairs_blocks_per_cu() {

@@ -50,6 +50,9 @@ def test_batch_collide_bitwise_equals_solo():
         solo.append((Q, Qh))
     torch.cuda.synchronize()
     with bnq.Batch(plans, fs) as B:
+        # five (d, N, C_phi) groups; the trilinear sums of all six quantum
+        # members (three cells) share one launch per evaluation
+        assert B.layout() == (5, 1)
         Qs = [torch.full_like(f, np.nan) for f in fs]
         Qhs = [torch.zeros(f.shape, dtype=torch.complex128, device=f.device) for f in fs]
         B.collide(Qs, Qhs)
@@ -129,6 +132,7 @@ def test_dynamic_schedule_batch_matches_solo():
         solo.append(Q)
     torch.cuda.synchronize()
     with bnq.Batch(plans, fs) as B:
+        assert B.layout()[1] == 1  # one shared queue launch over (3, 6), (3, 8) and (2, 16)
         Qs = [torch.empty_like(f) for f in fs]
         B.collide(Qs)
         torch.cuda.synchronize()

@@ -80,11 +80,58 @@ def test_fp32c_and_fp64_instances_in_one_batch():
         solo.append(Q)
     torch.cuda.synchronize()
     with bnq.Batch(plans, fs) as B:
+        # groups (3, 6) FP32c, (3, 6) FP64, (2, 16) FP32c; one shared
+        # trilinear launch per precision
+        assert B.layout() == (3, 2)
         Qs = [torch.empty_like(f) for f in fs]
         B.collide(Qs)
         torch.cuda.synchronize()
     for i, (a, b) in enumerate(zip(solo, Qs)):
         assert torch.equal(a, b), f"instance {i} differs from its solo evaluation"
+    for pl in plans:
+        pl.close()
+
+
+@pytest.mark.parametrize("schedule", ["static", "dynamic"])
+def test_fp32c_mixed_cells_share_one_trilinear_launch(schedule):
+    """Instances of five cells in FP32c, stepped as one graph-replayed batch
+    whose trilinear sums run as one matrix-core launch per stage: bitwise
+    the solo trajectories (static), within 1e-12 of them (dynamic tickets
+    change the summation order), and within the FP32c bar of the oracle's
+    RK4 step for the 2-D instances and the 3-D N = 6 one."""
+    import oracle
+    from tests.parity import check
+    dev = torch.device("cuda:0")
+    sched = bnq.SCHED_STATIC if schedule == "static" else bnq.SCHED_DYNAMIC
+    specs = [(2, 8, 1), (2, 16, -1), (3, 6, -1), (3, 8, 1), (3, 8, -1), (2, 12, 0)]
+    L, dt = 5.0, 0.002
+    plans, fb, fsolo, f0s = [], [], [], []
+    for i, (d, N, eps) in enumerate(specs):
+        f = inp.gaussian_mixture(d, N, L, seed=90 + i, fmax=0.9 if eps == -1 else None)
+        plans.append(bnq.Plan(bnq.Params(d=d, N=N, eps=eps, L=L, precision=bnq.FP32C, schedule=sched)))
+        fb.append(torch.tensor(f, device=dev))
+        fsolo.append(torch.tensor(f, device=dev))
+        f0s.append(f)
+    for pl, f in zip(plans, fsolo):
+        pl.step(f, dt, bnq.RK4)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with bnq.Batch(plans, fb) as B:
+        assert B.layout() == (5, 1)  # (3, 8) eps = +-1 are one group
+        B.step(dt, bnq.RK4, graph=True, stream=s)
+        s.synchronize()
+    for i, (a, b) in enumerate(zip(fsolo, fb)):
+        if sched == bnq.SCHED_STATIC:
+            assert torch.equal(a, b), f"instance {i} differs from its solo step"
+        else:
+            r = (torch.linalg.norm(a - b) / torch.linalg.norm(a)).item()
+            assert r <= 1e-12, f"instance {i}: {r}"
+    for i, (d, N, eps) in enumerate(specs):
+        if d == 3 and N > 6:
+            continue  # the oracle's 3-D N = 8 RK4 step takes half a minute
+        ref = oracle.Oracle(d, N).rk4_step(f0s[i], dt, eps, L)
+        check(fb[i].cpu().numpy(), ref, tol=TOL32)
     for pl in plans:
         pl.close()
 
