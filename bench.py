@@ -33,7 +33,7 @@ STATS = {-1: "fermions", 0: "classical", 1: "bosons"}
 METRIC = "collision pair-terms/s at N=32^3 (FP32c vs FP64); p50/p99 solve latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trilinear_3d32_fp64_hbm_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_13735_amd", "csrc", "t1_pairs.hip")
-PAIRS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairs_3d32_fp64_hbm_traffic.json")
+PAIRS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pairs_3d32_hbm_traffic.json")
 # the pair-sum kernels and the header that fixes their l-chunking (pair_split)
 PAIRS_SOURCE = (os.path.join(ROOT, "paper_2110_13735_amd", "csrc", "collide.hip"),
                 os.path.join(ROOT, "paper_2110_13735_amd", "csrc", "bnq_internal.h"))
@@ -99,7 +99,7 @@ def measured_traffic():
 
 
 def measured_pairs_traffic(kernel):
-    """The same for a pair-sum kernel (3-D N=32 FP64), keyed by kernel name."""
+    """The same for a pair-sum kernel (3-D N=32, FP64 or FP32c), keyed by kernel name."""
     if not os.path.exists(PAIRS_TRAFFIC_FILE):
         return None
     with open(PAIRS_TRAFFIC_FILE) as fh:
@@ -271,7 +271,8 @@ def main():
         pr_avg_s = (pr_ms / pr_n) * 1e-3 if pr_n else float("nan")
         bytes_launch = counts["classical"] * (4 if prec == bnq.FP32C else 8)
         achieved = bytes_launch / pr_avg_s / 1e9
-        tr = measured_pairs_traffic("pairs_kernel<double, false>") if (prec == bnq.FP64 and N == 32) else None
+        tr = measured_pairs_traffic(f"pairs_kernel<{'float' if prec == bnq.FP32C else 'double'}, false>") \
+            if N == 32 else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": round(achieved / PEAK_HBM_GBS, 4),
                     "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None, "kernel": "pairs_kernel",
@@ -398,7 +399,8 @@ def sub_eps0(args, f0, steps=10):
         pr_s = pr_ms / pr_n * 1e-3
         nbytes = plan.counts()["classical"] * (4 if prec == bnq.FP32C else 8)
         gbs = nbytes / pr_s / 1e9
-        tr = measured_pairs_traffic("pairs_kernel<double, false>") if (prec == bnq.FP64 and args.N == 32) else None
+        tr = measured_pairs_traffic(f"pairs_kernel<{'float' if prec == bnq.FP32C else 'double'}, false>") \
+            if args.N == 32 else None
         res[name] = {"value": 4.0 * terms * steps / elapsed, "unit": "pair-terms/s", "steps": steps,
                      "ms_per_step": 1e3 * elapsed / steps,
                      "roofline": {"bound": "hbm", "kernel": "pairs_kernel", "avg_ms": round(pr_s * 1e3, 4),
