@@ -740,6 +740,8 @@ def run_batch(args):
     plans, f_b, f_s, terms = [], [], [], 0.0
     tuned, tune_ms, tuned_pairs = set(), {}, {}
     for i in range(args.instances):
+        if i and i % 64 == 0:
+            _progress(f"{i} plans created")
         d, N, eps = cells[i % len(cells)]
         f0, L = inp.mixed_instance(d, N, eps, seed=i)
         p = bnq.Params(d=d, N=N, eps=eps, L=L, precision=prec, schedule=sched,
@@ -774,8 +776,11 @@ def run_batch(args):
               f"{layout[0]} groups, {layout[1]} shared trilinear launch(es) per stage")
 
     def solo_step():
-        for pl, f in zip(plans, f_s):
+        for j, (pl, f) in enumerate(zip(plans, f_s)):
             pl.step(f, dt)
+            if len(plans) > 144 and (j + 1) % 64 == 0:
+                torch.cuda.synchronize()
+                _progress(f"solo: {j + 1} of {len(plans)} instances stepped")
 
     for w in range(args.warmup):
         batch.step(dt, bnq.RK4, graph=True, stream=stream)
