@@ -423,13 +423,15 @@ bnq_status bnq_tune_set(int32_t d, int32_t N, int32_t precision, int32_t choice)
  * 16 otherwise (at most N).  The split changes the summation order, hence the
  * last bits of a result, within the parity tolerance.
  * bnq_plan_autotune_pairs(): times the pair sums (classical, and W when the
- *   plan has them) with 8, 16 and 32 slices (those <= min(N, 32)) on f
+ *   plan has them) with 8, 16 and 32 slices, each capped at min(N, 32) (a
+ *   count that repeats the previous one is not run again), on f
  *   (device, the plan's layout; one evaluation first forms the spectrum),
  *   reps timed runs each; keeps the fastest for this plan and records it for
  *   plans created afterwards.  ms_host (optional, 3 doubles): mean time of
  *   each candidate (0 where not run); split_host (optional): the split kept.
- *   Synchronises the stream.  Errors: EINVAL (also while a batch holds the
- *   plan), ENOMEM, EHIP.
+ *   Synchronises the stream.  A plan without pair sums keeps its split and
+ *   records nothing.  Errors: EINVAL (also while a batch holds the plan),
+ *   ENOMEM, EHIP.
  * bnq_tune_pairs_get(): *split = the recorded split for (d, N, precision,
  *   eps == 0) on the current device, or 0 if none.
  * bnq_tune_pairs_set(): records split (1 .. min(N, 32); 0 removes the record).
