@@ -194,3 +194,34 @@ def test_graph_replayed_batch_matches_oracle():
         assert err <= 1e-12, f"instance {i} {MIX[i]}: relative error {err:.2e}"
     for pl in plans:
         pl.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_shared_launch_cut_into_chunks_is_bitwise_solo(prec):
+    """Two 3-D N=32 quantum instances carry more than 2e13 trilinear terms, so
+    the shared trilinear sum of this batch runs as several launches per
+    evaluation, cut by item cost across instances of three sizes; under the
+    static schedule every instance is still bitwise its solo evaluation."""
+    dev = torch.device("cuda:0")
+    P = bnq.FP32C if prec == "fp32c" else bnq.FP64
+    specs = [(3, 32, -1), (3, 32, 1), (3, 24, -1), (2, 32, 1)]
+    plans, fs = [], []
+    for i, (d, N, eps) in enumerate(specs):
+        f = inp.gaussian_mixture(d, N, 6.0, seed=110 + i, fmax=0.9 if eps == -1 else None)
+        plans.append(bnq.Plan(bnq.Params(d=d, N=N, eps=eps, L=6.0, precision=P)))
+        fs.append(torch.tensor(f, device=dev))
+    solo = []
+    for pl, f in zip(plans, fs):
+        Qh = torch.empty(f.shape, dtype=torch.complex128, device=dev)
+        pl.collide(f, torch.empty_like(f), Qh)
+        solo.append(Qh)
+    torch.cuda.synchronize()
+    with bnq.Batch(plans, fs) as B:
+        assert B.layout() == (3, 1)
+        Qhs = [torch.zeros(f.shape, dtype=torch.complex128, device=dev) for f in fs]
+        B.collide([torch.empty_like(f) for f in fs], Qhs)
+        torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(solo, Qhs)):
+        assert torch.equal(a, b), f"instance {i} differs from its solo evaluation"
+    for pl in plans:
+        pl.close()
