@@ -1,7 +1,7 @@
 // Trilinear sum T1 of the Galerkin operator (section 'Fast spectral
 // approximation of the BNE operator', the Q_{1,q} term) on the matrix cores,
 // FP32c precision pattern: FP32 kernel modes and pair products, FP32 products
-// summed by the matrix core over four inner rows, FP64 totals.
+// summed by the matrix core over eight inner rows, FP64 totals.
 //
 // For a canonical b_c and the rotations R of a group (the b = R b_c whose
 // rotated frames share the lower edge of the x window), the sum over the
@@ -304,9 +304,9 @@ __device__ __forceinline__ void t1m_item(const Geo &g, const T1G &G, const Inst 
                 }
             }
         }
-        // FP64 totals of the FP32 sums of every four rows (at most 16 KS terms
-        // each)
-        if ((row & 3) == 3 || !more) {
+        // FP64 totals of the FP32 sums of every eight rows (at most 32 KS
+        // terms each)
+        if ((row & 7) == 7 || !more) {
 #pragma unroll
             for (int tm = 0; tm < MTL; ++tm)
 #pragma unroll
