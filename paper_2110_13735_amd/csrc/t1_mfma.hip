@@ -281,7 +281,11 @@ __device__ __forceinline__ void t1m_item(const Geo &g, const T1G &G, const Inst 
         const float *bf = buf + cur * RB;
         const float *kl = bf + BF;
         // operands in chunks of three k-steps (entries past the row are
-        // finite values of the buffer that no matrix product uses)
+        // finite values of the buffer that no matrix product uses); the
+        // waves issue them at raised priority, so that a wave with matrix
+        // products to issue goes before the other waves' staging
+        // instructions (529.7 against 537.0 ms per evaluation at 3-D N=32)
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int s0 = 0; s0 < KSM; s0 += 3) {
             if (s0 < KS) {
@@ -304,6 +308,7 @@ __device__ __forceinline__ void t1m_item(const Geo &g, const T1G &G, const Inst 
                 }
             }
         }
+        __builtin_amdgcn_s_setprio(0);
         // FP64 totals of the FP32 sums of every eight rows (at most 32 KS
         // terms each)
         if ((row & 7) == 7 || !more) {
